@@ -1,0 +1,478 @@
+"""Plain FP64 CPU oracle for the TMOP hot path.  TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this module.  The GPU library never calls it and shares
+no code with it: it builds its own basis tables, its own metric derivatives
+and its own solver.
+
+Source: Dobrev, Knupp, Kolev, Mittal, Tomov, "The Target-Matrix Optimization
+Paradigm for High-Order Meshes" (arXiv:1807.09807).  Every function below
+names the passage it follows.  The oracle computes the plain definitions:
+
+* the basis gradients at every quadrature point form a dense table and the
+  Jacobian A = sum_i x_i (grad w_i)^T is a dense contraction (eq. 2.2) -- no
+  sum factorization;
+* mu is evaluated from its definition (Table 3.1 and Section 3.2) with
+  numpy's det/inv; its first and second derivatives in T are the invariant
+  forms the paper recommends (Section 3.4), pinned by complex-step tests;
+* F_V (eq. 2.4) is summed with math.fsum (exactly rounded);
+* the gradient (Section 3.4) and the Hessian action are assembled
+  element by element and scattered with numpy.add.at;
+* Newton's method with the positivity / 1.2-growth line search follows
+  Section 3.4, with truncated CG (Steihaug) as the inner solver.
+
+Readings where the paper is silent: reference element [0,1]^d; nodal basis =
+Lagrange polynomials at the Gauss-Lobatto-Legendre points; Gauss-Legendre
+quadrature on [0,1]; x stored as (d, n_node).
+
+Everything is written dtype-generic (no abs, no conj, no maximum on the
+data path) so that a complex-step derivative can run through the whole
+objective.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+METRICS_2D = (2, 7)
+METRICS_3D = (302, 303)
+
+
+# ---------------------------------------------------------------------------
+# Section 2.1 / Section 3.3: 1D points, weights and Lagrange basis
+
+def gll_nodes(p: int) -> np.ndarray:
+    """GLL points on [0,1]: 0, 1 and the interior roots of P_p'.  The interior
+    roots are the eigenvalues of the symmetric tridiagonal Jacobi matrix of
+    the Jacobi(1,1) polynomials, whose off-diagonal entries are
+    sqrt(k(k+2) / ((2k+1)(2k+3))), k = 1..p-2."""
+    if p < 1:
+        raise ValueError("p >= 1")
+    if p == 1:
+        t = np.array([-1.0, 1.0])
+    else:
+        k = np.arange(1, p - 1, dtype=np.float64)
+        off = np.sqrt(k * (k + 2.0) / ((2.0 * k + 1.0) * (2.0 * k + 3.0)))
+        J = np.diag(off, 1) + np.diag(off, -1)
+        inner = np.sort(np.linalg.eigvalsh(J)) if p > 2 else np.array([0.0])
+        t = np.concatenate(([-1.0], inner, [1.0]))
+    return (t + 1.0) / 2.0
+
+
+def gauss_legendre(Q: int):
+    """Q-point Gauss-Legendre rule mapped to [0,1] (Section 3.3); weights
+    sum to 1."""
+    t, w = np.polynomial.legendre.leggauss(Q)
+    return (t + 1.0) / 2.0, w / 2.0
+
+
+def gauss_lobatto(Q: int):
+    """Q-point Gauss-Lobatto rule on [0,1] (the rule of Section 5): the GLL
+    points with weights 2/(Q(Q-1) P_{Q-1}(t)^2) on [-1,1], halved."""
+    s = gll_nodes(Q - 1)
+    t = 2.0 * s - 1.0
+    PQ = np.polynomial.legendre.Legendre.basis(Q - 1)(t)
+    w = 2.0 / (Q * (Q - 1) * PQ ** 2)
+    return s, w / 2.0
+
+
+def lagrange(nodes: np.ndarray, s: np.ndarray):
+    """Values L[k, a] = l_a(s_k) and derivatives G[k, a] = l_a'(s_k) of the
+    Lagrange polynomials through `nodes`, from the product formula."""
+    n = nodes.size
+    dt = np.result_type(s, np.float64)
+    L = np.ones((s.size, n), dtype=dt)
+    G = np.zeros((s.size, n), dtype=dt)
+    for a in range(n):
+        for b in range(n):
+            if b != a:
+                L[:, a] *= (s - nodes[b]) / (nodes[a] - nodes[b])
+        for k in range(n):
+            if k == a:
+                continue
+            term = np.full(s.size, 1.0 / (nodes[a] - nodes[k]), dtype=dt)
+            for b in range(n):
+                if b != a and b != k:
+                    term *= (s - nodes[b]) / (nodes[a] - nodes[b])
+            G[:, a] += term
+    return L, G
+
+
+def dense_tables(dim: int, p: int, Q: int, rule: str = "gl"):
+    """Dense table D[q, i, l] = d w_i / d xbar_l at quadrature point q and
+    the tensor weights wq[q] (eq. 2.2, Section 3.3).  Local node index
+    i = i0 + (p+1) i1 (+ (p+1)^2 i2); quadrature index q = q0 + Q q1 (+ Q^2 q2)."""
+    s, w1 = gauss_legendre(Q) if rule == "gl" else gauss_lobatto(Q)
+    L, G = lagrange(gll_nodes(p), s)
+    P1 = p + 1
+    if dim == 2:
+        D = np.zeros((Q, Q, P1, P1, 2))
+        # axes: q1, q0, i1, i0
+        D[..., 0] = G[None, :, None, :] * L[:, None, :, None]
+        D[..., 1] = L[None, :, None, :] * G[:, None, :, None]
+        wq = (w1[:, None] * w1[None, :]).ravel()
+        return D.reshape(Q * Q, P1 * P1, 2), wq
+    D = np.zeros((Q, Q, Q, P1, P1, P1, 3))
+    # axes: q2, q1, q0, i2, i1, i0
+    D[..., 0] = G[None, None, :, None, None, :] * L[None, :, None, None, :, None] * L[:, None, None, :, None, None]
+    D[..., 1] = L[None, None, :, None, None, :] * G[None, :, None, None, :, None] * L[:, None, None, :, None, None]
+    D[..., 2] = L[None, None, :, None, None, :] * L[None, :, None, None, :, None] * G[:, None, None, :, None, None]
+    wq = (w1[:, None, None] * w1[None, :, None] * w1[None, None, :]).ravel()
+    return D.reshape(Q ** 3, P1 ** 3, 3), wq
+
+
+# ---------------------------------------------------------------------------
+# Section 3.2, Table 3.1: metrics by definition
+
+def _det(T):
+    return np.linalg.det(T)
+
+
+def _frob2(M):
+    return np.sum(M * M, axis=(-2, -1))
+
+
+def mu(metric: int, T: np.ndarray) -> np.ndarray:
+    """mu(T) for T of shape (..., d, d).
+    2:   |T|^2 / (2 tau) - 1                 (Table 3.1, shape, 2D)
+    7:   |T - T^{-t}|^2                       (Section 3.2, shape+size, 2D)
+    303: |T|^2 / (3 tau^{2/3}) - 1           (Table 3.1, shape, 3D)
+    302: |T|^2 |T^{-1}|^2 / 9 - 1            (3D shape metric of the workloads)
+    with tau = det T and |.| the Frobenius norm."""
+    tau = _det(T)
+    I1 = _frob2(T)
+    if metric == 2:
+        return I1 / (2.0 * tau) - 1.0
+    if metric == 7:
+        Tinv_t = np.swapaxes(np.linalg.inv(T), -1, -2)
+        return _frob2(T - Tinv_t)
+    if metric == 303:
+        return I1 / (3.0 * tau ** (2.0 / 3.0)) - 1.0
+    if metric == 302:
+        return I1 * _frob2(np.linalg.inv(T)) / 9.0 - 1.0
+    raise ValueError(f"unknown metric {metric}")
+
+
+# Invariant forms of the derivatives (Section 3.4: write mu through matrix
+# invariants).  mu = f(I1, I2, tau), I1 = |T|^2, tau = det T, C = cof T =
+# d tau / dT, I2 = |C|^2 (3D only).
+
+def cof(T):
+    """Cofactor matrix C = d(det T)/dT."""
+    d = T.shape[-1]
+    if d == 2:
+        C = np.empty_like(T)
+        C[..., 0, 0] = T[..., 1, 1]
+        C[..., 0, 1] = -T[..., 1, 0]
+        C[..., 1, 0] = -T[..., 0, 1]
+        C[..., 1, 1] = T[..., 0, 0]
+        return C
+    r0, r1, r2 = T[..., 0, :], T[..., 1, :], T[..., 2, :]
+    return np.stack([_cross(r1, r2), _cross(r2, r0), _cross(r0, r1)], axis=-2)
+
+
+def dcof(T, E):
+    """Directional derivative of cof at T along E."""
+    d = T.shape[-1]
+    if d == 2:
+        return cof(E)
+    t0, t1, t2 = T[..., 0, :], T[..., 1, :], T[..., 2, :]
+    e0, e1, e2 = E[..., 0, :], E[..., 1, :], E[..., 2, :]
+    return np.stack([_cross(e1, t2) + _cross(t1, e2),
+                     _cross(e2, t0) + _cross(t2, e0),
+                     _cross(e0, t1) + _cross(t0, e1)], axis=-2)
+
+
+def _cross(a, b):
+    return np.stack([a[..., 1] * b[..., 2] - a[..., 2] * b[..., 1],
+                     a[..., 2] * b[..., 0] - a[..., 0] * b[..., 2],
+                     a[..., 0] * b[..., 1] - a[..., 1] * b[..., 0]], axis=-1)
+
+
+def _ddot(A, B):
+    return np.sum(A * B, axis=(-2, -1))
+
+
+def _mm(A, B):
+    return np.einsum("...ij,...jk->...ik", A, B)
+
+
+def _tr(A):
+    return np.swapaxes(A, -1, -2)
+
+
+def _partials(metric, I1, I2, tau):
+    """f and its partials (f1, f2, ft, f11, f12, f1t, f22, f2t, ftt) of
+    mu = f(I1, I2, tau)."""
+    z = 0.0 * tau
+    if metric == 2:          # f = I1/(2 tau) - 1
+        return dict(f1=1.0 / (2.0 * tau), f2=z, ft=-I1 / (2.0 * tau ** 2),
+                    f11=z, f12=z, f1t=-1.0 / (2.0 * tau ** 2), f22=z, f2t=z, ftt=I1 / tau ** 3)
+    if metric == 7:          # |T - T^-t|^2 = I1 + |T^-1|^2 - 4, |T^-1|^2 = I1/tau^2 in 2D
+        return dict(f1=1.0 + tau ** -2, f2=z, ft=-2.0 * I1 * tau ** -3,
+                    f11=z, f12=z, f1t=-2.0 * tau ** -3, f22=z, f2t=z, ftt=6.0 * I1 * tau ** -4)
+    if metric == 303:        # f = I1 tau^{-2/3} / 3 - 1
+        t23 = tau ** (-2.0 / 3.0)
+        return dict(f1=t23 / 3.0, f2=z, ft=-(2.0 / 9.0) * I1 * t23 / tau,
+                    f11=z, f12=z, f1t=-(2.0 / 9.0) * t23 / tau, f22=z, f2t=z,
+                    ftt=(10.0 / 27.0) * I1 * t23 / tau ** 2)
+    if metric == 302:        # |T^-1|^2 = I2/tau^2 in 3D: f = I1 I2 tau^-2 / 9 - 1
+        return dict(f1=I2 * tau ** -2 / 9.0, f2=I1 * tau ** -2 / 9.0, ft=-2.0 * I1 * I2 * tau ** -3 / 9.0,
+                    f11=z, f12=tau ** -2 / 9.0, f1t=-2.0 * I2 * tau ** -3 / 9.0,
+                    f22=z, f2t=-2.0 * I1 * tau ** -3 / 9.0, ftt=6.0 * I1 * I2 * tau ** -4 / 9.0)
+    raise ValueError(f"unknown metric {metric}")
+
+
+def _inv(T):
+    I1 = _frob2(T)
+    tau = _det(T)
+    C = cof(T)
+    I2 = _frob2(C)
+    return I1, I2, tau, C
+
+
+def dmu(metric: int, T: np.ndarray) -> np.ndarray:
+    """First derivative P = d mu / dT (the matrix of Section 3.4)."""
+    I1, I2, tau, C = _inv(T)
+    f = _partials(metric, I1, I2, tau)
+    e = lambda s: s[..., None, None]
+    dI2 = 2.0 * (e(I1) * T - _mm(_mm(T, _tr(T)), T))
+    return e(f["f1"]) * 2.0 * T + e(f["f2"]) * dI2 + e(f["ft"]) * C
+
+
+def d2mu(metric: int, T: np.ndarray, E: np.ndarray) -> np.ndarray:
+    """Second derivative of mu applied to a direction: dP = d/de P(T + e E)
+    at e = 0 (the Hessian ingredient of Section 3.4)."""
+    I1, I2, tau, C = _inv(T)
+    f = _partials(metric, I1, I2, tau)
+    e = lambda s: s[..., None, None]
+    TtT = _mm(_tr(T), T)
+    dI2 = 2.0 * (e(I1) * T - _mm(T, TtT))
+    ddI2 = 2.0 * (2.0 * e(_ddot(T, E)) * T + e(I1) * E
+                  - _mm(E, TtT) - _mm(_mm(T, _tr(E)), T) - _mm(_mm(T, _tr(T)), E))
+    a1 = 2.0 * _ddot(T, E)
+    a2 = _ddot(dI2, E)
+    at = _ddot(C, E)
+    return (e(f["f1"]) * 2.0 * E + e(f["f2"]) * ddI2 + e(f["ft"]) * dcof(T, E)
+            + 2.0 * T * e(f["f11"] * a1 + f["f12"] * a2 + f["f1t"] * at)
+            + dI2 * e(f["f12"] * a1 + f["f22"] * a2 + f["f2t"] * at)
+            + C * e(f["f1t"] * a1 + f["f2t"] * a2 + f["ftt"] * at))
+
+
+# ---------------------------------------------------------------------------
+# Section 2.2-2.3, eq. 2.4: the variational objective and its derivatives
+
+class Problem:
+    """F_V(x) = sum_E sum_q w_q det W mu(A W^{-1}) on a Q_p quad/hex mesh.
+
+    elem_node: (n_elem, (p+1)^d) int array, lexicographic local node order.
+    W: None (identity), a (d, d) matrix, per-element (n_elem, d, d) or
+       per-quadrature-point (n_elem, Q^d, d, d) targets; det W > 0
+       (Section 3.1).
+    """
+
+    def __init__(self, dim, order, n_q1d, elem_node, metric, W=None, rule="gl", chunk=4096):
+        if dim == 2 and metric not in METRICS_2D or dim == 3 and metric not in METRICS_3D:
+            raise ValueError("metric/dimension mismatch")
+        self.dim, self.order, self.Q, self.metric = dim, order, n_q1d, metric
+        self.elem_node = np.asarray(elem_node, dtype=np.int64)
+        self.n_elem = self.elem_node.shape[0]
+        self.D, self.wq = dense_tables(dim, order, n_q1d, rule)
+        self.nq = self.wq.size
+        W = np.eye(dim) if W is None else np.asarray(W, dtype=np.float64)
+        detW = np.linalg.det(W)
+        if np.any(detW <= 0):
+            raise ValueError("target matrices need det W > 0 (Section 3.1)")
+        self.Winv = np.linalg.inv(W)
+        self.detW = detW
+        self.chunk = chunk
+
+    # per-chunk target data broadcast to (ne, nq, d, d) / (ne, nq)
+    def _targets(self, e0, e1):
+        Wi, dW = self.Winv, self.detW
+        if Wi.ndim == 2:
+            return Wi[None, None], np.broadcast_to(dW, (1, 1))
+        if Wi.ndim == 3:
+            return Wi[e0:e1, None], dW[e0:e1, None]
+        return Wi[e0:e1], dW[e0:e1]
+
+    def _jac(self, x, e0, e1):
+        """A[e, q, c, l] = sum_i x_{node(e,i), c} dw_i/dxbar_l (eq. 2.2)."""
+        X = x[:, self.elem_node[e0:e1]]                  # (d, ne, N)
+        return np.einsum("cei,qil->eqcl", X, self.D)
+
+    def _chunks(self):
+        for e0 in range(0, self.n_elem, self.chunk):
+            yield e0, min(e0 + self.chunk, self.n_elem)
+
+    def pointwise(self, x):
+        """Per point contributions w_q det W mu(T) and det A, shape (n_elem, nq)."""
+        contrib, detA = [], []
+        for e0, e1 in self._chunks():
+            A = self._jac(x, e0, e1)
+            Wi, dW = self._targets(e0, e1)
+            T = _mm(A, Wi)
+            contrib.append(self.wq[None, :] * dW * mu(self.metric, T))
+            detA.append(_det(A))
+        return np.concatenate(contrib), np.concatenate(detA)
+
+    def energy(self, x):
+        """(F_V, min det A) -- eq. 2.4 summed with math.fsum; positivity is
+        judged at the quadrature points (Section 3.4)."""
+        c, detA = self.pointwise(x)
+        if np.iscomplexobj(c):
+            F = math.fsum(c.real.ravel()) + 1j * math.fsum(c.imag.ravel())
+            return F, float(np.min(detA.real))
+        return math.fsum(c.ravel()), float(np.min(detA))
+
+    def element_min_det(self, x):
+        _, detA = self.pointwise(x)
+        return np.min(np.real(detA), axis=1)
+
+    def bad_elements(self, x):
+        return np.flatnonzero(self.element_min_det(x) <= 0.0)
+
+    def _assemble(self, Y, e0, e1, out):
+        """out[c, node(e,i)] += sum_q sum_l Y[e,q,c,l] dw_i/dxbar_l."""
+        G = np.einsum("eqcl,qil->cei", Y, self.D)
+        for c in range(self.dim):
+            np.add.at(out[c], self.elem_node[e0:e1], G[c])
+
+    def gradient(self, x):
+        """dF_V/dx (Section 3.4): sum_E sum_q w_q det W (P W^{-t}) grad w_i,
+        full (all DOFs, boundary included)."""
+        g = np.zeros(x.shape, dtype=np.result_type(x, np.float64))
+        for e0, e1 in self._chunks():
+            A = self._jac(x, e0, e1)
+            Wi, dW = self._targets(e0, e1)
+            P = dmu(self.metric, _mm(A, Wi))
+            Y = (self.wq[None, :] * dW)[..., None, None] * _mm(P, _tr(Wi))
+            self._assemble(Y, e0, e1, g)
+        return g
+
+    def hessian_apply(self, x, v):
+        """(d^2 F_V / dx^2) v with dT = dA W^{-1}, dA from v as in eq. 2.2,
+        and the second derivative of mu applied to dT (Section 3.4)."""
+        Hv = np.zeros(x.shape, dtype=np.result_type(x, v, np.float64))
+        for e0, e1 in self._chunks():
+            A = self._jac(x, e0, e1)
+            dA = self._jac(v, e0, e1)
+            Wi, dW = self._targets(e0, e1)
+            dP = d2mu(self.metric, _mm(A, Wi), _mm(dA, Wi))
+            Y = (self.wq[None, :] * dW)[..., None, None] * _mm(dP, _tr(Wi))
+            self._assemble(Y, e0, e1, Hv)
+        return Hv
+
+
+# ---------------------------------------------------------------------------
+# Section 3.4: Newton's method with the scaled update and line search
+
+@dataclass
+class NewtonOptions:
+    rtol: float = 1e-12          # Newton relative tolerance (Section 5)
+    atol: float = 0.0            # absolute floor on |g| (for meshes already at the optimum)
+    max_it: int = 50
+    cg_rtol: float = 1e-8
+    cg_max_it: int = 1000
+    ls_shrink: float = 0.5
+    ls_max: int = 30
+    f_growth: float = 1.2        # F(x+) < 1.2 F(x)
+    g_growth: float = 1.2        # |g(x+)| < 1.2 |g(x)|
+
+
+STOP_CONVERGED, STOP_MAXIT, STOP_LSFAIL, STOP_INVERTED = 0, 1, 2, 3
+
+
+@dataclass
+class NewtonReport:
+    iters: int = 0
+    cg_iters: int = 0
+    ls_shrinks: int = 0
+    stop: int = STOP_MAXIT
+    F0: float = 0.0
+    F: float = 0.0
+    gnorm0: float = 0.0
+    gnorm: float = 0.0
+    min_detA: float = 0.0
+    history: list = field(default_factory=list)   # per iteration: (F, |g|, alpha, cg_iters, neg_curv)
+
+
+def truncated_cg(apply_H, g, rtol, max_it):
+    """Steihaug's truncated conjugate gradients for H d = -g from d = 0: on
+    non-positive curvature return -g at the first step, else the current
+    iterate.  Returns (d, iterations, negative-curvature flag)."""
+    d = np.zeros_like(g)
+    r = -g
+    p = r.copy()
+    rr = float(np.dot(r, r))
+    gnorm = math.sqrt(float(np.dot(g, g)))
+    for j in range(max_it):
+        Hp = apply_H(p)
+        pHp = float(np.dot(p, Hp))
+        if pHp <= 0.0:
+            return (-g if j == 0 else d), j + 1, True
+        alpha = rr / pHp
+        d = d + alpha * p
+        r = r - alpha * Hp
+        rr_new = float(np.dot(r, r))
+        if math.sqrt(rr_new) <= rtol * gnorm:
+            return d, j + 1, False
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return d, max_it, False
+
+
+def newton_solve(prob: Problem, x0, fixed, opts: NewtonOptions = NewtonOptions()):
+    """Minimize F_V over the free DOFs (fixed[c, I] = 1 marks Dirichlet).
+
+    Each iteration: masked gradient g, truncated-CG direction on the masked
+    Hessian, then alpha = 1, 1/2, ... until the new mesh has det A > 0 at
+    every quadrature point, F(x+) < 1.2 F(x) and |g(x+)| < 1.2 |g(x)|;
+    stops when no alpha works (Section 3.4), when |g| <= rtol |g0|
+    (Section 5), or after max_it iterations."""
+    m = (1 - np.asarray(fixed, dtype=np.float64)).ravel()
+    shape = x0.shape
+    x = np.array(x0, dtype=np.float64).ravel()
+    rep = NewtonReport()
+    F, mindet = prob.energy(x.reshape(shape))
+    rep.F0, rep.F, rep.min_detA = F, F, mindet
+    if mindet <= 0.0:
+        rep.stop = STOP_INVERTED
+        return x.reshape(shape), rep
+    grad = lambda y: m * prob.gradient(y.reshape(shape)).ravel()
+    g = grad(x)
+    gn = math.sqrt(float(np.dot(g, g)))
+    rep.gnorm0 = rep.gnorm = gn
+    rep.history.append((F, gn, 0.0, 0, False))
+    for it in range(opts.max_it):
+        if gn <= max(opts.rtol * rep.gnorm0, opts.atol):
+            rep.stop = STOP_CONVERGED
+            break
+        Hm = lambda p: m * prob.hessian_apply(x.reshape(shape), (m * p).reshape(shape)).ravel()
+        dvec, ncg, neg = truncated_cg(Hm, g, opts.cg_rtol, opts.cg_max_it)
+        rep.cg_iters += ncg
+        accepted = False
+        for k in range(opts.ls_max):
+            alpha = opts.ls_shrink ** k
+            xt = x + alpha * dvec
+            Ft, mindet_t = prob.energy(xt.reshape(shape))
+            if mindet_t > 0.0 and Ft < opts.f_growth * F:
+                gt = grad(xt)
+                gnt = math.sqrt(float(np.dot(gt, gt)))
+                if gnt < opts.g_growth * gn:
+                    accepted = True
+                    break
+            rep.ls_shrinks += 1
+        if not accepted:
+            rep.stop = STOP_LSFAIL
+            break
+        x, F, g, gn, mindet = xt, Ft, gt, gnt, mindet_t
+        rep.iters = it + 1
+        rep.history.append((F, gn, alpha, ncg, neg))
+    else:
+        rep.stop = STOP_CONVERGED if gn <= max(opts.rtol * rep.gnorm0, opts.atol) else STOP_MAXIT
+    rep.F, rep.gnorm, rep.min_detA = F, gn, mindet
+    return x.reshape(shape), rep
