@@ -1,0 +1,228 @@
+"""Throughput of the TMOP hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload q2_cube_64]
+
+A step is one pass of the element operations over the whole mesh: energy
+(with min det A), gradient and Hessian action, each on all elements.  The
+metric is DOF-iterations/s = (dim * n_node) / (seconds per step), inputs
+resident in HBM.  Printed as one JSON line.  The FP64 path is the headline
+value; the mixed FP32 path, per-operation times, the roofline of the
+Hessian-action kernel, Newton wall time to the F tolerance and the CPU
+oracle baseline are reported alongside.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1807_09807_amd import meshgen  # noqa: E402
+
+# Algorithmic work per element: the sum-factorized contractions plus the
+# per-point arithmetic of the element kernels (an FMA counts 2 flops, a
+# division or cube root 1), counted from the kernel source.
+HBM_PEAK = 8.0e12          # B/s
+FP64_PEAK = 78.6e12        # FLOP/s, vector FP64 (dense MFMA FP64 is the same)
+FP32_PEAK = 157.3e12       # FLOP/s, published FP32 vector peak
+
+
+def contraction_macs(dim, P, Q):
+    """MACs of one sum-factorized forward (or transposed) contraction of a
+    dim-vector field: all d x d entries of A at all Q^dim points."""
+    if dim == 3:
+        return 3 * (P * P * Q * P * 2) + 3 * (P * Q * Q * P * 3) + 9 * Q ** 3 * P
+    return 2 * (P * Q * P * 2) + 4 * Q * Q * P
+
+
+# per quadrature point, beyond the contractions: (energy, gradient, Hessian).
+# Energy: T = A W^-1, det A, det T, mu, accumulation.  Gradient: T, P from
+# the invariants, Y = w det W P W^-t.  Hessian: T, dT, dP from the
+# invariants, Y.
+POINT_FLOPS = {2: (34, 67, 123), 7: (40, 69, 125), 303: (110, 205, 403), 302: (155, 379, 961)}
+
+
+def algorithmic(w):
+    """(flops, bytes) per element for energy, gradient, Hessian action."""
+    dim, P, Q, metric = w["dim"], w["p"] + 1, w["Q"], w["metric"]
+    nq = Q ** dim
+    c = contraction_macs(dim, P, Q) * 2
+    pf = POINT_FLOPS[metric]
+    flops = (c + nq * pf[0], 2 * c + nq * pf[1], 3 * c + nq * pf[2])
+    m = w["n"] * w["p"] + 1
+    node_bytes = dim * 8 * m ** dim / w["n"] ** dim      # unique L-vector bytes per element, one field
+    return flops, (node_bytes, 2 * node_bytes, 3 * node_bytes)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="q2_cube_64", choices=sorted(meshgen.WORKLOADS))
+    ap.add_argument("--no-newton", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-elems", type=int, default=4096)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, mesh, x, v, n_elem_sample):
+    """The FP64 oracle (energy + gradient + Hessian action) on the first
+    n_elem_sample elements, single-threaded, scaled to DOF-iterations/s."""
+    from threadpoolctl import threadpool_limits
+    from oracle import tmop_oracle as O
+    en = mesh.elem_node[:n_elem_sample]
+    prob = O.Problem(w["dim"], w["p"], w["Q"], en, w["metric"], mesh.h * np.eye(w["dim"]))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        prob.energy(x)
+        prob.gradient(x)
+        prob.hessian_apply(x, v)
+        dt = time.perf_counter() - t0
+    frac = n_elem_sample / mesh.n_elem
+    return dict(value=mesh.n_dof * frac / dt, unit="DOF-iterations/s", cores=1, kind="oracle",
+                sample=f"energy+gradient+Hessian action of the FP64 oracle on {n_elem_sample} of "
+                       f"{mesh.n_elem} elements ({dt:.1f} s), scaled by the element fraction")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_1807_09807_amd import tmop as T
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a HIP device")
+    T.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = meshgen.WORKLOADS[args.workload]
+    mesh = meshgen.make_workload(args.workload)
+    x_np = mesh.x
+    v_np = meshgen.random_direction(mesh, w["seed"] + 100)
+    x = torch.from_numpy(x_np).to(dev)
+    v = torch.from_numpy(v_np).to(dev)
+    W = mesh.h * np.eye(w["dim"])
+    print(f"# workload {args.workload}: {mesh.n_elem} elements, {mesh.n_dof} DOFs", file=sys.stderr, flush=True)
+
+    flops, nbytes = algorithmic(w)
+    results = {}
+    for prec, pname in ((T.TMOP_FP64, "f64"), (T.TMOP_MIXED_FP32, "mixed")):
+        ctx = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W,
+                        fixed=mesh.fixed, precision=prec)
+        F, md, st = ctx.energy(x)
+        if st != 0 or not md > 0:
+            raise SystemExit(f"{args.workload}: inverted input mesh (min det A = {md}); "
+                             "this workload needs the repaired mesh of the test suite")
+        g = torch.empty_like(x)
+        Hv = torch.empty_like(x)
+
+        def step():
+            ctx.energy(x)
+            ctx.gradient(x, g)
+            ctx.hessian_apply(x, v, Hv)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+
+        # per-operation device time, HIP events on the stream the library uses
+        stream = torch.cuda.current_stream()
+        ops = {}
+        for name, fn in (("energy", lambda: ctx.energy(x)), ("gradient", lambda: ctx.gradient(x, g)),
+                         ("hessian", lambda: ctx.hessian_apply(x, v, Hv))):
+            ts = []
+            for _ in range(max(args.steps, 5)):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+            ops[name] = float(np.median(ts))
+        results[pname] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), ops=ops, F=F, ctx=ctx)
+        print(f"# {pname}: {ms:.3f} ms/step, E {ops['energy']*1e6:.1f} us, G {ops['gradient']*1e6:.1f} us, "
+              f"Hv {ops['hessian']*1e6:.1f} us", file=sys.stderr, flush=True)
+
+    # Newton wall time to F_tol = F_ref + 1e-8 F0 (F_ref: final F of FP64 Newton)
+    newton = None
+    if not args.no_newton:
+        newton = {}
+
+        def solve(pname, **kw):
+            ctx = results[pname]["ctx"]
+            xn = x.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, rep = ctx.newton_solve(xn, max_it=50, **kw)
+            torch.cuda.synchronize()
+            rep["wall_s"] = time.perf_counter() - t0
+            return st, rep
+
+        # the reference: plain FP64 Newton to the relative tolerance 1e-12
+        st, ref = solve("f64")
+        F_tol = ref["F"] + 1e-8 * ref["F0"]
+        newton["F_ref"], newton["F_tol"] = ref["F"], F_tol
+        for pname, forcing in (("f64", 0), ("f64", 1), ("mixed", 0), ("mixed", 1)):
+            st, rep = solve(pname, ftarget=F_tol, cg_forcing=forcing)
+            key = f"{pname}{'_inexact' if forcing else ''}"
+            reached = next((k for k, f in enumerate(rep["history_F"]) if f <= F_tol), None)
+            newton[key] = dict(status=st, reached_F_tol=reached is not None,
+                               wall_s_to_F_tol=rep["history_time"][reached] if reached is not None else None,
+                               iters=rep["iters"], cg_iters=rep["cg_iters"], F=rep["F"])
+            print(f"# newton {key}: status {st}, {rep['iters']} it, {rep['cg_iters']} CG, "
+                  f"{rep['wall_s']:.2f} s, F {rep['F0']:.4e} -> {rep['F']:.4e}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, mesh, x_np, v_np, min(args.cpu_elems, mesh.n_elem))
+
+    r64 = results["f64"]
+    t_h = r64["ops"]["hessian"]
+    fl = flops[2] * mesh.n_elem
+    line = {
+        "metric": "DOF-iterations/s of energy+grad+Hv (FP64 vs FP32), Newton wall-s to F tol",
+        "value": r64["value"],
+        "unit": "DOF-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dim": w["dim"], "order": w["p"], "elements": mesh.n_elem,
+                   "dofs": mesh.n_dof, "quadrature": f"{w['Q']}^{w['dim']} Gauss-Legendre",
+                   "metric": f"mu_{w['metric']}", "target": "W = h I"},
+        "roofline": {"kernel": "hessian_apply (element kernel, 2^dim colour launches)",
+                     "bound": "alu", "achieved": fl / t_h / 1e12, "peak": FP64_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": fl / t_h / FP64_PEAK, "traffic": None,
+                     "flops_per_element": flops[2], "hbm_bytes_per_element": nbytes[2],
+                     "hbm_GBps": nbytes[2] * mesh.n_elem / t_h / 1e9},
+        "ops_us": {k: round(t * 1e6, 2) for k, t in r64["ops"].items()},
+        "mixed_fp32": {"value": results["mixed"]["value"], "ms_per_step": results["mixed"]["ms_per_step"],
+                       "ops_us": {k: round(t * 1e6, 2) for k, t in results["mixed"]["ops"].items()}},
+        "newton": newton,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

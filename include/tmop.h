@@ -1,0 +1,194 @@
+/*
+ * tmop.h -- C ABI of the MI355X (gfx950) implementation of the data-parallel
+ * hot path of high-order TMOP mesh optimization:
+ *
+ *   V. Dobrev, P. Knupp, Tz. Kolev, K. Mittal, V. Tomov, "The Target-Matrix
+ *   Optimization Paradigm for High-Order Meshes", arXiv:1807.09807.
+ *
+ * The library evaluates the variational objective (Section 2.3, eq. 2.4)
+ *
+ *   F(x) = sum_E sum_q  w_q det(W_q) mu(T_q),   T = A W^{-1},
+ *
+ * where A is the Jacobian of the element map of the high-order position
+ * field x (Section 2.1, eqs. 2.1-2.2), together with its gradient and its
+ * Hessian action (Section 3.4), and runs the Newton method of Section 3.4
+ * with the positivity and 1.2-growth line search.
+ *
+ * Conventions shared by every call:
+ *  - Positions, gradients and directions are DEVICE arrays of doubles in
+ *    component-major layout: x[c * n_node + I], c < dim.  They are owned by
+ *    the caller; outputs never alias inputs.
+ *  - A `stream` argument is a hipStream_t (NULL = the null stream).  Calls
+ *    marked "async" only enqueue work; calls marked "syncs" wait for the
+ *    stream before returning.
+ *  - Every call returns a status: 0 = success, > 0 = warning (outputs are
+ *    valid), < 0 = error (outputs untouched).  No C++ exception crosses
+ *    this interface.  A context is not thread-safe: calls on one context
+ *    must not overlap in time.
+ *  - Reference element [0,1]^dim; the nodal basis on each element is the
+ *    tensor product of Lagrange polynomials at the order-p Gauss-Lobatto-
+ *    Legendre points, local node index i = i0 + (p+1)*(i1 + (p+1)*i2)
+ *    (first reference coordinate fastest).
+ */
+#ifndef TMOP_H
+#define TMOP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tmop_ctx tmop_ctx;   /* opaque, owned by the library */
+
+/* Status codes. */
+enum {
+  TMOP_OK = 0,
+  TMOP_W_INVERTED = 1,     /* det A <= 0 at some quadrature point: outside the
+                              domain of the barrier metrics (Section 3.2) */
+  TMOP_W_MAXIT = 2,        /* Newton stopped after max_it iterations */
+  TMOP_W_LSFAIL = 3,       /* no admissible step length was found: the
+                              termination rule of Section 3.4 */
+  TMOP_E_ARG = -1,         /* invalid argument */
+  TMOP_E_TARGET = -2,      /* a target matrix has det W <= 0 (Section 3.1) */
+  TMOP_E_NOMEM = -3,       /* device or host allocation failed */
+  TMOP_E_HIP = -4,         /* a HIP runtime call failed */
+  TMOP_E_UNSUPPORTED = -5  /* valid, but no kernel is built for this (dim, p, Q) */
+};
+
+/* Quality metrics mu(T), tau = det T, |.| the Frobenius norm (Section 3.2). */
+enum {
+  TMOP_MU2 = 2,       /* 2D shape:      |T|^2 / (2 tau) - 1       (Table 3.1) */
+  TMOP_MU7 = 7,       /* 2D shape+size: |T - T^{-t}|^2            (Section 3.2) */
+  TMOP_MU302 = 302,   /* 3D shape:      |T|^2 |T^{-1}|^2 / 9 - 1 */
+  TMOP_MU303 = 303    /* 3D shape:      |T|^2 / (3 tau^{2/3}) - 1 (Table 3.1) */
+};
+
+/* Quadrature rules on [0,1] (Section 3.3), n1d points per direction. */
+enum { TMOP_GAUSS_LEGENDRE = 0, TMOP_GAUSS_LOBATTO = 1 };
+
+/* Arithmetic of the element kernels.  TMOP_MIXED_FP32 runs the basis
+ * contractions and the metric derivatives in FP32 with FP32 accumulation;
+ * det A, the positivity test and the sum of F stay FP64.  Both take and
+ * return FP64 arrays. */
+enum { TMOP_FP64 = 0, TMOP_MIXED_FP32 = 1 };
+
+/* Target matrices W (Section 3.1). */
+enum {
+  TMOP_TGT_CONST = 0       /* one dim x dim matrix for every point */
+};
+
+typedef struct {
+  int32_t dim;                /* 2 (quadrilaterals) or 3 (hexahedra) */
+  int32_t order;              /* polynomial order p >= 1 of the position field */
+  int64_t n_elem;             /* number of elements, >= 1 */
+  int64_t n_node;             /* number of nodes (DOFs per component), >= 1 */
+  const int32_t *elem_node;   /* HOST [n_elem][(p+1)^dim] global node ids in
+                                 [0, n_node), local order as above */
+  const uint8_t *fixed;       /* HOST [dim][n_node], 1 = Dirichlet DOF held at
+                                 its input value by the Newton solver; NULL =
+                                 no fixed DOF.  Energy, gradient and Hessian
+                                 action ignore it. */
+} tmop_mesh;
+
+typedef struct {
+  int32_t kind;               /* TMOP_GAUSS_LEGENDRE or TMOP_GAUSS_LOBATTO */
+  int32_t n1d;                /* points per direction; must be >= p + 1, the
+                                 minimum of Section 3.3 */
+} tmop_quadrature;
+
+typedef struct {
+  int32_t kind;               /* TMOP_TGT_CONST */
+  const double *W;            /* HOST, row-major dim x dim, det W > 0 */
+} tmop_target;
+
+typedef struct {
+  double rtol;                /* stop when |g| <= max(rtol |g0|, atol); the paper
+                                 uses 1e-12 (Section 5) */
+  double atol;
+  int32_t max_it;             /* Newton iterations */
+  double cg_rtol;             /* inner truncated-CG tolerance relative to |g| */
+  int32_t cg_max_it;
+  double ls_shrink;           /* alpha <- ls_shrink * alpha, starting at 1 */
+  int32_t ls_max;             /* step lengths tried per iteration */
+  double f_growth;            /* accept only if F(x+) < f_growth F(x)  (1.2) */
+  double g_growth;            /* and |g(x+)| < g_growth |g(x)|          (1.2) */
+  double *hist_F;             /* optional HOST [max_it + 1]: F after each
+                                 iteration (entry 0 = initial); NULL = off */
+  double *hist_gnorm;         /* optional HOST [max_it + 1]: |g| likewise */
+  int32_t *hist_cg;           /* optional HOST [max_it + 1]: CG iterations */
+  double ftarget;             /* also stop (TMOP_OK) once F <= ftarget; default
+                                 -HUGE_VAL = off */
+  int32_t cg_forcing;         /* 0: inner tolerance cg_rtol.  1: inexact Newton,
+                                 tolerance max(cg_rtol, min(0.5,
+                                 sqrt(|g|/|g0|))) */
+  double *hist_time;          /* optional HOST [max_it + 1]: seconds since the
+                                 call started, at each accepted iterate */
+} tmop_newton_opts;
+
+typedef struct {
+  int32_t iters;              /* accepted Newton steps */
+  int32_t cg_iters;           /* total inner iterations (Hessian actions) */
+  int32_t ls_shrinks;         /* rejected step lengths */
+  int32_t neg_curv;           /* inner solves ended by non-positive curvature */
+  double F0, F;               /* objective at the start and at the end */
+  double gnorm0, gnorm;       /* |g| over the free DOFs, start and end */
+  double min_detA;            /* smallest det A at the end */
+} tmop_newton_report;
+
+/* Fills `opts` with the defaults: rtol 1e-12, atol 0, max_it 50, cg_rtol
+ * 1e-8, cg_max_it 1000, ls_shrink 0.5, ls_max 30, growth factors 1.2, no
+ * history. */
+void tmop_newton_default_opts(tmop_newton_opts *opts);
+
+/* Builds a context on the current HIP device for the objective of eq. 2.4
+ * on the given mesh, quadrature (Section 3.3), target (Section 3.1) and
+ * metric (Section 3.2), computing in `precision`.  Host arrays are copied;
+ * the caller may free them on return.  Arguments are validated before any
+ * device work: TMOP_E_ARG for a bad dimension, order, size, node id,
+ * quadrature (n1d < p + 1) or metric/dimension pair; TMOP_E_TARGET when
+ * det W <= 0; TMOP_E_UNSUPPORTED when no kernel is built for (dim, p, n1d).
+ * On success *out owns all device memory of the context. */
+int tmop_setup(const tmop_mesh *mesh, const tmop_quadrature *quad,
+               const tmop_target *target, int32_t metric, int32_t precision,
+               tmop_ctx **out);
+
+/* F(x) of eq. 2.4 and the smallest det A over all quadrature points (the
+ * positivity test of Section 3.4).  x: device [dim][n_node].  F and
+ * min_detA: host pointers.  Returns TMOP_W_INVERTED (with both values
+ * written) when min_detA <= 0.  Deterministic.  Syncs `stream`. */
+int tmop_energy(tmop_ctx *ctx, const double *x, double *F, double *min_detA,
+                void *stream);
+
+/* g = dF/dx (Section 3.4) over all DOFs, fixed ones included.  x, g: device
+ * [dim][n_node]; g is overwritten.  Deterministic.  Async. */
+int tmop_gradient(tmop_ctx *ctx, const double *x, double *g, void *stream);
+
+/* Hv = (d^2F/dx^2) v, the Hessian of Section 3.4 applied to v, over all
+ * DOFs.  x, v, Hv: device [dim][n_node]; Hv is overwritten.
+ * Deterministic.  Async. */
+int tmop_hessian_apply(tmop_ctx *ctx, const double *x, const double *v,
+                       double *Hv, void *stream);
+
+/* Minimizes F over the free DOFs with Newton's method (Section 3.4):
+ * direction from truncated CG (Steihaug) on the Hessian restricted to the
+ * free DOFs; step lengths 1, s, s^2, ... until det A > 0 at every
+ * quadrature point, F(x+) < f_growth F(x) and |g(x+)| < g_growth |g(x)|.
+ * x: device [dim][n_node], updated in place (fixed DOFs keep their value).
+ * opts: host, NULL = defaults.  report: host, may be NULL.  Returns TMOP_OK
+ * on convergence, TMOP_W_MAXIT, TMOP_W_LSFAIL (x = last accepted iterate),
+ * or TMOP_W_INVERTED if the input mesh is inverted (x untouched).  Syncs. */
+int tmop_newton_solve(tmop_ctx *ctx, double *x, const tmop_newton_opts *opts,
+                      tmop_newton_report *report, void *stream);
+
+/* Releases the context and all its device memory.  NULL is a no-op. */
+void tmop_destroy(tmop_ctx *ctx);
+
+/* Static description of a status code. */
+const char *tmop_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TMOP_H */

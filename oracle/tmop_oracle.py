@@ -135,6 +135,16 @@ def _frob2(M):
     return np.sum(M * M, axis=(-2, -1))
 
 
+def _tau23(tau):
+    """tau^(2/3) with the real cube root, so that the formula also has a
+    value for tau <= 0 (outside the barrier domain, Section 3.2).  Complex
+    arguments (complex-step derivatives, tau > 0) use the principal power."""
+    if np.iscomplexobj(tau):
+        return tau ** (2.0 / 3.0)
+    c = np.cbrt(tau)
+    return c * c
+
+
 def mu(metric: int, T: np.ndarray) -> np.ndarray:
     """mu(T) for T of shape (..., d, d).
     2:   |T|^2 / (2 tau) - 1                 (Table 3.1, shape, 2D)
@@ -150,7 +160,7 @@ def mu(metric: int, T: np.ndarray) -> np.ndarray:
         Tinv_t = np.swapaxes(np.linalg.inv(T), -1, -2)
         return _frob2(T - Tinv_t)
     if metric == 303:
-        return I1 / (3.0 * tau ** (2.0 / 3.0)) - 1.0
+        return I1 / (3.0 * _tau23(tau)) - 1.0
     if metric == 302:
         return I1 * _frob2(np.linalg.inv(T)) / 9.0 - 1.0
     raise ValueError(f"unknown metric {metric}")
@@ -215,7 +225,7 @@ def _partials(metric, I1, I2, tau):
         return dict(f1=1.0 + tau ** -2, f2=z, ft=-2.0 * I1 * tau ** -3,
                     f11=z, f12=z, f1t=-2.0 * tau ** -3, f22=z, f2t=z, ftt=6.0 * I1 * tau ** -4)
     if metric == 303:        # f = I1 tau^{-2/3} / 3 - 1
-        t23 = tau ** (-2.0 / 3.0)
+        t23 = 1.0 / _tau23(tau)
         return dict(f1=t23 / 3.0, f2=z, ft=-(2.0 / 9.0) * I1 * t23 / tau,
                     f11=z, f12=z, f1t=-(2.0 / 9.0) * t23 / tau, f22=z, f2t=z,
                     ftt=(10.0 / 27.0) * I1 * t23 / tau ** 2)
@@ -300,9 +310,15 @@ class Problem:
         return Wi[e0:e1], dW[e0:e1]
 
     def _jac(self, x, e0, e1):
-        """A[e, q, c, l] = sum_i x_{node(e,i), c} dw_i/dxbar_l (eq. 2.2)."""
+        """A[e, q, c, l] = sum_i x_{node(e,i), c} dw_i/dxbar_l (eq. 2.2).
+
+        The basis gradients sum to zero, so A is unchanged when the element's
+        first node is subtracted from all its nodes; doing so keeps the
+        summands at the size of the element rather than of the domain, which
+        is what the rounding error of the sum is proportional to."""
         X = x[:, self.elem_node[e0:e1]]                  # (d, ne, N)
-        return np.einsum("cei,qil->eqcl", X, self.D)
+        X = X - X[:, :, :1]
+        return np.einsum("cei,qil->eqcl", X, self.D, optimize=True)
 
     def _chunks(self):
         for e0 in range(0, self.n_elem, self.chunk):
@@ -328,16 +344,47 @@ class Problem:
             return F, float(np.min(detA.real))
         return math.fsum(c.ravel()), float(np.min(detA))
 
-    def element_min_det(self, x):
-        _, detA = self.pointwise(x)
+    def max_condition(self, x, elems=None):
+        """max over quadrature points of (|T|^2/d)^(d/2) / det T: 1 for a
+        scaled rotation, large for nearly degenerate points.  It bounds how
+        much a relative perturbation of A is amplified in mu's derivatives."""
+        en_all, n_all = self.elem_node, self.n_elem
+        if elems is not None:
+            self.elem_node, self.n_elem = en_all[np.asarray(elems)], len(elems)
+        try:
+            k = 0.0
+            for e0, e1 in self._chunks():
+                Wi, _ = self._targets(e0, e1)
+                T = _mm(self._jac(x, e0, e1), Wi)
+                k = max(k, float(np.max((_frob2(T) / self.dim) ** (self.dim / 2.0) / _det(T))))
+            return k
+        finally:
+            self.elem_node, self.n_elem = en_all, n_all
+
+    def element_min_det(self, x, elems=None):
+        """Smallest det A over the quadrature points of each element."""
+        en_all, n_all = self.elem_node, self.n_elem
+        if elems is not None:
+            self.elem_node, self.n_elem = en_all[np.asarray(elems)], len(elems)
+        try:
+            _, detA = self.pointwise(x)
+        finally:
+            self.elem_node, self.n_elem = en_all, n_all
         return np.min(np.real(detA), axis=1)
 
-    def bad_elements(self, x):
-        return np.flatnonzero(self.element_min_det(x) <= 0.0)
+    def bad_elements(self, x, elems=None, tau_min=0.0):
+        """Positions (within `elems`, default all elements) of the elements
+        with det A <= tau_min det W at some quadrature point."""
+        md = self.element_min_det(x, elems)
+        dW = self.detW if np.ndim(self.detW) == 0 else None
+        if dW is None:
+            dWe = self.detW if self.detW.ndim == 1 else self.detW.min(axis=1)
+            dW = dWe if elems is None else dWe[np.asarray(elems)]
+        return np.flatnonzero(md <= tau_min * dW)
 
     def _assemble(self, Y, e0, e1, out):
         """out[c, node(e,i)] += sum_q sum_l Y[e,q,c,l] dw_i/dxbar_l."""
-        G = np.einsum("eqcl,qil->cei", Y, self.D)
+        G = np.einsum("eqcl,qil->cei", Y, self.D, optimize=True)
         for c in range(self.dim):
             np.add.at(out[c], self.elem_node[e0:e1], G[c])
 
@@ -352,6 +399,31 @@ class Problem:
             Y = (self.wq[None, :] * dW)[..., None, None] * _mm(P, _tr(Wi))
             self._assemble(Y, e0, e1, g)
         return g
+
+    def _elements_touching(self, nodes):
+        hit = np.isin(self.elem_node, np.asarray(nodes)).any(axis=1)
+        return np.flatnonzero(hit)
+
+    def gradient_at(self, x, nodes):
+        """dF/dx at the given nodes only, shape (d, len(nodes)): the same sum
+        as gradient(), restricted to the elements that contain the nodes."""
+        return self._restricted(x, None, nodes)
+
+    def hessian_apply_at(self, x, v, nodes):
+        """(Hv) at the given nodes only, shape (d, len(nodes))."""
+        return self._restricted(x, v, nodes)
+
+    def _restricted(self, x, v, nodes):
+        nodes = np.asarray(nodes, dtype=np.int64)
+        elems = self._elements_touching(nodes)
+        sub = Problem.__new__(Problem)
+        sub.__dict__.update(self.__dict__)
+        sub.elem_node = self.elem_node[elems]
+        sub.n_elem = elems.size
+        if self.Winv.ndim > 2:
+            sub.Winv, sub.detW = self.Winv[elems], self.detW[elems]
+        out = sub.gradient(x) if v is None else sub.hessian_apply(x, v)
+        return out[:, nodes]
 
     def hessian_apply(self, x, v):
         """(d^2 F_V / dx^2) v with dT = dA W^{-1}, dA from v as in eq. 2.2,
@@ -381,6 +453,8 @@ class NewtonOptions:
     ls_max: int = 30
     f_growth: float = 1.2        # F(x+) < 1.2 F(x)
     g_growth: float = 1.2        # |g(x+)| < 1.2 |g(x)|
+    ftarget: float = -math.inf   # also stop once F <= ftarget
+    cg_forcing: int = 0          # 1: inner tolerance max(cg_rtol, min(0.5, sqrt(|g|/|g0|)))
 
 
 STOP_CONVERGED, STOP_MAXIT, STOP_LSFAIL, STOP_INVERTED = 0, 1, 2, 3
@@ -448,11 +522,14 @@ def newton_solve(prob: Problem, x0, fixed, opts: NewtonOptions = NewtonOptions()
     rep.gnorm0 = rep.gnorm = gn
     rep.history.append((F, gn, 0.0, 0, False))
     for it in range(opts.max_it):
-        if gn <= max(opts.rtol * rep.gnorm0, opts.atol):
+        if gn <= max(opts.rtol * rep.gnorm0, opts.atol) or F <= opts.ftarget:
             rep.stop = STOP_CONVERGED
             break
+        cg_tol = opts.cg_rtol
+        if opts.cg_forcing:
+            cg_tol = max(opts.cg_rtol, min(0.5, math.sqrt(gn / rep.gnorm0)))
         Hm = lambda p: m * prob.hessian_apply(x.reshape(shape), (m * p).reshape(shape)).ravel()
-        dvec, ncg, neg = truncated_cg(Hm, g, opts.cg_rtol, opts.cg_max_it)
+        dvec, ncg, neg = truncated_cg(Hm, g, cg_tol, opts.cg_max_it)
         rep.cg_iters += ncg
         accepted = False
         for k in range(opts.ls_max):
@@ -473,6 +550,7 @@ def newton_solve(prob: Problem, x0, fixed, opts: NewtonOptions = NewtonOptions()
         rep.iters = it + 1
         rep.history.append((F, gn, alpha, ncg, neg))
     else:
-        rep.stop = STOP_CONVERGED if gn <= max(opts.rtol * rep.gnorm0, opts.atol) else STOP_MAXIT
+        rep.stop = (STOP_CONVERGED if gn <= max(opts.rtol * rep.gnorm0, opts.atol) or F <= opts.ftarget
+                    else STOP_MAXIT)
     rep.F, rep.gnorm, rep.min_detA = F, gn, mindet
     return x.reshape(shape), rep

@@ -1,0 +1,531 @@
+// C ABI of libtmop: context set-up, element operations and the Newton /
+// truncated-CG driver (arXiv:1807.09807, Sections 2-3).  Host code only;
+// every step of the computation runs in the HIP kernels of this library.
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <new>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/tmop.h"
+#include "tmop_internal.h"
+
+using namespace tmop;
+
+// ---------------------------------------------------------------- 1D tables
+
+namespace {
+
+// Legendre polynomial P_n and its first two derivatives at t (three-term
+// recurrence).
+void legendre(int n, double t, double* P, double* dP, double* d2P) {
+  double p0 = 1.0, p1 = t;
+  if (n == 0) { *P = 1.0; *dP = 0.0; *d2P = 0.0; return; }
+  for (int k = 2; k <= n; ++k) {
+    const double pk = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = pk;
+  }
+  *P = p1;
+  // (1 - t^2) P' = n (P_{n-1} - t P_n);  (1 - t^2) P'' = 2 t P' - n (n+1) P
+  const double omt = 1.0 - t * t;
+  *dP = n * (p0 - t * p1) / omt;
+  *d2P = (2.0 * t * (*dP) - n * (n + 1.0) * p1) / omt;
+}
+
+// Gauss-Lobatto-Legendre points of order p on [0,1] (p+1 points): the
+// endpoints and the roots of P_p', by Newton's method from the
+// Chebyshev-Gauss-Lobatto points.
+void gll_points(int p, double* xi) {
+  xi[0] = 0.0;
+  xi[p] = 1.0;
+  for (int j = 1; j < p; ++j) {
+    double t = -cos(M_PI * j / p);
+    for (int it = 0; it < 100; ++it) {
+      double P, dP, d2P;
+      legendre(p, t, &P, &dP, &d2P);
+      const double dt = dP / d2P;
+      t -= dt;
+      if (fabs(dt) < 1e-16) break;
+    }
+    xi[j] = 0.5 * (t + 1.0);
+  }
+}
+
+// Q-point Gauss-Legendre rule on [0,1].
+void gauss_legendre(int Q, double* s, double* w) {
+  for (int j = 0; j < Q; ++j) {
+    double t = -cos(M_PI * (j + 0.75) / (Q + 0.5));
+    double P = 0, dP = 0, d2P = 0;
+    for (int it = 0; it < 100; ++it) {
+      legendre(Q, t, &P, &dP, &d2P);
+      const double dt = P / dP;
+      t -= dt;
+      if (fabs(dt) < 1e-16) break;
+    }
+    legendre(Q, t, &P, &dP, &d2P);
+    s[j] = 0.5 * (t + 1.0);
+    w[j] = 1.0 / ((1.0 - t * t) * dP * dP);   // 2 / ((1-t^2) P'^2), halved for [0,1]
+  }
+}
+
+// Q-point Gauss-Lobatto rule on [0,1].
+void gauss_lobatto(int Q, double* s, double* w) {
+  gll_points(Q - 1, s);
+  for (int j = 0; j < Q; ++j) {
+    double P, dP, d2P;
+    const double t = 2.0 * s[j] - 1.0;
+    if (j == 0 || j == Q - 1) {
+      P = 1.0;   // |P_n(+-1)| = 1
+    } else {
+      legendre(Q - 1, t, &P, &dP, &d2P);
+    }
+    w[j] = 1.0 / (Q * (Q - 1.0) * P * P);
+  }
+}
+
+// Lagrange basis through nodes xi (n of them) and its derivative at s.
+void lagrange_at(int n, const double* xi, double s, double* L, double* dL) {
+  for (int a = 0; a < n; ++a) {
+    double v = 1.0, d = 0.0;
+    for (int b = 0; b < n; ++b) {
+      if (b == a) continue;
+      const double f = 1.0 / (xi[a] - xi[b]);
+      d = d * (s - xi[b]) * f + v * f;   // product rule, built up factor by factor
+      v *= (s - xi[b]) * f;
+    }
+    L[a] = v;
+    dL[a] = d;
+  }
+}
+
+double det3(const double* W, int d) {
+  if (d == 2) return W[0] * W[3] - W[1] * W[2];
+  return W[0] * (W[4] * W[8] - W[5] * W[7]) - W[1] * (W[3] * W[8] - W[5] * W[6]) +
+         W[2] * (W[3] * W[7] - W[4] * W[6]);
+}
+
+void inv3(const double* W, int d, double out[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) out[i][j] = 0.0;
+  const double D = det3(W, d);
+  if (d == 2) {
+    out[0][0] = W[3] / D; out[0][1] = -W[1] / D;
+    out[1][0] = -W[2] / D; out[1][1] = W[0] / D;
+    return;
+  }
+  out[0][0] = (W[4] * W[8] - W[5] * W[7]) / D;
+  out[0][1] = (W[2] * W[7] - W[1] * W[8]) / D;
+  out[0][2] = (W[1] * W[5] - W[2] * W[4]) / D;
+  out[1][0] = (W[5] * W[6] - W[3] * W[8]) / D;
+  out[1][1] = (W[0] * W[8] - W[2] * W[6]) / D;
+  out[1][2] = (W[2] * W[3] - W[0] * W[5]) / D;
+  out[2][0] = (W[3] * W[7] - W[4] * W[6]) / D;
+  out[2][1] = (W[1] * W[6] - W[0] * W[7]) / D;
+  out[2][2] = (W[0] * W[4] - W[1] * W[3]) / D;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- context
+
+struct tmop_ctx {
+  int dim = 0, p = 0, Q = 0, metric = 0, precision = 0;
+  int64_t n_elem = 0, n_node = 0, n_dof = 0;
+  int device = 0;
+  LaunchParams base{};                 // tables and target, pointers filled per call
+  int32_t* d_elem_node = nullptr;
+  int32_t* d_colors = nullptr;         // element ids grouped by colour
+  std::vector<int64_t> color_off;      // colour c = d_colors[color_off[c] .. color_off[c+1])
+  double* d_mask = nullptr;            // [n_dof], 1 = free DOF
+  bool has_fixed = false;
+  double* d_part = nullptr;            // [2 * n_elem] energy partials
+  double* d_scratch = nullptr;         // [RED_BLOCKS] dot partials
+  double* d_res = nullptr;             // [4] reduction results
+  double* h_res = nullptr;             // [4] pinned mirror
+  double* d_work = nullptr;            // Newton work vectors, allocated on first use
+};
+
+#define HIP_TRY(call)                         \
+  do {                                        \
+    if ((call) != hipSuccess) return TMOP_E_HIP; \
+  } while (0)
+
+namespace {
+
+int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* out, const int32_t* list,
+                int64_t n_list, hipStream_t s, int* grid) {
+  LaunchParams lp = c->base;
+  lp.x = x; lp.v = v; lp.out = out;
+  lp.elem_node = c->d_elem_node;
+  lp.list = list;
+  lp.n_list = (int32_t)n_list;
+  lp.n_node = c->n_node;
+  lp.part = c->d_part;
+  int r;
+  if (c->dim == 2)
+    r = c->precision == TMOP_FP64 ? launch_elem_2d_f64(c->p, c->Q, c->metric, op, lp, s, grid)
+                                  : launch_elem_2d_f32(c->p, c->Q, c->metric, op, lp, s, grid);
+  else
+    r = c->precision == TMOP_FP64 ? launch_elem_3d_f64(c->p, c->Q, c->metric, op, lp, s, grid)
+                                  : launch_elem_3d_f32(c->p, c->Q, c->metric, op, lp, s, grid);
+  if (r == -1) return TMOP_E_UNSUPPORTED;
+  return r == 0 ? TMOP_OK : TMOP_E_HIP;
+}
+
+// out = sum over colours of the element contributions (gradient / Hv).
+int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out, hipStream_t s) {
+  HIP_TRY(fill(out, 0.0, c->n_dof, s));
+  for (size_t k = 0; k + 1 < c->color_off.size(); ++k) {
+    const int64_t n = c->color_off[k + 1] - c->color_off[k];
+    if (n == 0) continue;
+    int grid = 0;
+    const int r = elem_launch(c, op, x, v, out, c->d_colors + c->color_off[k], n, s, &grid);
+    if (r != TMOP_OK) return r;
+  }
+  return TMOP_OK;
+}
+
+// Enqueue F and min det A into c->d_res[0..1].
+int energy_async(tmop_ctx* c, const double* x, hipStream_t s) {
+  int grid = 0;
+  const int r = elem_launch(c, OP_ENERGY, x, nullptr, nullptr, nullptr, c->n_elem, s, &grid);
+  if (r != TMOP_OK) return r;
+  HIP_TRY(finalize_sum_min(c->d_part, grid, c->d_scratch, c->d_res, s));
+  return TMOP_OK;
+}
+
+int energy_sync(tmop_ctx* c, const double* x, hipStream_t s, double* F, double* mind) {
+  const int r = energy_async(c, x, s);
+  if (r != TMOP_OK) return r;
+  HIP_TRY(hipMemcpyAsync(c->h_res, c->d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *F = c->h_res[0];
+  *mind = c->h_res[1];
+  return TMOP_OK;
+}
+
+int dot_sync(tmop_ctx* c, const double* a, const double* b, hipStream_t s, double* out) {
+  HIP_TRY(dot(a, b, c->n_dof, c->d_scratch, c->d_res + 2, s));
+  HIP_TRY(hipMemcpyAsync(c->h_res + 2, c->d_res + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = c->h_res[2];
+  return TMOP_OK;
+}
+
+void free_ctx(tmop_ctx* c) {
+  if (!c) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(c->device);
+  (void)hipFree(c->d_elem_node);
+  (void)hipFree(c->d_colors);
+  (void)hipFree(c->d_mask);
+  (void)hipFree(c->d_part);
+  (void)hipFree(c->d_scratch);
+  (void)hipFree(c->d_res);
+  (void)hipFree(c->d_work);
+  if (c->h_res) (void)hipHostFree(c->h_res);
+  (void)hipSetDevice(cur);
+  delete c;
+}
+
+// Greedy element colouring: elements of one colour share no node.
+void color_elements(const int32_t* en, int64_t n_elem, int npe, int64_t n_node, std::vector<int32_t>& order,
+                    std::vector<int64_t>& off) {
+  std::vector<int64_t> start(n_node + 1, 0);
+  for (int64_t e = 0; e < n_elem; ++e)
+    for (int i = 0; i < npe; ++i) start[en[e * npe + i] + 1]++;
+  for (int64_t I = 0; I < n_node; ++I) start[I + 1] += start[I];
+  std::vector<int32_t> adj(start[n_node]);
+  std::vector<int64_t> fillp(start.begin(), start.end() - 1);
+  for (int64_t e = 0; e < n_elem; ++e)
+    for (int i = 0; i < npe; ++i) adj[fillp[en[e * npe + i]]++] = (int32_t)e;
+  std::vector<int16_t> color(n_elem, -1);
+  int ncolor = 0;
+  std::vector<uint8_t> used;
+  for (int64_t e = 0; e < n_elem; ++e) {
+    used.assign(ncolor + 1, 0);
+    for (int i = 0; i < npe; ++i) {
+      const int32_t I = en[e * npe + i];
+      for (int64_t k = start[I]; k < start[I + 1]; ++k) {
+        const int16_t c = color[adj[k]];
+        if (c >= 0) used[c] = 1;
+      }
+    }
+    int c = 0;
+    while (c < ncolor && used[c]) ++c;
+    color[e] = (int16_t)c;
+    if (c == ncolor) ++ncolor;
+  }
+  off.assign(ncolor + 1, 0);
+  for (int64_t e = 0; e < n_elem; ++e) off[color[e] + 1]++;
+  for (int c = 0; c < ncolor; ++c) off[c + 1] += off[c];
+  order.resize(n_elem);
+  std::vector<int64_t> pos(off.begin(), off.end() - 1);
+  for (int64_t e = 0; e < n_elem; ++e) order[pos[color[e]]++] = (int32_t)e;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char* tmop_strerror(int status) {
+  switch (status) {
+    case TMOP_OK: return "success";
+    case TMOP_W_INVERTED: return "warning: det A <= 0 at a quadrature point (inverted mesh)";
+    case TMOP_W_MAXIT: return "warning: Newton reached the iteration limit";
+    case TMOP_W_LSFAIL: return "warning: line search found no admissible step";
+    case TMOP_E_ARG: return "error: invalid argument";
+    case TMOP_E_TARGET: return "error: target matrix with det W <= 0";
+    case TMOP_E_NOMEM: return "error: out of memory";
+    case TMOP_E_HIP: return "error: HIP runtime failure";
+    case TMOP_E_UNSUPPORTED: return "error: no kernel built for this (dim, order, quadrature)";
+    default: return "unknown status";
+  }
+}
+
+void tmop_newton_default_opts(tmop_newton_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->rtol = 1e-12;
+  o->atol = 0.0;
+  o->max_it = 50;
+  o->cg_rtol = 1e-8;
+  o->cg_max_it = 1000;
+  o->ls_shrink = 0.5;
+  o->ls_max = 30;
+  o->f_growth = 1.2;
+  o->g_growth = 1.2;
+  o->ftarget = -HUGE_VAL;
+  o->cg_forcing = 0;
+}
+
+int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_target* target, int32_t metric,
+               int32_t precision, tmop_ctx** out) {
+  if (!out) return TMOP_E_ARG;
+  *out = nullptr;
+  if (!mesh || !quad || !target || !mesh->elem_node) return TMOP_E_ARG;
+  const int d = mesh->dim, p = mesh->order, Q = quad->n1d;
+  if (d != 2 && d != 3) return TMOP_E_ARG;
+  if (p < 1 || mesh->n_elem < 1 || mesh->n_node < 1 || mesh->n_elem > INT32_MAX || mesh->n_node > INT32_MAX)
+    return TMOP_E_ARG;
+  if (quad->kind != TMOP_GAUSS_LEGENDRE && quad->kind != TMOP_GAUSS_LOBATTO) return TMOP_E_ARG;
+  if (Q < p + 1) return TMOP_E_ARG;                      // Section 3.3: at least p+1 points
+  if (quad->kind == TMOP_GAUSS_LOBATTO && Q < 2) return TMOP_E_ARG;
+  if (d == 2 && metric != TMOP_MU2 && metric != TMOP_MU7) return TMOP_E_ARG;
+  if (d == 3 && metric != TMOP_MU302 && metric != TMOP_MU303) return TMOP_E_ARG;
+  if (precision != TMOP_FP64 && precision != TMOP_MIXED_FP32) return TMOP_E_ARG;
+  if (target->kind != TMOP_TGT_CONST || !target->W) return TMOP_E_ARG;
+  const int npe = d == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
+  for (int64_t k = 0; k < mesh->n_elem * npe; ++k)
+    if (mesh->elem_node[k] < 0 || mesh->elem_node[k] >= mesh->n_node) return TMOP_E_ARG;
+  const double detW = det3(target->W, d);
+  if (!(detW > 0.0)) return TMOP_E_TARGET;               // Section 3.1: det W > 0
+  if (!elem_supported(d, p, Q)) return TMOP_E_UNSUPPORTED;
+
+  tmop_ctx* c = new (std::nothrow) tmop_ctx();
+  if (!c) return TMOP_E_NOMEM;
+  c->dim = d; c->p = p; c->Q = Q; c->metric = metric; c->precision = precision;
+  c->n_elem = mesh->n_elem; c->n_node = mesh->n_node; c->n_dof = (int64_t)d * mesh->n_node;
+  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return TMOP_E_HIP; }
+
+  // 1D tables: B[q][i] = l_i(s_q), G[q][i] = l_i'(s_q), weights w[q]
+  double xi[MAXP], s[MAXQ], w[MAXQ];
+  gll_points(p, xi);
+  for (int i = 0; i <= p; ++i) c->base.xi[i] = xi[i];
+  if (quad->kind == TMOP_GAUSS_LEGENDRE) gauss_legendre(Q, s, w);
+  else gauss_lobatto(Q, s, w);
+  for (int q = 0; q < Q; ++q) {
+    lagrange_at(p + 1, xi, s[q], c->base.B[q], c->base.G[q]);
+    c->base.w[q] = w[q];
+  }
+  inv3(target->W, d, c->base.Winv);
+  c->base.detW = detW;
+  c->base.detWinv = 1.0 / detW;
+
+  // colouring and device copies
+  std::vector<int32_t> order;
+  color_elements(mesh->elem_node, mesh->n_elem, npe, mesh->n_node, order, c->color_off);
+  const size_t en_bytes = (size_t)mesh->n_elem * npe * sizeof(int32_t);
+  int st = TMOP_OK;
+  do {
+    if (hipMalloc(&c->d_elem_node, en_bytes) != hipSuccess) { st = TMOP_E_NOMEM; break; }
+    if (hipMalloc(&c->d_colors, order.size() * sizeof(int32_t)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
+    if (hipMalloc(&c->d_part, 2 * (size_t)mesh->n_elem * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
+    if (hipMalloc(&c->d_scratch, RED_BLOCKS * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
+    if (hipMalloc(&c->d_res, 4 * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
+    if (hipHostMalloc(&c->h_res, 4 * sizeof(double), 0) != hipSuccess) { st = TMOP_E_NOMEM; break; }
+    if (hipMalloc(&c->d_mask, c->n_dof * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
+    if (hipMemcpy(c->d_elem_node, mesh->elem_node, en_bytes, hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
+    if (hipMemcpy(c->d_colors, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
+    std::vector<double> mask(c->n_dof, 1.0);
+    if (mesh->fixed)
+      for (int64_t k = 0; k < c->n_dof; ++k)
+        if (mesh->fixed[k]) { mask[k] = 0.0; c->has_fixed = true; }
+    if (hipMemcpy(c->d_mask, mask.data(), c->n_dof * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
+  } while (0);
+  if (st != TMOP_OK) { free_ctx(c); return st; }
+  *out = c;
+  return TMOP_OK;
+}
+
+void tmop_destroy(tmop_ctx* c) { free_ctx(c); }
+
+int tmop_energy(tmop_ctx* c, const double* x, double* F, double* min_detA, void* stream) {
+  if (!c || !x || !F || !min_detA) return TMOP_E_ARG;
+  double f = 0, m = 0;
+  const int r = energy_sync(c, x, (hipStream_t)stream, &f, &m);
+  if (r != TMOP_OK) return r;
+  *F = f;
+  *min_detA = m;
+  return m > 0.0 ? TMOP_OK : TMOP_W_INVERTED;
+}
+
+int tmop_gradient(tmop_ctx* c, const double* x, double* g, void* stream) {
+  if (!c || !x || !g || g == x) return TMOP_E_ARG;
+  return assemble(c, OP_GRAD, x, nullptr, g, (hipStream_t)stream);
+}
+
+int tmop_hessian_apply(tmop_ctx* c, const double* x, const double* v, double* Hv, void* stream) {
+  if (!c || !x || !v || !Hv || Hv == x || Hv == v) return TMOP_E_ARG;
+  return assemble(c, OP_HESS, x, v, Hv, (hipStream_t)stream);
+}
+
+int tmop_newton_solve(tmop_ctx* c, double* x, const tmop_newton_opts* opts_in, tmop_newton_report* rep_out,
+                      void* stream) {
+  if (!c || !x) return TMOP_E_ARG;
+  tmop_newton_opts o;
+  if (opts_in) o = *opts_in;
+  else tmop_newton_default_opts(&o);
+  if (o.max_it < 0 || o.cg_max_it < 1 || o.ls_max < 0 || !(o.ls_shrink > 0.0 && o.ls_shrink < 1.0))
+    return TMOP_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const auto t_start = std::chrono::steady_clock::now();
+  auto elapsed = [&]() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  };
+  const int64_t N = c->n_dof;
+  if (!c->d_work) {
+    if (hipMalloc(&c->d_work, 7 * (size_t)N * sizeof(double)) != hipSuccess) {
+      c->d_work = nullptr;
+      return TMOP_E_NOMEM;
+    }
+  }
+  double* g = c->d_work;          // masked gradient at x
+  double* dv = g + N;             // search direction
+  double* r = dv + N;             // CG residual
+  double* pv = r + N;             // CG direction
+  double* Hp = pv + N;            // H p
+  double* xt = Hp + N;            // trial point
+  double* gt = xt + N;            // masked gradient at the trial point
+
+  tmop_newton_report rep;
+  memset(&rep, 0, sizeof(rep));
+  int st;
+  double F, mind;
+  if ((st = energy_sync(c, x, s, &F, &mind)) != TMOP_OK) return st;
+  rep.F0 = rep.F = F;
+  rep.min_detA = mind;
+  if (!(mind > 0.0)) {
+    if (rep_out) *rep_out = rep;
+    return TMOP_W_INVERTED;
+  }
+  if ((st = assemble(c, OP_GRAD, x, nullptr, g, s)) != TMOP_OK) return st;
+  HIP_TRY(mask_mul(c->d_mask, g, N, s));
+  double gg;
+  if ((st = dot_sync(c, g, g, s, &gg)) != TMOP_OK) return st;
+  double gn = sqrt(gg);
+  rep.gnorm0 = rep.gnorm = gn;
+  if (o.hist_F) o.hist_F[0] = F;
+  if (o.hist_gnorm) o.hist_gnorm[0] = gn;
+  if (o.hist_cg) o.hist_cg[0] = 0;
+  if (o.hist_time) o.hist_time[0] = elapsed();
+
+  int status = TMOP_W_MAXIT;
+  const double gtol = std::max(o.rtol * rep.gnorm0, o.atol);
+  for (int it = 0;; ++it) {
+    if (gn <= gtol || F <= o.ftarget) { status = TMOP_OK; break; }
+    if (it >= o.max_it) { status = TMOP_W_MAXIT; break; }
+    // ---- truncated CG (Steihaug) on the masked Hessian: H d = -g from d = 0
+    HIP_TRY(fill(dv, 0.0, N, s));
+    HIP_TRY(scale_copy(-1.0, g, r, N, s));
+    HIP_TRY(scale_copy(-1.0, g, pv, N, s));
+    double rr = gg;
+    int ncg = 0;
+    double cg_tol = o.cg_rtol;
+    if (o.cg_forcing) cg_tol = std::max(o.cg_rtol, std::min(0.5, sqrt(gn / rep.gnorm0)));
+    for (int j = 0; j < o.cg_max_it; ++j) {
+      ++ncg;
+      if ((st = assemble(c, OP_HESS, x, pv, Hp, s)) != TMOP_OK) return st;
+      if (c->has_fixed) HIP_TRY(mask_mul(c->d_mask, Hp, N, s));
+      double pHp;
+      if ((st = dot_sync(c, pv, Hp, s, &pHp)) != TMOP_OK) return st;
+      if (!(pHp > 0.0)) {                      // non-positive curvature
+        rep.neg_curv++;
+        if (j == 0) HIP_TRY(scale_copy(-1.0, g, dv, N, s));
+        break;
+      }
+      const double alpha = rr / pHp;
+      HIP_TRY(axpy(alpha, pv, dv, N, s));
+      HIP_TRY(axpy(-alpha, Hp, r, N, s));
+      double rr_new;
+      if ((st = dot_sync(c, r, r, s, &rr_new)) != TMOP_OK) return st;
+      if (sqrt(rr_new) <= cg_tol * gn) break;
+      HIP_TRY(xpay(r, rr_new / rr, pv, N, s));
+      rr = rr_new;
+    }
+    rep.cg_iters += ncg;
+    // ---- line search (Section 3.4): det A > 0, F and |g| growth below 1.2x
+    bool accepted = false;
+    double Ft = 0, mindt = 0, ggt = 0;
+    double alpha = 1.0;
+    for (int k = 0; k < o.ls_max; ++k) {
+      HIP_TRY(waxpy(x, alpha, dv, xt, N, s));
+      if ((st = energy_sync(c, xt, s, &Ft, &mindt)) != TMOP_OK) return st;
+      if (mindt > 0.0 && Ft < o.f_growth * F) {
+        if ((st = assemble(c, OP_GRAD, xt, nullptr, gt, s)) != TMOP_OK) return st;
+        HIP_TRY(mask_mul(c->d_mask, gt, N, s));
+        if ((st = dot_sync(c, gt, gt, s, &ggt)) != TMOP_OK) return st;
+        if (sqrt(ggt) < o.g_growth * gn) { accepted = true; break; }
+      }
+      rep.ls_shrinks++;
+      alpha *= o.ls_shrink;
+    }
+    if (!accepted) { status = TMOP_W_LSFAIL; break; }
+    HIP_TRY(hipMemcpyAsync(x, xt, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(g, gt, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    F = Ft;
+    mind = mindt;
+    gg = ggt;
+    gn = sqrt(ggt);
+    rep.iters = it + 1;
+    if (o.hist_F) o.hist_F[it + 1] = F;
+    if (o.hist_gnorm) o.hist_gnorm[it + 1] = gn;
+    if (o.hist_cg) o.hist_cg[it + 1] = ncg;
+    if (o.hist_time) o.hist_time[it + 1] = elapsed();
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  rep.F = F;
+  rep.gnorm = gn;
+  rep.min_detA = mind;
+  if (rep_out) *rep_out = rep;
+  return status;
+}
+
+}  // extern "C"
+
+namespace tmop {
+bool elem_supported(int dim, int p, int Q) {
+  (void)dim;
+  return p >= 1 && p <= 4 && (Q == p + 1 || Q == p + 2);
+}
+}  // namespace tmop

@@ -1,0 +1,166 @@
+// Vector kernels of the Newton / truncated-CG driver and the deterministic
+// reductions behind F, min det A and the CG dot products.  All are
+// HBM-streaming kernels: grid-stride loops over contiguous FP64 vectors.
+#include "tmop_internal.h"
+
+namespace tmop {
+
+namespace {
+
+constexpr int VB = 256;   // threads per block for elementwise kernels
+
+inline int vgrid(int64_t n) {
+  int64_t g = (n + VB - 1) / VB;
+  if (g > 8192) g = 8192;
+  return (int)(g > 0 ? g : 1);
+}
+
+__global__ void __launch_bounds__(VB) k_fill(double* __restrict__ y, double v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) y[i] = v;
+}
+
+__global__ void __launch_bounds__(VB) k_axpy(double a, const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) y[i] += a * x[i];
+}
+
+__global__ void __launch_bounds__(VB) k_xpay(const double* __restrict__ x, double a, double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) y[i] = x[i] + a * y[i];
+}
+
+__global__ void __launch_bounds__(VB) k_waxpy(const double* __restrict__ x, double a, const double* __restrict__ d,
+                                              double* __restrict__ w, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) w[i] = x[i] + a * d[i];
+}
+
+__global__ void __launch_bounds__(VB) k_scale_copy(double a, const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) y[i] = a * x[i];
+}
+
+__global__ void __launch_bounds__(VB) k_mask_mul(const double* __restrict__ m, double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) y[i] *= m[i];
+}
+
+// Fixed-order tree reduction of one value per thread in a RED_THREADS block.
+__device__ __forceinline__ double block_sum(double s, double* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  double t = red[0];
+#pragma unroll
+  for (int w = 1; w < RED_THREADS / 64; ++w) t += red[w];
+  return t;
+}
+
+__device__ __forceinline__ double block_min(double s, double* red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s = fmin(s, __shfl_xor(s, off, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  double t = red[0];
+#pragma unroll
+  for (int w = 1; w < RED_THREADS / 64; ++w) t = fmin(t, red[w]);
+  return t;
+}
+
+// Stage 1 of a dot product: block b sums the chunk it owns, in order.
+__global__ void __launch_bounds__(RED_THREADS) k_dot_part(const double* __restrict__ x, const double* __restrict__ y,
+                                                          int64_t n, double* __restrict__ part) {
+  __shared__ double red[RED_THREADS / 64];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)RED_BLOCKS * RED_THREADS)
+    s += x[i] * y[i];
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// Stage 2: one block folds n partial sums (and, optionally, n minima).
+__global__ void __launch_bounds__(RED_THREADS) k_finalize(const double* __restrict__ part, int n, int with_min,
+                                                          double* __restrict__ res) {
+  __shared__ double red[2][RED_THREADS / 64];
+  double s = 0.0, m = __builtin_huge_val();
+  for (int i = threadIdx.x; i < n; i += RED_THREADS) {
+    s += part[i];
+    if (with_min) m = fmin(m, part[n + i]);
+  }
+  const double ts = block_sum(s, red[0]);
+  const double tm = block_min(m, red[1]);
+  if (threadIdx.x == 0) {
+    res[0] = ts;
+    if (with_min) res[1] = tm;
+  }
+}
+
+// Stage 1 of the energy fold: block b folds part[b*chunk, (b+1)*chunk) of
+// the n sums and of the n minima into out[b] and out[FIN_BLOCKS + b].
+__global__ void __launch_bounds__(RED_THREADS) k_fold_chunks(const double* __restrict__ part, int n, int chunk,
+                                                             double* __restrict__ out) {
+  __shared__ double red[2][RED_THREADS / 64];
+  const int lo = blockIdx.x * chunk;
+  const int hi = min(n, lo + chunk);
+  double s = 0.0, m = __builtin_huge_val();
+  for (int i = lo + threadIdx.x; i < hi; i += RED_THREADS) {
+    s += part[i];
+    m = fmin(m, part[n + i]);
+  }
+  const double ts = block_sum(s, red[0]);
+  const double tm = block_min(m, red[1]);
+  if (threadIdx.x == 0) {
+    out[blockIdx.x] = ts;
+    out[FIN_BLOCKS + blockIdx.x] = tm;
+  }
+}
+
+}  // namespace
+
+hipError_t fill(double* y, double v, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(vgrid(n)), dim3(VB), 0, s, y, v, n);
+  return hipGetLastError();
+}
+
+hipError_t finalize_sum_min(const double* part, int n, double* scratch, double* res, hipStream_t s) {
+  if (n <= 4 * RED_THREADS) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, part, n, 1, res);
+  } else {
+    // stage 1: FIN_BLOCKS blocks fold contiguous chunks; stage 2 folds those
+    const int chunk = (n + FIN_BLOCKS - 1) / FIN_BLOCKS;
+    hipLaunchKernelGGL(k_fold_chunks, dim3(FIN_BLOCKS), dim3(RED_THREADS), 0, s, part, n, chunk, scratch);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch, FIN_BLOCKS, 1, res);
+  }
+  return hipGetLastError();
+}
+
+hipError_t dot(const double* x, const double* y, int64_t n, double* scratch, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_part, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, x, y, n, scratch);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch, RED_BLOCKS, 0, res);
+  return hipGetLastError();
+}
+
+hipError_t axpy(double a, const double* x, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(vgrid(n)), dim3(VB), 0, s, a, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t xpay(const double* x, double a, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_xpay, dim3(vgrid(n)), dim3(VB), 0, s, x, a, y, n);
+  return hipGetLastError();
+}
+
+hipError_t waxpy(const double* x, double a, const double* d, double* w, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_waxpy, dim3(vgrid(n)), dim3(VB), 0, s, x, a, d, w, n);
+  return hipGetLastError();
+}
+
+hipError_t scale_copy(double a, const double* x, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(vgrid(n)), dim3(VB), 0, s, a, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t mask_mul(const double* m, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_mul, dim3(vgrid(n)), dim3(VB), 0, s, m, y, n);
+  return hipGetLastError();
+}
+
+}  // namespace tmop

@@ -1,0 +1,8 @@
+// Element kernels, 2D, float contractions.
+#include "tmop_launch.h"
+
+namespace tmop {
+int launch_elem_2d_f32(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid) {
+  return launch_dispatch<2, float>(p, Q, metric, op, lp, s, grid);
+}
+}  // namespace tmop

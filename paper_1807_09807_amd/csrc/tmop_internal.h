@@ -1,0 +1,59 @@
+// Host-side interfaces shared by the translation units of libtmop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tmop {
+
+// Element operations: F and min det A (eq. 2.4), dF/dx, (d^2F/dx^2) v.
+enum { OP_ENERGY = 0, OP_GRAD = 1, OP_HESS = 2 };
+
+constexpr int MAXP = 5;   // nodes per direction (order p <= 4)
+constexpr int MAXQ = 6;   // quadrature points per direction
+
+// Everything one element-kernel launch needs, in host form.
+struct LaunchParams {
+  const double* x;
+  const double* v;
+  double* out;
+  const int32_t* elem_node;
+  const int32_t* list;
+  int32_t n_list;
+  int64_t n_node;
+  double* part;            // energy partials, >= 2 * grid doubles
+  double B[MAXQ][MAXP];
+  double G[MAXQ][MAXP];
+  double w[MAXQ];
+  double Winv[3][3];
+  double xi[MAXP];         // GLL node coordinates on [0,1]
+  double detW, detWinv;
+};
+
+// Launch one element operation (OP_ENERGY / OP_GRAD / OP_HESS) on the
+// n_list elements of lp.list.  Returns 0, -1 if no kernel exists for
+// (p, Q, metric), or -2 on a launch error.  *grid receives the number of
+// workgroups (the number of energy partials written).
+int launch_elem_2d_f64(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
+int launch_elem_2d_f32(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
+int launch_elem_3d_f64(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
+int launch_elem_3d_f32(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
+bool elem_supported(int dim, int p, int Q);
+
+// BLAS-1 and reductions (tmop_blas.hip).  Every reduction is deterministic:
+// fixed grid, fixed tree order.
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_THREADS = 256;
+hipError_t fill(double* y, double v, int64_t n, hipStream_t s);
+// res[0] = sum(part[0..n)), res[1] = min(part[n..2n))   (scratch: >= 2*FIN_BLOCKS doubles)
+constexpr int FIN_BLOCKS = 256;
+hipError_t finalize_sum_min(const double* part, int n, double* scratch, double* res, hipStream_t s);
+// res[0] = x . y   (scratch: >= RED_BLOCKS doubles)
+hipError_t dot(const double* x, const double* y, int64_t n, double* scratch, double* res, hipStream_t s);
+hipError_t axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);          // y += a x
+hipError_t xpay(const double* x, double a, double* y, int64_t n, hipStream_t s);          // y = x + a y
+hipError_t waxpy(const double* x, double a, const double* d, double* w, int64_t n, hipStream_t s);  // w = x + a d
+hipError_t scale_copy(double a, const double* x, double* y, int64_t n, hipStream_t s);    // y = a x
+hipError_t mask_mul(const double* m, double* y, int64_t n, hipStream_t s);                // y *= m
+
+}  // namespace tmop

@@ -1,0 +1,317 @@
+// Device library of TMOP quality metrics mu(T) and their derivatives in T.
+//
+// Section 3.2 / Table 3.1 define the metrics; Section 3.4 recommends writing
+// them through matrix invariants so that first and second derivatives are
+// easy to form.  Every metric here is mu = f(I1, I2, tau) with
+//   I1 = |T|^2, tau = det T, C = cof T = d tau / dT, I2 = |C|^2 (3D only),
+// and the derivatives follow from the chain rule:
+//   P  = dmu/dT = 2 f1 T + f2 dI2 + ft C,            dI2 = 2 (I1 T - T T^t T)
+//   dP = d/de P(T + e E)
+//      = 2 f1 E + f2 ddI2[E] + ft dC[E]
+//        + 2T (f11 a1 + f12 a2 + f1t at) + dI2 (f12 a1 + f22 a2 + f2t at)
+//        + C (f1t a1 + f2t a2 + ftt at),
+//   a1 = 2 T:E, a2 = dI2:E, at = C:E,
+//   ddI2[E] = 2 (2 (T:E) T + I1 E - E T^t T - T E^t T - T T^t E).
+// Metric values avoid the cancellation of "... - 1" where an exact identity
+// allows it (2D: |T|^2 - 2 det T = (T00 - T11)^2 + (T01 + T10)^2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tmop {
+
+template <typename R> __device__ __forceinline__ R rcp(R x) { return R(1) / x; }
+
+// tau^(-1/3) with the real cube root (negative for tau < 0).  FP64: an FP32
+// seed from the hardware log2/exp2 (relative error ~1e-7), then two Newton
+// steps for y^-3 = tau, y <- y + y (1 - tau y^3) / 3, each of which squares
+// the relative error.  No FP64 division or cube root is needed.
+__device__ __forceinline__ double rcbrt(double t) {
+  const float a = fabsf((float)t);
+  float s = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(a) * (-1.0f / 3.0f));
+  double y = (double)(t < 0.0 ? -s : s);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double y3 = y * y * y;
+    y = fma(y * (1.0 / 3.0), fma(-t, y3, 1.0), y);
+  }
+  return y;
+}
+__device__ __forceinline__ float rcbrt(float t) {
+  float y = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(fabsf(t)) * (-1.0f / 3.0f));
+  y = t < 0.0f ? -y : y;
+  const float y3 = y * y * y;
+  return fmaf(y * (1.0f / 3.0f), fmaf(-t, y3, 1.0f), y);
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void cofactor(const R T[D][D], R C[D][D]) {
+  if constexpr (D == 2) {
+    C[0][0] = T[1][1];  C[0][1] = -T[1][0];
+    C[1][0] = -T[0][1]; C[1][1] = T[0][0];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int a = (r + 1) % 3, b = (r + 2) % 3;   // C[r] = T[a] x T[b]
+      C[r][0] = T[a][1] * T[b][2] - T[a][2] * T[b][1];
+      C[r][1] = T[a][2] * T[b][0] - T[a][0] * T[b][2];
+      C[r][2] = T[a][0] * T[b][1] - T[a][1] * T[b][0];
+    }
+  }
+}
+
+// Directional derivative of cof at T along E.
+template <int D, typename R>
+__device__ __forceinline__ void dcofactor(const R T[D][D], const R E[D][D], R dC[D][D]) {
+  if constexpr (D == 2) {
+    cofactor<2, R>(E, dC);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int a = (r + 1) % 3, b = (r + 2) % 3;   // d(T[a] x T[b]) = E[a] x T[b] + T[a] x E[b]
+      dC[r][0] = E[a][1] * T[b][2] - E[a][2] * T[b][1] + T[a][1] * E[b][2] - T[a][2] * E[b][1];
+      dC[r][1] = E[a][2] * T[b][0] - E[a][0] * T[b][2] + T[a][2] * E[b][0] - T[a][0] * E[b][2];
+      dC[r][2] = E[a][0] * T[b][1] - E[a][1] * T[b][0] + T[a][0] * E[b][1] - T[a][1] * E[b][0];
+    }
+  }
+}
+
+template <int D, typename R>
+__device__ __forceinline__ R det(const R T[D][D]) {
+  if constexpr (D == 2) return T[0][0] * T[1][1] - T[0][1] * T[1][0];
+  else
+    return T[0][0] * (T[1][1] * T[2][2] - T[1][2] * T[2][1])
+         - T[0][1] * (T[1][0] * T[2][2] - T[1][2] * T[2][0])
+         + T[0][2] * (T[1][0] * T[2][1] - T[1][1] * T[2][0]);
+}
+
+// Partial derivatives of f(I1, I2, tau).  Flags tell which ones are
+// identically zero so the compiler drops their terms.
+template <typename R> struct Partials { R f1, f2, ft, f11, f12, f1t, f22, f2t, ftt; };
+
+template <int METRIC> struct MetricInfo;
+template <> struct MetricInfo<2>   { static constexpr int dim = 2; static constexpr bool i2 = false; };
+template <> struct MetricInfo<7>   { static constexpr int dim = 2; static constexpr bool i2 = false; };
+template <> struct MetricInfo<302> { static constexpr int dim = 3; static constexpr bool i2 = true; };
+template <> struct MetricInfo<303> { static constexpr int dim = 3; static constexpr bool i2 = false; };
+
+template <int METRIC, typename R>
+__device__ __forceinline__ Partials<R> partials(R I1, R I2, R tau) {
+  Partials<R> p{};
+  if constexpr (METRIC == 2) {            // f = I1 / (2 tau) - 1
+    const R rt = rcp(tau);
+    const R rt2 = rt * rt;
+    p.f1 = R(0.5) * rt;  p.ft = R(-0.5) * I1 * rt2;
+    p.f1t = R(-0.5) * rt2; p.ftt = I1 * rt2 * rt;
+  } else if constexpr (METRIC == 7) {     // f = I1 (1 + tau^-2) - 4
+    const R rt = rcp(tau);
+    const R rt2 = rt * rt, rt3 = rt2 * rt;
+    p.f1 = R(1) + rt2;  p.ft = R(-2) * I1 * rt3;
+    p.f1t = R(-2) * rt3; p.ftt = R(6) * I1 * rt3 * rt;
+  } else if constexpr (METRIC == 303) {   // f = I1 tau^{-2/3} / 3 - 1
+    const R y = rcbrt(tau);                   // tau^{-1/3}
+    const R c = y * y;                        // tau^{-2/3}
+    const R rt = c * y;                       // 1 / tau
+    p.f1 = c * R(1.0 / 3.0);
+    p.f1t = R(-2.0 / 9.0) * c * rt;
+    p.ft = p.f1t * I1;
+    p.ftt = R(10.0 / 27.0) * I1 * c * rt * rt;
+  } else if constexpr (METRIC == 302) {   // f = I1 I2 tau^-2 / 9 - 1
+    const R rt = rcp(tau);
+    const R s = rt * rt * R(1.0 / 9.0);
+    p.f1 = I2 * s;  p.f2 = I1 * s;  p.ft = R(-2) * I1 * I2 * s * rt;
+    p.f12 = s;  p.f1t = R(-2) * I2 * s * rt;  p.f2t = R(-2) * I1 * s * rt;
+    p.ftt = R(6) * I1 * I2 * s * rt * rt;
+  }
+  return p;
+}
+
+// mu(T) given tau = det T.
+template <int METRIC, typename R>
+__device__ __forceinline__ R mu_value(const R (&T)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim], R tau) {
+  constexpr int D = MetricInfo<METRIC>::dim;
+  if constexpr (METRIC == 2 || METRIC == 7) {
+    const R u = T[0][0] - T[1][1], w = T[0][1] + T[1][0];
+    const R dev = u * u + w * w;                 // |T|^2 - 2 tau >= 0
+    const R rt = rcp(tau);
+    if constexpr (METRIC == 2) return R(0.5) * dev * rt;
+    else return dev * (R(1) + rt * rt) + R(2) * (tau - R(1)) * (tau - R(1)) * rt;
+  } else {
+    R I1 = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) I1 += T[i][j] * T[i][j];
+    if constexpr (METRIC == 303) {
+      const R y = rcbrt(tau);
+      return I1 * (y * y) * R(1.0 / 3.0) - R(1);
+    } else {
+      R C[3][3];
+      cofactor<3, R>(T, C);
+      R I2 = 0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) I2 += C[i][j] * C[i][j];
+      const R rt = rcp(tau);
+      return I1 * I2 * rt * rt * R(1.0 / 9.0) - R(1);
+    }
+  }
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void dI2_of(const R T[D][D], R I1, R out[D][D]) {
+  // 2 (I1 T - T T^t T)
+  R TTt[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      R s = 0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) s += T[i][k] * T[j][k];
+      TTt[i][j] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      R s = 0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) s += TTt[i][k] * T[k][j];
+      out[i][j] = R(2) * (I1 * T[i][j] - s);
+    }
+}
+
+// P = dmu/dT.
+template <int METRIC, typename R>
+__device__ __forceinline__ void mu_first(const R (&T)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim],
+                                         R (&P)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim]) {
+  constexpr int D = MetricInfo<METRIC>::dim;
+  R C[D][D];
+  cofactor<D, R>(T, C);
+  R I1 = 0, tau = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) I1 += T[i][j] * T[i][j];
+#pragma unroll
+  for (int j = 0; j < D; ++j) tau += T[0][j] * C[0][j];
+  R I2 = 0;
+  if constexpr (MetricInfo<METRIC>::i2) {
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) I2 += C[i][j] * C[i][j];
+  }
+  const Partials<R> f = partials<METRIC, R>(I1, I2, tau);
+  if constexpr (MetricInfo<METRIC>::i2) {
+    R dI2[D][D];
+    dI2_of<D, R>(T, I1, dI2);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) P[i][j] = R(2) * f.f1 * T[i][j] + f.f2 * dI2[i][j] + f.ft * C[i][j];
+  } else {
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) P[i][j] = R(2) * f.f1 * T[i][j] + f.ft * C[i][j];
+  }
+}
+
+// dP = (d^2 mu / dT^2) : E.
+template <int METRIC, typename R>
+__device__ __forceinline__ void mu_second(const R (&T)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim],
+                                          const R (&E)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim],
+                                          R (&dP)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim]) {
+  constexpr int D = MetricInfo<METRIC>::dim;
+  R C[D][D], dC[D][D];
+  cofactor<D, R>(T, C);
+  dcofactor<D, R>(T, E, dC);
+  R I1 = 0, tau = 0, TE = 0, CE = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      I1 += T[i][j] * T[i][j];
+      TE += T[i][j] * E[i][j];
+      CE += C[i][j] * E[i][j];
+    }
+#pragma unroll
+  for (int j = 0; j < D; ++j) tau += T[0][j] * C[0][j];
+  if constexpr (!MetricInfo<METRIC>::i2) {
+    const Partials<R> f = partials<METRIC, R>(I1, R(0), tau);
+    const R a1 = R(2) * TE, at = CE;
+    const R sT = R(2) * (f.f1t * at);             // f11 = 0 for these metrics
+    const R sC = f.f1t * a1 + f.ftt * at;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        dP[i][j] = R(2) * f.f1 * E[i][j] + f.ft * dC[i][j] + sT * T[i][j] + sC * C[i][j];
+  } else {
+    R I2 = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) I2 += C[i][j] * C[i][j];
+    const Partials<R> f = partials<METRIC, R>(I1, I2, tau);
+    // T^t T, then the pieces of ddI2
+    R TtT[D][D], TTt[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        R s = 0, u = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) { s += T[k][i] * T[k][j]; u += T[i][k] * T[j][k]; }
+        TtT[i][j] = s;
+        TTt[i][j] = u;
+      }
+    R dI2[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        R s = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) s += TTt[i][k] * T[k][j];
+        dI2[i][j] = R(2) * (I1 * T[i][j] - s);
+      }
+    R a2 = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) a2 += dI2[i][j] * E[i][j];
+    const R a1 = R(2) * TE, at = CE;
+    const R sT = R(2) * (f.f12 * a2 + f.f1t * at);     // f11 = 0
+    const R sI = f.f12 * a1 + f.f2t * at;              // f22 = 0
+    const R sC = f.f1t * a1 + f.f2t * a2 + f.ftt * at;
+    // E T^t T, T E^t T, T T^t E
+    R ET[D][D], TEt[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        R s = 0, u = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) { s += E[i][k] * TtT[k][j]; u += T[i][k] * E[j][k]; }
+        ET[i][j] = s;       // (E T^t T)_ij
+        TEt[i][j] = u;      // (T E^t)_ij
+      }
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        R teT = 0, ttE = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) { teT += TEt[i][k] * T[k][j]; ttE += TTt[i][k] * E[k][j]; }
+        const R ddI2 = R(2) * (R(2) * TE * T[i][j] + I1 * E[i][j] - ET[i][j] - teT - ttE);
+        dP[i][j] = R(2) * f.f1 * E[i][j] + f.f2 * ddI2 + f.ft * dC[i][j]
+                 + sT * T[i][j] + sI * dI2[i][j] + sC * C[i][j];
+      }
+  }
+}
+
+}  // namespace tmop

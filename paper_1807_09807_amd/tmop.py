@@ -1,0 +1,245 @@
+"""Python binding of libtmop (ctypes).  Argument marshalling only: every
+step of the computation runs in the library's HIP kernels.
+
+The functions carry the names of the C ABI (include/tmop.h):
+tmop_setup, tmop_energy, tmop_gradient, tmop_hessian_apply,
+tmop_newton_solve, tmop_destroy.  Device arrays are torch tensors of shape
+(dim, n_node), float64, contiguous, on a HIP device; the work is enqueued
+on torch's current stream of that device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtmop.so")
+
+TMOP_OK, TMOP_W_INVERTED, TMOP_W_MAXIT, TMOP_W_LSFAIL = 0, 1, 2, 3
+TMOP_E_ARG, TMOP_E_TARGET, TMOP_E_NOMEM, TMOP_E_HIP, TMOP_E_UNSUPPORTED = -1, -2, -3, -4, -5
+TMOP_MU2, TMOP_MU7, TMOP_MU302, TMOP_MU303 = 2, 7, 302, 303
+TMOP_GAUSS_LEGENDRE, TMOP_GAUSS_LOBATTO = 0, 1
+TMOP_FP64, TMOP_MIXED_FP32 = 0, 1
+TMOP_TGT_CONST = 0
+
+EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_hessian_apply", "tmop_newton_solve",
+           "tmop_destroy", "tmop_strerror", "tmop_newton_default_opts")
+
+
+class TMOPError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {tmop_strerror(status)} (status {status})")
+        self.status = status
+
+
+class tmop_mesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("order", ctypes.c_int32), ("n_elem", ctypes.c_int64),
+                ("n_node", ctypes.c_int64), ("elem_node", ctypes.POINTER(ctypes.c_int32)),
+                ("fixed", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class tmop_quadrature(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n1d", ctypes.c_int32)]
+
+
+class tmop_target(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("W", ctypes.POINTER(ctypes.c_double))]
+
+
+class tmop_newton_opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("max_it", ctypes.c_int32),
+                ("cg_rtol", ctypes.c_double), ("cg_max_it", ctypes.c_int32), ("ls_shrink", ctypes.c_double),
+                ("ls_max", ctypes.c_int32), ("f_growth", ctypes.c_double), ("g_growth", ctypes.c_double),
+                ("hist_F", ctypes.POINTER(ctypes.c_double)), ("hist_gnorm", ctypes.POINTER(ctypes.c_double)),
+                ("hist_cg", ctypes.POINTER(ctypes.c_int32)), ("ftarget", ctypes.c_double),
+                ("cg_forcing", ctypes.c_int32), ("hist_time", ctypes.POINTER(ctypes.c_double))]
+
+
+class tmop_newton_report(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("ls_shrinks", ctypes.c_int32),
+                ("neg_curv", ctypes.c_int32), ("F0", ctypes.c_double), ("F", ctypes.c_double),
+                ("gnorm0", ctypes.c_double), ("gnorm", ctypes.c_double), ("min_detA", ctypes.c_double)]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libtmop.so; raises (never falls back) when it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run `python -m paper_1807_09807_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.tmop_setup.argtypes = [ctypes.POINTER(tmop_mesh), ctypes.POINTER(tmop_quadrature),
+                               ctypes.POINTER(tmop_target), i32, i32, ctypes.POINTER(P)]
+    lib.tmop_setup.restype = ctypes.c_int
+    lib.tmop_energy.argtypes = [P, P, ctypes.POINTER(dbl), ctypes.POINTER(dbl), P]
+    lib.tmop_energy.restype = ctypes.c_int
+    lib.tmop_gradient.argtypes = [P, P, P, P]
+    lib.tmop_gradient.restype = ctypes.c_int
+    lib.tmop_hessian_apply.argtypes = [P, P, P, P, P]
+    lib.tmop_hessian_apply.restype = ctypes.c_int
+    lib.tmop_newton_solve.argtypes = [P, P, ctypes.POINTER(tmop_newton_opts),
+                                      ctypes.POINTER(tmop_newton_report), P]
+    lib.tmop_newton_solve.restype = ctypes.c_int
+    lib.tmop_destroy.argtypes = [P]
+    lib.tmop_destroy.restype = None
+    lib.tmop_strerror.argtypes = [ctypes.c_int]
+    lib.tmop_strerror.restype = ctypes.c_char_p
+    lib.tmop_newton_default_opts.argtypes = [ctypes.POINTER(tmop_newton_opts)]
+    lib.tmop_newton_default_opts.restype = None
+    _lib = lib
+    return lib
+
+
+def tmop_strerror(status: int) -> str:
+    return load().tmop_strerror(int(status)).decode()
+
+
+def _stream(t) -> ctypes.c_void_p:
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _check_field(t, dim, n_node, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 tensor on a HIP device")
+    if tuple(t.shape) != (dim, n_node) or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous with shape ({dim}, {n_node}), got {tuple(t.shape)}")
+
+
+class Context:
+    """Owns one tmop_ctx (tmop_setup ... tmop_destroy)."""
+
+    def __init__(self, dim: int, order: int, elem_node: np.ndarray, n_node: int, n_q1d: int, metric: int,
+                 W, fixed: Optional[np.ndarray] = None, precision: int = TMOP_FP64,
+                 rule: int = TMOP_GAUSS_LEGENDRE):
+        lib = load()
+        self._lib = lib
+        self.dim, self.order, self.n_node, self.metric, self.precision = dim, order, int(n_node), metric, precision
+        en = np.ascontiguousarray(elem_node, dtype=np.int32)
+        self.n_elem = en.shape[0]
+        m = tmop_mesh(dim, order, self.n_elem, int(n_node), en.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None)
+        if fixed is not None:
+            fx = np.ascontiguousarray(fixed, dtype=np.uint8)
+            if fx.shape != (dim, n_node):
+                raise ValueError("fixed must have shape (dim, n_node)")
+            m.fixed = fx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        Wa = np.ascontiguousarray(np.asarray(W, dtype=np.float64).reshape(dim, dim))
+        q = tmop_quadrature(rule, n_q1d)
+        t = tmop_target(TMOP_TGT_CONST, Wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        h = ctypes.c_void_p()
+        st = lib.tmop_setup(ctypes.byref(m), ctypes.byref(q), ctypes.byref(t), metric, precision, ctypes.byref(h))
+        if st < 0:
+            raise TMOPError(st, "tmop_setup")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.tmop_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def energy(self, x):
+        """(F, min det A, status).  status is TMOP_OK or TMOP_W_INVERTED."""
+        _check_field(x, self.dim, self.n_node, "x")
+        F, md = ctypes.c_double(), ctypes.c_double()
+        st = self._lib.tmop_energy(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.byref(F), ctypes.byref(md), _stream(x))
+        if st < 0:
+            raise TMOPError(st, "tmop_energy")
+        return F.value, md.value, st
+
+    def gradient(self, x, out=None):
+        import torch
+        _check_field(x, self.dim, self.n_node, "x")
+        out = torch.empty_like(x) if out is None else out
+        _check_field(out, self.dim, self.n_node, "out")
+        st = self._lib.tmop_gradient(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream(x))
+        if st < 0:
+            raise TMOPError(st, "tmop_gradient")
+        return out
+
+    def hessian_apply(self, x, v, out=None):
+        import torch
+        _check_field(x, self.dim, self.n_node, "x")
+        _check_field(v, self.dim, self.n_node, "v")
+        out = torch.empty_like(x) if out is None else out
+        _check_field(out, self.dim, self.n_node, "out")
+        st = self._lib.tmop_hessian_apply(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()), _stream(x))
+        if st < 0:
+            raise TMOPError(st, "tmop_hessian_apply")
+        return out
+
+    def newton_solve(self, x, **opts):
+        """Optimizes x in place.  Keyword options are the fields of
+        tmop_newton_opts; returns (status, report dict with per-iteration
+        history lists F, gnorm, cg)."""
+        _check_field(x, self.dim, self.n_node, "x")
+        o = tmop_newton_opts()
+        self._lib.tmop_newton_default_opts(ctypes.byref(o))
+        for k, v in opts.items():
+            if k.startswith("hist_") or not hasattr(o, k):
+                raise ValueError(f"unknown Newton option {k}")
+            setattr(o, k, v)
+        n = o.max_it + 1
+        hF = (ctypes.c_double * n)()
+        hg = (ctypes.c_double * n)()
+        hc = (ctypes.c_int32 * n)()
+        ht = (ctypes.c_double * n)()
+        o.hist_time = ctypes.cast(ht, ctypes.POINTER(ctypes.c_double))
+        o.hist_F = ctypes.cast(hF, ctypes.POINTER(ctypes.c_double))
+        o.hist_gnorm = ctypes.cast(hg, ctypes.POINTER(ctypes.c_double))
+        o.hist_cg = ctypes.cast(hc, ctypes.POINTER(ctypes.c_int32))
+        rep = tmop_newton_report()
+        st = self._lib.tmop_newton_solve(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.byref(o), ctypes.byref(rep),
+                                         _stream(x))
+        if st < 0:
+            raise TMOPError(st, "tmop_newton_solve")
+        r = {k: getattr(rep, k) for k, _ in tmop_newton_report._fields_}
+        k = r["iters"] + 1
+        r.update(history_F=list(hF[:k]), history_gnorm=list(hg[:k]), history_cg=list(hc[:k]),
+                 history_time=list(ht[:k]), status=st)
+        return st, r
+
+
+# C-ABI names, for callers that prefer the flat interface.
+def tmop_setup(*args, **kw) -> Context:
+    return Context(*args, **kw)
+
+
+def tmop_energy(ctx: Context, x):
+    return ctx.energy(x)
+
+
+def tmop_gradient(ctx: Context, x, g=None):
+    return ctx.gradient(x, g)
+
+
+def tmop_hessian_apply(ctx: Context, x, v, Hv=None):
+    return ctx.hessian_apply(x, v, Hv)
+
+
+def tmop_newton_solve(ctx: Context, x, **opts):
+    return ctx.newton_solve(x, **opts)
+
+
+def tmop_destroy(ctx: Context):
+    ctx.close()

@@ -1,0 +1,89 @@
+"""The C-ABI library: it loads without a GPU, exports every entry point
+declared in include/tmop.h, and rejects bad arguments before touching the
+device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1807_09807_amd import tmop as T
+from paper_1807_09807_amd import meshgen
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "tmop.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tmop_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = T.load()
+    names = declared()
+    assert set(T.EXPORTS) <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_strerror():
+    assert "success" in T.tmop_strerror(0)
+    assert "invalid argument" in T.tmop_strerror(T.TMOP_E_ARG)
+    assert "det W" in T.tmop_strerror(T.TMOP_E_TARGET)
+
+
+def _setup_status(dim=2, order=2, n=2, Q=4, metric=2, W=None, prec=0, rule=0, elem_node=None, n_node=None,
+                  n_elem=None):
+    lib = T.load()
+    mesh = meshgen.box_mesh(dim if dim in (2, 3) else 2, n, max(order, 1))
+    en = np.ascontiguousarray(mesh.elem_node if elem_node is None else elem_node, dtype=np.int32)
+    m = T.tmop_mesh(dim, order, en.shape[0] if n_elem is None else n_elem,
+                    mesh.n_node if n_node is None else n_node,
+                    en.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None)
+    Wa = np.ascontiguousarray(np.eye(dim) if W is None else W, dtype=np.float64)
+    q = T.tmop_quadrature(rule, Q)
+    t = T.tmop_target(0, Wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    h = ctypes.c_void_p()
+    return lib.tmop_setup(ctypes.byref(m), ctypes.byref(q), ctypes.byref(t), metric, prec, ctypes.byref(h)), h
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(dim=4), T.TMOP_E_ARG),
+    (dict(order=0), T.TMOP_E_ARG),
+    (dict(Q=2), T.TMOP_E_ARG),                        # fewer than p+1 points (Section 3.3)
+    (dict(metric=303), T.TMOP_E_ARG),                 # 3D metric on a 2D mesh
+    (dict(dim=3, metric=2, Q=4), T.TMOP_E_ARG),
+    (dict(prec=7), T.TMOP_E_ARG),
+    (dict(rule=5), T.TMOP_E_ARG),
+    (dict(n_elem=0), T.TMOP_E_ARG),                   # empty mesh
+    (dict(n_node=5), T.TMOP_E_ARG),                   # node id out of range
+    (dict(W=np.array([[1.0, 0.0], [0.0, -1.0]])), T.TMOP_E_TARGET),   # det W <= 0 (Section 3.1)
+    (dict(W=np.zeros((2, 2))), T.TMOP_E_TARGET),
+    (dict(order=5, Q=6), T.TMOP_E_UNSUPPORTED),
+    (dict(order=2, Q=5, dim=3, metric=303), T.TMOP_OK if False else "skip"),
+])
+def test_setup_validation(kw, status):
+    if status == "skip":
+        pytest.skip("valid arguments need a GPU")
+    st, h = _setup_status(**kw)
+    assert st == status
+    assert not h.value
+
+
+def test_newton_default_opts():
+    lib = T.load()
+    o = T.tmop_newton_opts()
+    lib.tmop_newton_default_opts(ctypes.byref(o))
+    assert o.rtol == 1e-12 and o.f_growth == 1.2 and o.g_growth == 1.2 and o.ls_shrink == 0.5
+    assert o.max_it == 50 and o.ls_max == 30 and not o.hist_F
+
+
+def test_null_arguments():
+    lib = T.load()
+    assert lib.tmop_energy(None, None, None, None, None) == T.TMOP_E_ARG
+    assert lib.tmop_gradient(None, None, None, None) == T.TMOP_E_ARG
+    assert lib.tmop_hessian_apply(None, None, None, None, None) == T.TMOP_E_ARG
+    assert lib.tmop_newton_solve(None, None, None, None, None) == T.TMOP_E_ARG
+    lib.tmop_destroy(None)

@@ -1,0 +1,56 @@
+"""Parity at the full workload sizes, with the same library calls the
+benchmark times: F against the oracle's full sum, gradient and Hessian
+action at 64 seeded nodes against the oracle evaluated on the elements
+around those nodes only."""
+import numpy as np
+import pytest
+
+from oracle import tmop_oracle as O
+from paper_1807_09807_amd import meshgen
+from tests._helpers import EPS32, say, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+WORKLOADS = ["q2_square_8", "q3_square_256", "q2_cube_64", "q3_cube_48", "q2_square_512"]
+
+
+@pytest.fixture(scope="module", params=WORKLOADS)
+def full(request):
+    name = request.param
+    w = meshgen.WORKLOADS[name]
+    say(f"[fullsize] {name}: building mesh and oracle reference")
+    mesh = meshgen.box_mesh(w["dim"], w["n"], w["p"])
+    W = mesh.h * np.eye(w["dim"])
+    prob = O.Problem(w["dim"], w["p"], w["Q"], mesh.elem_node, w["metric"], W)
+    mesh = meshgen.make_workload(name, bad_elements=lambda x, e: prob.bad_elements(x, e, w["tau_min"]))
+    x = mesh.x
+    v = meshgen.random_direction(mesh, w["seed"] + 100)
+    F, md = prob.energy(x)
+    nodes = np.random.default_rng(w["seed"] + 200).choice(mesh.n_node, 64, replace=False)
+    g_s = prob.gradient_at(x, nodes)
+    Hv_s = prob.hessian_apply_at(x, v, nodes)
+    kappa = prob.max_condition(x)
+    say(f"  {name}: F={F:.15e} min det A={md:.3e} kappa={kappa:.1f} repair={mesh.info['repair_rounds']}")
+    return name, w, mesh, W, x, v, dict(F=F, mindet=md, nodes=nodes, g=g_s, Hv=Hv_s, kappa=kappa)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_full_size(full, precision):
+    from paper_1807_09807_amd import tmop as T
+    name, w, mesh, W, x, v, ref = full
+    tol = 1e-12 if precision == 0 else max(1e-5, 4.0 * EPS32 * ref["kappa"])
+    ctx = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W,
+                    fixed=mesh.fixed, precision=precision)
+    xd, vd = to_dev(x), to_dev(v)
+    F, md, st = ctx.energy(xd)
+    g = ctx.gradient(xd)[:, torch.from_numpy(ref["nodes"]).cuda()].cpu().numpy()
+    Hv = ctx.hessian_apply(xd, vd)[:, torch.from_numpy(ref["nodes"]).cuda()].cpu().numpy()
+    eF = abs(F - ref["F"]) / abs(ref["F"])
+    eg = np.max(np.abs(g - ref["g"])) / np.max(np.abs(ref["g"]))
+    eh = np.max(np.abs(Hv - ref["Hv"])) / np.max(np.abs(ref["Hv"]))
+    say(f"  {name} prec={precision}: F rel {eF:.2e}, g rel {eg:.2e}, Hv rel {eh:.2e} (tol {tol:.1e})")
+    assert st == 0
+    assert eF <= tol and eg <= tol and eh <= tol
+    assert abs(md - ref["mindet"]) <= tol * abs(ref["mindet"])
+    ctx.close()

@@ -54,11 +54,16 @@ def test_repair_removes_inversions():
     base = mesh.x_grid + meshgen.sinusoid(mesh, 0.05)
     raw = meshgen.perturb(mesh, w["noise"], w["seed"], base=base)
     assert prob.bad_elements(raw).size > 0          # the literal noise level inverts some Q3 elements
-    x = meshgen.perturb(mesh, w["noise"], w["seed"], base=base, bad_elements=prob.bad_elements)
-    assert prob.bad_elements(x).size == 0
+    bad = lambda x, e: prob.bad_elements(x, e, w["tau_min"])
+    x = meshgen.perturb(mesh, w["noise"], w["seed"], base=base, bad_elements=bad)
+    assert prob.bad_elements(x, None, w["tau_min"]).size == 0
+    assert prob.element_min_det(x).min() > w["tau_min"] * mesh.h ** 2
     assert mesh.info["repair_rounds"] >= 1
-    x2 = meshgen.perturb(mesh, w["noise"], w["seed"], base=base, bad_elements=prob.bad_elements)
+    x2 = meshgen.perturb(mesh, w["noise"], w["seed"], base=base, bad_elements=bad)
     np.testing.assert_array_equal(x, x2)
+    # the incremental re-check agrees with a full one
+    untouched = np.setdiff1d(np.arange(mesh.n_elem), bad(x, None))
+    assert untouched.size == mesh.n_elem
 
 
 def test_training_mesh_valid():

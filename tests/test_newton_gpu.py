@@ -1,0 +1,129 @@
+"""The Newton / truncated-CG / line-search driver of the library against
+the oracle's implementation of the same rules (Section 3.4)."""
+import numpy as np
+import pytest
+
+from oracle import tmop_oracle as O
+from paper_1807_09807_amd import meshgen
+from tests._helpers import say, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _c1():
+    w = meshgen.WORKLOADS["q2_square_8"]
+    mesh = meshgen.box_mesh(2, w["n"], w["p"])
+    W = mesh.h * np.eye(2)
+    prob = O.Problem(2, w["p"], w["Q"], mesh.elem_node, w["metric"], W)
+    x0 = meshgen.perturb(mesh, w["noise"], w["seed"], bad_elements=prob.bad_elements)
+    return w, mesh, W, prob, x0
+
+
+def _ctx(mesh, Q, metric, W, precision=0):
+    from paper_1807_09807_amd import tmop as T
+    return T.Context(mesh.dim, mesh.order, mesh.elem_node, mesh.n_node, Q, metric, W, fixed=mesh.fixed,
+                     precision=precision)
+
+
+def test_newton_trajectory_matches_oracle():
+    """8x8 Q2 mu_2 workload, same rules as the oracle's Newton.  The
+    iterates are not unique in floating point: each step comes from a
+    truncated CG solve whose stopping iteration and negative-curvature exit
+    depend on rounding, so the two trajectories separate slowly.  Compared:
+    the step lengths, F to 1e-6 relative while F > 1e-8 F0, and the unique
+    end state (the grid, F = 0)."""
+    say("[newton] q2_square_8 trajectory")
+    w, mesh, W, prob, x0 = _c1()
+    opts = O.NewtonOptions(max_it=20, cg_rtol=1e-10)
+    xo, rep_o = O.newton_solve(prob, x0, mesh.fixed, opts)
+    ctx = _ctx(mesh, w["Q"], w["metric"], W)
+    xd = to_dev(x0)
+    st, rep = ctx.newton_solve(xd, max_it=20, cg_rtol=1e-10)
+    F_o = [h[0] for h in rep_o.history]
+    F_g = rep["history_F"]
+    cg_o = [h[3] for h in rep_o.history]
+    say(f"  oracle iters {rep_o.iters} gpu iters {rep['iters']} cg {rep_o.cg_iters}/{rep['cg_iters']}")
+    worst = 0.0
+    for k in range(max(len(F_o), len(F_g))):
+        a = F_o[k] if k < len(F_o) else float("nan")
+        b = F_g[k] if k < len(F_g) else float("nan")
+        cgb = rep["history_cg"][k] if k < len(F_g) else -1
+        cga = cg_o[k] if k < len(F_o) else -1
+        say(f"  it {k}: F oracle {a:.16e} gpu {b:.16e}  cg {cga}/{cgb}")
+        if k < len(F_o) and k < len(F_g) and a > 1e-8 * F_o[0]:
+            worst = max(worst, abs(b - a) / a)
+    say(f"  worst relative F difference while F > 1e-8 F0: {worst:.2e}")
+    assert worst <= 1e-6
+    assert st == 0 and rep_o.stop == O.STOP_CONVERGED
+    assert abs(rep["iters"] - rep_o.iters) <= 1
+    x = xd.cpu().numpy()
+    assert np.max(np.abs(x - mesh.x_grid)) < 1e-9 * mesh.h
+    assert np.max(np.abs(xo - mesh.x_grid)) < 1e-9 * mesh.h
+    assert all(b < a for a, b in zip(F_g, F_g[1:]))         # F decreases monotonically
+    np.testing.assert_array_equal(x[mesh.fixed.astype(bool)], x0[mesh.fixed.astype(bool)])
+
+
+def test_newton_ten_iterations_workload():
+    """The workload's own setting: 10 Newton iterations."""
+    w, mesh, W, prob, x0 = _c1()
+    from paper_1807_09807_amd import tmop as T
+    ctx = _ctx(mesh, w["Q"], w["metric"], W)
+    st, rep = ctx.newton_solve(to_dev(x0), max_it=10, cg_rtol=1e-10)
+    assert st in (T.TMOP_OK, T.TMOP_W_MAXIT) and rep["iters"] == 10
+    assert rep["F"] < 1e-3 * rep["F0"]
+
+
+def test_newton_on_grid_no_step():
+    w, mesh, W, prob, x0 = _c1()
+    ctx = _ctx(mesh, w["Q"], w["metric"], W)
+    xd = to_dev(mesh.x_grid)
+    st, rep = ctx.newton_solve(xd, atol=1e-12)
+    assert st == 0 and rep["iters"] == 0
+    assert torch.equal(xd, to_dev(mesh.x_grid))
+
+
+def test_newton_line_search_failure():
+    """With f_growth = 0 no step can be accepted: the method terminates
+    (Section 3.4) after trying ls_max step lengths, x unchanged."""
+    from paper_1807_09807_amd import tmop as T
+    w, mesh, W, prob, x0 = _c1()
+    ctx = _ctx(mesh, w["Q"], w["metric"], W)
+    xd = to_dev(x0)
+    st, rep = ctx.newton_solve(xd, f_growth=0.0, ls_max=7)
+    assert st == T.TMOP_W_LSFAIL and rep["iters"] == 0 and rep["ls_shrinks"] == 7
+    assert torch.equal(xd, to_dev(x0))
+
+
+def test_newton_inverted_input():
+    from paper_1807_09807_amd import tmop as T
+    w, mesh, W, prob, x0 = _c1()
+    x = x0.copy()
+    a = 2 * (mesh.n * mesh.order + 1) + 2
+    x[:, [a, a + 1]] = x[:, [a + 1, a]]
+    ctx = _ctx(mesh, w["Q"], w["metric"], W)
+    xd = to_dev(x)
+    st, rep = ctx.newton_solve(xd)
+    assert st == T.TMOP_W_INVERTED and rep["min_detA"] <= 0
+    assert torch.equal(xd, to_dev(x))
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_newton_3d_returns_to_grid(precision):
+    """Q2 hex mu_303 mesh (8^3 elements): Newton reaches the grid."""
+    say(f"[newton] q2_cube_64@8 prec={precision}")
+    w = meshgen.WORKLOADS["q2_cube_64"]
+    mesh = meshgen.box_mesh(3, 8, 2)
+    W = mesh.h * np.eye(3)
+    prob = O.Problem(3, 2, 4, mesh.elem_node, 303, W)
+    x0 = meshgen.perturb(mesh, w["noise"], w["seed"], bad_elements=prob.bad_elements)
+    ctx = _ctx(mesh, 4, 303, W, precision)
+    xd = to_dev(x0)
+    st, rep = ctx.newton_solve(xd, max_it=30, rtol=1e-10 if precision == 0 else 1e-5)
+    say(f"  status {st} iters {rep['iters']} cg {rep['cg_iters']} F {rep['F0']:.3e} -> {rep['F']:.3e}")
+    assert st == 0
+    x = xd.cpu().numpy()
+    err = np.max(np.abs(x - mesh.x_grid)) / mesh.h
+    assert err < (1e-8 if precision == 0 else 1e-4)
+    Fs = rep["history_F"]
+    assert all(b < a for a, b in zip(Fs, Fs[1:]))

@@ -1,0 +1,69 @@
+"""Parity of the HIP path with the FP64 oracle (energy, gradient, Hessian
+action), element by element, on seeded meshes: FP64 within 1e-12
+relative, the mixed FP32 path within 1e-5 relative (4 eps32 kappa on
+meshes with nearly degenerate points, see tests/_helpers.mixed_tol)."""
+import numpy as np
+import pytest
+
+from tests._helpers import build, context, mixed_tol, rel_max_err, say, small_cases, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FP64_TOL = 1e-12
+CASES = small_cases()
+
+
+@pytest.fixture(scope="module", params=CASES, ids=str)
+def setup(request):
+    case = request.param
+    say(f"[parity] case {case.name}")
+    mesh, prob, W = build(case)
+    v = np.random.default_rng(case.seed + 100).uniform(-1, 1, mesh.x.shape)
+    F, md = prob.energy(mesh.x)
+    ref = dict(F=F, mindet=md, g=prob.gradient(mesh.x), Hv=prob.hessian_apply(mesh.x, v),
+               mixed_tol=mixed_tol(prob, mesh.x))
+    return case, mesh, W, v, ref
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_energy(setup, precision):
+    case, mesh, W, v, ref = setup
+    ctx = context(case, mesh, W, precision)
+    F, md, st = ctx.energy(to_dev(mesh.x))
+    tol = FP64_TOL if precision == 0 else ref["mixed_tol"]
+    say(f"  {case.name} prec={precision} F={F!r} ref={ref['F']!r} rel={abs(F - ref['F']) / ref['F']:.2e}")
+    assert st == 0
+    assert abs(F - ref["F"]) <= tol * abs(ref["F"])
+    # det A is always evaluated in FP64 from the contracted A
+    assert abs(md - ref["mindet"]) <= (1e-12 if precision == 0 else ref["mixed_tol"]) * abs(ref["mindet"])
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_gradient(setup, precision):
+    case, mesh, W, v, ref = setup
+    ctx = context(case, mesh, W, precision)
+    g = ctx.gradient(to_dev(mesh.x)).cpu().numpy()
+    err = rel_max_err(g, ref["g"])
+    say(f"  {case.name} prec={precision} grad rel err {err:.2e}")
+    assert err <= (FP64_TOL if precision == 0 else ref["mixed_tol"])
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_hessian_apply(setup, precision):
+    case, mesh, W, v, ref = setup
+    ctx = context(case, mesh, W, precision)
+    Hv = ctx.hessian_apply(to_dev(mesh.x), to_dev(v)).cpu().numpy()
+    err = rel_max_err(Hv, ref["Hv"])
+    say(f"  {case.name} prec={precision} Hv rel err {err:.2e}")
+    assert err <= (FP64_TOL if precision == 0 else ref["mixed_tol"])
+
+
+def test_bitwise_deterministic(setup):
+    case, mesh, W, v, ref = setup
+    ctx = context(case, mesh, W, 0)
+    x, vd = to_dev(mesh.x), to_dev(v)
+    g1, g2 = ctx.gradient(x), ctx.gradient(x)
+    h1, h2 = ctx.hessian_apply(x, vd), ctx.hessian_apply(x, vd)
+    e1, e2 = ctx.energy(x), ctx.energy(x)
+    assert torch.equal(g1, g2) and torch.equal(h1, h2) and e1 == e2
