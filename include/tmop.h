@@ -164,6 +164,13 @@ int tmop_energy(tmop_ctx *ctx, const double *x, double *F, double *min_detA,
  * [dim][n_node]; g is overwritten.  Deterministic.  Async. */
 int tmop_gradient(tmop_ctx *ctx, const double *x, double *g, void *stream);
 
+/* g = s * dF/dx, where s is the DEVICE scalar *scale (NULL: s = 1), folded
+ * into the quadrature weights of the gradient kernel: the chain rule of a
+ * reverse-mode caller (upstream gradient times dF/dx, Section 3.4) without
+ * a host round trip.  Otherwise as tmop_gradient.  Async. */
+int tmop_gradient_scaled(tmop_ctx *ctx, const double *x, const double *scale, double *g,
+                         void *stream);
+
 /* Hv = (d^2F/dx^2) v, the Hessian of Section 3.4 applied to v, over all
  * DOFs.  x, v, Hv: device [dim][n_node]; Hv is overwritten.
  * Deterministic.  Async. */

@@ -30,11 +30,11 @@ def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OUT_DIR, src + ".o")
+def _compile(src: str, out_dir: str = OUT_DIR, extra=()) -> str:
+    obj = os.path.join(out_dir, src + ".o")
     path = os.path.join(CSRC, src)
     if src.endswith(".hip"):
-        cmd = ["hipcc", *HIP_FLAGS, "-c", path, "-o", obj]
+        cmd = ["hipcc", *HIP_FLAGS, *extra, "-c", path, "-o", obj]
     else:
         cmd = ["hipcc", *HOST_FLAGS, "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -46,21 +46,24 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = True) -> str:
-    os.makedirs(OUT_DIR, exist_ok=True)
+def build(jobs: int | None = None, verbose: bool = True, lib: str = LIB, out_dir: str = OUT_DIR,
+          extra=()) -> str:
+    """Compile every source (hipcc, gfx950) and link `lib`.  `extra` adds
+    compiler flags (e.g. -D tuning macros) for variant builds."""
+    os.makedirs(out_dir, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)), 16)
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda f: _compile(f, out_dir, tuple(extra)), srcs))
+    tmp = lib + ".tmp"
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":

@@ -160,8 +160,9 @@ struct tmop_ctx {
 namespace {
 
 int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* out, const int32_t* list,
-                int64_t n_list, hipStream_t s, int* grid) {
+                int64_t n_list, hipStream_t s, int* grid, const double* scale = nullptr) {
   LaunchParams lp = c->base;
+  lp.scale = scale;
   lp.x = x; lp.v = v; lp.out = out;
   lp.elem_node = c->d_elem_node;
   lp.list = list;
@@ -180,13 +181,14 @@ int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* o
 }
 
 // out = sum over colours of the element contributions (gradient / Hv).
-int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out, hipStream_t s) {
+int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out, hipStream_t s,
+             const double* scale = nullptr) {
   HIP_TRY(fill(out, 0.0, c->n_dof, s));
   for (size_t k = 0; k + 1 < c->color_off.size(); ++k) {
     const int64_t n = c->color_off[k + 1] - c->color_off[k];
     if (n == 0) continue;
     int grid = 0;
-    const int r = elem_launch(c, op, x, v, out, c->d_colors + c->color_off[k], n, s, &grid);
+    const int r = elem_launch(c, op, x, v, out, c->d_colors + c->color_off[k], n, s, &grid, scale);
     if (r != TMOP_OK) return r;
   }
   return TMOP_OK;
@@ -349,6 +351,11 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
     c->base.w[q] = w[q];
   }
   inv3(target->W, d, c->base.Winv);
+  c->base.iso = true;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j)
+      if (target->W[i * d + j] != (i == j ? target->W[0] : 0.0)) c->base.iso = false;
+  c->base.s_inv = 1.0 / target->W[0];
   c->base.detW = detW;
   c->base.detWinv = 1.0 / detW;
 
@@ -393,6 +400,11 @@ int tmop_energy(tmop_ctx* c, const double* x, double* F, double* min_detA, void*
 int tmop_gradient(tmop_ctx* c, const double* x, double* g, void* stream) {
   if (!c || !x || !g || g == x) return TMOP_E_ARG;
   return assemble(c, OP_GRAD, x, nullptr, g, (hipStream_t)stream);
+}
+
+int tmop_gradient_scaled(tmop_ctx* c, const double* x, const double* scale, double* g, void* stream) {
+  if (!c || !x || !g || g == x) return TMOP_E_ARG;
+  return assemble(c, OP_GRAD, x, nullptr, g, (hipStream_t)stream, scale);
 }
 
 int tmop_hessian_apply(tmop_ctx* c, const double* x, const double* v, double* Hv, void* stream) {

@@ -14,17 +14,21 @@
 // Thread mapping (3D): each element gets Q*Q lanes, lane (a, b).  Each 1D
 // pass gives a lane a full "pencil" along the contracted direction, so every
 // value it loads is reused Q (or P) times from registers:
-//   pass 1 (z):  lane (i0, i1) -- reads its P nodes from HBM, writes U to LDS
+//   pass 1 (z):  lane (i0, i1) -- its P nodes (loaded up front), U to LDS
 //   pass 2 (y):  lane (i0, q2) -- reads U, writes V to LDS
 //   pass 3 (x):  lane (q1, q2) -- reads V into registers and walks q0:
 //                A -> T = A W^-1 -> metric -> Y = w det W (dmu) W^-t,
 //                accumulating the transposed x-contraction in registers
 //   pass 3', 2', 1' mirror 3, 2, 1 and end with the scatter to the nodes.
+// LDS: lane (i0, q2) of pass 2 owns one area that holds first its U pencil,
+// then its V pencil (it reads all of U before writing V), later the
+// transposed data the same way, so U and V never coexist.
 // 2D is the same with one pass fewer and Q lanes per element.
 //
 // Scatter: the host launches one kernel per element colour; elements of a
 // colour share no node, so the update out[node] += value is a plain
-// read-modify-write and the result is bitwise reproducible.
+// read-modify-write (the old value is loaded early to hide its latency) and
+// the result is bitwise reproducible.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -45,15 +49,18 @@ struct ElemArgs {
   const int32_t* __restrict__ elem_node; // [n_elem][P^dim]
   const int32_t* __restrict__ list;      // elements to process (nullptr: 0..n_list-1)
   double* __restrict__ part;             // OP_ENERGY: [2 * gridDim.x] (sums, then mins)
+  const double* __restrict__ scale;      // OP_GRAD: optional device scalar multiplying g (nullptr = 1)
   int64_t n_node;
   int32_t n_list;
   R B[Q][P];
   R G[Q][P];
   double w[Q];                           // 1D quadrature weights
   R Winv[3][3];                          // W^{-1} (constant target)
+  R s_inv;                               // isotropic target W = s I: 1/s
+  double Winvd[3][3];                    // W^{-1} in FP64 (energy)
+  double s_invd;
   double xi[P];                          // 1D GLL node coordinates
   double detW;
-  double Winvd[3][3];                    // W^{-1} in FP64 (energy)
 };
 
 // Elements per block and block size: the smallest element count that best
@@ -70,12 +77,21 @@ constexpr int pick_epb(int tpe, int lds_bytes_per_elem) {
   return best;
 }
 
+// LDS padding of the 3D lane areas and of the per-element block (values):
+// they set the bank pattern of the pass-2/3 accesses.
+#ifndef TMOP_AREA_PAD
+#define TMOP_AREA_PAD 0
+#endif
+#ifndef TMOP_ELEM_PAD
+#define TMOP_ELEM_PAD 2
+#endif
+
 template <int DIM, int P, int Q, typename R>
 struct Cfg {
   static constexpr int TPE = DIM == 3 ? Q * Q : Q;
-  static constexpr int NU = DIM == 3 ? 2 * 3 * Q * P * P : 2 * 2 * Q * P;
-  static constexpr int NV = DIM == 3 ? 3 * 3 * Q * Q * P : 0;
-  static constexpr int EPB = pick_epb(TPE, (NU + NV) * (int)sizeof(R));
+  static constexpr int AREA = DIM == 3 ? 9 * Q + TMOP_AREA_PAD : 0;   // 3D: values per (i0, q2) lane area
+  static constexpr int NE = DIM == 3 ? Q * P * AREA + TMOP_ELEM_PAD : 2 * 2 * Q * P;   // LDS values per element
+  static constexpr int EPB = pick_epb(TPE, NE * (int)sizeof(R));
   static constexpr int BLOCK = (EPB * TPE + 63) / 64 * 64;
 };
 
@@ -109,50 +125,48 @@ __device__ __forceinline__ void block_reduce_sum_min(double s, double m, double*
   }
 }
 
-template <int D, typename R>
-__device__ __forceinline__ double det_fp64(const R (&A)[D][D]) {
-  double a[D][D];
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = 0; j < D; ++j) a[i][j] = (double)A[i][j];
-  return det<D, double>(a);
-}
-
-// T = A W^{-1}
-template <int D, typename R>
-__device__ __forceinline__ void right_mul(const R (&A)[D][D], const R (&Wi)[3][3], R (&T)[D][D]) {
+// T = A W^{-1} (ISO: W = s I, T = A / s)
+template <int D, typename R, bool ISO>
+__device__ __forceinline__ void right_mul(const R (&A)[D][D], const R (&Wi)[3][3], R si, R (&T)[D][D]) {
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      R s = 0;
+      if constexpr (ISO) {
+        T[i][j] = A[i][j] * si;
+      } else {
+        R s = 0;
 #pragma unroll
-      for (int k = 0; k < D; ++k) s += A[i][k] * Wi[k][j];
-      T[i][j] = s;
+        for (int k = 0; k < D; ++k) s += A[i][k] * Wi[k][j];
+        T[i][j] = s;
+      }
     }
 }
 
-// Y = s * M W^{-t}
-template <int D, typename R>
-__device__ __forceinline__ void stress(const R (&M)[D][D], const R (&Wi)[3][3], R s, R (&Y)[D][D]) {
+// Y = s M W^{-t} (ISO: Y = (s / w) M)
+template <int D, typename R, bool ISO>
+__device__ __forceinline__ void stress(const R (&M)[D][D], const R (&Wi)[3][3], R si, R s, R (&Y)[D][D]) {
+  if constexpr (ISO) s *= si;
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      R t = 0;
+      if constexpr (ISO) {
+        Y[i][j] = s * M[i][j];
+      } else {
+        R t = 0;
 #pragma unroll
-      for (int k = 0; k < D; ++k) t += M[i][k] * Wi[j][k];
-      Y[i][j] = s * t;
+        for (int k = 0; k < D; ++k) t += M[i][k] * Wi[j][k];
+        Y[i][j] = s * t;
+      }
     }
 }
 
-// Per-point kernel of the three operations.  Given A (and dA), returns the
+// Per-point kernel of the three operations.  Given A (and dA), adds the
 // energy contribution (OP_ENERGY) or fills Y (OP_GRAD / OP_HESS).
-template <int D, int METRIC, typename R, int OP>
-__device__ __forceinline__ void point_op(const R (&A)[D][D], const R (&dA)[D][D], const R (&Wi)[3][3],
-                                         double wdet, const double (&Wid)[3][3], double& acc, double& mind,
-                                         R (&Y)[D][D]) {
+template <int D, int METRIC, typename R, int OP, bool ISO, int P, int Q>
+__device__ __forceinline__ void point_op(const ElemArgs<P, Q, R>& a, const R (&A)[D][D], const R (&dA)[D][D],
+                                         double wdet, double& acc, double& mind, R (&Y)[D][D]) {
   if constexpr (OP == OP_ENERGY) {
     // The energy value, det A and their sums are FP64 in both paths: the
     // FP32 path promotes its contracted A (mu's "... - 1" would otherwise
@@ -162,43 +176,31 @@ __device__ __forceinline__ void point_op(const R (&A)[D][D], const R (&dA)[D][D]
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int j = 0; j < D; ++j) Ad[i][j] = (double)A[i][j];
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) s += Ad[i][k] * Wid[k][j];
-        Td[i][j] = s;
-      }
     const double detA = det<D, double>(Ad);
-    acc += wdet * mu_value<METRIC, double>(Td, det<D, double>(Td));
+    double tau;
+    if constexpr (ISO) {
+      right_mul<D, double, true>(Ad, a.Winvd, a.s_invd, Td);
+      tau = detA * (D == 2 ? a.s_invd * a.s_invd : a.s_invd * a.s_invd * a.s_invd);
+    } else {
+      right_mul<D, double, false>(Ad, a.Winvd, a.s_invd, Td);
+      tau = det<D, double>(Td);
+    }
+    acc += wdet * mu_value<METRIC, double>(Td, tau);
     mind = fmin(mind, detA);
-    return;
-  }
-  R T[D][D];
-  right_mul<D, R>(A, Wi, T);
-  if constexpr (OP == OP_GRAD) {
-    R Pm[D][D];
-    mu_first<METRIC, R>(T, Pm);
-    stress<D, R>(Pm, Wi, (R)wdet, Y);
   } else {
-    R dT[D][D], dP[D][D];
-    right_mul<D, R>(dA, Wi, dT);
-    mu_second<METRIC, R>(T, dT, dP);
-    stress<D, R>(dP, Wi, (R)wdet, Y);
+    R T[D][D];
+    right_mul<D, R, ISO>(A, a.Winv, a.s_inv, T);
+    if constexpr (OP == OP_GRAD) {
+      R Pm[D][D];
+      mu_first<METRIC, R>(T, Pm);
+      stress<D, R, ISO>(Pm, a.Winv, a.s_inv, (R)wdet, Y);
+    } else {
+      R dT[D][D], dP[D][D];
+      right_mul<D, R, ISO>(dA, a.Winv, a.s_inv, dT);
+      mu_second<METRIC, R>(T, dT, dP);
+      stress<D, R, ISO>(dP, a.Winv, a.s_inv, (R)wdet, Y);
+    }
   }
-}
-
-// ------------------------------------------------------------------ 3D
-
-template <int P, int Q>
-__device__ __forceinline__ constexpr int uidx3(int t, int c, int q2, int i1, int i0) {
-  return ((t * 3 + c) * Q + q2) * (P * P) + i1 * P + i0;
-}
-template <int P, int Q>
-__device__ __forceinline__ constexpr int vidx3(int t, int c, int q2, int q1, int i0) {
-  return ((t * 3 + c) * Q + q2) * (Q * P) + q1 * P + i0;
 }
 
 // Both paths contract the field relative to the element: A only depends on
@@ -230,29 +232,43 @@ __device__ __forceinline__ void element_frame(const double* __restrict__ f, int6
   }
 }
 
-// Passes 1 and 2 of the forward contraction of field f into sV.
+// ------------------------------------------------------------------ 3D
+
+// Offsets in the LDS area of pass-2 lane (i0, q2).
+template <int P> __device__ __forceinline__ constexpr int uoff(int t, int c, int i1) { return (t * 3 + c) * P + i1; }
+template <int Q> __device__ __forceinline__ constexpr int voff(int t, int c, int q1) { return (t * 3 + c) * Q + q1; }
+
+// The pencil of pass-1 lane (i0, i1): its P nodes of field f relative to the
+// element frame, for every component.  Only called by lanes with i0, i1 < P.
 template <int P, int Q, typename R, bool AFFINE>
-__device__ __forceinline__ void fwd12_3d(const ElemArgs<P, Q, R>& a, const double* __restrict__ f,
-                                         const int (&node)[P], const int32_t* __restrict__ en, int ta, int tb,
-                                         R* __restrict__ sU, R* __restrict__ sV, R (&J0r)[3][3]) {
+__device__ __forceinline__ void load_pencil_3d(const ElemArgs<P, Q, R>& a, const double* __restrict__ f,
+                                               const int (&node)[P], const int32_t* __restrict__ en, int i0,
+                                               int i1, R (&X)[3][P], R (&J0r)[3][3]) {
   double org[3], J0[3][3];
   element_frame<3, P, AFFINE>(f, a.n_node, en, org, J0);
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int l = 0; l < 3; ++l) J0r[c][l] = (R)J0[c][l];
-  if (ta < P && tb < P) {
-    R X[3][P];
 #pragma unroll
-    for (int i2 = 0; i2 < P; ++i2)
+  for (int i2 = 0; i2 < P; ++i2)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if constexpr (AFFINE)
-          X[c][i2] = (R)(f[c * a.n_node + node[i2]] - org[c] - J0[c][0] * a.xi[ta] - J0[c][1] * a.xi[tb] -
-                         J0[c][2] * a.xi[i2]);
-        else
-          X[c][i2] = (R)(f[c * a.n_node + node[i2]] - org[c]);
-      }
+    for (int c = 0; c < 3; ++c) {
+      if constexpr (AFFINE)
+        X[c][i2] = (R)(f[c * a.n_node + node[i2]] - org[c] - J0[c][0] * a.xi[i0] - J0[c][1] * a.xi[i1] -
+                       J0[c][2] * a.xi[i2]);
+      else
+        X[c][i2] = (R)(f[c * a.n_node + node[i2]] - org[c]);
+    }
+}
+
+// Passes 1 and 2 of the forward contraction; lane (q1 = ta, q2 = tb) then
+// reads its V pencil into registers.
+template <int P, int Q, typename R>
+__device__ __forceinline__ void fwd_3d(const ElemArgs<P, Q, R>& a, const R (&X)[3][P], int ta, int tb,
+                                       R* __restrict__ s, R (&V)[3][3][P]) {
+  constexpr int AREA = 9 * Q;
+  if (ta < P && tb < P) {   // pass 1, lane (i0 = ta, i1 = tb): U of all q2
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -260,43 +276,55 @@ __device__ __forceinline__ void fwd12_3d(const ElemArgs<P, Q, R>& a, const doubl
         R ub = 0, ug = 0;
 #pragma unroll
         for (int i2 = 0; i2 < P; ++i2) { ub += a.B[q2][i2] * X[c][i2]; ug += a.G[q2][i2] * X[c][i2]; }
-        sU[uidx3<P, Q>(0, c, q2, tb, ta)] = ub;
-        sU[uidx3<P, Q>(1, c, q2, tb, ta)] = ug;
+        R* ar = s + (q2 * P + ta) * AREA;
+        ar[uoff<P>(0, c, tb)] = ub;
+        ar[uoff<P>(1, c, tb)] = ug;
       }
   }
   __syncthreads();
-  if (ta < P) {   // lane (i0 = ta, q2 = tb)
+  if (ta < P && tb < Q) {   // pass 2, lane (i0 = ta, q2 = tb): own area, U in, V out
+    R* ar = s + (tb * P + ta) * AREA;
+    R ub[3][P], ug[3][P];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      R ub[P], ug[P];
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int i1 = 0; i1 < P; ++i1) { ub[i1] = sU[uidx3<P, Q>(0, c, tb, i1, ta)]; ug[i1] = sU[uidx3<P, Q>(1, c, tb, i1, ta)]; }
+      for (int i1 = 0; i1 < P; ++i1) { ub[c][i1] = ar[uoff<P>(0, c, i1)]; ug[c][i1] = ar[uoff<P>(1, c, i1)]; }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int q1 = 0; q1 < Q; ++q1) {
         R bb = 0, gb = 0, bg = 0;
 #pragma unroll
         for (int i1 = 0; i1 < P; ++i1) {
-          bb += a.B[q1][i1] * ub[i1];
-          gb += a.G[q1][i1] * ub[i1];
-          bg += a.B[q1][i1] * ug[i1];
+          bb += a.B[q1][i1] * ub[c][i1];
+          gb += a.G[q1][i1] * ub[c][i1];
+          bg += a.B[q1][i1] * ug[c][i1];
         }
-        sV[vidx3<P, Q>(0, c, tb, q1, ta)] = bb;
-        sV[vidx3<P, Q>(1, c, tb, q1, ta)] = gb;
-        sV[vidx3<P, Q>(2, c, tb, q1, ta)] = bg;
+        ar[voff<Q>(0, c, q1)] = bb;
+        ar[voff<Q>(1, c, q1)] = gb;
+        ar[voff<Q>(2, c, q1)] = bg;
       }
-    }
   }
   __syncthreads();
+  if (tb < Q) {             // pass 3 input, lane (q1 = ta, q2 = tb)
+#pragma unroll
+    for (int i0 = 0; i0 < P; ++i0) {
+      const R* ar = s + (tb * P + i0) * AREA;
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) V[t][c][i0] = ar[voff<Q>(t, c, ta)];
+    }
+  }
 }
 
-template <int P, int Q, int METRIC, typename R, int OP>
+template <int P, int Q, int METRIC, typename R, int OP, bool ISO>
 __global__ void __launch_bounds__((Cfg<3, P, Q, R>::BLOCK))
 elem_kernel_3d(const ElemArgs<P, Q, R> a) {
   using C = Cfg<3, P, Q, R>;
-  constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P * P;
+  constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P * P, AREA = C::AREA;
   constexpr bool AFFINE = sizeof(R) == 4;   // FP32 contracts the deviation from the vertex-affine map
-  __shared__ R sU_all[EPB * C::NU];
-  __shared__ R sV_all[EPB * C::NV];
+  __shared__ R s_all[EPB * C::NE];
   __shared__ double red[2 * (C::BLOCK / 64)];
 
   const int tid = threadIdx.x;
@@ -310,38 +338,23 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
   const bool active = le_raw < EPB && k < a.n_list;
   const int kk = k < a.n_list ? k : a.n_list - 1;
   const int e = a.list ? a.list[kk] : kk;
-  R* sU = sU_all + le * C::NU;
-  R* sV = sV_all + le * C::NV;
+  R* s = s_all + le * C::NE;
+  const bool p1 = ta < P && tb < P;          // pass-1 lane (i0 = ta, i1 = tb)
 
+  // all global loads of the element's fields first
   const int32_t* en = a.elem_node + (int64_t)e * NPE;
   int node[P];
 #pragma unroll
-  for (int i2 = 0; i2 < P; ++i2)
-    node[i2] = (ta < P && tb < P) ? en[ta + P * tb + P * P * i2] : 0;
-  // forward for x, V into registers (lane (q1 = ta, q2 = tb))
-  R J0x[3][3], J0v[3][3];
-  fwd12_3d<P, Q, R, AFFINE>(a, a.x, node, en, ta, tb, sU, sV, J0x);
-  R V[3][3][P];
-  if (tb < Q) {
-#pragma unroll
-    for (int tt = 0; tt < 3; ++tt)
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int i0 = 0; i0 < P; ++i0) V[tt][c][i0] = sV[vidx3<P, Q>(tt, c, tb, ta, i0)];
-  }
-  R dV[3][3][P];
+  for (int i2 = 0; i2 < P; ++i2) node[i2] = p1 ? en[ta + P * tb + P * P * i2] : en[0];
+  R X[3][P], dX[3][P], J0x[3][3], J0v[3][3];
+  load_pencil_3d<P, Q, R, AFFINE>(a, a.x, node, en, p1 ? ta : 0, p1 ? tb : 0, X, J0x);
+  if constexpr (OP == OP_HESS) load_pencil_3d<P, Q, R, AFFINE>(a, a.v, node, en, p1 ? ta : 0, p1 ? tb : 0, dX, J0v);
+
+  R V[3][3][P], dV[3][3][P];
+  fwd_3d<P, Q, R>(a, X, ta, tb, s, V);
   if constexpr (OP == OP_HESS) {
     __syncthreads();
-    fwd12_3d<P, Q, R, AFFINE>(a, a.v, node, en, ta, tb, sU, sV, J0v);
-    if (tb < Q) {
-#pragma unroll
-      for (int tt = 0; tt < 3; ++tt)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int i0 = 0; i0 < P; ++i0) dV[tt][c][i0] = sV[vidx3<P, Q>(tt, c, tb, ta, i0)];
-    }
+    fwd_3d<P, Q, R>(a, dX, ta, tb, s, dV);
   }
 
   double acc = 0.0, mind = __builtin_huge_val();
@@ -354,7 +367,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
       for (int i0 = 0; i0 < P; ++i0) Racc[tt][c][i0] = 0;
 
   if (tb < Q) {
-    const double w12 = a.w[ta] * a.w[tb] * a.detW;
+    const double w12 = a.w[ta] * a.w[tb] * a.detW * (a.scale ? *a.scale : 1.0);
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[3][3], dA[3][3];
@@ -382,7 +395,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
         }
       }
       R Y[3][3];
-      point_op<3, METRIC, R, OP>(A, dA, a.Winv, w12 * a.w[q0], a.Winvd, acc, mind, Y);
+      point_op<3, METRIC, R, OP, ISO>(a, A, dA, w12 * a.w[q0], acc, mind, Y);
       if constexpr (OP != OP_ENERGY) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -399,57 +412,69 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
   if constexpr (OP == OP_ENERGY) {
     if (!active) { acc = 0.0; mind = __builtin_huge_val(); }
     block_reduce_sum_min<C::BLOCK>(acc, mind, red, a.part + blk, a.part + gridDim.x + blk);
-    return;
   } else {
-    // pass 3': each lane writes its own V slots, so no barrier is needed first
+    // the scatter's old values, loaded now so the passes below hide latency
+    double old[3][P];
+    if (active && p1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i2 = 0; i2 < P; ++i2) old[c][i2] = a.out[c * a.n_node + node[i2]];
+    }
+    // pass 3': lane (q1, q2) writes into exactly the V slots it read
     if (tb < Q) {
+#pragma unroll
+      for (int i0 = 0; i0 < P; ++i0) {
+        R* ar = s + (tb * P + i0) * AREA;
+#pragma unroll
+        for (int tt = 0; tt < 3; ++tt)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) ar[voff<Q>(tt, c, ta)] = Racc[tt][c][i0];
+      }
+    }
+    __syncthreads();
+    // pass 2': lane (i0 = ta, q2 = tb), own area
+    if (ta < P && tb < Q) {
+      R* ar = s + (tb * P + ta) * AREA;
+      R r[3][3][Q];
 #pragma unroll
       for (int tt = 0; tt < 3; ++tt)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-          for (int i0 = 0; i0 < P; ++i0) sV[vidx3<P, Q>(tt, c, tb, ta, i0)] = Racc[tt][c][i0];
-    }
-    __syncthreads();
-    // pass 2': lane (i0 = ta, q2 = tb)
-    if (ta < P && tb < Q) {
+          for (int q1 = 0; q1 < Q; ++q1) r[tt][c][q1] = ar[voff<Q>(tt, c, q1)];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        R r0[Q], r1[Q], r2[Q];
-#pragma unroll
-        for (int q1 = 0; q1 < Q; ++q1) {
-          r0[q1] = sV[vidx3<P, Q>(0, c, tb, q1, ta)];
-          r1[q1] = sV[vidx3<P, Q>(1, c, tb, q1, ta)];
-          r2[q1] = sV[vidx3<P, Q>(2, c, tb, q1, ta)];
-        }
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int i1 = 0; i1 < P; ++i1) {
           R sb = 0, sg = 0;
 #pragma unroll
           for (int q1 = 0; q1 < Q; ++q1) {
-            sb += a.B[q1][i1] * r0[q1] + a.G[q1][i1] * r1[q1];
-            sg += a.B[q1][i1] * r2[q1];
+            sb += a.B[q1][i1] * r[0][c][q1] + a.G[q1][i1] * r[1][c][q1];
+            sg += a.B[q1][i1] * r[2][c][q1];
           }
-          sU[uidx3<P, Q>(0, c, tb, i1, ta)] = sb;
-          sU[uidx3<P, Q>(1, c, tb, i1, ta)] = sg;
+          ar[uoff<P>(0, c, i1)] = sb;
+          ar[uoff<P>(1, c, i1)] = sg;
         }
-      }
     }
     __syncthreads();
     // pass 1': lane (i0 = ta, i1 = tb), then the scatter
-    if (active && ta < P && tb < P) {
+    if (active && p1) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         R sb[Q], sg[Q];
 #pragma unroll
-        for (int q2 = 0; q2 < Q; ++q2) { sb[q2] = sU[uidx3<P, Q>(0, c, q2, tb, ta)]; sg[q2] = sU[uidx3<P, Q>(1, c, q2, tb, ta)]; }
+        for (int q2 = 0; q2 < Q; ++q2) {
+          const R* ar = s + (q2 * P + ta) * AREA;
+          sb[q2] = ar[uoff<P>(0, c, tb)];
+          sg[q2] = ar[uoff<P>(1, c, tb)];
+        }
 #pragma unroll
         for (int i2 = 0; i2 < P; ++i2) {
-          R s = 0;
+          R v = 0;
 #pragma unroll
-          for (int q2 = 0; q2 < Q; ++q2) s += a.B[q2][i2] * sb[q2] + a.G[q2][i2] * sg[q2];
-          double* o = a.out + c * a.n_node + node[i2];
-          *o = *o + (double)s;
+          for (int q2 = 0; q2 < Q; ++q2) v += a.B[q2][i2] * sb[q2] + a.G[q2][i2] * sg[q2];
+          a.out[c * a.n_node + node[i2]] = old[c][i2] + (double)v;
         }
       }
     }
@@ -463,29 +488,33 @@ __device__ __forceinline__ constexpr int uidx2(int t, int c, int q1, int i0) {
   return ((t * 2 + c) * Q + q1) * P + i0;
 }
 
-// Pass 1 of the forward contraction of f into sU, then U into registers of
-// lane q1 = ta.
 template <int P, int Q, typename R, bool AFFINE>
-__device__ __forceinline__ void fwd1_2d(const ElemArgs<P, Q, R>& a, const double* __restrict__ f,
-                                        const int (&node)[P], const int32_t* __restrict__ en, int ta,
-                                        R* __restrict__ sU, R (&U)[2][2][P], R (&J0r)[2][2]) {
+__device__ __forceinline__ void load_pencil_2d(const ElemArgs<P, Q, R>& a, const double* __restrict__ f,
+                                               const int (&node)[P], const int32_t* __restrict__ en, int i0,
+                                               R (&X)[2][P], R (&J0r)[2][2]) {
   double org[3], J0[3][3];
   element_frame<2, P, AFFINE>(f, a.n_node, en, org, J0);
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int l = 0; l < 2; ++l) J0r[c][l] = (R)J0[c][l];
+#pragma unroll
+  for (int i1 = 0; i1 < P; ++i1)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if constexpr (AFFINE)
+        X[c][i1] = (R)(f[c * a.n_node + node[i1]] - org[c] - J0[c][0] * a.xi[i0] - J0[c][1] * a.xi[i1]);
+      else
+        X[c][i1] = (R)(f[c * a.n_node + node[i1]] - org[c]);
+    }
+}
+
+// Pass 1 (y) of the forward contraction into LDS, then lane q1 = ta reads
+// its U pencil.
+template <int P, int Q, typename R>
+__device__ __forceinline__ void fwd_2d(const ElemArgs<P, Q, R>& a, const R (&X)[2][P], int ta, R* __restrict__ s,
+                                       R (&U)[2][2][P]) {
   if (ta < P) {   // lane i0 = ta
-    R X[2][P];
-#pragma unroll
-    for (int i1 = 0; i1 < P; ++i1)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        if constexpr (AFFINE)
-          X[c][i1] = (R)(f[c * a.n_node + node[i1]] - org[c] - J0[c][0] * a.xi[ta] - J0[c][1] * a.xi[i1]);
-        else
-          X[c][i1] = (R)(f[c * a.n_node + node[i1]] - org[c]);
-      }
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -493,8 +522,8 @@ __device__ __forceinline__ void fwd1_2d(const ElemArgs<P, Q, R>& a, const double
         R ub = 0, ug = 0;
 #pragma unroll
         for (int i1 = 0; i1 < P; ++i1) { ub += a.B[q1][i1] * X[c][i1]; ug += a.G[q1][i1] * X[c][i1]; }
-        sU[uidx2<P, Q>(0, c, q1, ta)] = ub;
-        sU[uidx2<P, Q>(1, c, q1, ta)] = ug;
+        s[uidx2<P, Q>(0, c, q1, ta)] = ub;
+        s[uidx2<P, Q>(1, c, q1, ta)] = ug;
       }
   }
   __syncthreads();
@@ -504,17 +533,17 @@ __device__ __forceinline__ void fwd1_2d(const ElemArgs<P, Q, R>& a, const double
 #pragma unroll
       for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int i0 = 0; i0 < P; ++i0) U[tt][c][i0] = sU[uidx2<P, Q>(tt, c, ta, i0)];
+        for (int i0 = 0; i0 < P; ++i0) U[tt][c][i0] = s[uidx2<P, Q>(tt, c, ta, i0)];
   }
 }
 
-template <int P, int Q, int METRIC, typename R, int OP>
+template <int P, int Q, int METRIC, typename R, int OP, bool ISO>
 __global__ void __launch_bounds__((Cfg<2, P, Q, R>::BLOCK))
 elem_kernel_2d(const ElemArgs<P, Q, R> a) {
   using C = Cfg<2, P, Q, R>;
   constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P;
   constexpr bool AFFINE = sizeof(R) == 4;
-  __shared__ R sU_all[EPB * C::NU];
+  __shared__ R s_all[EPB * C::NE];
   __shared__ double red[2 * (C::BLOCK / 64)];
 
   const int tid = threadIdx.x;
@@ -526,17 +555,22 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
   const bool active = le_raw < EPB && k < a.n_list;
   const int kk = k < a.n_list ? k : a.n_list - 1;
   const int e = a.list ? a.list[kk] : kk;
-  R* sU = sU_all + le * C::NU;
+  R* s = s_all + le * C::NE;
+  const bool p1 = ta < P;
 
   const int32_t* en = a.elem_node + (int64_t)e * NPE;
   int node[P];
 #pragma unroll
-  for (int i1 = 0; i1 < P; ++i1) node[i1] = ta < P ? en[ta + P * i1] : 0;
-  R U[2][2][P], dU[2][2][P], J0x[2][2], J0v[2][2];
-  fwd1_2d<P, Q, R, AFFINE>(a, a.x, node, en, ta, sU, U, J0x);
+  for (int i1 = 0; i1 < P; ++i1) node[i1] = p1 ? en[ta + P * i1] : en[0];
+  R X[2][P], dX[2][P], J0x[2][2], J0v[2][2];
+  load_pencil_2d<P, Q, R, AFFINE>(a, a.x, node, en, p1 ? ta : 0, X, J0x);
+  if constexpr (OP == OP_HESS) load_pencil_2d<P, Q, R, AFFINE>(a, a.v, node, en, p1 ? ta : 0, dX, J0v);
+
+  R U[2][2][P], dU[2][2][P];
+  fwd_2d<P, Q, R>(a, X, ta, s, U);
   if constexpr (OP == OP_HESS) {
     __syncthreads();
-    fwd1_2d<P, Q, R, AFFINE>(a, a.v, node, en, ta, sU, dU, J0v);
+    fwd_2d<P, Q, R>(a, dX, ta, s, dU);
   }
 
   double acc = 0.0, mind = __builtin_huge_val();
@@ -549,7 +583,7 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
       for (int i0 = 0; i0 < P; ++i0) Racc[tt][c][i0] = 0;
 
   if (ta < Q) {   // lane q1 = ta
-    const double w1 = a.w[ta] * a.detW;
+    const double w1 = a.w[ta] * a.detW * (a.scale ? *a.scale : 1.0);
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[2][2], dA[2][2];
@@ -569,7 +603,7 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
         }
       }
       R Y[2][2];
-      point_op<2, METRIC, R, OP>(A, dA, a.Winv, w1 * a.w[q0], a.Winvd, acc, mind, Y);
+      point_op<2, METRIC, R, OP, ISO>(a, A, dA, w1 * a.w[q0], acc, mind, Y);
       if constexpr (OP != OP_ENERGY) {
 #pragma unroll
         for (int c = 0; c < 2; ++c)
@@ -585,8 +619,14 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
   if constexpr (OP == OP_ENERGY) {
     if (!active) { acc = 0.0; mind = __builtin_huge_val(); }
     block_reduce_sum_min<C::BLOCK>(acc, mind, red, a.part + blk, a.part + gridDim.x + blk);
-    return;
   } else {
+    double old[2][P];
+    if (active && p1) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int i1 = 0; i1 < P; ++i1) old[c][i1] = a.out[c * a.n_node + node[i1]];
+    }
     // pass 2': lane q1 writes its own U slots, no barrier needed first
     if (ta < Q) {
 #pragma unroll
@@ -594,23 +634,22 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
-          for (int i0 = 0; i0 < P; ++i0) sU[uidx2<P, Q>(tt, c, ta, i0)] = Racc[tt][c][i0];
+          for (int i0 = 0; i0 < P; ++i0) s[uidx2<P, Q>(tt, c, ta, i0)] = Racc[tt][c][i0];
     }
     __syncthreads();
     // pass 1': lane i0 = ta, then the scatter
-    if (active && ta < P) {
+    if (active && p1) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         R rb[Q], rg[Q];
 #pragma unroll
-        for (int q1 = 0; q1 < Q; ++q1) { rb[q1] = sU[uidx2<P, Q>(0, c, q1, ta)]; rg[q1] = sU[uidx2<P, Q>(1, c, q1, ta)]; }
+        for (int q1 = 0; q1 < Q; ++q1) { rb[q1] = s[uidx2<P, Q>(0, c, q1, ta)]; rg[q1] = s[uidx2<P, Q>(1, c, q1, ta)]; }
 #pragma unroll
         for (int i1 = 0; i1 < P; ++i1) {
-          R s = 0;
+          R v = 0;
 #pragma unroll
-          for (int q1 = 0; q1 < Q; ++q1) s += a.B[q1][i1] * rb[q1] + a.G[q1][i1] * rg[q1];
-          double* o = a.out + c * a.n_node + node[i1];
-          *o = *o + (double)s;
+          for (int q1 = 0; q1 < Q; ++q1) v += a.B[q1][i1] * rb[q1] + a.G[q1][i1] * rg[q1];
+          a.out[c * a.n_node + node[i1]] = old[c][i1] + (double)v;
         }
       }
     }

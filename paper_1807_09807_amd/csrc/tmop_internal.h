@@ -22,11 +22,14 @@ struct LaunchParams {
   int32_t n_list;
   int64_t n_node;
   double* part;            // energy partials, >= 2 * grid doubles
+  const double* scale;     // gradient: optional device scalar factor
   double B[MAXQ][MAXP];
   double G[MAXQ][MAXP];
   double w[MAXQ];
   double Winv[3][3];
   double xi[MAXP];         // GLL node coordinates on [0,1]
+  bool iso;                // W = s I: kernels scale by s_inv instead of multiplying by W^{-1}
+  double s_inv;
   double detW, detWinv;
 };
 

@@ -8,12 +8,12 @@
 
 namespace tmop {
 
-template <int DIM, int P, int Q, int METRIC, typename R, int OP>
+template <int DIM, int P, int Q, int METRIC, typename R, int OP, bool ISO>
 static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   using C = Cfg<DIM, P, Q, R>;
   ElemArgs<P, Q, R> a;
   a.x = lp.x; a.v = lp.v; a.out = lp.out;
-  a.elem_node = lp.elem_node; a.list = lp.list; a.part = lp.part;
+  a.elem_node = lp.elem_node; a.list = lp.list; a.part = lp.part; a.scale = lp.scale;
   a.n_node = lp.n_node; a.n_list = lp.n_list;
   for (int q = 0; q < Q; ++q) {
     a.w[q] = lp.w[q];
@@ -22,30 +22,35 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) a.Winv[i][j] = (R)lp.Winv[i][j];
   for (int i = 0; i < P; ++i) a.xi[i] = lp.xi[i];
+  a.s_inv = (R)lp.s_inv;
+  a.s_invd = lp.s_inv;
   a.detW = lp.detW;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) a.Winvd[i][j] = lp.Winv[i][j];
   const int g = (lp.n_list + C::EPB - 1) / C::EPB;
   *grid = g;
   if (g == 0) return 0;
-  if constexpr (DIM == 3) hipLaunchKernelGGL((elem_kernel_3d<P, Q, METRIC, R, OP>), dim3(g), dim3(C::BLOCK), 0, s, a);
-  else hipLaunchKernelGGL((elem_kernel_2d<P, Q, METRIC, R, OP>), dim3(g), dim3(C::BLOCK), 0, s, a);
+  if constexpr (DIM == 3) hipLaunchKernelGGL((elem_kernel_3d<P, Q, METRIC, R, OP, ISO>), dim3(g), dim3(C::BLOCK), 0, s, a);
+  else hipLaunchKernelGGL((elem_kernel_2d<P, Q, METRIC, R, OP, ISO>), dim3(g), dim3(C::BLOCK), 0, s, a);
   return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <int DIM, int P, int Q, int M, typename R, bool ISO>
+static int launch_op(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
+  if (op == OP_ENERGY) return launch_one<DIM, P, Q, M, R, OP_ENERGY, ISO>(lp, s, grid);
+  if (op == OP_GRAD) return launch_one<DIM, P, Q, M, R, OP_GRAD, ISO>(lp, s, grid);
+  if (op == OP_HESS) return launch_one<DIM, P, Q, M, R, OP_HESS, ISO>(lp, s, grid);
+  return -1;
 }
 
 template <int DIM, int P, int Q, typename R>
 static int launch_pq(int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid) {
   constexpr int M0 = DIM == 2 ? 2 : 302;
   constexpr int M1 = DIM == 2 ? 7 : 303;
-  if (metric == M0) {
-    if (op == OP_ENERGY) return launch_one<DIM, P, Q, M0, R, OP_ENERGY>(lp, s, grid);
-    if (op == OP_GRAD) return launch_one<DIM, P, Q, M0, R, OP_GRAD>(lp, s, grid);
-    if (op == OP_HESS) return launch_one<DIM, P, Q, M0, R, OP_HESS>(lp, s, grid);
-  } else if (metric == M1) {
-    if (op == OP_ENERGY) return launch_one<DIM, P, Q, M1, R, OP_ENERGY>(lp, s, grid);
-    if (op == OP_GRAD) return launch_one<DIM, P, Q, M1, R, OP_GRAD>(lp, s, grid);
-    if (op == OP_HESS) return launch_one<DIM, P, Q, M1, R, OP_HESS>(lp, s, grid);
-  }
+  if (metric == M0)
+    return lp.iso ? launch_op<DIM, P, Q, M0, R, true>(op, lp, s, grid) : launch_op<DIM, P, Q, M0, R, false>(op, lp, s, grid);
+  if (metric == M1)
+    return lp.iso ? launch_op<DIM, P, Q, M1, R, true>(op, lp, s, grid) : launch_op<DIM, P, Q, M1, R, false>(op, lp, s, grid);
   return -1;
 }
 

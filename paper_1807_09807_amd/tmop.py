@@ -26,8 +26,8 @@ TMOP_GAUSS_LEGENDRE, TMOP_GAUSS_LOBATTO = 0, 1
 TMOP_FP64, TMOP_MIXED_FP32 = 0, 1
 TMOP_TGT_CONST = 0
 
-EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_hessian_apply", "tmop_newton_solve",
-           "tmop_destroy", "tmop_strerror", "tmop_newton_default_opts")
+EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_gradient_scaled", "tmop_hessian_apply",
+           "tmop_newton_solve", "tmop_destroy", "tmop_strerror", "tmop_newton_default_opts")
 
 
 class TMOPError(RuntimeError):
@@ -84,6 +84,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tmop_energy.restype = ctypes.c_int
     lib.tmop_gradient.argtypes = [P, P, P, P]
     lib.tmop_gradient.restype = ctypes.c_int
+    lib.tmop_gradient_scaled.argtypes = [P, P, P, P, P]
+    lib.tmop_gradient_scaled.restype = ctypes.c_int
     lib.tmop_hessian_apply.argtypes = [P, P, P, P, P]
     lib.tmop_hessian_apply.restype = ctypes.c_int
     lib.tmop_newton_solve.argtypes = [P, P, ctypes.POINTER(tmop_newton_opts),
@@ -174,6 +176,23 @@ class Context:
         st = self._lib.tmop_gradient(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream(x))
         if st < 0:
             raise TMOPError(st, "tmop_gradient")
+        return out
+
+    def gradient_scaled(self, x, scale, out=None):
+        """out = scale * dF/dx with `scale` a one-element float64 device
+        tensor (the reverse-mode upstream gradient)."""
+        import torch
+        _check_field(x, self.dim, self.n_node, "x")
+        if not (isinstance(scale, torch.Tensor) and scale.dtype == torch.float64 and scale.numel() == 1
+                and scale.device == x.device):
+            raise TypeError("scale must be a one-element float64 tensor on x's device")
+        scale = scale.contiguous()
+        out = torch.empty_like(x) if out is None else out
+        _check_field(out, self.dim, self.n_node, "out")
+        st = self._lib.tmop_gradient_scaled(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(scale.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), _stream(x))
+        if st < 0:
+            raise TMOPError(st, "tmop_gradient_scaled")
         return out
 
     def hessian_apply(self, x, v, out=None):

@@ -1,0 +1,94 @@
+"""F_V as a torch.autograd.Function (forward: energy kernel; backward: the
+hand-written gradient kernel): checked with gradcheck, against central
+finite differences and against the oracle gradient."""
+import numpy as np
+import pytest
+
+from oracle import tmop_oracle as O
+from paper_1807_09807_amd import meshgen
+from tests._helpers import EPS32, say, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _ctx(mesh, w, W, precision):
+    from paper_1807_09807_amd import tmop as T
+    return T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=mesh.fixed,
+                     precision=precision)
+
+
+def test_gradcheck_small_q3_hex():
+    """torch.autograd.gradcheck (FP64) on a 2^3 Q3 mu_302 mesh."""
+    from paper_1807_09807_amd.autograd import TMOPEnergy
+    w = dict(meshgen.WORKLOADS["q3_cube_48"])
+    mesh = meshgen.box_mesh(3, 2, 3)
+    W = mesh.h * np.eye(3)
+    prob = O.Problem(3, 3, w["Q"], mesh.elem_node, w["metric"], W)
+    x0 = meshgen.perturb(mesh, 0.05, 3, bad_elements=prob.bad_elements)
+    ctx = _ctx(mesh, w, W, 0)
+    x = to_dev(x0).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda y: TMOPEnergy.apply(y, ctx), (x,), eps=1e-6, atol=1e-7, rtol=1e-5)
+
+
+def test_backward_scales_by_upstream_gradient():
+    from paper_1807_09807_amd.autograd import TMOPEnergy
+    w = meshgen.WORKLOADS["q2_cube_64"]
+    mesh = meshgen.box_mesh(3, 3, 2)
+    W = mesh.h * np.eye(3)
+    prob = O.Problem(3, 2, 4, mesh.elem_node, 303, W)
+    x0 = meshgen.perturb(mesh, 0.1, 4, bad_elements=prob.bad_elements)
+    ctx = _ctx(mesh, w, W, 0)
+    x = to_dev(x0).requires_grad_(True)
+    (3.5 * TMOPEnergy.apply(x, ctx) ** 2).backward()
+    F = prob.energy(x0)[0]
+    ref = 7.0 * F * prob.gradient(x0)
+    got = x.grad.cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_q3_cube_48_finite_differences_and_oracle(precision):
+    """The 48^3 Q3 mu_302 workload: backward at 64 seeded free nodes
+    against central finite differences of the forward (step 1e-6) and
+    against the oracle gradient at those nodes."""
+    from paper_1807_09807_amd.autograd import TMOPEnergy
+    name = "q3_cube_48"
+    w = meshgen.WORKLOADS[name]
+    say(f"[autograd] {name} prec={precision}")
+    mesh = meshgen.box_mesh(3, w["n"], w["p"])
+    W = mesh.h * np.eye(3)
+    prob = O.Problem(3, w["p"], w["Q"], mesh.elem_node, w["metric"], W)
+    mesh = meshgen.make_workload(name, bad_elements=lambda x, e: prob.bad_elements(x, e, w["tau_min"]))
+    free = np.flatnonzero(~mesh.fixed.astype(bool).any(axis=0))
+    rng = np.random.default_rng(w["seed"] + 1)
+    nodes = rng.choice(free, 64, replace=False)
+    comps = rng.integers(0, 3, 64)
+    ctx = _ctx(mesh, w, W, precision)
+    x = to_dev(mesh.x).requires_grad_(True)
+    TMOPEnergy.apply(x, ctx).backward()
+    g = x.grad.detach()
+    g_s = np.array([g[c, I].item() for c, I in zip(comps, nodes)])
+    # Central finite differences of the FP64 forward, the exact F.  The
+    # mixed path's own forward jitters by ~eps32 |dF/dA| |A| because A is
+    # rounded to FP32, which a 1e-6 step turns into O(1e-4) noise, so both
+    # backward passes are compared with differences of the FP64 F.
+    ctx64 = ctx if precision == 0 else _ctx(mesh, w, W, 0)
+    h = 1e-6
+    xd = x.detach().clone()
+    fd = np.empty(64)
+    for k, (c, I) in enumerate(zip(comps, nodes)):
+        xd[c, I] += h
+        fp = ctx64.energy(xd)[0]
+        xd[c, I] -= 2 * h
+        fm = ctx64.energy(xd)[0]
+        xd[c, I] += h
+        fd[k] = (fp - fm) / (2 * h)
+    g_or = prob.gradient_at(mesh.x, nodes)[comps, np.arange(64)]
+    scale = np.max(np.abs(g_or))
+    e_fd = np.max(np.abs(g_s - fd)) / scale
+    e_or = np.max(np.abs(g_s - g_or)) / scale
+    say(f"  backward vs FD {e_fd:.2e}, vs oracle {e_or:.2e}")
+    # FD: truncation O(h^2) and rounding eps*F/h relative to |g|
+    assert e_fd <= 1e-5
+    assert e_or <= (1e-12 if precision == 0 else max(1e-5, 4 * EPS32 * prob.max_condition(mesh.x)))
