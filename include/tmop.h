@@ -188,6 +188,50 @@ int tmop_hessian_apply(tmop_ctx *ctx, const double *x, const double *v,
 int tmop_newton_solve(tmop_ctx *ctx, double *x, const tmop_newton_opts *opts,
                       tmop_newton_report *report, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned initial guess for the Newton method of Section 3.4 (a layer on
+ * top of the paper's method): a per-element MLP on 2D Q2 meshes that maps
+ * an element's 9 nodes, relative to its centroid and divided by the target
+ * size h (W = h I), to a displacement of those nodes in units of h.
+ *   18 -> 64 -> 64 -> 64 -> 18, GELU on the hidden layers.
+ * Feature / output index c * 9 + i (component c, local node i).  The
+ * parameters are one flat FP32 array of TMOP_MLP_NPARAMS values:
+ *   W1[18][64] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[64][18] b4[18]
+ * The layers compute with the weights rounded to BF16 (nearest even) and
+ * FP32 biases, activations and accumulation; training keeps FP32 master
+ * weights and Adam moments (beta1 0.9, beta2 0.999, eps 1e-8).  Features X,
+ * outputs Y and labels L are DEVICE float arrays [n][18]. */
+#define TMOP_MLP_NPARAMS 10706
+typedef struct tmop_mlp tmop_mlp;
+
+/* New network on the current device from HOST params (copied); Adam state
+ * zeroed. */
+int tmop_mlp_create(const float *params, tmop_mlp **out);
+void tmop_mlp_destroy(tmop_mlp *mlp);
+/* Current FP32 master parameters to HOST params.  Syncs the device. */
+int tmop_mlp_get_params(tmop_mlp *mlp, float *params);
+/* Y = MLP(X) for n samples.  Async. */
+int tmop_mlp_forward(tmop_mlp *mlp, const float *X, float *Y, int64_t n, void *stream);
+/* dparams (DEVICE [TMOP_MLP_NPARAMS]) = d(sum dY * Y)/dparams, taken through
+ * the BF16-valued weights; dX (DEVICE [n][18], or NULL) likewise.  Async. */
+int tmop_mlp_backward(tmop_mlp *mlp, const float *X, const float *dY, int64_t n, float *dparams,
+                      float *dX, void *stream);
+/* One Adam step on the mean squared error between MLP(X) and L over n
+ * samples; *loss (HOST, may be NULL) receives the loss before the step.
+ * Syncs when loss != NULL. */
+int tmop_mlp_train_step(tmop_mlp *mlp, const float *X, const float *L, int64_t n, float lr,
+                        double *loss, void *stream);
+/* Element features of x (ctx: dim 2, order 2, isotropic target) into X
+ * [n_elem][18].  Async. */
+int tmop_mlp_features(tmop_ctx *ctx, const double *x, float *X, void *stream);
+/* Training labels: ((x* - x) on the element minus its element mean) / h
+ * into L [n_elem][18].  Async. */
+int tmop_mlp_labels(tmop_ctx *ctx, const double *x, const double *xstar, float *L, void *stream);
+/* Initial guess: x_out = x + h * (average over the elements containing each
+ * node of MLP(features(x))), fixed DOFs of the mesh unchanged.  x, x_out:
+ * DEVICE [2][n_node], not aliased.  Deterministic.  Async. */
+int tmop_mlp_propose(tmop_ctx *ctx, tmop_mlp *mlp, const double *x, double *x_out, void *stream);
+
 /* Releases the context and all its device memory.  NULL is a no-op. */
 void tmop_destroy(tmop_ctx *ctx);
 

@@ -135,22 +135,6 @@ void inv3(const double* W, int d, double out[3][3]) {
 
 // ---------------------------------------------------------------- context
 
-struct tmop_ctx {
-  int dim = 0, p = 0, Q = 0, metric = 0, precision = 0;
-  int64_t n_elem = 0, n_node = 0, n_dof = 0;
-  int device = 0;
-  LaunchParams base{};                 // tables and target, pointers filled per call
-  int32_t* d_elem_node = nullptr;
-  int32_t* d_colors = nullptr;         // element ids grouped by colour
-  std::vector<int64_t> color_off;      // colour c = d_colors[color_off[c] .. color_off[c+1])
-  double* d_mask = nullptr;            // [n_dof], 1 = free DOF
-  bool has_fixed = false;
-  double* d_part = nullptr;            // [2 * n_elem] energy partials
-  double* d_scratch = nullptr;         // [RED_BLOCKS] dot partials
-  double* d_res = nullptr;             // [4] reduction results
-  double* h_res = nullptr;             // [4] pinned mirror
-  double* d_work = nullptr;            // Newton work vectors, allocated on first use
-};
 
 #define HIP_TRY(call)                         \
   do {                                        \
