@@ -50,6 +50,36 @@ def contraction_macs(dim, P, Q):
 POINT_FLOPS = {2: (34, 67, 123), 7: (40, 69, 125), 303: (110, 205, 403), 302: (155, 379, 961)}
 POINT_FLOPS_ISO = {2: (21, 40, 84), 7: (27, 42, 86), 303: (53, 107, 260), 302: (98, 281, 818)}
 
+# HBM traffic of one Hessian-action colour launch (FP64), from rocprofv3
+# --pmc FETCH_SIZE and WRITE_SIZE passes (KiB per dispatch), valid for the
+# element-kernel sources whose SHA-256 is recorded with them.  The counters
+# are scaled by what they read for a 256 MiB device copy in the same
+# profile: FETCH_SIZE 131,089 KiB (factor 2.0), WRITE_SIZE 262,144 KiB (1.0).
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+KERNEL_SOURCES = ("tmop_elem.h", "tmop_metrics.h", "tmop_launch.h")
+MEASURED_TRAFFIC = {
+    "q2_cube_64": dict(src_sha256="1b65fb7c0fbc02426b092075eb86c72b39f1ee2acc58fad6b8e18e664f7cb803",
+                       fetch_kib=46841.5, write_kib=27966.7),
+}
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1807_09807_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """Calibrated HBM bytes per Hessian-action colour launch, or None when
+    no counters were taken for this workload at the current kernel sources."""
+    m = MEASURED_TRAFFIC.get(workload)
+    if m is None or m["src_sha256"] != kernel_digest():
+        return None
+    return 1024.0 * (FETCH_SCALE * m["fetch_kib"] + WRITE_SCALE * m["write_kib"])
+
 
 def algorithmic(w, iso=True):
     """(flops, bytes) per element for energy, gradient, Hessian action."""
@@ -74,7 +104,34 @@ def parse():
     ap.add_argument("--cpu-elems", type=int, default=4096)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer, so a profile holds a kernel of known HBM traffic")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-initial-guess pipeline")
+    ap.add_argument("--train-meshes", type=int, default=2000)
+    ap.add_argument("--eval-seeds", type=int, default=4)
     return ap.parse_args()
+
+
+def learned_guess(args, log):
+    """The learned initial guess on the 512^2 Q2 mu_2 workload: training data
+    from the library's Newton solutions of seeded 64^2 meshes, Adam
+    training, then plain vs learned Newton to F_tol on unseen meshes."""
+    from paper_1807_09807_amd import mlp as ML
+    log(f"# learned guess: {args.train_meshes} training meshes of 64^2")
+    data = ML.generate_training_data(n_mesh=args.train_meshes, n=64, seed0=1000)
+    log(f"#   data {data.info['seconds']:.1f} s ({data.X.shape[0]} element samples, Newton status per union solve "
+        f"{sorted(set(data.info['newton_status']))}, worst |g|/|g0| {data.info['max_rel_gnorm']:.1e})")
+    net, tinfo = ML.train(data, epochs=6, batch_meshes=2, lr=2e-3, seed=0)
+    log(f"#   training {tinfo['seconds']:.1f} s, {tinfo['steps']} Adam steps of {tinfo['batch']} samples, "
+        f"last-batch loss per epoch {[round(l, 6) for l in tinfo['loss_history']]}")
+    rows = ML.evaluate(net, n=512, seeds=tuple(10000 + k for k in range(args.eval_seeds)), log=log)
+    sp = [r["plain"]["wall_s"] / r["learned"]["wall_s"] for r in rows]
+    return dict(train_meshes=args.train_meshes, samples=int(data.X.shape[0]), data_s=data.info["seconds"],
+                train_s=tinfo["seconds"], train_samples_per_s=tinfo["steps"] * tinfo["batch"] / tinfo["seconds"],
+                loss_history=tinfo["loss_history"], eval=rows,
+                speedup_wall_median=float(np.median(sp)),
+                reference_converged=[r["reference"]["converged"] for r in rows],
+                proposal_F_over_F0=[r["F_proposal"] / r["F0"] for r in rows],
+                newton_iters_plain=[r["plain"]["iters"] for r in rows],
+                newton_iters_learned=[r["learned"]["iters"] for r in rows])
 
 
 def copy_calibration(torch, dev):
@@ -170,7 +227,17 @@ def main():
                 e1.synchronize()
                 ts.append(e0.elapsed_time(e1) * 1e-3)
             ops[name] = float(np.median(ts))
-        results[pname] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), ops=ops, F=F, ctx=ctx)
+        # per-launch device time of the element kernels over K steps
+        ctx.timing_enable(True)
+        for _ in range(args.steps):
+            step()
+        launch = {}
+        for op, name in enumerate(("energy", "gradient", "hessian")):
+            tot_ms, n = ctx.timing_read(op)
+            launch[name] = dict(launches=n, us_per_launch=tot_ms * 1e3 / n, us_per_op=tot_ms * 1e3 / args.steps)
+        ctx.timing_enable(False)
+        results[pname] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), ops=ops, F=F, ctx=ctx,
+                              launch=launch)
         print(f"# {pname}: {ms:.3f} ms/step, E {ops['energy']*1e6:.1f} us, G {ops['gradient']*1e6:.1f} us, "
               f"Hv {ops['hessian']*1e6:.1f} us", file=sys.stderr, flush=True)
 
@@ -203,13 +270,20 @@ def main():
             print(f"# newton {key}: status {st}, {rep['iters']} it, {rep['cg_iters']} CG, "
                   f"{rep['wall_s']:.2f} s, F {rep['F0']:.4e} -> {rep['F']:.4e}", file=sys.stderr, flush=True)
 
+    learned = None
+    if not args.no_learned:
+        learned = learned_guess(args, lambda m: print(m, file=sys.stderr, flush=True))
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, mesh, x_np, v_np, min(args.cpu_elems, mesh.n_elem))
 
     r64 = results["f64"]
-    t_h = r64["ops"]["hessian"]
-    fl = flops[2] * mesh.n_elem
+    hl = r64["launch"]["hessian"]
+    per_op = hl["launches"] / args.steps                      # colour launches per Hessian action
+    t_l = hl["us_per_launch"] * 1e-6
+    fl = flops[2] * mesh.n_elem / per_op                     # algorithmic flops per launch
+    traffic = measured_traffic(args.workload)
     line = {
         "metric": "DOF-iterations/s of energy+grad+Hv (FP64 vs FP32), Newton wall-s to F tol",
         "value": r64["value"],
@@ -226,15 +300,21 @@ def main():
         "config": {"workload": args.workload, "dim": w["dim"], "order": w["p"], "elements": mesh.n_elem,
                    "dofs": mesh.n_dof, "quadrature": f"{w['Q']}^{w['dim']} Gauss-Legendre",
                    "metric": f"mu_{w['metric']}", "target": "W = h I"},
-        "roofline": {"kernel": "hessian_apply (element kernel, 2^dim colour launches)",
-                     "bound": "alu", "achieved": fl / t_h / 1e12, "peak": FP64_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": fl / t_h / FP64_PEAK, "traffic": None,
-                     "flops_per_element": flops[2], "hbm_bytes_per_element": nbytes[2],
-                     "hbm_GBps": nbytes[2] * mesh.n_elem / t_h / 1e9},
+        "roofline": {"kernel": "Hessian-action element kernel (FP64), one colour launch",
+                     "bound": "alu", "achieved": fl / t_l / 1e12, "peak": FP64_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": fl / t_l / FP64_PEAK, "traffic": traffic,
+                     "launch_us": hl["us_per_launch"], "launches_per_op": per_op,
+                     "elements_per_launch": mesh.n_elem / per_op,
+                     "flops_per_element": flops[2], "algorithmic_bytes_per_element": nbytes[2],
+                     "algorithmic_GBps": nbytes[2] * mesh.n_elem / per_op / t_l / 1e9,
+                     "traffic_GBps": traffic / t_l / 1e9 if traffic else None},
+        "launch_us": {p: {k: round(v["us_per_launch"], 2) for k, v in results[p]["launch"].items()}
+                      for p in ("f64", "mixed")},
         "ops_us": {k: round(t * 1e6, 2) for k, t in r64["ops"].items()},
         "mixed_fp32": {"value": results["mixed"]["value"], "ms_per_step": results["mixed"]["ms_per_step"],
                        "ops_us": {k: round(t * 1e6, 2) for k, t in results["mixed"]["ops"].items()}},
         "newton": newton,
+        "learned_guess": learned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

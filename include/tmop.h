@@ -232,6 +232,20 @@ int tmop_mlp_labels(tmop_ctx *ctx, const double *x, const double *xstar, float *
  * DEVICE [2][n_node], not aliased.  Deterministic.  Async. */
 int tmop_mlp_propose(tmop_ctx *ctx, tmop_mlp *mlp, const double *x, double *x_out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Per-launch timing of the element kernels (a measurement aid, not part of
+ * the method): while enabled, every element-kernel launch of ctx (one per
+ * energy evaluation; one per colour for gradient and Hessian action, the
+ * zero fill of the output excluded) is bracketed by two HIP events on the
+ * caller's stream; tmop_timing_read waits for them and returns the summed
+ * device time in milliseconds and the number of launches for one
+ * operation: 0 energy, 1 gradient, 2 Hessian action.
+ * tmop_timing_enable(ctx, on) clears the totals and turns timing on (1) or
+ * off (0).  Both return TMOP_OK, TMOP_E_ARG (NULL ctx / out pointers, op
+ * outside 0..2) or TMOP_E_HIP. */
+int tmop_timing_enable(tmop_ctx *ctx, int enable);
+int tmop_timing_read(tmop_ctx *ctx, int op, double *ms_total, int64_t *launches);
+
 /* Releases the context and all its device memory.  NULL is a no-op. */
 void tmop_destroy(tmop_ctx *ctx);
 

@@ -153,6 +153,18 @@ int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* o
   lp.n_list = (int32_t)n_list;
   lp.n_node = c->n_node;
   lp.part = c->d_part;
+  tmop_ctx::TimedLaunch tl{op, nullptr, nullptr};
+  if (c->timing) {
+    for (hipEvent_t* e : {&tl.a, &tl.b}) {
+      if (!c->ev_free.empty()) {
+        *e = c->ev_free.back();
+        c->ev_free.pop_back();
+      } else if (hipEventCreate(e) != hipSuccess) {
+        return TMOP_E_HIP;
+      }
+    }
+    if (hipEventRecord(tl.a, s) != hipSuccess) return TMOP_E_HIP;
+  }
   int r;
   if (c->dim == 2)
     r = c->precision == TMOP_FP64 ? launch_elem_2d_f64(c->p, c->Q, c->metric, op, lp, s, grid)
@@ -160,8 +172,34 @@ int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* o
   else
     r = c->precision == TMOP_FP64 ? launch_elem_3d_f64(c->p, c->Q, c->metric, op, lp, s, grid)
                                   : launch_elem_3d_f32(c->p, c->Q, c->metric, op, lp, s, grid);
+  if (c->timing) {
+    if (r != 0 || hipEventRecord(tl.b, s) != hipSuccess) {
+      c->ev_free.push_back(tl.a);
+      c->ev_free.push_back(tl.b);
+    } else {
+      c->ev_pending.push_back(tl);
+    }
+  }
   if (r == -1) return TMOP_E_UNSUPPORTED;
   return r == 0 ? TMOP_OK : TMOP_E_HIP;
+}
+
+// Waits for the pending timed launches and adds their durations.
+int collect_timing(tmop_ctx* c) {
+  int st = TMOP_OK;
+  for (auto& t : c->ev_pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess) {
+      st = TMOP_E_HIP;
+    } else {
+      c->t_ms[t.op] += ms;
+      c->t_launches[t.op] += 1;
+    }
+    c->ev_free.push_back(t.a);
+    c->ev_free.push_back(t.b);
+  }
+  c->ev_pending.clear();
+  return st;
 }
 
 // out = sum over colours of the element contributions (gradient / Hv).
@@ -218,6 +256,8 @@ void free_ctx(tmop_ctx* c) {
   (void)hipFree(c->d_res);
   (void)hipFree(c->d_work);
   if (c->h_res) (void)hipHostFree(c->h_res);
+  (void)collect_timing(c);
+  for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
   (void)hipSetDevice(cur);
   delete c;
 }
@@ -370,6 +410,28 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
 }
 
 void tmop_destroy(tmop_ctx* c) { free_ctx(c); }
+
+int tmop_timing_enable(tmop_ctx* c, int enable) {
+  if (!c) return TMOP_E_ARG;
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(c->device) != hipSuccess) return TMOP_E_HIP;
+  const int st = collect_timing(c);
+  (void)hipSetDevice(cur);
+  c->timing = enable != 0;
+  for (int k = 0; k < 3; ++k) {
+    c->t_ms[k] = 0.0;
+    c->t_launches[k] = 0;
+  }
+  return st;
+}
+
+int tmop_timing_read(tmop_ctx* c, int op, double* ms_total, int64_t* launches) {
+  if (!c || op < 0 || op > 2 || !ms_total || !launches) return TMOP_E_ARG;
+  const int st = collect_timing(c);
+  *ms_total = c->t_ms[op];
+  *launches = c->t_launches[op];
+  return st;
+}
 
 int tmop_energy(tmop_ctx* c, const double* x, double* F, double* min_detA, void* stream) {
   if (!c || !x || !F || !min_detA) return TMOP_E_ARG;

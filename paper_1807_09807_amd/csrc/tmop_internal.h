@@ -79,4 +79,11 @@ struct tmop_ctx {
   double* d_res = nullptr;             // [4] reduction results
   double* h_res = nullptr;             // [4] pinned mirror
   double* d_work = nullptr;            // Newton work vectors, allocated on first use
+  // optional per-launch timing of the element kernels (HIP events)
+  struct TimedLaunch { int op; hipEvent_t a, b; };
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<TimedLaunch> ev_pending;
+  double t_ms[3] = {0.0, 0.0, 0.0};
+  int64_t t_launches[3] = {0, 0, 0};
 };

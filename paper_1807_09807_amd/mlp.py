@@ -155,7 +155,8 @@ def propose(ctx: T.Context, mlp: MLP, x, out=None):
 
 # ----------------------------------------------------------------------------- pipeline
 
-NEWTON_OPTS = dict(max_it=50, rtol=1e-10, cg_forcing=1)
+NEWTON_OPTS = dict(max_it=300, rtol=1e-10, cg_forcing=1)
+EVAL_OPTS = NEWTON_OPTS
 
 
 @dataclass
@@ -183,31 +184,55 @@ def box_context(n: int, precision=T.TMOP_FP64):
     return mesh, ctx
 
 
-def generate_training_data(n_mesh: int = 2000, n: int = 64, seed0: int = 1000, log=None) -> TrainingData:
-    """Features and labels of n_mesh seeded n x n Q2 mu_2 meshes; labels from
-    the library's Newton solution of each mesh."""
+def union_context(n: int, copies: int, precision=T.TMOP_FP64):
+    """One context for `copies` disjoint n x n Q2 meshes (node ids of copy k
+    offset by k n_node): the objective is the sum of the copies' objectives,
+    so one Newton solve optimizes all of them with full-size launches."""
+    mesh = meshgen.box_mesh(2, n, 2)
+    en = np.concatenate([mesh.elem_node + k * mesh.n_node for k in range(copies)])
+    fixed = np.tile(mesh.fixed, (1, copies))
+    ctx = T.Context(2, 2, en, copies * mesh.n_node, 4, T.TMOP_MU2, mesh.h * np.eye(2), fixed=fixed,
+                    precision=precision)
+    return mesh, ctx
+
+
+def generate_training_data(n_mesh: int = 2000, n: int = 64, seed0: int = 1000, batch: int = 125,
+                           log=None) -> TrainingData:
+    """Features and labels of n_mesh seeded n x n Q2 mu_2 meshes (seeds
+    seed0, seed0 + 1, ...); labels from the library's Newton solution,
+    solved `batch` meshes at a time on a union context."""
     import torch
-    mesh, ctx = box_context(n)
-    ne = mesh.n_elem
+    mesh, one = box_context(n)
+    ne, nn = mesh.n_elem, mesh.n_node
     X = torch.empty((n_mesh * ne, 18), dtype=torch.float32, device="cuda")
     L = torch.empty_like(X)
-    bad = _valid_by_library(ctx)
+    bad = _valid_by_library(one)
+    ctxs = {}
     t0 = time.perf_counter()
-    iters, cg = 0, 0
-    for k in range(n_mesh):
-        tm = meshgen.training_mesh(n, seed0 + k, bad_elements=bad)
-        x0 = torch.from_numpy(tm.x).cuda()
+    iters, cg, statuses, grel = 0, 0, [], []
+    for k0 in range(0, n_mesh, batch):
+        b = min(batch, n_mesh - k0)
+        if b not in ctxs:
+            ctxs[b] = union_context(n, b)[1]
+        ctx = ctxs[b]
+        xs_host = [meshgen.training_mesh(n, seed0 + k0 + j, bad_elements=bad).x for j in range(b)]
+        x0 = torch.from_numpy(np.concatenate(xs_host, axis=1)).cuda()
         xs = x0.clone()
         st, rep = ctx.newton_solve(xs, **NEWTON_OPTS)
         iters += rep["iters"]
         cg += rep["cg_iters"]
-        sl = slice(k * ne, (k + 1) * ne)
+        statuses.append(st)
+        grel.append(rep["gnorm"] / rep["gnorm0"])
+        sl = slice(k0 * ne, (k0 + b) * ne)
         _check(_bind(T.load()).tmop_mlp_features(ctx.handle, _ptr(x0), _ptr(X[sl]), _stream(x0)), "features")
         labels(ctx, x0, xs, out=L[sl])
-        if log and (k + 1) % 200 == 0:
-            log(f"  training data: {k + 1}/{n_mesh} meshes, {time.perf_counter() - t0:.1f} s")
+        if log:
+            log(f"  training data: {k0 + b}/{n_mesh} meshes ({b * nn} nodes per solve, status {st}, "
+                f"{rep['iters']} it, {rep['cg_iters']} CG), {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
-    return TrainingData(X, L, n_mesh, ne, dict(seconds=time.perf_counter() - t0, newton_iters=iters, cg_iters=cg))
+    return TrainingData(X, L, n_mesh, ne, dict(seconds=time.perf_counter() - t0, newton_iters=iters, cg_iters=cg,
+                                               batch=batch, newton_status=statuses,
+                                               max_rel_gnorm=max(grel)))
 
 
 def train(data: TrainingData, epochs: int = 4, batch_meshes: int = 2, lr: float = 1e-3, seed: int = 0,
@@ -238,7 +263,9 @@ def train(data: TrainingData, epochs: int = 4, batch_meshes: int = 2, lr: float 
 def evaluate(mlp, n: int = 512, seeds=(10000,), precision=T.TMOP_FP64, log=None):
     """Plain Newton from x0 against learned-guess Newton, per seed: wall
     seconds and iterations to F_tol = F_ref + 1e-8 F0 (F_ref: final F of
-    plain Newton), with fallback to x0 if the proposal is unusable."""
+    plain Newton run to its relative gradient tolerance; the row records
+    whether that reference converged), with fallback to x0 if the
+    proposal is unusable."""
     import torch
     mesh, ctx = box_context(n, precision)
     bad = _valid_by_library(ctx)
@@ -248,14 +275,14 @@ def evaluate(mlp, n: int = 512, seeds=(10000,), precision=T.TMOP_FP64, log=None)
         x0 = torch.from_numpy(tm.x).cuda()
         # reference: plain Newton to the relative tolerance
         xr = x0.clone()
-        st, ref = ctx.newton_solve(xr, **NEWTON_OPTS)
+        st_ref, ref = ctx.newton_solve(xr, **EVAL_OPTS)
         F0 = ref["F0"]
         F_tol = ref["F"] + 1e-8 * F0
         # plain Newton to F_tol
         xp = x0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st_p, rp = ctx.newton_solve(xp, ftarget=F_tol, **NEWTON_OPTS)
+        st_p, rp = ctx.newton_solve(xp, ftarget=F_tol, **EVAL_OPTS)
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
         # learned: propose, check, Newton (fallback to x0)
@@ -268,15 +295,16 @@ def evaluate(mlp, n: int = 512, seeds=(10000,), precision=T.TMOP_FP64, log=None)
             Fm, md, stm = ctx.energy(xl)
             used = stm == T.TMOP_OK and md > 0 and Fm < F0
         xs = xl if used else x0.clone()
-        st_l, rl = ctx.newton_solve(xs, ftarget=F_tol, **NEWTON_OPTS)
+        st_l, rl = ctx.newton_solve(xs, ftarget=F_tol, **EVAL_OPTS)
         torch.cuda.synchronize()
         t_learn = time.perf_counter() - t0
         row = dict(seed=sd, F0=F0, F_tol=F_tol, F_proposal=Fm if mlp is not None else None, used_proposal=used,
+                   reference=dict(iters=ref["iters"], F=ref["F"], status=st_ref, converged=st_ref == T.TMOP_OK),
                    plain=dict(iters=rp["iters"], cg=rp["cg_iters"], wall_s=t_plain, F=rp["F"], status=st_p),
                    learned=dict(iters=rl["iters"], cg=rl["cg_iters"], wall_s=t_learn, F=rl["F"], status=st_l))
         rows.append(row)
         if log:
-            log(f"  eval seed {sd}: plain {rp['iters']} it / {rp['cg_iters']} CG / {t_plain:.3f} s; learned "
+            log(f"  eval seed {sd}: reference {ref['iters']} it (status {st_ref}); plain {rp['iters']} it / {rp['cg_iters']} CG / {t_plain:.3f} s; learned "
                 f"{'(proposal used) ' if used else '(fallback) '}{rl['iters']} it / {rl['cg_iters']} CG / "
                 f"{t_learn:.3f} s; F0 {F0:.4e} -> proposal {row['F_proposal']}")
     return rows

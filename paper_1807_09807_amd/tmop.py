@@ -27,7 +27,8 @@ TMOP_FP64, TMOP_MIXED_FP32 = 0, 1
 TMOP_TGT_CONST = 0
 
 EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_gradient_scaled", "tmop_hessian_apply",
-           "tmop_newton_solve", "tmop_destroy", "tmop_strerror", "tmop_newton_default_opts")
+           "tmop_newton_solve", "tmop_destroy", "tmop_strerror", "tmop_newton_default_opts",
+           "tmop_timing_enable", "tmop_timing_read")
 
 
 class TMOPError(RuntimeError):
@@ -97,6 +98,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tmop_strerror.restype = ctypes.c_char_p
     lib.tmop_newton_default_opts.argtypes = [ctypes.POINTER(tmop_newton_opts)]
     lib.tmop_newton_default_opts.restype = None
+    lib.tmop_timing_enable.argtypes = [P, ctypes.c_int]
+    lib.tmop_timing_enable.restype = ctypes.c_int
+    lib.tmop_timing_read.argtypes = [P, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    lib.tmop_timing_read.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -206,6 +211,22 @@ class Context:
         if st < 0:
             raise TMOPError(st, "tmop_hessian_apply")
         return out
+
+    def timing_enable(self, on: bool = True):
+        """Clears the per-launch kernel timing totals and turns timing on/off."""
+        st = self._lib.tmop_timing_enable(self._h, int(bool(on)))
+        if st < 0:
+            raise TMOPError(st, "tmop_timing_enable")
+
+    def timing_read(self, op: int):
+        """(summed device ms, launch count) of the element kernels of one
+        operation (0 energy, 1 gradient, 2 Hessian action) since the last
+        timing_enable."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        st = self._lib.tmop_timing_read(self._h, int(op), ctypes.byref(ms), ctypes.byref(n))
+        if st < 0:
+            raise TMOPError(st, "tmop_timing_read")
+        return ms.value, n.value
 
     def newton_solve(self, x, **opts):
         """Optimizes x in place.  Keyword options are the fields of

@@ -97,3 +97,27 @@ def test_unused_nodes_get_zero():
     g = ctx.gradient(to_dev(x)).cpu().numpy()
     Hv = ctx.hessian_apply(to_dev(x), to_dev(np.ones_like(x))).cpu().numpy()
     assert g[0, -1] == 0.0 and g[1, -1] == 0.0 and Hv[0, -1] == 0.0 and Hv[1, -1] == 0.0
+
+
+def test_kernel_timing_counts_launches():
+    """Timing on: one energy launch per energy call, one launch per colour
+    for gradient and Hessian action (2^dim colours on a box mesh with at
+    least two elements per direction); results unchanged by timing."""
+    say("[edge] kernel timing")
+    mesh = meshgen.box_mesh(3, 4, 2)
+    ctx = _ctx(mesh, 4, 303)
+    x = to_dev(meshgen.perturb(mesh, 0.05, 1))
+    v = to_dev(meshgen.random_direction(mesh, 2))
+    h0 = ctx.hessian_apply(x, v).clone()
+    ctx.timing_enable(True)
+    for _ in range(3):
+        ctx.energy(x)
+        ctx.gradient(x)
+        h1 = ctx.hessian_apply(x, v)
+    counts = [ctx.timing_read(op) for op in range(3)]
+    ctx.timing_enable(False)
+    assert [n for _, n in counts] == [3, 24, 24]
+    assert all(ms > 0 for ms, _ in counts)
+    assert torch.equal(h0, h1)
+    ctx.energy(x)
+    assert ctx.timing_read(0) == (0.0, 0)
