@@ -42,13 +42,16 @@ def contraction_macs(dim, P, Q):
     return 2 * (P * Q * P * 2) + 4 * Q * Q * P
 
 
-# per quadrature point, beyond the contractions: (energy, gradient, Hessian).
-# Energy: T = A W^-1, det A, det T, mu, accumulation.  Gradient: T, P from
-# the invariants, Y = w det W P W^-t.  Hessian: T, dT, dP from the
-# invariants, Y.  With an isotropic target W = s I (every workload here)
-# T = A / s and Y = (w det W / s) P: 9 products instead of a 3x3 product.
-POINT_FLOPS = {2: (34, 67, 123), 7: (40, 69, 125), 303: (110, 205, 403), 302: (155, 379, 961)}
-POINT_FLOPS_ISO = {2: (21, 40, 84), 7: (27, 42, 86), 303: (53, 107, 260), 302: (98, 281, 818)}
+# Per quadrature point, beyond the contractions: (energy, gradient, Hessian)
+# flops of the point formulas with an isotropic target W = s I (every
+# workload here), counted from the kernel source: 1/s rides in the G table,
+# so the contraction yields T and the transposed contraction takes Y = k P
+# with the weight k = w det W folded into the metric's scalar coefficients.
+#   energy    det T, det A = det W det T, mu(T), w det W, accumulation
+#   gradient  cof T, I1, tau, the partials, P = k1 T + kt cof T (+ k2 dI2)
+#   Hessian   cof T, dcof[E], I1, T:E, cof T:E, tau, the partials, and
+#             dP = kE E + kd dcof + sT T + sC cof T (+ the I2 terms of mu_302)
+POINT_FLOPS = {2: (15, 31, 72), 7: (21, 32, 74), 303: (40, 87, 232), 302: (85, 242, 717)}
 
 # HBM traffic of one Hessian-action colour launch (FP64), from rocprofv3
 # --pmc FETCH_SIZE and WRITE_SIZE passes (KiB per dispatch), valid for the
@@ -81,12 +84,12 @@ def measured_traffic(workload):
     return 1024.0 * (FETCH_SCALE * m["fetch_kib"] + WRITE_SCALE * m["write_kib"])
 
 
-def algorithmic(w, iso=True):
+def algorithmic(w):
     """(flops, bytes) per element for energy, gradient, Hessian action."""
     dim, P, Q, metric = w["dim"], w["p"] + 1, w["Q"], w["metric"]
     nq = Q ** dim
     c = contraction_macs(dim, P, Q) * 2
-    pf = (POINT_FLOPS_ISO if iso else POINT_FLOPS)[metric]
+    pf = POINT_FLOPS[metric]
     flops = (c + nq * pf[0], 2 * c + nq * pf[1], 3 * c + nq * pf[2])
     m = w["n"] * w["p"] + 1
     node_bytes = dim * 8 * m ** dim / w["n"] ** dim      # unique L-vector bytes per element, one field

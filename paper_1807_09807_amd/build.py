@@ -26,13 +26,13 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include")]
 
 
-def sources():
-    return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
+def sources(src_dir: str = CSRC):
+    return sorted(f for f in os.listdir(src_dir) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str, out_dir: str = OUT_DIR, extra=()) -> str:
+def _compile(src: str, out_dir: str = OUT_DIR, extra=(), src_dir: str = CSRC) -> str:
     obj = os.path.join(out_dir, src + ".o")
-    path = os.path.join(CSRC, src)
+    path = os.path.join(src_dir, src)
     if src.endswith(".hip"):
         cmd = ["hipcc", *HIP_FLAGS, *extra, "-c", path, "-o", obj]
     else:
@@ -47,14 +47,14 @@ def _compile(src: str, out_dir: str = OUT_DIR, extra=()) -> str:
 
 
 def build(jobs: int | None = None, verbose: bool = True, lib: str = LIB, out_dir: str = OUT_DIR,
-          extra=()) -> str:
-    """Compile every source (hipcc, gfx950) and link `lib`.  `extra` adds
-    compiler flags (e.g. -D tuning macros) for variant builds."""
+          extra=(), src_dir: str = CSRC) -> str:
+    """Compile every source of `src_dir` (hipcc, gfx950) and link `lib`.
+    `extra` adds compiler flags (e.g. -D tuning macros) for variant builds."""
     os.makedirs(out_dir, exist_ok=True)
-    srcs = sources()
+    srcs = sources(src_dir)
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)), 16)
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda f: _compile(f, out_dir, tuple(extra)), srcs))
+        objs = list(ex.map(lambda f: _compile(f, out_dir, tuple(extra), src_dir), srcs))
     tmp = lib + ".tmp"
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -13,7 +13,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "../../include/tmop.h"
+#include "tmop.h"
 #include "tmop_internal.h"
 
 using namespace tmop;

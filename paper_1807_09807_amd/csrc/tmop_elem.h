@@ -14,15 +14,15 @@
 // Thread mapping (3D): each element gets Q*Q lanes, lane (a, b).  Each 1D
 // pass gives a lane a full "pencil" along the contracted direction, so every
 // value it loads is reused Q (or P) times from registers:
-//   pass 1 (z):  lane (i0, i1) -- its P nodes (loaded up front), U to LDS
-//   pass 2 (y):  lane (i0, q2) -- reads U, writes V to LDS
-//   pass 3 (x):  lane (q1, q2) -- reads V into registers and walks q0:
-//                A -> T = A W^-1 -> metric -> Y = w det W (dmu) W^-t,
-//                accumulating the transposed x-contraction in registers
-//   pass 3', 2', 1' mirror 3, 2, 1 and end with the scatter to the nodes.
-// LDS: lane (i0, q2) of pass 2 owns one area that holds first its U pencil,
-// then its V pencil (it reads all of U before writing V), later the
-// transposed data the same way, so U and V never coexist.
+//   pass 1 (z):   lane (i0, i1) -- its P nodes (loaded up front), U to LDS
+//   pass 23 (y):  lane (q1, q2) -- contracts the slab of U at q2 for its own
+//                 q1 into its x-pencils V (registers), then walks q0:
+//                 A -> T = A W^-1 -> metric -> Y = w det W (dmu) W^-t,
+//                 accumulating the transposed x-contraction in registers
+//   pass 3', 2', 1' hand the transposed sums back through LDS one
+//                 component at a time and end with the scatter to the nodes.
+// All Q*Q lanes work in pass 23; LDS holds U (or one component's transposed
+// data), 2 Q P^2 values per component and element.
 // 2D is the same with one pass fewer and Q lanes per element.
 //
 // Scatter: the host launches one kernel per element colour; elements of a
@@ -41,6 +41,9 @@ namespace tmop {
 
 // Kernel arguments.  The 1D tables and the constant target travel in the
 // kernel-argument segment, so the unrolled loops read them as scalars.
+// Isotropic target W = s I: every term of A (and of the transposed
+// contraction) holds exactly one G factor, so G carries the factor 1/s and
+// the contraction yields T = A W^{-1} directly (and Y needs no W^{-t}).
 template <int P, int Q, typename R>
 struct ElemArgs {
   const double* __restrict__ x;          // [dim][n_node]
@@ -55,10 +58,9 @@ struct ElemArgs {
   R B[Q][P];
   R G[Q][P];
   double w[Q];                           // 1D quadrature weights
-  R Winv[3][3];                          // W^{-1} (constant target)
-  R s_inv;                               // isotropic target W = s I: 1/s
+  R Winv[3][3];                          // W^{-1} (constant target; unused when isotropic)
   double Winvd[3][3];                    // W^{-1} in FP64 (energy)
-  double s_invd;
+  double jscale;                         // factor of the affine-frame Jacobian: 1/s if isotropic, else 1
   double xi[P];                          // 1D GLL node coordinates
   double detW;
 };
@@ -77,11 +79,39 @@ constexpr int pick_epb(int tpe, int lds_bytes_per_elem) {
   return best;
 }
 
-// LDS padding of the 3D lane areas and of the per-element block (values):
-// they set the bank pattern of the pass-2/3 accesses.
-#ifndef TMOP_AREA_PAD
-#define TMOP_AREA_PAD 0
-#endif
+// LDS of one element (values).  Energy and gradient:
+//   U [q2][c][i0][i1][t2]  pass 1 -> pass 23: the z-contraction, t2 = B, G
+//   R [q2][i0][t][q1]      pass 3' -> pass 2': one component of the
+//                          x-transposed contraction (t = the three terms)
+//   S [i0][i1][q2][t2]     pass 2' -> pass 1': one component of the
+//                          y-transposed contraction; S follows R
+// U is dead before R and S are written, so they share the space.
+// Hessian action: pass 2 on lanes (i0, q2), each with its own area of 9 Q
+// values that holds first its U pencil, then its V pencils (read back by the
+// pass-3 lanes); R and S reuse the space afterwards.
+template <int P, int Q> struct Lds3 {
+  static constexpr int NU = Q * 3 * P * P * 2;
+  static constexpr int NR = Q * P * 3 * Q;
+  static constexpr int NS = P * P * Q * 2;
+  static constexpr int AREA = 9 * Q;
+  static constexpr int NA = Q * P * AREA;
+  static constexpr int N = NU > NR + NS ? NU : NR + NS;
+  static constexpr int NH = NA > NR + NS ? NA : NR + NS;
+  static __device__ __forceinline__ constexpr int u(int q2, int c, int i0, int i1) {
+    return (((q2 * 3 + c) * P + i0) * P + i1) * 2;
+  }
+  static __device__ __forceinline__ constexpr int r(int q2, int i0, int t, int q1) {
+    return ((q2 * P + i0) * 3 + t) * Q + q1;
+  }
+  static __device__ __forceinline__ constexpr int s(int i0, int i1, int q2) { return NR + ((i0 * P + i1) * Q + q2) * 2; }
+  // area of pass-2 lane (i0, q2); U pencil at (t, c, i1), V pencil at (t, c, q1)
+  static __device__ __forceinline__ constexpr int area(int q2, int i0) { return (q2 * P + i0) * AREA; }
+  static __device__ __forceinline__ constexpr int au(int t, int c, int i1) { return (t * 3 + c) * P + i1; }
+  static __device__ __forceinline__ constexpr int av(int t, int c, int q1) { return (t * 3 + c) * Q + q1; }
+};
+
+// LDS padding of the per-element block (values): it sets the bank pattern
+// of the accesses of neighbouring elements.
 #ifndef TMOP_ELEM_PAD
 #define TMOP_ELEM_PAD 2
 #endif
@@ -89,9 +119,10 @@ constexpr int pick_epb(int tpe, int lds_bytes_per_elem) {
 template <int DIM, int P, int Q, typename R>
 struct Cfg {
   static constexpr int TPE = DIM == 3 ? Q * Q : Q;
-  static constexpr int AREA = DIM == 3 ? 9 * Q + TMOP_AREA_PAD : 0;   // 3D: values per (i0, q2) lane area
-  static constexpr int NE = DIM == 3 ? Q * P * AREA + TMOP_ELEM_PAD : 2 * 2 * Q * P;   // LDS values per element
-  static constexpr int EPB = pick_epb(TPE, NE * (int)sizeof(R));
+  // LDS values per element: energy / gradient, Hessian action
+  static constexpr int NE = DIM == 3 ? Lds3<P, Q>::N + TMOP_ELEM_PAD : 2 * 2 * Q * P;
+  static constexpr int NEH = DIM == 3 ? Lds3<P, Q>::NH + TMOP_ELEM_PAD : 2 * 2 * Q * P;
+  static constexpr int EPB = pick_epb(TPE, NEH * (int)sizeof(R));
   static constexpr int BLOCK = (EPB * TPE + 63) / 64 * 64;
 };
 
@@ -125,15 +156,15 @@ __device__ __forceinline__ void block_reduce_sum_min(double s, double m, double*
   }
 }
 
-// T = A W^{-1} (ISO: W = s I, T = A / s)
+// T = A W^{-1} (ISO: the contraction already produced T)
 template <int D, typename R, bool ISO>
-__device__ __forceinline__ void right_mul(const R (&A)[D][D], const R (&Wi)[3][3], R si, R (&T)[D][D]) {
+__device__ __forceinline__ void right_mul(const R (&A)[D][D], const R (&Wi)[3][3], R (&T)[D][D]) {
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       if constexpr (ISO) {
-        T[i][j] = A[i][j] * si;
+        T[i][j] = A[i][j];
       } else {
         R s = 0;
 #pragma unroll
@@ -143,21 +174,20 @@ __device__ __forceinline__ void right_mul(const R (&A)[D][D], const R (&Wi)[3][3
     }
 }
 
-// Y = s M W^{-t} (ISO: Y = (s / w) M)
+// Y = M W^{-t} (ISO: the transposed contraction's G carries W^{-t}, Y = M)
 template <int D, typename R, bool ISO>
-__device__ __forceinline__ void stress(const R (&M)[D][D], const R (&Wi)[3][3], R si, R s, R (&Y)[D][D]) {
-  if constexpr (ISO) s *= si;
+__device__ __forceinline__ void stress(const R (&M)[D][D], const R (&Wi)[3][3], R (&Y)[D][D]) {
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       if constexpr (ISO) {
-        Y[i][j] = s * M[i][j];
+        Y[i][j] = M[i][j];
       } else {
         R t = 0;
 #pragma unroll
         for (int k = 0; k < D; ++k) t += M[i][k] * Wi[j][k];
-        Y[i][j] = s * t;
+        Y[i][j] = t;
       }
     }
 }
@@ -176,29 +206,31 @@ __device__ __forceinline__ void point_op(const ElemArgs<P, Q, R>& a, const R (&A
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int j = 0; j < D; ++j) Ad[i][j] = (double)A[i][j];
-    const double detA = det<D, double>(Ad);
-    double tau;
-    if constexpr (ISO) {
-      right_mul<D, double, true>(Ad, a.Winvd, a.s_invd, Td);
-      tau = detA * (D == 2 ? a.s_invd * a.s_invd : a.s_invd * a.s_invd * a.s_invd);
+    double detA, tau;
+    if constexpr (ISO) {          // the contraction gave T; det A = det T det W
+      right_mul<D, double, true>(Ad, a.Winvd, Td);
+      tau = det<D, double>(Td);
+      detA = tau * a.detW;
     } else {
-      right_mul<D, double, false>(Ad, a.Winvd, a.s_invd, Td);
+      detA = det<D, double>(Ad);
+      right_mul<D, double, false>(Ad, a.Winvd, Td);
       tau = det<D, double>(Td);
     }
     acc += wdet * mu_value<METRIC, double>(Td, tau);
     mind = fmin(mind, detA);
   } else {
+    // the weight w det W is folded into the metric's scalar coefficients
     R T[D][D];
-    right_mul<D, R, ISO>(A, a.Winv, a.s_inv, T);
+    right_mul<D, R, ISO>(A, a.Winv, T);
     if constexpr (OP == OP_GRAD) {
       R Pm[D][D];
-      mu_first<METRIC, R>(T, Pm);
-      stress<D, R, ISO>(Pm, a.Winv, a.s_inv, (R)wdet, Y);
+      mu_first<METRIC, R>(T, (R)wdet, Pm);
+      stress<D, R, ISO>(Pm, a.Winv, Y);
     } else {
       R dT[D][D], dP[D][D];
-      right_mul<D, R, ISO>(dA, a.Winv, a.s_inv, dT);
-      mu_second<METRIC, R>(T, dT, dP);
-      stress<D, R, ISO>(dP, a.Winv, a.s_inv, (R)wdet, Y);
+      right_mul<D, R, ISO>(dA, a.Winv, dT);
+      mu_second<METRIC, R>(T, dT, (R)wdet, dP);
+      stress<D, R, ISO>(dP, a.Winv, Y);
     }
   }
 }
@@ -234,10 +266,6 @@ __device__ __forceinline__ void element_frame(const double* __restrict__ f, int6
 
 // ------------------------------------------------------------------ 3D
 
-// Offsets in the LDS area of pass-2 lane (i0, q2).
-template <int P> __device__ __forceinline__ constexpr int uoff(int t, int c, int i1) { return (t * 3 + c) * P + i1; }
-template <int Q> __device__ __forceinline__ constexpr int voff(int t, int c, int q1) { return (t * 3 + c) * Q + q1; }
-
 // The pencil of pass-1 lane (i0, i1): its P nodes of field f relative to the
 // element frame, for every component.  Only called by lanes with i0, i1 < P.
 template <int P, int Q, typename R, bool AFFINE>
@@ -249,7 +277,7 @@ __device__ __forceinline__ void load_pencil_3d(const ElemArgs<P, Q, R>& a, const
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int l = 0; l < 3; ++l) J0r[c][l] = (R)J0[c][l];
+    for (int l = 0; l < 3; ++l) J0r[c][l] = (R)(J0[c][l] * a.jscale);
 #pragma unroll
   for (int i2 = 0; i2 < P; ++i2)
 #pragma unroll
@@ -262,12 +290,60 @@ __device__ __forceinline__ void load_pencil_3d(const ElemArgs<P, Q, R>& a, const
     }
 }
 
-// Passes 1 and 2 of the forward contraction; lane (q1 = ta, q2 = tb) then
-// reads its V pencil into registers.
+// Forward contraction up to the x-pencils.  Pass 1 (lane (i0, i1)): z, into
+// U.  Pass 23 (lane (q1, q2)): y for its own q1 straight from U, giving the
+// three x-pencils V[t][c][i0] of point row (q1, q2):
+//   t = 0: B_y B_z (used with G_x), 1: G_y B_z, 2: B_y G_z (used with B_x).
+// Bq, Gq: row q1 of the tables.
 template <int P, int Q, typename R>
 __device__ __forceinline__ void fwd_3d(const ElemArgs<P, Q, R>& a, const R (&X)[3][P], int ta, int tb,
-                                       R* __restrict__ s, R (&V)[3][3][P]) {
-  constexpr int AREA = 9 * Q;
+                                       const R (&Bq)[P], const R (&Gq)[P], R* __restrict__ s,
+                                       R (&V)[3][3][P]) {
+  using L = Lds3<P, Q>;
+  if (ta < P && tb < P) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int q2 = 0; q2 < Q; ++q2) {
+        R ub = 0, ug = 0;
+#pragma unroll
+        for (int i2 = 0; i2 < P; ++i2) { ub += a.B[q2][i2] * X[c][i2]; ug += a.G[q2][i2] * X[c][i2]; }
+        R* p = s + L::u(q2, c, ta, tb);
+        p[0] = ub;
+        p[1] = ug;
+      }
+  }
+  __syncthreads();
+  if (tb < Q) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i0 = 0; i0 < P; ++i0) {
+        R ub[P], ug[P];
+#pragma unroll
+        for (int i1 = 0; i1 < P; ++i1) {
+          const R* p = s + L::u(tb, c, i0, i1);
+          ub[i1] = p[0];
+          ug[i1] = p[1];
+        }
+        R bb = 0, gb = 0, bg = 0;
+#pragma unroll
+        for (int i1 = 0; i1 < P; ++i1) { bb += Bq[i1] * ub[i1]; gb += Gq[i1] * ub[i1]; bg += Bq[i1] * ug[i1]; }
+        V[0][c][i0] = bb;
+        V[1][c][i0] = gb;
+        V[2][c][i0] = bg;
+      }
+  }
+}
+
+// Forward contraction of the Hessian action (register pressure: its x-pencils
+// come from LDS just before the point loop).  Pass 1 (lane (i0, i1)): z, into
+// the areas.  Pass 2 (lane (i0, q2)): y for every q1, in its own area.  Then
+// lane (q1, q2) reads its x-pencils V[t][c][i0].
+template <int P, int Q, typename R>
+__device__ __forceinline__ void fwd_3d_areas(const ElemArgs<P, Q, R>& a, const R (&X)[3][P], int ta, int tb,
+                                             R* __restrict__ s, R (&V)[3][3][P]) {
+  using L = Lds3<P, Q>;
   if (ta < P && tb < P) {   // pass 1, lane (i0 = ta, i1 = tb): U of all q2
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -276,19 +352,19 @@ __device__ __forceinline__ void fwd_3d(const ElemArgs<P, Q, R>& a, const R (&X)[
         R ub = 0, ug = 0;
 #pragma unroll
         for (int i2 = 0; i2 < P; ++i2) { ub += a.B[q2][i2] * X[c][i2]; ug += a.G[q2][i2] * X[c][i2]; }
-        R* ar = s + (q2 * P + ta) * AREA;
-        ar[uoff<P>(0, c, tb)] = ub;
-        ar[uoff<P>(1, c, tb)] = ug;
+        R* ar = s + L::area(q2, ta);
+        ar[L::au(0, c, tb)] = ub;
+        ar[L::au(1, c, tb)] = ug;
       }
   }
   __syncthreads();
   if (ta < P && tb < Q) {   // pass 2, lane (i0 = ta, q2 = tb): own area, U in, V out
-    R* ar = s + (tb * P + ta) * AREA;
+    R* ar = s + L::area(tb, ta);
     R ub[3][P], ug[3][P];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int i1 = 0; i1 < P; ++i1) { ub[c][i1] = ar[uoff<P>(0, c, i1)]; ug[c][i1] = ar[uoff<P>(1, c, i1)]; }
+      for (int i1 = 0; i1 < P; ++i1) { ub[c][i1] = ar[L::au(0, c, i1)]; ug[c][i1] = ar[L::au(1, c, i1)]; }
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -300,20 +376,20 @@ __device__ __forceinline__ void fwd_3d(const ElemArgs<P, Q, R>& a, const R (&X)[
           gb += a.G[q1][i1] * ub[c][i1];
           bg += a.B[q1][i1] * ug[c][i1];
         }
-        ar[voff<Q>(0, c, q1)] = bb;
-        ar[voff<Q>(1, c, q1)] = gb;
-        ar[voff<Q>(2, c, q1)] = bg;
+        ar[L::av(0, c, q1)] = bb;
+        ar[L::av(1, c, q1)] = gb;
+        ar[L::av(2, c, q1)] = bg;
       }
   }
   __syncthreads();
-  if (tb < Q) {             // pass 3 input, lane (q1 = ta, q2 = tb)
+  if (tb < Q) {             // lane (q1 = ta, q2 = tb) reads its x-pencils
 #pragma unroll
     for (int i0 = 0; i0 < P; ++i0) {
-      const R* ar = s + (tb * P + i0) * AREA;
+      const R* ar = s + L::area(tb, i0);
 #pragma unroll
       for (int t = 0; t < 3; ++t)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) V[t][c][i0] = ar[voff<Q>(t, c, ta)];
+        for (int c = 0; c < 3; ++c) V[t][c][i0] = ar[L::av(t, c, ta)];
     }
   }
 }
@@ -322,9 +398,11 @@ template <int P, int Q, int METRIC, typename R, int OP, bool ISO>
 __global__ void __launch_bounds__((Cfg<3, P, Q, R>::BLOCK))
 elem_kernel_3d(const ElemArgs<P, Q, R> a) {
   using C = Cfg<3, P, Q, R>;
-  constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P * P, AREA = C::AREA;
+  using L = Lds3<P, Q>;
+  constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P * P;
   constexpr bool AFFINE = sizeof(R) == 4;   // FP32 contracts the deviation from the vertex-affine map
-  __shared__ R s_all[EPB * C::NE];
+  constexpr int NE = OP == OP_HESS ? C::NEH : C::NE;
+  __shared__ R s_all[EPB * NE];
   __shared__ double red[2 * (C::BLOCK / 64)];
 
   const int tid = threadIdx.x;
@@ -338,7 +416,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
   const bool active = le_raw < EPB && k < a.n_list;
   const int kk = k < a.n_list ? k : a.n_list - 1;
   const int e = a.list ? a.list[kk] : kk;
-  R* s = s_all + le * C::NE;
+  R* s = s_all + le * NE;
   const bool p1 = ta < P && tb < P;          // pass-1 lane (i0 = ta, i1 = tb)
 
   // all global loads of the element's fields first
@@ -351,12 +429,29 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
   if constexpr (OP == OP_HESS) load_pencil_3d<P, Q, R, AFFINE>(a, a.v, node, en, p1 ? ta : 0, p1 ? tb : 0, dX, J0v);
 
   R V[3][3][P], dV[3][3][P];
-  fwd_3d<P, Q, R>(a, X, ta, tb, s, V);
   if constexpr (OP == OP_HESS) {
+    fwd_3d_areas<P, Q, R>(a, X, ta, tb, s, V);
     __syncthreads();
-    fwd_3d<P, Q, R>(a, dX, ta, tb, s, dV);
+    fwd_3d_areas<P, Q, R>(a, dX, ta, tb, s, dV);
+  } else {
+    // row q1 = ta of the tables (pass 23 contracts y for its own q1)
+    R Bq[P], Gq[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) { Bq[i] = a.B[0][i]; Gq[i] = a.G[0][i]; }
+#pragma unroll
+    for (int q = 1; q < Q; ++q)
+      if (ta == q) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) { Bq[i] = a.B[q][i]; Gq[i] = a.G[q][i]; }
+      }
+    fwd_3d<P, Q, R>(a, X, ta, tb, Bq, Gq, s, V);
+    // keep the scheduler from starting the point loop inside the forward
+    // passes (that raises the register peak of the kernel)
+    __builtin_amdgcn_sched_barrier(0);
   }
 
+  // pass 3, lane (q1, q2): x-contraction per point q0, the point kernel, and
+  // the x-transposed contraction accumulated in registers
   double acc = 0.0, mind = __builtin_huge_val();
   R Racc[3][3][P];
 #pragma unroll
@@ -421,53 +516,44 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
 #pragma unroll
         for (int i2 = 0; i2 < P; ++i2) old[c][i2] = a.out[c * a.n_node + node[i2]];
     }
-    // pass 3': lane (q1, q2) writes into exactly the V slots it read
-    if (tb < Q) {
+    __syncthreads();   // U is dead: R and S may overwrite it
+    // the transposed y- and z-contractions, one component at a time
 #pragma unroll
-      for (int i0 = 0; i0 < P; ++i0) {
-        R* ar = s + (tb * P + i0) * AREA;
+    for (int c = 0; c < 3; ++c) {
+      if (tb < Q) {    // pass 3': lane (q1, q2) hands over its x-transposed sums
+#pragma unroll
+        for (int i0 = 0; i0 < P; ++i0)
+#pragma unroll
+          for (int tt = 0; tt < 3; ++tt) s[L::r(tb, i0, tt, ta)] = Racc[tt][c][i0];
+      }
+      __syncthreads();
+      if (ta < P && tb < Q) {   // pass 2': lane (i0 = ta, q2 = tb), sum over q1
+        R r[3][Q];
 #pragma unroll
         for (int tt = 0; tt < 3; ++tt)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) ar[voff<Q>(tt, c, ta)] = Racc[tt][c][i0];
-      }
-    }
-    __syncthreads();
-    // pass 2': lane (i0 = ta, q2 = tb), own area
-    if (ta < P && tb < Q) {
-      R* ar = s + (tb * P + ta) * AREA;
-      R r[3][3][Q];
-#pragma unroll
-      for (int tt = 0; tt < 3; ++tt)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int q1 = 0; q1 < Q; ++q1) r[tt][c][q1] = ar[voff<Q>(tt, c, q1)];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
+          for (int q1 = 0; q1 < Q; ++q1) r[tt][q1] = s[L::r(tb, ta, tt, q1)];
 #pragma unroll
         for (int i1 = 0; i1 < P; ++i1) {
           R sb = 0, sg = 0;
 #pragma unroll
           for (int q1 = 0; q1 < Q; ++q1) {
-            sb += a.B[q1][i1] * r[0][c][q1] + a.G[q1][i1] * r[1][c][q1];
-            sg += a.B[q1][i1] * r[2][c][q1];
+            sb += a.B[q1][i1] * r[0][q1] + a.G[q1][i1] * r[1][q1];
+            sg += a.B[q1][i1] * r[2][q1];
           }
-          ar[uoff<P>(0, c, i1)] = sb;
-          ar[uoff<P>(1, c, i1)] = sg;
+          R* p = s + L::s(ta, i1, tb);
+          p[0] = sb;
+          p[1] = sg;
         }
-    }
-    __syncthreads();
-    // pass 1': lane (i0 = ta, i1 = tb), then the scatter
-    if (active && p1) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      }
+      __syncthreads();
+      if (active && p1) {       // pass 1': lane (i0 = ta, i1 = tb), sum over q2, scatter
         R sb[Q], sg[Q];
 #pragma unroll
         for (int q2 = 0; q2 < Q; ++q2) {
-          const R* ar = s + (q2 * P + ta) * AREA;
-          sb[q2] = ar[uoff<P>(0, c, tb)];
-          sg[q2] = ar[uoff<P>(1, c, tb)];
+          const R* p = s + L::s(ta, tb, q2);
+          sb[q2] = p[0];
+          sg[q2] = p[1];
         }
 #pragma unroll
         for (int i2 = 0; i2 < P; ++i2) {
@@ -497,7 +583,7 @@ __device__ __forceinline__ void load_pencil_2d(const ElemArgs<P, Q, R>& a, const
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int l = 0; l < 2; ++l) J0r[c][l] = (R)J0[c][l];
+    for (int l = 0; l < 2; ++l) J0r[c][l] = (R)(J0[c][l] * a.jscale);
 #pragma unroll
   for (int i1 = 0; i1 < P; ++i1)
 #pragma unroll
@@ -543,7 +629,8 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
   using C = Cfg<2, P, Q, R>;
   constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P;
   constexpr bool AFFINE = sizeof(R) == 4;
-  __shared__ R s_all[EPB * C::NE];
+  constexpr int NE = OP == OP_HESS ? C::NEH : C::NE;
+  __shared__ R s_all[EPB * NE];
   __shared__ double red[2 * (C::BLOCK / 64)];
 
   const int tid = threadIdx.x;

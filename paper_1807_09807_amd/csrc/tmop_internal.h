@@ -30,7 +30,7 @@ struct LaunchParams {
   double w[MAXQ];
   double Winv[3][3];
   double xi[MAXP];         // GLL node coordinates on [0,1]
-  bool iso;                // W = s I: kernels scale by s_inv instead of multiplying by W^{-1}
+  bool iso;                // W = s I: kernels fold 1/s into the G table instead of multiplying by W^{-1}
   double s_inv;
   double detW, detWinv;
 };

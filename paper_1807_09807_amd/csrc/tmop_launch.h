@@ -15,15 +15,15 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   a.x = lp.x; a.v = lp.v; a.out = lp.out;
   a.elem_node = lp.elem_node; a.list = lp.list; a.part = lp.part; a.scale = lp.scale;
   a.n_node = lp.n_node; a.n_list = lp.n_list;
+  const double gs = ISO ? lp.s_inv : 1.0;   // isotropic target: G carries 1/s
   for (int q = 0; q < Q; ++q) {
     a.w[q] = lp.w[q];
-    for (int i = 0; i < P; ++i) { a.B[q][i] = (R)lp.B[q][i]; a.G[q][i] = (R)lp.G[q][i]; }
+    for (int i = 0; i < P; ++i) { a.B[q][i] = (R)lp.B[q][i]; a.G[q][i] = (R)(lp.G[q][i] * gs); }
   }
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) a.Winv[i][j] = (R)lp.Winv[i][j];
   for (int i = 0; i < P; ++i) a.xi[i] = lp.xi[i];
-  a.s_inv = (R)lp.s_inv;
-  a.s_invd = lp.s_inv;
+  a.jscale = gs;
   a.detW = lp.detW;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) a.Winvd[i][j] = lp.Winv[i][j];

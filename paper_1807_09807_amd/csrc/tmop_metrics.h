@@ -183,9 +183,9 @@ __device__ __forceinline__ void dI2_of(const R T[D][D], R I1, R out[D][D]) {
     }
 }
 
-// P = dmu/dT.
+// P = k dmu/dT (k folds a caller's scalar weight into the coefficients).
 template <int METRIC, typename R>
-__device__ __forceinline__ void mu_first(const R (&T)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim],
+__device__ __forceinline__ void mu_first(const R (&T)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim], R k,
                                          R (&P)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim]) {
   constexpr int D = MetricInfo<METRIC>::dim;
   R C[D][D];
@@ -205,25 +205,27 @@ __device__ __forceinline__ void mu_first(const R (&T)[MetricInfo<METRIC>::dim][M
       for (int j = 0; j < D; ++j) I2 += C[i][j] * C[i][j];
   }
   const Partials<R> f = partials<METRIC, R>(I1, I2, tau);
+  const R k1 = R(2) * k * f.f1, kt = k * f.ft;
   if constexpr (MetricInfo<METRIC>::i2) {
     R dI2[D][D];
     dI2_of<D, R>(T, I1, dI2);
+    const R k2 = k * f.f2;
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
-      for (int j = 0; j < D; ++j) P[i][j] = R(2) * f.f1 * T[i][j] + f.f2 * dI2[i][j] + f.ft * C[i][j];
+      for (int j = 0; j < D; ++j) P[i][j] = k1 * T[i][j] + k2 * dI2[i][j] + kt * C[i][j];
   } else {
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
-      for (int j = 0; j < D; ++j) P[i][j] = R(2) * f.f1 * T[i][j] + f.ft * C[i][j];
+      for (int j = 0; j < D; ++j) P[i][j] = k1 * T[i][j] + kt * C[i][j];
   }
 }
 
-// dP = (d^2 mu / dT^2) : E.
+// dP = k (d^2 mu / dT^2) : E (k folded into the coefficients).
 template <int METRIC, typename R>
 __device__ __forceinline__ void mu_second(const R (&T)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim],
-                                          const R (&E)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim],
+                                          const R (&E)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim], R k,
                                           R (&dP)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim]) {
   constexpr int D = MetricInfo<METRIC>::dim;
   R C[D][D], dC[D][D];
@@ -243,13 +245,14 @@ __device__ __forceinline__ void mu_second(const R (&T)[MetricInfo<METRIC>::dim][
   if constexpr (!MetricInfo<METRIC>::i2) {
     const Partials<R> f = partials<METRIC, R>(I1, R(0), tau);
     const R a1 = R(2) * TE, at = CE;
-    const R sT = R(2) * (f.f1t * at);             // f11 = 0 for these metrics
-    const R sC = f.f1t * a1 + f.ftt * at;
+    const R kE = R(2) * k * f.f1, kd = k * f.ft;
+    const R sT = R(2) * k * (f.f1t * at);         // f11 = 0 for these metrics
+    const R sC = k * (f.f1t * a1 + f.ftt * at);
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int j = 0; j < D; ++j)
-        dP[i][j] = R(2) * f.f1 * E[i][j] + f.ft * dC[i][j] + sT * T[i][j] + sC * C[i][j];
+        dP[i][j] = kE * E[i][j] + kd * dC[i][j] + sT * T[i][j] + sC * C[i][j];
   } else {
     R I2 = 0;
 #pragma unroll
@@ -285,9 +288,10 @@ __device__ __forceinline__ void mu_second(const R (&T)[MetricInfo<METRIC>::dim][
 #pragma unroll
       for (int j = 0; j < D; ++j) a2 += dI2[i][j] * E[i][j];
     const R a1 = R(2) * TE, at = CE;
-    const R sT = R(2) * (f.f12 * a2 + f.f1t * at);     // f11 = 0
-    const R sI = f.f12 * a1 + f.f2t * at;              // f22 = 0
-    const R sC = f.f1t * a1 + f.f2t * a2 + f.ftt * at;
+    const R sT = R(2) * k * (f.f12 * a2 + f.f1t * at);     // f11 = 0
+    const R sI = k * (f.f12 * a1 + f.f2t * at);            // f22 = 0
+    const R sC = k * (f.f1t * a1 + f.f2t * a2 + f.ftt * at);
+    const R kE = R(2) * k * f.f1, k2 = k * f.f2, kd = k * f.ft;
     // E T^t T, T E^t T, T T^t E
     R ET[D][D], TEt[D][D];
 #pragma unroll
@@ -308,7 +312,7 @@ __device__ __forceinline__ void mu_second(const R (&T)[MetricInfo<METRIC>::dim][
 #pragma unroll
         for (int k = 0; k < D; ++k) { teT += TEt[i][k] * T[k][j]; ttE += TTt[i][k] * E[k][j]; }
         const R ddI2 = R(2) * (R(2) * TE * T[i][j] + I1 * E[i][j] - ET[i][j] - teT - ttE);
-        dP[i][j] = R(2) * f.f1 * E[i][j] + f.f2 * ddI2 + f.ft * dC[i][j]
+        dP[i][j] = kE * E[i][j] + k2 * ddI2 + kd * dC[i][j]
                  + sT * T[i][j] + sI * dI2[i][j] + sC * C[i][j];
       }
   }

@@ -24,7 +24,7 @@
 #include <algorithm>
 #include <new>
 
-#include "../../include/tmop.h"
+#include "tmop.h"
 #include "tmop_internal.h"
 
 namespace {
