@@ -143,12 +143,14 @@ void inv3(const double* W, int d, double out[3][3]) {
 
 namespace {
 
-int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* out, const int32_t* list,
-                int64_t n_list, hipStream_t s, int* grid, const double* scale = nullptr) {
+// Element kernels over n_list elements: conn[k * npe ...] (list == nullptr)
+// or conn[list[k] * npe ...].
+int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* out, const int32_t* conn,
+                const int32_t* list, int64_t n_list, hipStream_t s, int* grid, const double* scale = nullptr) {
   LaunchParams lp = c->base;
   lp.scale = scale;
   lp.x = x; lp.v = v; lp.out = out;
-  lp.elem_node = c->d_elem_node;
+  lp.elem_node = conn;
   lp.list = list;
   lp.n_list = (int32_t)n_list;
   lp.n_node = c->n_node;
@@ -210,7 +212,8 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
     const int64_t n = c->color_off[k + 1] - c->color_off[k];
     if (n == 0) continue;
     int grid = 0;
-    const int r = elem_launch(c, op, x, v, out, c->d_colors + c->color_off[k], n, s, &grid, scale);
+    const int r = elem_launch(c, op, x, v, out, c->d_elem_node_col + c->color_off[k] * c->npe, nullptr, n, s,
+                              &grid, scale);
     if (r != TMOP_OK) return r;
   }
   return TMOP_OK;
@@ -219,7 +222,7 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
 // Enqueue F and min det A into c->d_res[0..1].
 int energy_async(tmop_ctx* c, const double* x, hipStream_t s) {
   int grid = 0;
-  const int r = elem_launch(c, OP_ENERGY, x, nullptr, nullptr, nullptr, c->n_elem, s, &grid);
+  const int r = elem_launch(c, OP_ENERGY, x, nullptr, nullptr, c->d_elem_node, nullptr, c->n_elem, s, &grid);
   if (r != TMOP_OK) return r;
   HIP_TRY(finalize_sum_min(c->d_part, grid, c->d_scratch, c->d_res, s));
   return TMOP_OK;
@@ -250,6 +253,7 @@ void free_ctx(tmop_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipFree(c->d_elem_node);
   (void)hipFree(c->d_colors);
+  (void)hipFree(c->d_elem_node_col);
   (void)hipFree(c->d_mask);
   (void)hipFree(c->d_part);
   (void)hipFree(c->d_scratch);
@@ -386,6 +390,7 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
   // colouring and device copies
   std::vector<int32_t> order;
   color_elements(mesh->elem_node, mesh->n_elem, npe, mesh->n_node, order, c->color_off);
+  c->npe = npe;
   const size_t en_bytes = (size_t)mesh->n_elem * npe * sizeof(int32_t);
   int st = TMOP_OK;
   do {
@@ -398,6 +403,13 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
     if (hipMalloc(&c->d_mask, c->n_dof * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipMemcpy(c->d_elem_node, mesh->elem_node, en_bytes, hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
     if (hipMemcpy(c->d_colors, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
+    {   // the connectivity in colour order
+      std::vector<int32_t> en_col((size_t)mesh->n_elem * npe);
+      for (size_t j = 0; j < order.size(); ++j)
+        memcpy(&en_col[j * npe], mesh->elem_node + (size_t)order[j] * npe, npe * sizeof(int32_t));
+      if (hipMalloc(&c->d_elem_node_col, en_bytes) != hipSuccess) { st = TMOP_E_NOMEM; break; }
+      if (hipMemcpy(c->d_elem_node_col, en_col.data(), en_bytes, hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
+    }
     std::vector<double> mask(c->n_dof, 1.0);
     if (mesh->fixed)
       for (int64_t k = 0; k < c->n_dof; ++k)

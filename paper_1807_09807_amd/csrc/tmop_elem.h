@@ -516,7 +516,67 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
 #pragma unroll
         for (int i2 = 0; i2 < P; ++i2) old[c][i2] = a.out[c * a.n_node + node[i2]];
     }
-    __syncthreads();   // U is dead: R and S may overwrite it
+    __syncthreads();   // the forward data is dead
+    if constexpr (OP == OP_HESS) {
+      // all components at once through the lane areas.  Pass 3': lane
+      // (q1, q2) writes into exactly the V slots it read.
+      if (tb < Q) {
+#pragma unroll
+        for (int i0 = 0; i0 < P; ++i0) {
+          R* ar = s + L::area(tb, i0);
+#pragma unroll
+          for (int tt = 0; tt < 3; ++tt)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ar[L::av(tt, c, ta)] = Racc[tt][c][i0];
+        }
+      }
+      __syncthreads();
+      // pass 2': lane (i0 = ta, q2 = tb), own area, sum over q1
+      if (ta < P && tb < Q) {
+        R* ar = s + L::area(tb, ta);
+        R r[3][3][Q];
+#pragma unroll
+        for (int tt = 0; tt < 3; ++tt)
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q1 = 0; q1 < Q; ++q1) r[tt][c][q1] = ar[L::av(tt, c, q1)];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int i1 = 0; i1 < P; ++i1) {
+            R sb = 0, sg = 0;
+#pragma unroll
+            for (int q1 = 0; q1 < Q; ++q1) {
+              sb += a.B[q1][i1] * r[0][c][q1] + a.G[q1][i1] * r[1][c][q1];
+              sg += a.B[q1][i1] * r[2][c][q1];
+            }
+            ar[L::au(0, c, i1)] = sb;
+            ar[L::au(1, c, i1)] = sg;
+          }
+      }
+      __syncthreads();
+      // pass 1': lane (i0 = ta, i1 = tb), sum over q2, then the scatter
+      if (active && p1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          R sb[Q], sg[Q];
+#pragma unroll
+          for (int q2 = 0; q2 < Q; ++q2) {
+            const R* ar = s + L::area(q2, ta);
+            sb[q2] = ar[L::au(0, c, tb)];
+            sg[q2] = ar[L::au(1, c, tb)];
+          }
+#pragma unroll
+          for (int i2 = 0; i2 < P; ++i2) {
+            R v = 0;
+#pragma unroll
+            for (int q2 = 0; q2 < Q; ++q2) v += a.B[q2][i2] * sb[q2] + a.G[q2][i2] * sg[q2];
+            a.out[c * a.n_node + node[i2]] = old[c][i2] + (double)v;
+          }
+        }
+      }
+    } else {
     // the transposed y- and z-contractions, one component at a time
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -563,6 +623,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
           a.out[c * a.n_node + node[i2]] = old[c][i2] + (double)v;
         }
       }
+    }
     }
   }
 }

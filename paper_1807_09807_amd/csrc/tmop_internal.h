@@ -71,6 +71,8 @@ struct tmop_ctx {
   tmop::LaunchParams base{};           // tables and target, pointers filled per call
   int32_t* d_elem_node = nullptr;
   int32_t* d_colors = nullptr;         // element ids grouped by colour
+  int32_t* d_elem_node_col = nullptr;  // connectivity in colour order: colour launches index it directly
+  int npe = 0;                         // nodes per element
   std::vector<int64_t> color_off;      // colour c = d_colors[color_off[c] .. color_off[c+1])
   double* d_mask = nullptr;            // [n_dof], 1 = free DOF
   bool has_fixed = false;
