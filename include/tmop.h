@@ -177,6 +177,15 @@ int tmop_gradient_scaled(tmop_ctx *ctx, const double *x, const double *scale, do
 int tmop_hessian_apply(tmop_ctx *ctx, const double *x, const double *v,
                        double *Hv, void *stream);
 
+/* F and min det A as tmop_energy (eq. 2.4), and g = dF/dx as tmop_gradient
+ * (Section 3.4), in one pass over the elements: the line search of Section
+ * 3.4 needs both at every trial point.  The energy partials ride along in
+ * the gradient's colour launches.  g: device [dim][n_node], caller-owned, not aliasing x.
+ * Returns TMOP_OK, TMOP_W_INVERTED (min det A <= 0; F, g still computed) or
+ * an error.  Syncs the stream. */
+int tmop_energy_gradient(tmop_ctx *ctx, const double *x, double *F, double *min_detA, double *g,
+                         void *stream);
+
 /* Minimizes F over the free DOFs with Newton's method (Section 3.4):
  * direction from truncated CG (Steihaug) on the Hessian restricted to the
  * free DOFs; step lengths 1, s, s^2, ... until det A > 0 at every
@@ -235,14 +244,15 @@ int tmop_mlp_propose(tmop_ctx *ctx, tmop_mlp *mlp, const double *x, double *x_ou
 /* ------------------------------------------------------------------------
  * Per-launch timing of the element kernels (a measurement aid, not part of
  * the method): while enabled, every element-kernel launch of ctx (one per
- * energy evaluation; one per colour for gradient and Hessian action, the
- * zero fill of the output excluded) is bracketed by two HIP events on the
- * caller's stream; tmop_timing_read waits for them and returns the summed
- * device time in milliseconds and the number of launches for one
- * operation: 0 energy, 1 gradient, 2 Hessian action.
+ * energy evaluation; one per colour for gradient, Hessian action and
+ * energy + gradient, the zero fill of the output excluded) is bracketed by
+ * two HIP events on the caller's stream; tmop_timing_read waits for them and
+ * returns the summed device time in milliseconds and the number of launches
+ * for one operation: 0 energy, 1 gradient, 2 Hessian action, 3 energy +
+ * gradient (tmop_energy_gradient).
  * tmop_timing_enable(ctx, on) clears the totals and turns timing on (1) or
  * off (0).  Both return TMOP_OK, TMOP_E_ARG (NULL ctx / out pointers, op
- * outside 0..2) or TMOP_E_HIP. */
+ * outside 0..3) or TMOP_E_HIP. */
 int tmop_timing_enable(tmop_ctx *ctx, int enable);
 int tmop_timing_read(tmop_ctx *ctx, int op, double *ms_total, int64_t *launches);
 

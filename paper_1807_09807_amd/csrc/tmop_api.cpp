@@ -144,9 +144,11 @@ void inv3(const double* W, int d, double out[3][3]) {
 namespace {
 
 // Element kernels over n_list elements: conn[k * npe ...] (list == nullptr)
-// or conn[list[k] * npe ...].
+// or conn[list[k] * npe ...].  Energy partials (OP_ENERGY, OP_EG) go to
+// d_part[part_off + b] (sums) and d_part[n_elem + part_off + b] (minima).
 int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* out, const int32_t* conn,
-                const int32_t* list, int64_t n_list, hipStream_t s, int* grid, const double* scale = nullptr) {
+                const int32_t* list, int64_t n_list, hipStream_t s, int* grid, const double* scale = nullptr,
+                int64_t part_off = 0) {
   LaunchParams lp = c->base;
   lp.scale = scale;
   lp.x = x; lp.v = v; lp.out = out;
@@ -154,7 +156,8 @@ int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* o
   lp.list = list;
   lp.n_list = (int32_t)n_list;
   lp.n_node = c->n_node;
-  lp.part = c->d_part;
+  lp.part = c->d_part + part_off;
+  lp.part_min = c->d_part + c->n_elem + part_off;
   tmop_ctx::TimedLaunch tl{op, nullptr, nullptr};
   if (c->timing) {
     for (hipEvent_t* e : {&tl.a, &tl.b}) {
@@ -204,18 +207,22 @@ int collect_timing(tmop_ctx* c) {
   return st;
 }
 
-// out = sum over colours of the element contributions (gradient / Hv).
+// out = sum over colours of the element contributions (gradient / Hv; with
+// OP_EG also the energy partials of every colour, *nblocks of them).
 int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out, hipStream_t s,
-             const double* scale = nullptr) {
+             const double* scale = nullptr, int64_t* nblocks = nullptr) {
   HIP_TRY(fill(out, 0.0, c->n_dof, s));
+  int64_t off = 0;
   for (size_t k = 0; k + 1 < c->color_off.size(); ++k) {
     const int64_t n = c->color_off[k + 1] - c->color_off[k];
     if (n == 0) continue;
     int grid = 0;
     const int r = elem_launch(c, op, x, v, out, c->d_elem_node_col + c->color_off[k] * c->npe, nullptr, n, s,
-                              &grid, scale);
+                              &grid, scale, off);
     if (r != TMOP_OK) return r;
+    off += grid;
   }
+  if (nblocks) *nblocks = off;
   return TMOP_OK;
 }
 
@@ -224,18 +231,31 @@ int energy_async(tmop_ctx* c, const double* x, hipStream_t s) {
   int grid = 0;
   const int r = elem_launch(c, OP_ENERGY, x, nullptr, nullptr, c->d_elem_node, nullptr, c->n_elem, s, &grid);
   if (r != TMOP_OK) return r;
-  HIP_TRY(finalize_sum_min(c->d_part, grid, c->d_scratch, c->d_res, s));
+  HIP_TRY(finalize_sum_min(c->d_part, grid, (int)c->n_elem, c->d_scratch, c->d_res, s));
+  return TMOP_OK;
+}
+
+// F, min det A into c->d_res[0..1] and g (unmasked), in one pass.
+int energy_gradient_async(tmop_ctx* c, const double* x, double* g, hipStream_t s) {
+  int64_t nb = 0;
+  const int r = assemble(c, OP_EG, x, nullptr, g, s, nullptr, &nb);
+  if (r != TMOP_OK) return r;
+  HIP_TRY(finalize_sum_min(c->d_part, (int)nb, (int)c->n_elem, c->d_scratch, c->d_res, s));
+  return TMOP_OK;
+}
+
+int read_res(tmop_ctx* c, hipStream_t s, double* F, double* mind) {
+  HIP_TRY(hipMemcpyAsync(c->h_res, c->d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *F = c->h_res[0];
+  *mind = c->h_res[1];
   return TMOP_OK;
 }
 
 int energy_sync(tmop_ctx* c, const double* x, hipStream_t s, double* F, double* mind) {
   const int r = energy_async(c, x, s);
   if (r != TMOP_OK) return r;
-  HIP_TRY(hipMemcpyAsync(c->h_res, c->d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  *F = c->h_res[0];
-  *mind = c->h_res[1];
-  return TMOP_OK;
+  return read_res(c, s, F, mind);
 }
 
 int dot_sync(tmop_ctx* c, const double* a, const double* b, hipStream_t s, double* out) {
@@ -430,7 +450,7 @@ int tmop_timing_enable(tmop_ctx* c, int enable) {
   const int st = collect_timing(c);
   (void)hipSetDevice(cur);
   c->timing = enable != 0;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     c->t_ms[k] = 0.0;
     c->t_launches[k] = 0;
   }
@@ -438,7 +458,7 @@ int tmop_timing_enable(tmop_ctx* c, int enable) {
 }
 
 int tmop_timing_read(tmop_ctx* c, int op, double* ms_total, int64_t* launches) {
-  if (!c || op < 0 || op > 2 || !ms_total || !launches) return TMOP_E_ARG;
+  if (!c || op < 0 || op > 3 || !ms_total || !launches) return TMOP_E_ARG;
   const int st = collect_timing(c);
   *ms_total = c->t_ms[op];
   *launches = c->t_launches[op];
@@ -463,6 +483,18 @@ int tmop_gradient(tmop_ctx* c, const double* x, double* g, void* stream) {
 int tmop_gradient_scaled(tmop_ctx* c, const double* x, const double* scale, double* g, void* stream) {
   if (!c || !x || !g || g == x) return TMOP_E_ARG;
   return assemble(c, OP_GRAD, x, nullptr, g, (hipStream_t)stream, scale);
+}
+
+int tmop_energy_gradient(tmop_ctx* c, const double* x, double* F, double* min_detA, double* g, void* stream) {
+  if (!c || !x || !F || !min_detA || !g || g == x) return TMOP_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  int r = energy_gradient_async(c, x, g, s);
+  if (r != TMOP_OK) return r;
+  double f = 0, m = 0;
+  if ((r = read_res(c, s, &f, &m)) != TMOP_OK) return r;
+  *F = f;
+  *min_detA = m;
+  return m > 0.0 ? TMOP_OK : TMOP_W_INVERTED;
 }
 
 int tmop_hessian_apply(tmop_ctx* c, const double* x, const double* v, double* Hv, void* stream) {
@@ -502,14 +534,14 @@ int tmop_newton_solve(tmop_ctx* c, double* x, const tmop_newton_opts* opts_in, t
   memset(&rep, 0, sizeof(rep));
   int st;
   double F, mind;
-  if ((st = energy_sync(c, x, s, &F, &mind)) != TMOP_OK) return st;
+  if ((st = energy_gradient_async(c, x, g, s)) != TMOP_OK) return st;
+  if ((st = read_res(c, s, &F, &mind)) != TMOP_OK) return st;
   rep.F0 = rep.F = F;
   rep.min_detA = mind;
   if (!(mind > 0.0)) {
     if (rep_out) *rep_out = rep;
     return TMOP_W_INVERTED;
   }
-  if ((st = assemble(c, OP_GRAD, x, nullptr, g, s)) != TMOP_OK) return st;
   HIP_TRY(mask_mul(c->d_mask, g, N, s));
   double gg;
   if ((st = dot_sync(c, g, g, s, &gg)) != TMOP_OK) return st;
@@ -560,9 +592,11 @@ int tmop_newton_solve(tmop_ctx* c, double* x, const tmop_newton_opts* opts_in, t
     double alpha = 1.0;
     for (int k = 0; k < o.ls_max; ++k) {
       HIP_TRY(waxpy(x, alpha, dv, xt, N, s));
-      if ((st = energy_sync(c, xt, s, &Ft, &mindt)) != TMOP_OK) return st;
+      // F, det A and g at the trial point in one pass (g is used only when
+      // the first two tests pass)
+      if ((st = energy_gradient_async(c, xt, gt, s)) != TMOP_OK) return st;
+      if ((st = read_res(c, s, &Ft, &mindt)) != TMOP_OK) return st;
       if (mindt > 0.0 && Ft < o.f_growth * F) {
-        if ((st = assemble(c, OP_GRAD, xt, nullptr, gt, s)) != TMOP_OK) return st;
         HIP_TRY(mask_mul(c->d_mask, gt, N, s));
         if ((st = dot_sync(c, gt, gt, s, &ggt)) != TMOP_OK) return st;
         if (sqrt(ggt) < o.g_growth * gn) { accepted = true; break; }

@@ -76,14 +76,15 @@ __global__ void __launch_bounds__(RED_THREADS) k_dot_part(const double* __restri
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// Stage 2: one block folds n partial sums (and, optionally, n minima).
-__global__ void __launch_bounds__(RED_THREADS) k_finalize(const double* __restrict__ part, int n, int with_min,
-                                                          double* __restrict__ res) {
+// Stage 2: one block folds n partial sums part[0, n) (and, optionally, n
+// minima part[moff, moff + n)).
+__global__ void __launch_bounds__(RED_THREADS) k_finalize(const double* __restrict__ part, int n, int moff,
+                                                          int with_min, double* __restrict__ res) {
   __shared__ double red[2][RED_THREADS / 64];
   double s = 0.0, m = __builtin_huge_val();
   for (int i = threadIdx.x; i < n; i += RED_THREADS) {
     s += part[i];
-    if (with_min) m = fmin(m, part[n + i]);
+    if (with_min) m = fmin(m, part[moff + i]);
   }
   const double ts = block_sum(s, red[0]);
   const double tm = block_min(m, red[1]);
@@ -93,17 +94,17 @@ __global__ void __launch_bounds__(RED_THREADS) k_finalize(const double* __restri
   }
 }
 
-// Stage 1 of the energy fold: block b folds part[b*chunk, (b+1)*chunk) of
-// the n sums and of the n minima into out[b] and out[FIN_BLOCKS + b].
-__global__ void __launch_bounds__(RED_THREADS) k_fold_chunks(const double* __restrict__ part, int n, int chunk,
-                                                             double* __restrict__ out) {
+// Stage 1 of the energy fold: block b folds chunk b of the n sums part[0, n)
+// and of the n minima part[moff, moff + n) into out[b] and out[FIN_BLOCKS + b].
+__global__ void __launch_bounds__(RED_THREADS) k_fold_chunks(const double* __restrict__ part, int n, int moff,
+                                                             int chunk, double* __restrict__ out) {
   __shared__ double red[2][RED_THREADS / 64];
   const int lo = blockIdx.x * chunk;
   const int hi = min(n, lo + chunk);
   double s = 0.0, m = __builtin_huge_val();
   for (int i = lo + threadIdx.x; i < hi; i += RED_THREADS) {
     s += part[i];
-    m = fmin(m, part[n + i]);
+    m = fmin(m, part[moff + i]);
   }
   const double ts = block_sum(s, red[0]);
   const double tm = block_min(m, red[1]);
@@ -120,21 +121,21 @@ hipError_t fill(double* y, double v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t finalize_sum_min(const double* part, int n, double* scratch, double* res, hipStream_t s) {
+hipError_t finalize_sum_min(const double* part, int n, int moff, double* scratch, double* res, hipStream_t s) {
   if (n <= 4 * RED_THREADS) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, part, n, 1, res);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, part, n, moff, 1, res);
   } else {
     // stage 1: FIN_BLOCKS blocks fold contiguous chunks; stage 2 folds those
     const int chunk = (n + FIN_BLOCKS - 1) / FIN_BLOCKS;
-    hipLaunchKernelGGL(k_fold_chunks, dim3(FIN_BLOCKS), dim3(RED_THREADS), 0, s, part, n, chunk, scratch);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch, FIN_BLOCKS, 1, res);
+    hipLaunchKernelGGL(k_fold_chunks, dim3(FIN_BLOCKS), dim3(RED_THREADS), 0, s, part, n, moff, chunk, scratch);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch, FIN_BLOCKS, FIN_BLOCKS, 1, res);
   }
   return hipGetLastError();
 }
 
 hipError_t dot(const double* x, const double* y, int64_t n, double* scratch, double* res, hipStream_t s) {
   hipLaunchKernelGGL(k_dot_part, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, x, y, n, scratch);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch, RED_BLOCKS, 0, res);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch, RED_BLOCKS, 0, 0, res);
   return hipGetLastError();
 }
 

@@ -1,9 +1,11 @@
 // Element kernels of the TMOP hot path on gfx950.
 //
-// One kernel template covers the three element operations of the method:
+// One kernel template covers the element operations of the method:
 //   OP_ENERGY  sum_q w_q det W mu(T_q) and min det A    (eq. 2.4, Section 3.4)
 //   OP_GRAD    dF/dx scattered to the nodes              (Section 3.4)
 //   OP_HESS    (d^2F/dx^2) v scattered to the nodes      (Section 3.4)
+//   OP_EG      OP_ENERGY and OP_GRAD in one pass (the line search needs both
+//              at every trial point)
 //
 // The Jacobian A = sum_i x_i (grad w_i)^T (eq. 2.2) of a tensor-product
 // element is computed by sum factorization: one 1D contraction per
@@ -51,7 +53,8 @@ struct ElemArgs {
   double* __restrict__ out;              // [dim][n_node], OP_GRAD / OP_HESS
   const int32_t* __restrict__ elem_node; // [n_elem][P^dim]
   const int32_t* __restrict__ list;      // elements to process (nullptr: 0..n_list-1)
-  double* __restrict__ part;             // OP_ENERGY: [2 * gridDim.x] (sums, then mins)
+  double* __restrict__ part;             // OP_ENERGY, OP_EG: [gridDim.x] block sums of the energy
+  double* __restrict__ part_min;         // OP_ENERGY, OP_EG: [gridDim.x] block minima of det A
   const double* __restrict__ scale;      // OP_GRAD: optional device scalar multiplying g (nullptr = 1)
   int64_t n_node;
   int32_t n_list;
@@ -197,7 +200,7 @@ __device__ __forceinline__ void stress(const R (&M)[D][D], const R (&Wi)[3][3], 
 template <int D, int METRIC, typename R, int OP, bool ISO, int P, int Q>
 __device__ __forceinline__ void point_op(const ElemArgs<P, Q, R>& a, const R (&A)[D][D], const R (&dA)[D][D],
                                          double wdet, double& acc, double& mind, R (&Y)[D][D]) {
-  if constexpr (OP == OP_ENERGY) {
+  if constexpr (OP == OP_ENERGY || OP == OP_EG) {
     // The energy value, det A and their sums are FP64 in both paths: the
     // FP32 path promotes its contracted A (mu's "... - 1" would otherwise
     // leave an FP32 rounding floor under F).
@@ -218,11 +221,12 @@ __device__ __forceinline__ void point_op(const ElemArgs<P, Q, R>& a, const R (&A
     }
     acc += wdet * mu_value<METRIC, double>(Td, tau);
     mind = fmin(mind, detA);
-  } else {
+  }
+  if constexpr (OP != OP_ENERGY) {
     // the weight w det W is folded into the metric's scalar coefficients
     R T[D][D];
     right_mul<D, R, ISO>(A, a.Winv, T);
-    if constexpr (OP == OP_GRAD) {
+    if constexpr (OP == OP_GRAD || OP == OP_EG) {
       R Pm[D][D];
       mu_first<METRIC, R>(T, (R)wdet, Pm);
       stress<D, R, ISO>(Pm, a.Winv, Y);
@@ -504,10 +508,11 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
     }
   }
 
-  if constexpr (OP == OP_ENERGY) {
+  if constexpr (OP == OP_ENERGY || OP == OP_EG) {
     if (!active) { acc = 0.0; mind = __builtin_huge_val(); }
-    block_reduce_sum_min<C::BLOCK>(acc, mind, red, a.part + blk, a.part + gridDim.x + blk);
-  } else {
+    block_reduce_sum_min<C::BLOCK>(acc, mind, red, a.part + blk, a.part_min + blk);
+  }
+  if constexpr (OP != OP_ENERGY) {
     // the scatter's old values, loaded now so the passes below hide latency
     double old[3][P];
     if (active && p1) {
@@ -764,10 +769,11 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
     }
   }
 
-  if constexpr (OP == OP_ENERGY) {
+  if constexpr (OP == OP_ENERGY || OP == OP_EG) {
     if (!active) { acc = 0.0; mind = __builtin_huge_val(); }
-    block_reduce_sum_min<C::BLOCK>(acc, mind, red, a.part + blk, a.part + gridDim.x + blk);
-  } else {
+    block_reduce_sum_min<C::BLOCK>(acc, mind, red, a.part + blk, a.part_min + blk);
+  }
+  if constexpr (OP != OP_ENERGY) {
     double old[2][P];
     if (active && p1) {
 #pragma unroll

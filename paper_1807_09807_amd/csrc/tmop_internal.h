@@ -8,8 +8,9 @@
 
 namespace tmop {
 
-// Element operations: F and min det A (eq. 2.4), dF/dx, (d^2F/dx^2) v.
-enum { OP_ENERGY = 0, OP_GRAD = 1, OP_HESS = 2 };
+// Element operations: F and min det A (eq. 2.4), dF/dx, (d^2F/dx^2) v, and
+// F, min det A and dF/dx in one pass.
+enum { OP_ENERGY = 0, OP_GRAD = 1, OP_HESS = 2, OP_EG = 3 };
 
 constexpr int MAXP = 5;   // nodes per direction (order p <= 4)
 constexpr int MAXQ = 6;   // quadrature points per direction
@@ -23,7 +24,8 @@ struct LaunchParams {
   const int32_t* list;
   int32_t n_list;
   int64_t n_node;
-  double* part;            // energy partials, >= 2 * grid doubles
+  double* part;            // energy partials: sums (one per block)
+  double* part_min;        // energy partials: minima of det A
   const double* scale;     // gradient: optional device scalar factor
   double B[MAXQ][MAXP];
   double G[MAXQ][MAXP];
@@ -35,10 +37,12 @@ struct LaunchParams {
   double detW, detWinv;
 };
 
-// Launch one element operation (OP_ENERGY / OP_GRAD / OP_HESS) on the
-// n_list elements of lp.list.  Returns 0, -1 if no kernel exists for
-// (p, Q, metric), or -2 on a launch error.  *grid receives the number of
-// workgroups (the number of energy partials written).
+// Launch one element operation (OP_ENERGY / OP_GRAD / OP_HESS / OP_EG) on
+// n_list elements: element k has the nodes lp.elem_node[e * npe ...] with
+// e = lp.list[k] (or e = k without a list).  Returns 0, -1 if no kernel
+// exists for (p, Q, metric), or -2 on a launch error.  *grid receives the
+// number of workgroups, i.e. the number of energy partials written to
+// lp.part[0, grid) and lp.part_min[0, grid) (OP_ENERGY, OP_EG).
 int launch_elem_2d_f64(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
 int launch_elem_2d_f32(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
 int launch_elem_3d_f64(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
@@ -50,9 +54,10 @@ bool elem_supported(int dim, int p, int Q);
 constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;
 hipError_t fill(double* y, double v, int64_t n, hipStream_t s);
-// res[0] = sum(part[0..n)), res[1] = min(part[n..2n))   (scratch: >= 2*FIN_BLOCKS doubles)
 constexpr int FIN_BLOCKS = 256;
-hipError_t finalize_sum_min(const double* part, int n, double* scratch, double* res, hipStream_t s);
+// res[0] = sum of part[0, n), res[1] = min of part[moff, moff + n)
+// (scratch: >= 2 * FIN_BLOCKS doubles).
+hipError_t finalize_sum_min(const double* part, int n, int moff, double* scratch, double* res, hipStream_t s);
 // res[0] = x . y   (scratch: >= RED_BLOCKS doubles)
 hipError_t dot(const double* x, const double* y, int64_t n, double* scratch, double* res, hipStream_t s);
 hipError_t axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);          // y += a x
@@ -86,6 +91,6 @@ struct tmop_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev_free;
   std::vector<TimedLaunch> ev_pending;
-  double t_ms[3] = {0.0, 0.0, 0.0};
-  int64_t t_launches[3] = {0, 0, 0};
+  double t_ms[4] = {0.0, 0.0, 0.0, 0.0};      // per op: energy, gradient, Hessian action, energy+gradient
+  int64_t t_launches[4] = {0, 0, 0, 0};
 };

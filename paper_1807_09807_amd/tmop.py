@@ -2,7 +2,7 @@
 step of the computation runs in the library's HIP kernels.
 
 The functions carry the names of the C ABI (include/tmop.h):
-tmop_setup, tmop_energy, tmop_gradient, tmop_hessian_apply,
+tmop_setup, tmop_energy, tmop_gradient, tmop_energy_gradient, tmop_hessian_apply,
 tmop_newton_solve, tmop_destroy.  Device arrays are torch tensors of shape
 (dim, n_node), float64, contiguous, on a HIP device; the work is enqueued
 on torch's current stream of that device.
@@ -28,7 +28,7 @@ TMOP_TGT_CONST = 0
 
 EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_gradient_scaled", "tmop_hessian_apply",
            "tmop_newton_solve", "tmop_destroy", "tmop_strerror", "tmop_newton_default_opts",
-           "tmop_timing_enable", "tmop_timing_read")
+           "tmop_timing_enable", "tmop_timing_read", "tmop_energy_gradient")
 
 
 class TMOPError(RuntimeError):
@@ -98,6 +98,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tmop_strerror.restype = ctypes.c_char_p
     lib.tmop_newton_default_opts.argtypes = [ctypes.POINTER(tmop_newton_opts)]
     lib.tmop_newton_default_opts.restype = None
+    lib.tmop_energy_gradient.argtypes = [P, P, ctypes.POINTER(dbl), ctypes.POINTER(dbl), P, P]
+    lib.tmop_energy_gradient.restype = ctypes.c_int
     lib.tmop_timing_enable.argtypes = [P, ctypes.c_int]
     lib.tmop_timing_enable.restype = ctypes.c_int
     lib.tmop_timing_read.argtypes = [P, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
@@ -173,6 +175,19 @@ class Context:
             raise TMOPError(st, "tmop_energy")
         return F.value, md.value, st
 
+    def energy_gradient(self, x, out=None):
+        """(F, min det A, status, g) from one pass over the elements."""
+        import torch
+        _check_field(x, self.dim, self.n_node, "x")
+        out = torch.empty_like(x) if out is None else out
+        _check_field(out, self.dim, self.n_node, "out")
+        F, md = ctypes.c_double(), ctypes.c_double()
+        st = self._lib.tmop_energy_gradient(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.byref(F), ctypes.byref(md),
+                                            ctypes.c_void_p(out.data_ptr()), _stream(x))
+        if st < 0:
+            raise TMOPError(st, "tmop_energy_gradient")
+        return F.value, md.value, st, out
+
     def gradient(self, x, out=None):
         import torch
         _check_field(x, self.dim, self.n_node, "x")
@@ -220,8 +235,8 @@ class Context:
 
     def timing_read(self, op: int):
         """(summed device ms, launch count) of the element kernels of one
-        operation (0 energy, 1 gradient, 2 Hessian action) since the last
-        timing_enable."""
+        operation (0 energy, 1 gradient, 2 Hessian action, 3 energy +
+        gradient) since the last timing_enable."""
         ms, n = ctypes.c_double(), ctypes.c_int64()
         st = self._lib.tmop_timing_read(self._h, int(op), ctypes.byref(ms), ctypes.byref(n))
         if st < 0:
@@ -271,6 +286,10 @@ def tmop_energy(ctx: Context, x):
 
 def tmop_gradient(ctx: Context, x, g=None):
     return ctx.gradient(x, g)
+
+
+def tmop_energy_gradient(ctx: Context, x, g=None):
+    return ctx.energy_gradient(x, g)
 
 
 def tmop_hessian_apply(ctx: Context, x, v, Hv=None):

@@ -87,6 +87,7 @@ def test_null_arguments():
     assert lib.tmop_hessian_apply(None, None, None, None, None) == T.TMOP_E_ARG
     assert lib.tmop_newton_solve(None, None, None, None, None) == T.TMOP_E_ARG
     lib.tmop_destroy(None)
+    assert lib.tmop_energy_gradient(None, None, None, None, None, None) == T.TMOP_E_ARG
     assert lib.tmop_timing_enable(None, 1) == T.TMOP_E_ARG
     ms, n = ctypes.c_double(), ctypes.c_int64()
     assert lib.tmop_timing_read(None, 2, ctypes.byref(ms), ctypes.byref(n)) == T.TMOP_E_ARG

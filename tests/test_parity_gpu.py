@@ -59,6 +59,25 @@ def test_hessian_apply(setup, precision):
     assert err <= (FP64_TOL if precision == 0 else ref["mixed_tol"])
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_energy_gradient_one_pass(setup, precision):
+    """The fused pass gives the oracle's F, min det A and g, and the separate
+    calls' g bit for bit (same kernel arithmetic); F differs from the energy
+    call only in its summation order."""
+    case, mesh, W, v, ref = setup
+    ctx = context(case, mesh, W, precision)
+    x = to_dev(mesh.x)
+    F, md, st, g = ctx.energy_gradient(x)
+    tol = FP64_TOL if precision == 0 else ref["mixed_tol"]
+    assert st == 0
+    assert abs(F - ref["F"]) <= tol * abs(ref["F"])
+    assert abs(md - ref["mindet"]) <= (1e-12 if precision == 0 else ref["mixed_tol"]) * abs(ref["mindet"])
+    assert rel_max_err(g.cpu().numpy(), ref["g"]) <= tol
+    F1, md1, _ = ctx.energy(x)
+    assert abs(F - F1) <= 1e-13 * abs(F1) and md == md1
+    assert torch.equal(g, ctx.gradient(x))
+
+
 def test_bitwise_deterministic(setup):
     case, mesh, W, v, ref = setup
     ctx = context(case, mesh, W, 0)
