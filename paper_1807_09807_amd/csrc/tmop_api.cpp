@@ -148,8 +148,9 @@ namespace {
 // d_part[part_off + b] (sums) and d_part[n_elem + part_off + b] (minima).
 int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* out, const int32_t* conn,
                 const int32_t* list, int64_t n_list, hipStream_t s, int* grid, const double* scale = nullptr,
-                int64_t part_off = 0) {
+                int64_t part_off = 0, const uint32_t* first = nullptr) {
   LaunchParams lp = c->base;
+  lp.first = first;
   lp.scale = scale;
   lp.x = x; lp.v = v; lp.out = out;
   lp.elem_node = conn;
@@ -211,14 +212,16 @@ int collect_timing(tmop_ctx* c) {
 // OP_EG also the energy partials of every colour, *nblocks of them).
 int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out, hipStream_t s,
              const double* scale = nullptr, int64_t* nblocks = nullptr) {
-  HIP_TRY(fill(out, 0.0, c->n_dof, s));
+  // the first touch of every node writes instead of adding, so out needs no
+  // zero fill unless some node belongs to no element
+  if (!c->all_touched) HIP_TRY(fill(out, 0.0, c->n_dof, s));
   int64_t off = 0;
   for (size_t k = 0; k + 1 < c->color_off.size(); ++k) {
     const int64_t n = c->color_off[k + 1] - c->color_off[k];
     if (n == 0) continue;
     int grid = 0;
     const int r = elem_launch(c, op, x, v, out, c->d_elem_node_col + c->color_off[k] * c->npe, nullptr, n, s,
-                              &grid, scale, off);
+                              &grid, scale, off, c->d_first + c->color_off[k] * c->first_words);
     if (r != TMOP_OK) return r;
     off += grid;
   }
@@ -274,6 +277,7 @@ void free_ctx(tmop_ctx* c) {
   (void)hipFree(c->d_elem_node);
   (void)hipFree(c->d_colors);
   (void)hipFree(c->d_elem_node_col);
+  (void)hipFree(c->d_first);
   (void)hipFree(c->d_mask);
   (void)hipFree(c->d_part);
   (void)hipFree(c->d_scratch);
@@ -429,6 +433,23 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
         memcpy(&en_col[j * npe], mesh->elem_node + (size_t)order[j] * npe, npe * sizeof(int32_t));
       if (hipMalloc(&c->d_elem_node_col, en_bytes) != hipSuccess) { st = TMOP_E_NOMEM; break; }
       if (hipMemcpy(c->d_elem_node_col, en_col.data(), en_bytes, hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
+      // first touches in colour order (colours run in order, their elements
+      // share no node), and whether every node is touched at all
+      c->first_words = (npe + 31) / 32;
+      std::vector<uint32_t> first((size_t)mesh->n_elem * c->first_words, 0u);
+      std::vector<uint8_t> seen(mesh->n_node, 0);
+      for (int64_t j = 0; j < mesh->n_elem; ++j)
+        for (int l = 0; l < npe; ++l) {
+          const int32_t I = en_col[(size_t)j * npe + l];
+          if (!seen[I]) {
+            seen[I] = 1;
+            first[(size_t)j * c->first_words + l / 32] |= 1u << (l % 32);
+          }
+        }
+      c->all_touched = std::all_of(seen.begin(), seen.end(), [](uint8_t b) { return b != 0; });
+      const size_t fb = first.size() * sizeof(uint32_t);
+      if (hipMalloc(&c->d_first, fb) != hipSuccess) { st = TMOP_E_NOMEM; break; }
+      if (hipMemcpy(c->d_first, first.data(), fb, hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
     }
     std::vector<double> mask(c->n_dof, 1.0);
     if (mesh->fixed)

@@ -53,6 +53,9 @@ struct ElemArgs {
   double* __restrict__ out;              // [dim][n_node], OP_GRAD / OP_HESS
   const int32_t* __restrict__ elem_node; // [n_elem][P^dim]
   const int32_t* __restrict__ list;      // elements to process (nullptr: 0..n_list-1)
+  const uint32_t* __restrict__ first;    // scatter: bit l of word k * ((P^dim + 31) / 32) + l / 32 set when
+                                         // element k is the first to touch its local node l (its old value
+                                         // is 0, not read); nullptr: read every old value
   double* __restrict__ part;             // OP_ENERGY, OP_EG: [gridDim.x] block sums of the energy
   double* __restrict__ part_min;         // OP_ENERGY, OP_EG: [gridDim.x] block minima of det A
   const double* __restrict__ scale;      // OP_GRAD: optional device scalar multiplying g (nullptr = 1)
@@ -135,6 +138,13 @@ struct Cfg {
 __device__ __forceinline__ int xcd_block(int b, int nb) {
   const int xcd = b & 7, q = nb >> 3, r = nb & 7;
   return xcd * q + (xcd < r ? xcd : r) + (b >> 3);
+}
+
+// Whether element k (of this launch) is the first to touch its local node l.
+template <int NPE>
+__device__ __forceinline__ bool first_touch(const uint32_t* __restrict__ first, int k, int l) {
+  constexpr int NW = (NPE + 31) / 32;
+  return first && ((first[(int64_t)k * NW + l / 32] >> (l % 32)) & 1u);
 }
 
 // Deterministic block reduction of (sum, min) in a fixed tree order.
@@ -517,9 +527,11 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
     double old[3][P];
     if (active && p1) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+      for (int i2 = 0; i2 < P; ++i2) {
+        const bool fresh = first_touch<NPE>(a.first, kk, ta + P * tb + P * P * i2);
 #pragma unroll
-        for (int i2 = 0; i2 < P; ++i2) old[c][i2] = a.out[c * a.n_node + node[i2]];
+        for (int c = 0; c < 3; ++c) old[c][i2] = fresh ? 0.0 : a.out[c * a.n_node + node[i2]];
+      }
     }
     __syncthreads();   // the forward data is dead
     if constexpr (OP == OP_HESS) {
@@ -777,9 +789,11 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
     double old[2][P];
     if (active && p1) {
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
+      for (int i1 = 0; i1 < P; ++i1) {
+        const bool fresh = first_touch<NPE>(a.first, kk, ta + P * i1);
 #pragma unroll
-        for (int i1 = 0; i1 < P; ++i1) old[c][i1] = a.out[c * a.n_node + node[i1]];
+        for (int c = 0; c < 2; ++c) old[c][i1] = fresh ? 0.0 : a.out[c * a.n_node + node[i1]];
+      }
     }
     // pass 2': lane q1 writes its own U slots, no barrier needed first
     if (ta < Q) {

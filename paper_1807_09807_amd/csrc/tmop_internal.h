@@ -22,6 +22,7 @@ struct LaunchParams {
   double* out;
   const int32_t* elem_node;
   const int32_t* list;
+  const uint32_t* first;   // first-touch bits of the scatter (see ElemArgs), or nullptr
   int32_t n_list;
   int64_t n_node;
   double* part;            // energy partials: sums (one per block)
@@ -77,6 +78,9 @@ struct tmop_ctx {
   int32_t* d_elem_node = nullptr;
   int32_t* d_colors = nullptr;         // element ids grouped by colour
   int32_t* d_elem_node_col = nullptr;  // connectivity in colour order: colour launches index it directly
+  uint32_t* d_first = nullptr;         // colour order: bit l of element j's words = first touch of local node l
+  int first_words = 0;                 // words per element
+  bool all_touched = false;            // every node belongs to an element: the colour launches initialize out
   int npe = 0;                         // nodes per element
   std::vector<int64_t> color_off;      // colour c = d_colors[color_off[c] .. color_off[c+1])
   double* d_mask = nullptr;            // [n_dof], 1 = free DOF

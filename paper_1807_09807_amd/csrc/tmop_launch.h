@@ -13,7 +13,7 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   using C = Cfg<DIM, P, Q, R>;
   ElemArgs<P, Q, R> a;
   a.x = lp.x; a.v = lp.v; a.out = lp.out;
-  a.elem_node = lp.elem_node; a.list = lp.list; a.part = lp.part; a.part_min = lp.part_min; a.scale = lp.scale;
+  a.elem_node = lp.elem_node; a.list = lp.list; a.first = lp.first; a.part = lp.part; a.part_min = lp.part_min; a.scale = lp.scale;
   a.n_node = lp.n_node; a.n_list = lp.n_list;
   const double gs = ISO ? lp.s_inv : 1.0;   // isotropic target: G carries 1/s
   for (int q = 0; q < Q; ++q) {
