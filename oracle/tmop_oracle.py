@@ -19,7 +19,8 @@ names the passage it follows.  The oracle computes the plain definitions:
 * the gradient (Section 3.4) and the Hessian action are assembled
   element by element and scattered with numpy.add.at;
 * Newton's method with the positivity / 1.2-growth line search follows
-  Section 3.4, with truncated CG (Steihaug) as the inner solver.
+  Section 3.4, with truncated CG (Steihaug) or MINRES (the inner solver of
+  Section 5) on the masked Hessian, optionally Jacobi preconditioned.
 
 Readings where the paper is silent: reference element [0,1]^d; nodal basis =
 Lagrange polynomials at the Gauss-Lobatto-Legendre points; Gauss-Legendre
@@ -438,6 +439,31 @@ class Problem:
             self._assemble(Y, e0, e1, Hv)
         return Hv
 
+    def hessian_diagonal(self, x):
+        """The diagonal of d^2 F_V / dx^2 (Section 3.4), shape (d, n_node):
+        entry (c, I) is the Hessian action on the unit vector of DOF (c, I),
+        read at (c, I).  Element E's share for its local node i is
+        sum_q w_q det W  dT : mu''(T)[dT]  with dT = e_c (grad w_i)^T W^{-1}
+        (the unit vector's dA, row c = grad w_i, times W^{-1})."""
+        Dg = np.zeros(x.shape, dtype=np.result_type(x, np.float64))
+        d = self.dim
+        for e0, e1 in self._chunks():
+            A = self._jac(x, e0, e1)
+            Wi, dW = self._targets(e0, e1)
+            T = _mm(A, Wi)
+            ne = e1 - e0
+            share = np.zeros((d, ne, self.D.shape[1]), dtype=Dg.dtype)
+            for i in range(self.D.shape[1]):
+                for c in range(d):
+                    dA = np.zeros((ne, self.nq, d, d), dtype=Dg.dtype)
+                    dA[:, :, c, :] = self.D[None, :, i, :]
+                    dT = _mm(dA, Wi)
+                    q = _ddot(dT, d2mu(self.metric, T, dT))
+                    share[c, :, i] = np.sum(self.wq[None, :] * dW * q, axis=1)
+            for c in range(d):
+                np.add.at(Dg[c], self.elem_node[e0:e1], share[c])
+        return Dg
+
 
 # ---------------------------------------------------------------------------
 # Section 3.4: Newton's method with the scaled update and line search
@@ -455,6 +481,8 @@ class NewtonOptions:
     g_growth: float = 1.2        # |g(x+)| < 1.2 |g(x)|
     ftarget: float = -math.inf   # also stop once F <= ftarget
     cg_forcing: int = 0          # 1: inner tolerance max(cg_rtol, min(0.5, sqrt(|g|/|g0|)))
+    inner: str = "cg"            # "cg": truncated CG; "minres": MINRES, the solver of Section 5
+    precond: str = "none"        # "none" or "jacobi": M = |diag H| on the free DOFs
 
 
 STOP_CONVERGED, STOP_MAXIT, STOP_LSFAIL, STOP_INVERTED = 0, 1, 2, 3
@@ -474,36 +502,111 @@ class NewtonReport:
     history: list = field(default_factory=list)   # per iteration: (F, |g|, alpha, cg_iters, neg_curv)
 
 
-def truncated_cg(apply_H, g, rtol, max_it):
-    """Steihaug's truncated conjugate gradients for H d = -g from d = 0: on
-    non-positive curvature return -g at the first step, else the current
-    iterate.  Returns (d, iterations, negative-curvature flag)."""
+def truncated_cg(apply_H, g, rtol, max_it, minv=None):
+    """Steihaug's truncated conjugate gradients for H d = -g from d = 0, with
+    an optional diagonal preconditioner M (minv = 1 / diag M): on
+    non-positive curvature return the preconditioned steepest-descent
+    direction -M^{-1} g (-g without M) at the first step, else the current
+    iterate; stop once the residual |r|_2 <= rtol |g|_2.  Returns
+    (d, iterations, negative-curvature flag)."""
     d = np.zeros_like(g)
     r = -g
-    p = r.copy()
-    rr = float(np.dot(r, r))
+    z = r if minv is None else minv * r
+    p = z.copy()
+    rz = float(np.dot(r, z))
     gnorm = math.sqrt(float(np.dot(g, g)))
     for j in range(max_it):
         Hp = apply_H(p)
         pHp = float(np.dot(p, Hp))
         if pHp <= 0.0:
-            return (-g if j == 0 else d), j + 1, True
-        alpha = rr / pHp
+            return (p if j == 0 else d), j + 1, True
+        alpha = rz / pHp
         d = d + alpha * p
         r = r - alpha * Hp
-        rr_new = float(np.dot(r, r))
-        if math.sqrt(rr_new) <= rtol * gnorm:
+        if math.sqrt(float(np.dot(r, r))) <= rtol * gnorm:
             return d, j + 1, False
-        p = r + (rr_new / rr) * p
-        rr = rr_new
+        z = r if minv is None else minv * r
+        rz_new = float(np.dot(r, z))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
     return d, max_it, False
+
+
+def minres(apply_H, b, rtol, max_it, minv=None):
+    """MINRES (Paige and Saunders, 1975) for the symmetric, possibly
+    indefinite system H d = b from d = 0, with an optional symmetric positive
+    definite diagonal preconditioner M (minv = 1 / diag M).
+
+    Preconditioned Lanczos builds the tridiagonal T_k (diagonal alpha_k,
+    off-diagonal beta_{k+1}) of H in the M^{-1} inner product; Givens
+    rotations keep its QR factorization up to date, so the iterate
+    minimizing the M^{-1}-norm of the residual over the Krylov space is
+    reached by a three-term update of the directions w_k, and |phibar_k| is
+    that residual norm.  Stops when |phibar_k| <= rtol beta_1 (the residual
+    relative to the right-hand side, both in the M^{-1} norm: the 2-norm
+    without M).  Returns (d, iterations)."""
+    prec = (lambda u: u) if minv is None else (lambda u: minv * u)
+    d = np.zeros_like(b)
+    r_prev = np.zeros_like(b)            # r_{k-1}
+    r_cur = b.copy()                     # r_k
+    y = prec(r_cur)
+    beta = math.sqrt(float(np.dot(r_cur, y)))
+    beta1 = beta
+    if beta1 == 0.0:
+        return d, 0
+    beta_prev = 0.0
+    c, s = -1.0, 0.0                     # rotation of the previous step
+    dbar, eps = 0.0, 0.0                 # entries of the next column, pre-rotated
+    phibar = beta1
+    w_prev = np.zeros_like(b)            # w_{k-2}
+    w_cur = np.zeros_like(b)             # w_{k-1}
+    for k in range(1, max_it + 1):
+        v = y / beta                     # Lanczos vector v_k
+        Hv = apply_H(v)
+        alpha = float(np.dot(v, Hv))
+        r_next = Hv - (alpha / beta) * r_cur
+        if k > 1:
+            r_next = r_next - (beta / beta_prev) * r_prev
+        y = prec(r_next)
+        beta_next = math.sqrt(float(np.dot(r_next, y)))
+        # previous rotation on column k (entries dbar at row k-1, alpha at
+        # row k) and on column k+1 (beta_next at row k)
+        eps_k = eps
+        delta = c * dbar + s * alpha
+        gbar = s * dbar - c * alpha
+        eps = s * beta_next
+        dbar = -c * beta_next
+        # new rotation annihilating beta_next under gbar
+        gamma = math.hypot(gbar, beta_next)
+        if gamma == 0.0:
+            gamma = np.finfo(np.float64).tiny
+        c, s = gbar / gamma, beta_next / gamma
+        phi = c * phibar
+        phibar = s * phibar
+        w_new = (v - eps_k * w_prev - delta * w_cur) / gamma
+        d = d + phi * w_new
+        w_prev, w_cur = w_cur, w_new
+        r_prev, r_cur = r_cur, r_next
+        beta_prev, beta = beta, beta_next
+        if abs(phibar) <= rtol * beta1 or beta == 0.0:
+            return d, k
+    return d, max_it
+
+
+def jacobi_inverse(diag, m):
+    """1 / M for the Jacobi preconditioner M = |diag H| on the free DOFs
+    (mask m = 1) and 1 on fixed DOFs or where the diagonal vanishes."""
+    a = np.abs(np.asarray(diag, dtype=np.float64))
+    M = np.where((m > 0) & (a > 0.0), a, 1.0)
+    return 1.0 / M
 
 
 def newton_solve(prob: Problem, x0, fixed, opts: NewtonOptions = NewtonOptions()):
     """Minimize F_V over the free DOFs (fixed[c, I] = 1 marks Dirichlet).
 
-    Each iteration: masked gradient g, truncated-CG direction on the masked
-    Hessian, then alpha = 1, 1/2, ... until the new mesh has det A > 0 at
+    Each iteration: masked gradient g, a direction from the masked Hessian
+    (truncated CG, or MINRES as in Section 5; optionally Jacobi
+    preconditioned), then alpha = 1, 1/2, ... until the new mesh has det A > 0 at
     every quadrature point, F(x+) < 1.2 F(x) and |g(x+)| < 1.2 |g(x)|;
     stops when no alpha works (Section 3.4), when |g| <= rtol |g0|
     (Section 5), or after max_it iterations."""
@@ -529,7 +632,18 @@ def newton_solve(prob: Problem, x0, fixed, opts: NewtonOptions = NewtonOptions()
         if opts.cg_forcing:
             cg_tol = max(opts.cg_rtol, min(0.5, math.sqrt(gn / rep.gnorm0)))
         Hm = lambda p: m * prob.hessian_apply(x.reshape(shape), (m * p).reshape(shape)).ravel()
-        dvec, ncg, neg = truncated_cg(Hm, g, cg_tol, opts.cg_max_it)
+        minv = None
+        if opts.precond == "jacobi":
+            minv = jacobi_inverse(prob.hessian_diagonal(x.reshape(shape)).ravel(), m)
+        elif opts.precond != "none":
+            raise ValueError(f"unknown preconditioner {opts.precond}")
+        if opts.inner == "cg":
+            dvec, ncg, neg = truncated_cg(Hm, g, cg_tol, opts.cg_max_it, minv)
+        elif opts.inner == "minres":
+            dvec, ncg = minres(Hm, -g, cg_tol, opts.cg_max_it, minv)
+            neg = False
+        else:
+            raise ValueError(f"unknown inner solver {opts.inner}")
         rep.cg_iters += ncg
         accepted = False
         for k in range(opts.ls_max):
