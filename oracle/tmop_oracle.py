@@ -38,7 +38,7 @@ from typing import Optional
 
 import numpy as np
 
-METRICS_2D = (2, 7)
+METRICS_2D = (1, 2, 7, 9, 14, 77, 98)
 METRICS_3D = (302, 303)
 
 
@@ -148,18 +148,30 @@ def _tau23(tau):
 
 def mu(metric: int, T: np.ndarray) -> np.ndarray:
     """mu(T) for T of shape (..., d, d).
+    1:   |T|^2                                (Table 3.1, no barrier, 2D)
     2:   |T|^2 / (2 tau) - 1                 (Table 3.1, shape, 2D)
     7:   |T - T^{-t}|^2                       (Section 3.2, shape+size, 2D)
+    9:   tau |T - T^{-t}|^2                   (Table 3.1, shape+size, 2D)
+    14:  |T - I|^2                            (Section 3.2, shape+size+alignment, 2D)
+    77:  (tau - 1/tau)^2 / 2                  (Table 3.1, size, 2D)
+    98:  |T - I|^2 / tau                     (Section 4.3, shape+size+alignment, 2D)
     303: |T|^2 / (3 tau^{2/3}) - 1           (Table 3.1, shape, 3D)
     302: |T|^2 |T^{-1}|^2 / 9 - 1            (3D shape metric of the workloads)
     with tau = det T and |.| the Frobenius norm."""
     tau = _det(T)
     I1 = _frob2(T)
+    if metric == 1:
+        return I1
     if metric == 2:
         return I1 / (2.0 * tau) - 1.0
-    if metric == 7:
+    if metric in (7, 9):
         Tinv_t = np.swapaxes(np.linalg.inv(T), -1, -2)
-        return _frob2(T - Tinv_t)
+        return _frob2(T - Tinv_t) * (tau if metric == 9 else 1.0)
+    if metric in (14, 98):
+        d = T.shape[-1]
+        return _frob2(T - np.eye(d)) / (tau if metric == 98 else 1.0)
+    if metric == 77:
+        return 0.5 * (tau - 1.0 / tau) ** 2
     if metric == 303:
         return I1 / (3.0 * _tau23(tau)) - 1.0
     if metric == 302:
@@ -168,8 +180,9 @@ def mu(metric: int, T: np.ndarray) -> np.ndarray:
 
 
 # Invariant forms of the derivatives (Section 3.4: write mu through matrix
-# invariants).  mu = f(I1, I2, tau), I1 = |T|^2, tau = det T, C = cof T =
-# d tau / dT, I2 = |C|^2 (3D only).
+# invariants).  mu = f(I1, I2, tau, J), I1 = |T|^2, tau = det T, C = cof T =
+# d tau / dT, I2 = |C|^2 (3D only), J = tr T (dJ/dT = I, for the metrics
+# measured against T = I).
 
 def cof(T):
     """Cofactor matrix C = d(det T)/dT."""
@@ -215,10 +228,23 @@ def _tr(A):
     return np.swapaxes(A, -1, -2)
 
 
-def _partials(metric, I1, I2, tau):
-    """f and its partials (f1, f2, ft, f11, f12, f1t, f22, f2t, ftt) of
-    mu = f(I1, I2, tau)."""
+def _partials(metric, I1, I2, tau, J=None):
+    """The nonzero partials among (f1, f2, ft, fJ, f11, f12, f1t, f22, f2t,
+    ftt, fJt) of mu = f(I1, I2, tau, J); the others are zero."""
     z = 0.0 * tau
+    if metric == 1:          # f = I1
+        return dict(f1=1.0 + z)
+    if metric == 9:          # tau |T - T^-t|^2 = tau I1 + I1 / tau - 4 tau in 2D
+        return dict(f1=tau + 1.0 / tau, ft=I1 - I1 / tau ** 2 - 4.0, f1t=1.0 - 1.0 / tau ** 2,
+                    ftt=2.0 * I1 / tau ** 3)
+    if metric == 77:         # (tau - 1/tau)^2 / 2
+        return dict(ft=(tau - 1.0 / tau) * (1.0 + 1.0 / tau ** 2), ftt=1.0 + 3.0 / tau ** 4)
+    if metric == 14:         # |T - I|^2 = I1 - 2 J + d
+        return dict(f1=1.0 + z, fJ=-2.0 + z)
+    if metric == 98:         # (I1 - 2 J + 2) / tau  (2D)
+        n = I1 - 2.0 * J + 2.0
+        return dict(f1=1.0 / tau, fJ=-2.0 / tau, ft=-n / tau ** 2, f1t=-1.0 / tau ** 2,
+                    fJt=2.0 / tau ** 2, ftt=2.0 * n / tau ** 3)
     if metric == 2:          # f = I1/(2 tau) - 1
         return dict(f1=1.0 / (2.0 * tau), f2=z, ft=-I1 / (2.0 * tau ** 2),
                     f11=z, f12=z, f1t=-1.0 / (2.0 * tau ** 2), f22=z, f2t=z, ftt=I1 / tau ** 3)
@@ -242,23 +268,35 @@ def _inv(T):
     tau = _det(T)
     C = cof(T)
     I2 = _frob2(C)
-    return I1, I2, tau, C
+    J = np.trace(T, axis1=-2, axis2=-1)
+    return I1, I2, tau, C, J
+
+
+_PARTIAL_NAMES = ("f1", "f2", "ft", "fJ", "f11", "f12", "f1t", "f22", "f2t", "ftt", "fJt")
+
+
+def _all_partials(metric, I1, I2, tau, J):
+    f = _partials(metric, I1, I2, tau, J)
+    z = 0.0 * tau
+    return {k: f.get(k, z) for k in _PARTIAL_NAMES}
 
 
 def dmu(metric: int, T: np.ndarray) -> np.ndarray:
     """First derivative P = d mu / dT (the matrix of Section 3.4)."""
-    I1, I2, tau, C = _inv(T)
-    f = _partials(metric, I1, I2, tau)
+    I1, I2, tau, C, J = _inv(T)
+    f = _all_partials(metric, I1, I2, tau, J)
     e = lambda s: s[..., None, None]
     dI2 = 2.0 * (e(I1) * T - _mm(_mm(T, _tr(T)), T))
-    return e(f["f1"]) * 2.0 * T + e(f["f2"]) * dI2 + e(f["ft"]) * C
+    Id = np.eye(T.shape[-1])
+    return e(f["f1"]) * 2.0 * T + e(f["f2"]) * dI2 + e(f["ft"]) * C + e(f["fJ"]) * Id
 
 
 def d2mu(metric: int, T: np.ndarray, E: np.ndarray) -> np.ndarray:
     """Second derivative of mu applied to a direction: dP = d/de P(T + e E)
-    at e = 0 (the Hessian ingredient of Section 3.4)."""
-    I1, I2, tau, C = _inv(T)
-    f = _partials(metric, I1, I2, tau)
+    at e = 0 (the Hessian ingredient of Section 3.4).  The partials f1J and
+    fJJ vanish for every metric here."""
+    I1, I2, tau, C, J = _inv(T)
+    f = _all_partials(metric, I1, I2, tau, J)
     e = lambda s: s[..., None, None]
     TtT = _mm(_tr(T), T)
     dI2 = 2.0 * (e(I1) * T - _mm(T, TtT))
@@ -267,10 +305,13 @@ def d2mu(metric: int, T: np.ndarray, E: np.ndarray) -> np.ndarray:
     a1 = 2.0 * _ddot(T, E)
     a2 = _ddot(dI2, E)
     at = _ddot(C, E)
+    aJ = np.trace(E, axis1=-2, axis2=-1)
+    Id = np.eye(T.shape[-1])
     return (e(f["f1"]) * 2.0 * E + e(f["f2"]) * ddI2 + e(f["ft"]) * dcof(T, E)
             + 2.0 * T * e(f["f11"] * a1 + f["f12"] * a2 + f["f1t"] * at)
             + dI2 * e(f["f12"] * a1 + f["f22"] * a2 + f["f2t"] * at)
-            + C * e(f["f1t"] * a1 + f["f2t"] * a2 + f["ftt"] * at))
+            + C * e(f["f1t"] * a1 + f["f2t"] * a2 + f["ftt"] * at + f["fJt"] * aJ)
+            + Id * e(f["fJt"] * at))
 
 
 # ---------------------------------------------------------------------------

@@ -85,10 +85,13 @@ def test_metric_invariances(metric):
 H_CS = 1e-30
 
 
-@pytest.mark.parametrize("metric", [2, 7, 303, 302])
+ALL_METRICS = list(O.METRICS_2D) + list(O.METRICS_3D)
+
+
+@pytest.mark.parametrize("metric", ALL_METRICS)
 def test_first_derivative_complex_step(metric):
     """P : E equals Im mu(T + i h E) / h, mu taken from its definition."""
-    d = 2 if metric in (2, 7) else 3
+    d = 2 if metric in O.METRICS_2D else 3
     T = _rand_T(d, 40)
     E = RNG.standard_normal((40, d, d))
     cs = np.imag(O.mu(metric, T + 1j * H_CS * E)) / H_CS
@@ -96,10 +99,10 @@ def test_first_derivative_complex_step(metric):
     np.testing.assert_allclose(PE, cs, rtol=1e-13, atol=1e-13)
 
 
-@pytest.mark.parametrize("metric", [2, 7, 303, 302])
+@pytest.mark.parametrize("metric", ALL_METRICS)
 def test_second_derivative_complex_step(metric):
     """dP[E] equals Im P(T + i h E) / h (P pinned by the previous test)."""
-    d = 2 if metric in (2, 7) else 3
+    d = 2 if metric in O.METRICS_2D else 3
     T = _rand_T(d, 40)
     E = RNG.standard_normal((40, d, d))
     cs = np.imag(O.dmu(metric, T + 1j * H_CS * E)) / H_CS
@@ -109,6 +112,53 @@ def test_second_derivative_complex_step(metric):
     a = np.sum(F * O.d2mu(metric, T, E), axis=(1, 2))
     b = np.sum(E * O.d2mu(metric, T, F), axis=(1, 2))
     np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-12)
+
+
+def test_metric_types_of_table_3_1():
+    """The defining properties of the metric types of Section 3.2 for the
+    metrics beyond the workloads': mu_9 (shape+size) is rotation invariant
+    and vanishes exactly at rotations; mu_77 (size) depends on det T only;
+    mu_14 and mu_98 (shape+size+alignment) vanish only at T = I and are not
+    rotation invariant; mu_1 = |T|^2 is rotation invariant, scales as c^2
+    and has P = 2T."""
+    T = _rand_T(2, 50)
+    Q = _rot2(0.7)
+    m9 = O.mu(9, T)
+    np.testing.assert_allclose(O.mu(9, Q @ T), m9, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(O.mu(9, T @ Q), m9, rtol=1e-12, atol=1e-13)
+    assert np.all(m9 >= -1e-14)
+    assert abs(O.mu(9, Q[None])[0]) < 1e-14 and np.max(np.abs(O.dmu(9, Q[None]))) < 1e-14
+    assert O.mu(9, 2.0 * Q[None])[0] > 1.0
+    tau = np.linalg.det(T)
+    D = np.zeros_like(T)
+    D[:, 0, 0], D[:, 1, 1] = tau, 1.0
+    np.testing.assert_allclose(O.mu(77, T), O.mu(77, D), rtol=1e-12, atol=1e-14)
+    shear = np.array([[[1.0, 0.8], [0.0, 1.0]]])
+    assert abs(O.mu(77, shear)[0]) < 1e-15 and np.max(np.abs(O.dmu(77, shear))) < 1e-15
+    for m in (14, 98):
+        assert abs(O.mu(m, np.eye(2)[None])[0]) < 1e-15
+        assert np.max(np.abs(O.dmu(m, np.eye(2)[None]))) < 1e-15
+        assert np.all(O.mu(m, T) >= -1e-14)
+        assert abs(O.mu(m, Q[None])[0]) > 0.1          # a rotation is not the target
+    np.testing.assert_allclose(O.mu(1, Q @ T @ Q.T), O.mu(1, T), rtol=1e-12)
+    np.testing.assert_allclose(O.mu(1, 1.7 * T), 1.7 ** 2 * O.mu(1, T), rtol=1e-13)
+    np.testing.assert_allclose(O.dmu(1, T), 2.0 * T, rtol=1e-14)
+
+
+@pytest.mark.parametrize("metric,kind", [(1, "2|E|^2"), (9, "8|symE|^2"), (14, "2|E|^2"), (98, "2|E|^2"),
+                                         (77, "4(trE)^2")])
+def test_second_variation_at_identity_more(metric, kind):
+    """Second variations at T = I worked out by hand: mu_1 and mu_14 are
+    quadratics with Hessian 2 Id; mu_98 = |T - I|^2 / tau differs from mu_14
+    at T = I + eE only at order e^3; mu_9 = tau mu_7 with mu_7 = O(e^2) has
+    mu_7's 8 |sym E|^2; mu_77 ~ (2 tr E e)^2 / 2."""
+    E = RNG.standard_normal((30, 2, 2))
+    S = 0.5 * (E + np.swapaxes(E, 1, 2))
+    expected = {"2|E|^2": 2.0 * np.sum(E * E, axis=(1, 2)), "8|symE|^2": 8.0 * np.sum(S * S, axis=(1, 2)),
+                "4(trE)^2": 4.0 * np.trace(E, axis1=1, axis2=2) ** 2}[kind]
+    I = np.broadcast_to(np.eye(2), E.shape).copy()
+    got = np.sum(E * O.d2mu(metric, I, E), axis=(1, 2))
+    np.testing.assert_allclose(got, expected, rtol=1e-13, atol=1e-13)
 
 
 # ---------------------------------------------------------------- P4 second variation at T = I
@@ -263,7 +313,8 @@ def test_grid_is_minimizer(dim, metric):
 
 # ---------------------------------------------------------------- P6/P7 tiny meshes, end to end
 TINY = [(2, 1, 1, 2, 2), (2, 2, 2, 4, 2), (2, 2, 3, 5, 7), (2, 2, 2, 3, 7),
-        (3, 1, 1, 2, 303), (3, 2, 2, 4, 303), (3, 1, 3, 5, 302), (3, 2, 2, 3, 302)]
+        (3, 1, 1, 2, 303), (3, 2, 2, 4, 303), (3, 1, 3, 5, 302), (3, 2, 2, 3, 302),
+        (2, 2, 2, 3, 1), (2, 2, 2, 4, 9), (2, 2, 2, 3, 14), (2, 2, 3, 5, 77), (2, 2, 2, 4, 98)]
 
 
 def _tiny(dim, n, p, Q, metric, seed=7):
@@ -324,8 +375,9 @@ def test_global_invariants(case):
     scale = np.max(np.abs(g))
     np.testing.assert_allclose(g.sum(axis=1), 0.0, atol=1e-13 * scale * x.shape[1])   # translation
     M = x @ g.T
-    np.testing.assert_allclose(M, M.T, atol=1e-13 * scale * x.shape[1])              # rotation
-    if metric != 7:
+    if metric not in (14, 98):      # mu(QT) = mu(T): F is invariant under rotations of the mesh
+        np.testing.assert_allclose(M, M.T, atol=1e-13 * scale * x.shape[1])          # rotation
+    if metric in (2, 303, 302):     # shape metrics: F is invariant under scaling of the mesh
         assert abs(np.sum(x * g)) < 1e-13 * scale * x.shape[1]                         # scale
 
 
