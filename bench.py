@@ -8,8 +8,10 @@ does (tmop_energy_gradient), and the Hessian action, each over all
 elements.  The metric is DOF-iterations/s = (dim * n_node) / (seconds per
 step), inputs resident in HBM.  Printed as one JSON line.  The FP64 path is the headline
 value; the mixed FP32 path, per-operation times, the roofline of the
-Hessian-action kernel, Newton wall time to the F tolerance and the CPU
-oracle baseline are reported alongside.
+Hessian-action kernel, Newton wall time to the F tolerance (truncated CG
+with a fixed or an inexact-Newton inner tolerance, Jacobi preconditioned or
+not, and Jacobi-preconditioned MINRES) and the CPU oracle baseline are
+reported alongside.
 """
 from __future__ import annotations
 
@@ -220,7 +222,8 @@ def main():
         ops = {}
         for name, fn in (("energy", lambda: ctx.energy(x)), ("gradient", lambda: ctx.gradient(x, g)),
                          ("energy_gradient", lambda: ctx.energy_gradient(x, g)),
-                         ("hessian", lambda: ctx.hessian_apply(x, v, Hv))):
+                         ("hessian", lambda: ctx.hessian_apply(x, v, Hv)),
+                         ("hessian_diagonal", lambda: ctx.hessian_diagonal(x, Hv))):
             ts = []
             for _ in range(max(args.steps, 5)):
                 e0 = torch.cuda.Event(enable_timing=True)
@@ -236,16 +239,17 @@ def main():
         for _ in range(args.steps):
             ctx.energy(x)
             ctx.gradient(x, g)
+            ctx.hessian_diagonal(x, Hv)
             step()
         launch = {}
-        for op, name in enumerate(("energy", "gradient", "hessian", "energy_gradient")):
+        for op, name in enumerate(("energy", "gradient", "hessian", "energy_gradient", "hessian_diagonal")):
             tot_ms, n = ctx.timing_read(op)
             launch[name] = dict(launches=n, us_per_launch=tot_ms * 1e3 / n, us_per_op=tot_ms * 1e3 / args.steps)
         ctx.timing_enable(False)
         results[pname] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), ops=ops, F=F, ctx=ctx,
                               launch=launch)
         print(f"# {pname}: {ms:.3f} ms/step, E {ops['energy']*1e6:.1f} us, G {ops['gradient']*1e6:.1f} us, "
-              f"E+G {ops['energy_gradient']*1e6:.1f} us, Hv {ops['hessian']*1e6:.1f} us; per launch "
+              f"E+G {ops['energy_gradient']*1e6:.1f} us, Hv {ops['hessian']*1e6:.1f} us, diag {ops['hessian_diagonal']*1e6:.1f} us; per launch "
               + ", ".join(f"{k} {v['us_per_launch']:.1f}" for k, v in launch.items()), file=sys.stderr, flush=True)
 
     # Newton wall time to F_tol = F_ref + 1e-8 F0 (F_ref: final F of FP64 Newton)
@@ -267,9 +271,13 @@ def main():
         st, ref = solve("f64")
         F_tol = ref["F"] + 1e-8 * ref["F0"]
         newton["F_ref"], newton["F_tol"] = ref["F"], F_tol
-        for pname, forcing in (("f64", 0), ("f64", 1), ("mixed", 0), ("mixed", 1)):
-            st, rep = solve(pname, ftarget=F_tol, cg_forcing=forcing)
-            key = f"{pname}{'_inexact' if forcing else ''}"
+        J, MR = T.TMOP_PREC_JACOBI, T.TMOP_INNER_MINRES
+        variants = (("f64", "f64", dict()), ("f64_inexact", "f64", dict(cg_forcing=1)),
+                    ("mixed", "mixed", dict()), ("mixed_inexact", "mixed", dict(cg_forcing=1)),
+                    ("f64_jacobi", "f64", dict(precond=J)), ("f64_inexact_jacobi", "f64", dict(cg_forcing=1, precond=J)),
+                    ("f64_minres_jacobi", "f64", dict(inner=MR, precond=J)))
+        for key, pname, kw in variants:
+            st, rep = solve(pname, ftarget=F_tol, **kw)
             reached = next((k for k, f in enumerate(rep["history_F"]) if f <= F_tol), None)
             newton[key] = dict(status=st, reached_F_tol=reached is not None,
                                wall_s_to_F_tol=rep["history_time"][reached] if reached is not None else None,

@@ -58,8 +58,13 @@ enum {
 
 /* Quality metrics mu(T), tau = det T, |.| the Frobenius norm (Section 3.2). */
 enum {
+  TMOP_MU1 = 1,       /* 2D, no barrier: |T|^2                    (Table 3.1) */
   TMOP_MU2 = 2,       /* 2D shape:      |T|^2 / (2 tau) - 1       (Table 3.1) */
   TMOP_MU7 = 7,       /* 2D shape+size: |T - T^{-t}|^2            (Section 3.2) */
+  TMOP_MU9 = 9,       /* 2D shape+size: tau |T - T^{-t}|^2        (Table 3.1) */
+  TMOP_MU14 = 14,     /* 2D shape+size+alignment: |T - I|^2       (Section 3.2) */
+  TMOP_MU77 = 77,     /* 2D size:       (tau - 1/tau)^2 / 2       (Table 3.1) */
+  TMOP_MU98 = 98,     /* 2D shape+size+alignment: |T - I|^2 / tau (Section 4.3) */
   TMOP_MU302 = 302,   /* 3D shape:      |T|^2 |T^{-1}|^2 / 9 - 1 */
   TMOP_MU303 = 303    /* 3D shape:      |T|^2 / (3 tau^{2/3}) - 1 (Table 3.1) */
 };
@@ -72,6 +77,16 @@ enum { TMOP_GAUSS_LEGENDRE = 0, TMOP_GAUSS_LOBATTO = 1 };
  * det A, the positivity test and the sum of F stay FP64.  Both take and
  * return FP64 arrays. */
 enum { TMOP_FP64 = 0, TMOP_MIXED_FP32 = 1 };
+
+/* Inner linear solver of the Newton step (Section 3.4): Steihaug's truncated
+ * conjugate gradients, or MINRES, the solver of the paper's results
+ * (Section 5), which accepts the indefinite Hessians of the early
+ * iterations. */
+enum { TMOP_INNER_CG = 0, TMOP_INNER_MINRES = 1 };
+
+/* Preconditioner of the inner solver: none, or Jacobi, M = |diag H| on the
+ * free DOFs, from tmop_hessian_diagonal at the current iterate. */
+enum { TMOP_PREC_NONE = 0, TMOP_PREC_JACOBI = 1 };
 
 /* Target matrices W (Section 3.1). */
 enum {
@@ -124,11 +139,18 @@ typedef struct {
                                  sqrt(|g|/|g0|))) */
   double *hist_time;          /* optional HOST [max_it + 1]: seconds since the
                                  call started, at each accepted iterate */
+  int32_t inner;              /* TMOP_INNER_CG (default) or TMOP_INNER_MINRES;
+                                 MINRES stops when its residual estimate (the
+                                 M^{-1} norm with a preconditioner) falls
+                                 to the inner tolerance times its initial
+                                 value */
+  int32_t precond;            /* TMOP_PREC_NONE (default) or TMOP_PREC_JACOBI */
 } tmop_newton_opts;
 
 typedef struct {
   int32_t iters;              /* accepted Newton steps */
-  int32_t cg_iters;           /* total inner iterations (Hessian actions) */
+  int32_t cg_iters;           /* total inner iterations (Hessian actions), CG
+                                 or MINRES */
   int32_t ls_shrinks;         /* rejected step lengths */
   int32_t neg_curv;           /* inner solves ended by non-positive curvature */
   double F0, F;               /* objective at the start and at the end */
@@ -138,7 +160,7 @@ typedef struct {
 
 /* Fills `opts` with the defaults: rtol 1e-12, atol 0, max_it 50, cg_rtol
  * 1e-8, cg_max_it 1000, ls_shrink 0.5, ls_max 30, growth factors 1.2, no
- * history. */
+ * history, truncated CG without preconditioner. */
 void tmop_newton_default_opts(tmop_newton_opts *opts);
 
 /* Builds a context on the current HIP device for the objective of eq. 2.4
@@ -177,6 +199,15 @@ int tmop_gradient_scaled(tmop_ctx *ctx, const double *x, const double *scale, do
 int tmop_hessian_apply(tmop_ctx *ctx, const double *x, const double *v,
                        double *Hv, void *stream);
 
+/* diag = the diagonal of d^2F/dx^2 (Section 3.4) over all DOFs: entry
+ * (c, I) is the Hessian action on the unit vector of DOF (c, I), read at
+ * (c, I), i.e. sum over the elements E holding I of
+ * sum_q w_q det W  dT : mu''(T)[dT],  dT = e_c (grad w_i)^T W^{-1}.  The
+ * Jacobi preconditioner of tmop_newton_solve.  x, diag: device
+ * [dim][n_node]; diag is overwritten, not aliasing x.  Deterministic.
+ * Async. */
+int tmop_hessian_diagonal(tmop_ctx *ctx, const double *x, double *diag, void *stream);
+
 /* F and min det A as tmop_energy (eq. 2.4), and g = dF/dx as tmop_gradient
  * (Section 3.4), in one pass over the elements: the line search of Section
  * 3.4 needs both at every trial point.  The energy partials ride along in
@@ -187,8 +218,9 @@ int tmop_energy_gradient(tmop_ctx *ctx, const double *x, double *F, double *min_
                          void *stream);
 
 /* Minimizes F over the free DOFs with Newton's method (Section 3.4):
- * direction from truncated CG (Steihaug) on the Hessian restricted to the
- * free DOFs; step lengths 1, s, s^2, ... until det A > 0 at every
+ * direction from truncated CG (Steihaug) or MINRES (Section 5), optionally
+ * Jacobi preconditioned, on the Hessian restricted to the free DOFs; step
+ * lengths 1, s, s^2, ... until det A > 0 at every
  * quadrature point, F(x+) < f_growth F(x) and |g(x+)| < g_growth |g(x)|.
  * x: device [dim][n_node], updated in place (fixed DOFs keep their value).
  * opts: host, NULL = defaults.  report: host, may be NULL.  Returns TMOP_OK
@@ -249,10 +281,10 @@ int tmop_mlp_propose(tmop_ctx *ctx, tmop_mlp *mlp, const double *x, double *x_ou
  * two HIP events on the caller's stream; tmop_timing_read waits for them and
  * returns the summed device time in milliseconds and the number of launches
  * for one operation: 0 energy, 1 gradient, 2 Hessian action, 3 energy +
- * gradient (tmop_energy_gradient).
+ * gradient (tmop_energy_gradient), 4 Hessian diagonal.
  * tmop_timing_enable(ctx, on) clears the totals and turns timing on (1) or
  * off (0).  Both return TMOP_OK, TMOP_E_ARG (NULL ctx / out pointers, op
- * outside 0..3) or TMOP_E_HIP. */
+ * outside 0..4) or TMOP_E_HIP. */
 int tmop_timing_enable(tmop_ctx *ctx, int enable);
 int tmop_timing_read(tmop_ctx *ctx, int op, double *ms_total, int64_t *launches);
 

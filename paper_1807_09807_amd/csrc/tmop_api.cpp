@@ -261,6 +261,16 @@ int energy_sync(tmop_ctx* c, const double* x, hipStream_t s, double* F, double* 
   return read_res(c, s, F, mind);
 }
 
+// out[0] = x . y, out[1] = x . z with one host synchronization.
+int dot2_sync(tmop_ctx* c, const double* x, const double* y, const double* z, hipStream_t s, double* out) {
+  HIP_TRY(dot2(x, y, z, c->n_dof, c->d_scratch, c->d_res + 2, s));
+  HIP_TRY(hipMemcpyAsync(c->h_res + 2, c->d_res + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out[0] = c->h_res[2];
+  out[1] = c->h_res[3];
+  return TMOP_OK;
+}
+
 int dot_sync(tmop_ctx* c, const double* a, const double* b, hipStream_t s, double* out) {
   HIP_TRY(dot(a, b, c->n_dof, c->d_scratch, c->d_res + 2, s));
   HIP_TRY(hipMemcpyAsync(c->h_res + 2, c->d_res + 2, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -326,6 +336,159 @@ void color_elements(const int32_t* en, int64_t n_elem, int npe, int64_t n_node, 
   for (int64_t e = 0; e < n_elem; ++e) order[pos[color[e]]++] = (int32_t)e;
 }
 
+// Work vectors of the Newton driver: g, x_trial, g_trial, the direction d,
+// the preconditioner and seven solver vectors.
+constexpr int NEWTON_VECTORS = 12;
+struct Inner {
+  double* d;
+  double* minv;
+  double* v[7];
+};
+
+// Hp = m .* H(x) p: the Hessian restricted to the free DOFs (p is zero on
+// the fixed ones).
+int masked_hessian(tmop_ctx* c, const double* x, const double* p, double* Hp, hipStream_t s) {
+  const int st = assemble(c, OP_HESS, x, p, Hp, s);
+  if (st != TMOP_OK) return st;
+  if (c->has_fixed) HIP_TRY(mask_mul(c->d_mask, Hp, c->n_dof, s));
+  return TMOP_OK;
+}
+
+// Steihaug's truncated CG for H d = -g from d = 0, optionally with the
+// diagonal preconditioner minv = 1 / diag M.  Non-positive curvature at the
+// first step returns -M^{-1} g (the steepest-descent direction, -g without
+// M), later the current iterate; stops once |r|_2 <= tol |g|_2.
+int inner_tcg(tmop_ctx* c, const double* x, const double* g, double gn, double tol, int max_it,
+              const double* minv, Inner& w, hipStream_t s, int* ncg, bool* neg) {
+  const int64_t N = c->n_dof;
+  double* r = w.v[0];
+  double* p = w.v[1];
+  double* Hp = w.v[2];
+  double* z = minv ? w.v[3] : r;
+  int st;
+  HIP_TRY(fill(w.d, 0.0, N, s));
+  HIP_TRY(scale_copy(-1.0, g, r, N, s));
+  double rz, rr;
+  if (minv) {
+    HIP_TRY(mul(minv, r, z, N, s));
+    if ((st = dot_sync(c, r, z, s, &rz)) != TMOP_OK) return st;
+  } else {
+    rz = gn * gn;
+  }
+  HIP_TRY(hipMemcpyAsync(p, z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  *ncg = 0;
+  *neg = false;
+  for (int j = 0; j < max_it; ++j) {
+    ++*ncg;
+    if ((st = masked_hessian(c, x, p, Hp, s)) != TMOP_OK) return st;
+    double pHp;
+    if ((st = dot_sync(c, p, Hp, s, &pHp)) != TMOP_OK) return st;
+    if (!(pHp > 0.0)) {                      // non-positive curvature
+      *neg = true;
+      if (j == 0) HIP_TRY(hipMemcpyAsync(w.d, p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      break;
+    }
+    const double alpha = rz / pHp;
+    HIP_TRY(axpy(alpha, p, w.d, N, s));
+    HIP_TRY(axpy(-alpha, Hp, r, N, s));
+    double rz_new;
+    if (minv) {
+      HIP_TRY(mul(minv, r, z, N, s));
+      double two[2];
+      if ((st = dot2_sync(c, r, r, z, s, two)) != TMOP_OK) return st;
+      rr = two[0];
+      rz_new = two[1];
+    } else {
+      if ((st = dot_sync(c, r, r, s, &rr)) != TMOP_OK) return st;
+      rz_new = rr;
+    }
+    if (sqrt(rr) <= tol * gn) break;
+    HIP_TRY(xpay(z, rz_new / rz, p, N, s));
+    rz = rz_new;
+  }
+  return TMOP_OK;
+}
+
+// MINRES (Paige and Saunders) for H d = -g from d = 0, optionally with the
+// symmetric positive definite diagonal preconditioner minv = 1 / diag M.
+// Preconditioned Lanczos gives the tridiagonal of H in the M^{-1} inner
+// product; Givens rotations keep its QR factorization current, so the
+// iterate that minimizes the M^{-1}-norm of the residual over the Krylov
+// space follows from a three-term recurrence of the directions w_k, and
+// |phibar| is that residual norm.  Stops when |phibar| <= tol beta_1.
+int inner_minres(tmop_ctx* c, const double* x, const double* g, double tol, int max_it, const double* minv,
+                 Inner& w, hipStream_t s, int* nit) {
+  const int64_t N = c->n_dof;
+  double* r_prev = w.v[0];
+  double* r_cur = w.v[1];
+  double* hbuf = w.v[2];       // H v, then r_next
+  double* vbuf = w.v[3];
+  double* ybuf = w.v[4];
+  double* w_prev = w.v[5];
+  double* w_cur = w.v[6];
+  int st;
+  HIP_TRY(fill(w.d, 0.0, N, s));
+  HIP_TRY(scale_copy(-1.0, g, r_cur, N, s));
+  const double* y = r_cur;
+  if (minv) {
+    HIP_TRY(mul(minv, r_cur, ybuf, N, s));
+    y = ybuf;
+  }
+  double beta;
+  if ((st = dot_sync(c, r_cur, y, s, &beta)) != TMOP_OK) return st;
+  beta = sqrt(beta);
+  *nit = 0;
+  const double beta1 = beta;
+  if (!(beta1 > 0.0)) return TMOP_OK;
+  HIP_TRY(fill(w_prev, 0.0, N, s));
+  HIP_TRY(fill(w_cur, 0.0, N, s));
+  double beta_prev = 0.0, cs = -1.0, sn = 0.0, dbar = 0.0, eps = 0.0, phibar = beta1;
+  for (int k = 1; k <= max_it; ++k) {
+    ++*nit;
+    HIP_TRY(scale_copy(1.0 / beta, y, vbuf, N, s));          // Lanczos vector v_k
+    if ((st = masked_hessian(c, x, vbuf, hbuf, s)) != TMOP_OK) return st;
+    double alpha;
+    if ((st = dot_sync(c, vbuf, hbuf, s, &alpha)) != TMOP_OK) return st;
+    HIP_TRY(axpy(-alpha / beta, r_cur, hbuf, N, s));
+    if (k > 1) HIP_TRY(axpy(-beta / beta_prev, r_prev, hbuf, N, s));
+    // hbuf now holds r_{k+1}
+    y = hbuf;
+    if (minv) {
+      HIP_TRY(mul(minv, hbuf, ybuf, N, s));
+      y = ybuf;
+    }
+    double beta_next;
+    if ((st = dot_sync(c, hbuf, y, s, &beta_next)) != TMOP_OK) return st;
+    beta_next = sqrt(std::max(beta_next, 0.0));
+    // previous rotation on this column and on the next column's beta
+    const double eps_k = eps;
+    const double delta = cs * dbar + sn * alpha;
+    const double gbar = sn * dbar - cs * alpha;
+    eps = sn * beta_next;
+    dbar = -cs * beta_next;
+    // new rotation annihilating beta_next
+    double gamma = hypot(gbar, beta_next);
+    if (gamma == 0.0) gamma = 2.2250738585072014e-308;
+    cs = gbar / gamma;
+    sn = beta_next / gamma;
+    const double phi = cs * phibar;
+    phibar = sn * phibar;
+    // w_k = (v_k - eps_k w_{k-2} - delta w_{k-1}) / gamma, into w_prev's storage
+    HIP_TRY(minres_w(vbuf, eps_k, w_prev, delta, w_cur, 1.0 / gamma, N, s));
+    std::swap(w_prev, w_cur);
+    HIP_TRY(axpy(phi, w_cur, w.d, N, s));
+    // r_{k-1} <- r_k <- r_{k+1}; the oldest buffer takes the next H v
+    double* spare = r_prev;
+    r_prev = r_cur;
+    r_cur = hbuf;
+    hbuf = spare;
+    beta_prev = beta;
+    beta = beta_next;
+    if (fabs(phibar) <= tol * beta1 || !(beta > 0.0)) break;
+  }
+  return TMOP_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- C ABI
@@ -361,6 +524,8 @@ void tmop_newton_default_opts(tmop_newton_opts* o) {
   o->g_growth = 1.2;
   o->ftarget = -HUGE_VAL;
   o->cg_forcing = 0;
+  o->inner = TMOP_INNER_CG;
+  o->precond = TMOP_PREC_NONE;
 }
 
 int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_target* target, int32_t metric,
@@ -375,7 +540,9 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
   if (quad->kind != TMOP_GAUSS_LEGENDRE && quad->kind != TMOP_GAUSS_LOBATTO) return TMOP_E_ARG;
   if (Q < p + 1) return TMOP_E_ARG;                      // Section 3.3: at least p+1 points
   if (quad->kind == TMOP_GAUSS_LOBATTO && Q < 2) return TMOP_E_ARG;
-  if (d == 2 && metric != TMOP_MU2 && metric != TMOP_MU7) return TMOP_E_ARG;
+  if (d == 2 && metric != TMOP_MU1 && metric != TMOP_MU2 && metric != TMOP_MU7 && metric != TMOP_MU9 &&
+      metric != TMOP_MU14 && metric != TMOP_MU77 && metric != TMOP_MU98)
+    return TMOP_E_ARG;
   if (d == 3 && metric != TMOP_MU302 && metric != TMOP_MU303) return TMOP_E_ARG;
   if (precision != TMOP_FP64 && precision != TMOP_MIXED_FP32) return TMOP_E_ARG;
   if (target->kind != TMOP_TGT_CONST || !target->W) return TMOP_E_ARG;
@@ -421,7 +588,7 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
     if (hipMalloc(&c->d_elem_node, en_bytes) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipMalloc(&c->d_colors, order.size() * sizeof(int32_t)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipMalloc(&c->d_part, 2 * (size_t)mesh->n_elem * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
-    if (hipMalloc(&c->d_scratch, RED_BLOCKS * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
+    if (hipMalloc(&c->d_scratch, 2 * RED_BLOCKS * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipMalloc(&c->d_res, 4 * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipHostMalloc(&c->h_res, 4 * sizeof(double), 0) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipMalloc(&c->d_mask, c->n_dof * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
@@ -471,7 +638,7 @@ int tmop_timing_enable(tmop_ctx* c, int enable) {
   const int st = collect_timing(c);
   (void)hipSetDevice(cur);
   c->timing = enable != 0;
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 5; ++k) {
     c->t_ms[k] = 0.0;
     c->t_launches[k] = 0;
   }
@@ -479,7 +646,7 @@ int tmop_timing_enable(tmop_ctx* c, int enable) {
 }
 
 int tmop_timing_read(tmop_ctx* c, int op, double* ms_total, int64_t* launches) {
-  if (!c || op < 0 || op > 3 || !ms_total || !launches) return TMOP_E_ARG;
+  if (!c || op < 0 || op > 4 || !ms_total || !launches) return TMOP_E_ARG;
   const int st = collect_timing(c);
   *ms_total = c->t_ms[op];
   *launches = c->t_launches[op];
@@ -523,6 +690,11 @@ int tmop_hessian_apply(tmop_ctx* c, const double* x, const double* v, double* Hv
   return assemble(c, OP_HESS, x, v, Hv, (hipStream_t)stream);
 }
 
+int tmop_hessian_diagonal(tmop_ctx* c, const double* x, double* diag, void* stream) {
+  if (!c || !x || !diag || diag == x) return TMOP_E_ARG;
+  return assemble(c, OP_DIAG, x, nullptr, diag, (hipStream_t)stream);
+}
+
 int tmop_newton_solve(tmop_ctx* c, double* x, const tmop_newton_opts* opts_in, tmop_newton_report* rep_out,
                       void* stream) {
   if (!c || !x) return TMOP_E_ARG;
@@ -531,6 +703,9 @@ int tmop_newton_solve(tmop_ctx* c, double* x, const tmop_newton_opts* opts_in, t
   else tmop_newton_default_opts(&o);
   if (o.max_it < 0 || o.cg_max_it < 1 || o.ls_max < 0 || !(o.ls_shrink > 0.0 && o.ls_shrink < 1.0))
     return TMOP_E_ARG;
+  if ((o.inner != TMOP_INNER_CG && o.inner != TMOP_INNER_MINRES) ||
+      (o.precond != TMOP_PREC_NONE && o.precond != TMOP_PREC_JACOBI))
+    return TMOP_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   const auto t_start = std::chrono::steady_clock::now();
   auto elapsed = [&]() {
@@ -538,18 +713,18 @@ int tmop_newton_solve(tmop_ctx* c, double* x, const tmop_newton_opts* opts_in, t
   };
   const int64_t N = c->n_dof;
   if (!c->d_work) {
-    if (hipMalloc(&c->d_work, 7 * (size_t)N * sizeof(double)) != hipSuccess) {
+    if (hipMalloc(&c->d_work, (size_t)NEWTON_VECTORS * N * sizeof(double)) != hipSuccess) {
       c->d_work = nullptr;
       return TMOP_E_NOMEM;
     }
   }
   double* g = c->d_work;          // masked gradient at x
-  double* dv = g + N;             // search direction
-  double* r = dv + N;             // CG residual
-  double* pv = r + N;             // CG direction
-  double* Hp = pv + N;            // H p
-  double* xt = Hp + N;            // trial point
+  double* xt = g + N;             // trial point
   double* gt = xt + N;            // masked gradient at the trial point
+  Inner w;
+  w.d = gt + N;                   // search direction
+  w.minv = w.d + N;               // 1 / diag of the Jacobi preconditioner
+  for (int k = 0; k < 7; ++k) w.v[k] = w.minv + (k + 1) * N;   // solver vectors
 
   tmop_newton_report rep;
   memset(&rep, 0, sizeof(rep));
@@ -578,41 +753,27 @@ int tmop_newton_solve(tmop_ctx* c, double* x, const tmop_newton_opts* opts_in, t
   for (int it = 0;; ++it) {
     if (gn <= gtol || F <= o.ftarget) { status = TMOP_OK; break; }
     if (it >= o.max_it) { status = TMOP_W_MAXIT; break; }
-    // ---- truncated CG (Steihaug) on the masked Hessian: H d = -g from d = 0
-    HIP_TRY(fill(dv, 0.0, N, s));
-    HIP_TRY(scale_copy(-1.0, g, r, N, s));
-    HIP_TRY(scale_copy(-1.0, g, pv, N, s));
-    double rr = gg;
-    int ncg = 0;
     double cg_tol = o.cg_rtol;
     if (o.cg_forcing) cg_tol = std::max(o.cg_rtol, std::min(0.5, sqrt(gn / rep.gnorm0)));
-    for (int j = 0; j < o.cg_max_it; ++j) {
-      ++ncg;
-      if ((st = assemble(c, OP_HESS, x, pv, Hp, s)) != TMOP_OK) return st;
-      if (c->has_fixed) HIP_TRY(mask_mul(c->d_mask, Hp, N, s));
-      double pHp;
-      if ((st = dot_sync(c, pv, Hp, s, &pHp)) != TMOP_OK) return st;
-      if (!(pHp > 0.0)) {                      // non-positive curvature
-        rep.neg_curv++;
-        if (j == 0) HIP_TRY(scale_copy(-1.0, g, dv, N, s));
-        break;
-      }
-      const double alpha = rr / pHp;
-      HIP_TRY(axpy(alpha, pv, dv, N, s));
-      HIP_TRY(axpy(-alpha, Hp, r, N, s));
-      double rr_new;
-      if ((st = dot_sync(c, r, r, s, &rr_new)) != TMOP_OK) return st;
-      if (sqrt(rr_new) <= cg_tol * gn) break;
-      HIP_TRY(xpay(r, rr_new / rr, pv, N, s));
-      rr = rr_new;
+    const double* minv = nullptr;
+    if (o.precond == TMOP_PREC_JACOBI) {   // M = |diag H| at x on the free DOFs
+      if ((st = assemble(c, OP_DIAG, x, nullptr, w.minv, s)) != TMOP_OK) return st;
+      HIP_TRY(jacobi_inv(c->d_mask, w.minv, N, s));
+      minv = w.minv;
     }
+    int ncg = 0;
+    bool neg = false;
+    st = o.inner == TMOP_INNER_MINRES ? inner_minres(c, x, g, cg_tol, o.cg_max_it, minv, w, s, &ncg)
+                                      : inner_tcg(c, x, g, gn, cg_tol, o.cg_max_it, minv, w, s, &ncg, &neg);
+    if (st != TMOP_OK) return st;
     rep.cg_iters += ncg;
+    if (neg) rep.neg_curv++;
     // ---- line search (Section 3.4): det A > 0, F and |g| growth below 1.2x
     bool accepted = false;
     double Ft = 0, mindt = 0, ggt = 0;
     double alpha = 1.0;
     for (int k = 0; k < o.ls_max; ++k) {
-      HIP_TRY(waxpy(x, alpha, dv, xt, N, s));
+      HIP_TRY(waxpy(x, alpha, w.d, xt, N, s));
       // F, det A and g at the trial point in one pass (g is used only when
       // the first two tests pass)
       if ((st = energy_gradient_async(c, xt, gt, s)) != TMOP_OK) return st;

@@ -40,6 +40,27 @@ __global__ void __launch_bounds__(VB) k_mask_mul(const double* __restrict__ m, d
   for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) y[i] *= m[i];
 }
 
+__global__ void __launch_bounds__(VB) k_mul(const double* __restrict__ a, const double* __restrict__ x,
+                                            double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) y[i] = a[i] * x[i];
+}
+
+// Jacobi preconditioner: d <- 1 / |d| on free DOFs (mask m = 1) with a
+// nonzero diagonal, 1 elsewhere.
+__global__ void __launch_bounds__(VB) k_jacobi_inv(const double* __restrict__ m, double* __restrict__ d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+    const double a = fabs(d[i]);
+    d[i] = (m[i] > 0.0 && a > 0.0) ? 1.0 / a : 1.0;
+  }
+}
+
+// MINRES direction update w <- (v - a w - b u) s (w updated in place).
+__global__ void __launch_bounds__(VB) k_minres_w(const double* __restrict__ v, double a, double* __restrict__ w,
+                                                 double b, const double* __restrict__ u, double s, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB)
+    w[i] = (v[i] - a * w[i] - b * u[i]) * s;
+}
+
 // Fixed-order tree reduction of one value per thread in a RED_THREADS block.
 __device__ __forceinline__ double block_sum(double s, double* red) {
 #pragma unroll
@@ -74,6 +95,26 @@ __global__ void __launch_bounds__(RED_THREADS) k_dot_part(const double* __restri
     s += x[i] * y[i];
   const double t = block_sum(s, red);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// Stage 1 of two dot products sharing x: x . y into part[b], x . z into
+// part[RED_BLOCKS + b].
+__global__ void __launch_bounds__(RED_THREADS) k_dot2_part(const double* __restrict__ x, const double* __restrict__ y,
+                                                           const double* __restrict__ z, int64_t n,
+                                                           double* __restrict__ part) {
+  __shared__ double red[2][RED_THREADS / 64];
+  double s = 0.0, t = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)RED_BLOCKS * RED_THREADS) {
+    const double xi = x[i];
+    s += xi * y[i];
+    t += xi * z[i];
+  }
+  const double ts = block_sum(s, red[0]);
+  const double tt = block_sum(t, red[1]);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = ts;
+    part[RED_BLOCKS + blockIdx.x] = tt;
+  }
 }
 
 // Stage 2: one block folds n partial sums part[0, n) (and, optionally, n
@@ -136,6 +177,30 @@ hipError_t finalize_sum_min(const double* part, int n, int moff, double* scratch
 hipError_t dot(const double* x, const double* y, int64_t n, double* scratch, double* res, hipStream_t s) {
   hipLaunchKernelGGL(k_dot_part, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, x, y, n, scratch);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch, RED_BLOCKS, 0, 0, res);
+  return hipGetLastError();
+}
+
+hipError_t dot2(const double* x, const double* y, const double* z, int64_t n, double* scratch, double* res,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_dot2_part, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, x, y, z, n, scratch);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch, RED_BLOCKS, 0, 0, res);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch + RED_BLOCKS, RED_BLOCKS, 0, 0, res + 1);
+  return hipGetLastError();
+}
+
+hipError_t mul(const double* a, const double* x, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_mul, dim3(vgrid(n)), dim3(VB), 0, s, a, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t jacobi_inv(const double* m, double* d, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_jacobi_inv, dim3(vgrid(n)), dim3(VB), 0, s, m, d, n);
+  return hipGetLastError();
+}
+
+hipError_t minres_w(const double* v, double a, double* w, double b, const double* u, double sc, int64_t n,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_minres_w, dim3(vgrid(n)), dim3(VB), 0, s, v, a, w, b, u, sc, n);
   return hipGetLastError();
 }
 

@@ -824,4 +824,334 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
   }
 }
 
+// ------------------------------------------------------- Hessian diagonal
+//
+// diag(d^2F/dx^2) at DOF (c, I) collects, from every element E holding I as
+// local node i,  sum_q w_q det W  g_i^T K_c g_i  with g_i = W^{-t} grad w_i
+// at point q and K_c = d^2 mu / (dT_c. dT_c.) (mu_second_rows): the unit
+// vector of the DOF moves row c of A by (grad w_i)^T.  In reference
+// coordinates this is  sum_q sum_{l,m} Kt_c,lm (d_l w_i)(d_m w_i),
+// Kt_c = w det W W^{-1} K_c W^{-t} (isotropic W = sI: G carries 1/s and
+// Kt_c = w det W K_c).  The product (d_l w_i)(d_m w_i) of two tensor-product
+// gradients is again a tensor product, of the squared tables BB = B^2,
+// BG = B G, GG = G^2, so the diagonal is a transposed sum-factorized
+// contraction of the d(d+1)/2 fields Kt_c,lm (times 2 for l != m) per
+// component, with the table of pair (l, m) in direction d being GG if
+// l = m = d, BG if exactly one of l, m is d, else BB.
+template <int P, int Q, typename R>
+struct DiagArgs : ElemArgs<P, Q, R> {
+  R BB[Q][P];
+  R BG[Q][P];
+  R GG[Q][P];
+};
+
+// 3D pairs (l, m): 0 (0,0), 1 (1,1), 2 (2,2), 3 (0,1), 4 (0,2), 5 (1,2).
+//   x tables: GG BB BB BG BG BB;  y tables: BB GG BB BG BB BG;
+//   z tables: BB BB GG BB BG BG, so after the y-pass the pairs merge into
+//   three z-groups: BB (pairs 0, 1, 3), BG (4, 5), GG (2).
+// LDS per element: U of the forward passes, then per component the
+// x-transposed sums R6 [q2][i0][pair][q1] and the y-transposed sums
+// S3 [i0][i1][q2][group].
+template <int P, int Q> struct LdsDiag3 {
+  static constexpr int NR = Q * P * 6 * Q;
+  static constexpr int NS = P * P * Q * 3;
+  static constexpr int N = Lds3<P, Q>::NU > NR + NS ? Lds3<P, Q>::NU : NR + NS;
+  static __device__ __forceinline__ constexpr int r(int q2, int i0, int pr, int q1) {
+    return ((q2 * P + i0) * 6 + pr) * Q + q1;
+  }
+  static __device__ __forceinline__ constexpr int s(int i0, int i1, int q2) { return NR + ((i0 * P + i1) * Q + q2) * 3; }
+};
+
+// K_c <- W^{-1} K_c W^{-t} (general constant target), K_c symmetric and
+// stored as its unique entries (SymPairs order)
+template <int D, typename R>
+__device__ __forceinline__ void target_congruence(const R (&Wi)[3][3], R (&K6)[D][SymPairs<D>::N]) {
+  using SP = SymPairs<D>;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    R K[D][D], M[D][D];
+#pragma unroll
+    for (int pr = 0; pr < SP::N; ++pr) {
+      K[SP::l[pr]][SP::m[pr]] = K6[c][pr];
+      K[SP::m[pr]][SP::l[pr]] = K6[c][pr];
+    }
+#pragma unroll
+    for (int l = 0; l < D; ++l)
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        R t = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) t += K[l][k] * Wi[m][k];
+        M[l][m] = t;                         // (K_c W^{-t})_lm
+      }
+#pragma unroll
+    for (int pr = 0; pr < SP::N; ++pr) {
+      R t = 0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) t += Wi[SP::l[pr]][k] * M[k][SP::m[pr]];
+      K6[c][pr] = t;
+    }
+  }
+}
+
+template <int P, int Q, int METRIC, typename R, bool ISO>
+__global__ void __launch_bounds__((Cfg<3, P, Q, R>::BLOCK))
+diag_kernel_3d(const DiagArgs<P, Q, R> a) {
+  using C = Cfg<3, P, Q, R>;
+  using LD = LdsDiag3<P, Q>;
+  constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P * P;
+  constexpr bool AFFINE = sizeof(R) == 4;
+  constexpr int NE = LD::N + TMOP_ELEM_PAD;
+  __shared__ R s_all[EPB * NE];
+
+  const int tid = threadIdx.x;
+  const int le_raw = tid / TPE;
+  const int le = le_raw < EPB ? le_raw : EPB - 1;
+  const int t = tid - le_raw * TPE;
+  const int ta = le_raw < EPB ? t % Q : Q;
+  const int tb = le_raw < EPB ? t / Q : Q;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int k = blk * EPB + le;
+  const bool active = le_raw < EPB && k < a.n_list;
+  const int kk = k < a.n_list ? k : a.n_list - 1;
+  const int e = a.list ? a.list[kk] : kk;
+  R* s = s_all + le * NE;
+  const bool p1 = ta < P && tb < P;
+
+  const int32_t* en = a.elem_node + (int64_t)e * NPE;
+  int node[P];
+#pragma unroll
+  for (int i2 = 0; i2 < P; ++i2) node[i2] = p1 ? en[ta + P * tb + P * P * i2] : en[0];
+  R X[3][P], J0x[3][3];
+  load_pencil_3d<P, Q, R, AFFINE>(a, a.x, node, en, p1 ? ta : 0, p1 ? tb : 0, X, J0x);
+
+  R Bq[P], Gq[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) { Bq[i] = a.B[0][i]; Gq[i] = a.G[0][i]; }
+#pragma unroll
+  for (int q = 1; q < Q; ++q)
+    if (ta == q) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) { Bq[i] = a.B[q][i]; Gq[i] = a.G[q][i]; }
+    }
+  R V[3][3][P];
+  fwd_3d<P, Q, R>(a, X, ta, tb, Bq, Gq, s, V);
+  __builtin_amdgcn_sched_barrier(0);
+
+  // x-transposed sums of the six pair fields, lane (q1, q2)
+  R Rd[6][3][P];
+#pragma unroll
+  for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i0 = 0; i0 < P; ++i0) Rd[pr][c][i0] = 0;
+  if (tb < Q) {
+    const double w12 = a.w[ta] * a.w[tb] * a.detW;
+#pragma unroll
+    for (int q0 = 0; q0 < Q; ++q0) {
+      R A[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        R s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+        for (int i0 = 0; i0 < P; ++i0) {
+          s0 += a.G[q0][i0] * V[0][c][i0];
+          s1 += a.B[q0][i0] * V[1][c][i0];
+          s2 += a.B[q0][i0] * V[2][c][i0];
+        }
+        if constexpr (AFFINE) { s0 += J0x[c][0]; s1 += J0x[c][1]; s2 += J0x[c][2]; }
+        A[c][0] = s0; A[c][1] = s1; A[c][2] = s2;
+      }
+      R T[3][3], K[3][6];
+      right_mul<3, R, ISO>(A, a.Winv, T);
+      mu_second_rows<METRIC, R>(T, (R)(w12 * a.w[q0]), K);
+      if constexpr (!ISO) target_congruence<3, R>(a.Winv, K);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const R f0 = K[c][0], f1 = K[c][1], f2 = K[c][2];
+        const R f3 = R(2) * K[c][3], f4 = R(2) * K[c][4], f5 = R(2) * K[c][5];
+#pragma unroll
+        for (int i0 = 0; i0 < P; ++i0) {
+          Rd[0][c][i0] += a.GG[q0][i0] * f0;
+          Rd[1][c][i0] += a.BB[q0][i0] * f1;
+          Rd[2][c][i0] += a.BB[q0][i0] * f2;
+          Rd[3][c][i0] += a.BG[q0][i0] * f3;
+          Rd[4][c][i0] += a.BG[q0][i0] * f4;
+          Rd[5][c][i0] += a.BB[q0][i0] * f5;
+        }
+      }
+    }
+  }
+
+  bool fresh[P];
+#pragma unroll
+  for (int i2 = 0; i2 < P; ++i2) fresh[i2] = first_touch<NPE>(a.first, kk, ta + P * tb + P * P * i2);
+  __syncthreads();   // U is dead
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    // this component's old values, loaded before the passes that hide them
+    double old[P];
+    if (active && p1) {
+#pragma unroll
+      for (int i2 = 0; i2 < P; ++i2) old[i2] = fresh[i2] ? 0.0 : a.out[c * a.n_node + node[i2]];
+    }
+    if (tb < Q) {    // lane (q1, q2) hands over its x-transposed sums
+#pragma unroll
+      for (int i0 = 0; i0 < P; ++i0)
+#pragma unroll
+        for (int pr = 0; pr < 6; ++pr) s[LD::r(tb, i0, pr, ta)] = Rd[pr][c][i0];
+    }
+    __syncthreads();
+    if (ta < P && tb < Q) {   // lane (i0 = ta, q2 = tb): y-transposed, grouped by z table
+      R r[6][Q];
+#pragma unroll
+      for (int pr = 0; pr < 6; ++pr)
+#pragma unroll
+        for (int q1 = 0; q1 < Q; ++q1) r[pr][q1] = s[LD::r(tb, ta, pr, q1)];
+#pragma unroll
+      for (int i1 = 0; i1 < P; ++i1) {
+        R gbb = 0, gbg = 0, ggg = 0;
+#pragma unroll
+        for (int q1 = 0; q1 < Q; ++q1) {
+          gbb += a.BB[q1][i1] * r[0][q1] + a.GG[q1][i1] * r[1][q1] + a.BG[q1][i1] * r[3][q1];
+          gbg += a.BB[q1][i1] * r[4][q1] + a.BG[q1][i1] * r[5][q1];
+          ggg += a.BB[q1][i1] * r[2][q1];
+        }
+        R* p = s + LD::s(ta, i1, tb);
+        p[0] = gbb;
+        p[1] = gbg;
+        p[2] = ggg;
+      }
+    }
+    __syncthreads();
+    if (active && p1) {       // lane (i0 = ta, i1 = tb): z-transposed, then the scatter
+      R gbb[Q], gbg[Q], ggg[Q];
+#pragma unroll
+      for (int q2 = 0; q2 < Q; ++q2) {
+        const R* p = s + LD::s(ta, tb, q2);
+        gbb[q2] = p[0];
+        gbg[q2] = p[1];
+        ggg[q2] = p[2];
+      }
+#pragma unroll
+      for (int i2 = 0; i2 < P; ++i2) {
+        R v = 0;
+#pragma unroll
+        for (int q2 = 0; q2 < Q; ++q2) v += a.BB[q2][i2] * gbb[q2] + a.BG[q2][i2] * gbg[q2] + a.GG[q2][i2] * ggg[q2];
+        a.out[c * a.n_node + node[i2]] = old[i2] + (double)v;
+      }
+    }
+  }
+}
+
+// 2D pairs (l, m): 0 (0,0), 1 (1,1), 2 (0,1); x tables GG BB BG, y tables
+// BB GG BG.  LDS: the forward U, then the x-transposed sums [pair][c][q1][i0].
+template <int P, int Q, int METRIC, typename R, bool ISO>
+__global__ void __launch_bounds__((Cfg<2, P, Q, R>::BLOCK))
+diag_kernel_2d(const DiagArgs<P, Q, R> a) {
+  using C = Cfg<2, P, Q, R>;
+  constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P;
+  constexpr bool AFFINE = sizeof(R) == 4;
+  constexpr int NU = 2 * 2 * Q * P, NRD = 3 * 2 * Q * P;
+  constexpr int NE = NU > NRD ? NU : NRD;
+  __shared__ R s_all[EPB * NE];
+
+  const int tid = threadIdx.x;
+  const int le_raw = tid / TPE;
+  const int le = le_raw < EPB ? le_raw : EPB - 1;
+  const int ta = le_raw < EPB ? tid - le_raw * TPE : Q;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int k = blk * EPB + le;
+  const bool active = le_raw < EPB && k < a.n_list;
+  const int kk = k < a.n_list ? k : a.n_list - 1;
+  const int e = a.list ? a.list[kk] : kk;
+  R* s = s_all + le * NE;
+  const bool p1 = ta < P;
+
+  const int32_t* en = a.elem_node + (int64_t)e * NPE;
+  int node[P];
+#pragma unroll
+  for (int i1 = 0; i1 < P; ++i1) node[i1] = p1 ? en[ta + P * i1] : en[0];
+  R X[2][P], J0x[2][2];
+  load_pencil_2d<P, Q, R, AFFINE>(a, a.x, node, en, p1 ? ta : 0, X, J0x);
+  R U[2][2][P];
+  fwd_2d<P, Q, R>(a, X, ta, s, U);
+
+  R Rd[3][2][P];
+#pragma unroll
+  for (int pr = 0; pr < 3; ++pr)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int i0 = 0; i0 < P; ++i0) Rd[pr][c][i0] = 0;
+  if (ta < Q) {   // lane q1 = ta
+    const double w1 = a.w[ta] * a.detW;
+#pragma unroll
+    for (int q0 = 0; q0 < Q; ++q0) {
+      R A[2][2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        R s0 = 0, s1 = 0;
+#pragma unroll
+        for (int i0 = 0; i0 < P; ++i0) { s0 += a.G[q0][i0] * U[0][c][i0]; s1 += a.B[q0][i0] * U[1][c][i0]; }
+        if constexpr (AFFINE) { s0 += J0x[c][0]; s1 += J0x[c][1]; }
+        A[c][0] = s0; A[c][1] = s1;
+      }
+      R T[2][2], K[2][3];
+      right_mul<2, R, ISO>(A, a.Winv, T);
+      mu_second_rows<METRIC, R>(T, (R)(w1 * a.w[q0]), K);
+      if constexpr (!ISO) target_congruence<2, R>(a.Winv, K);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const R f0 = K[c][0], f1 = K[c][1], f2 = R(2) * K[c][2];
+#pragma unroll
+        for (int i0 = 0; i0 < P; ++i0) {
+          Rd[0][c][i0] += a.GG[q0][i0] * f0;
+          Rd[1][c][i0] += a.BB[q0][i0] * f1;
+          Rd[2][c][i0] += a.BG[q0][i0] * f2;
+        }
+      }
+    }
+  }
+
+  double old[2][P];
+  if (active && p1) {
+#pragma unroll
+    for (int i1 = 0; i1 < P; ++i1) {
+      const bool fresh = first_touch<NPE>(a.first, kk, ta + P * i1);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) old[c][i1] = fresh ? 0.0 : a.out[c * a.n_node + node[i1]];
+    }
+  }
+  __syncthreads();   // U is dead
+  if (ta < Q) {
+#pragma unroll
+    for (int pr = 0; pr < 3; ++pr)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int i0 = 0; i0 < P; ++i0) s[((pr * 2 + c) * Q + ta) * P + i0] = Rd[pr][c][i0];
+  }
+  __syncthreads();
+  if (active && p1) {   // lane i0 = ta: y-transposed, then the scatter
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      R r[3][Q];
+#pragma unroll
+      for (int pr = 0; pr < 3; ++pr)
+#pragma unroll
+        for (int q1 = 0; q1 < Q; ++q1) r[pr][q1] = s[((pr * 2 + c) * Q + q1) * P + ta];
+#pragma unroll
+      for (int i1 = 0; i1 < P; ++i1) {
+        R v = 0;
+#pragma unroll
+        for (int q1 = 0; q1 < Q; ++q1)
+          v += a.BB[q1][i1] * r[0][q1] + a.GG[q1][i1] * r[1][q1] + a.BG[q1][i1] * r[2][q1];
+        a.out[c * a.n_node + node[i1]] = old[c][i1] + (double)v;
+      }
+    }
+  }
+}
+
 }  // namespace tmop

@@ -1,8 +1,9 @@
-// Element kernels, 2D, double contractions.
+// Element kernels, 2D, double contractions: metrics mu_1, mu_2, mu_7, mu_9.
 #include "tmop_launch.h"
 
 namespace tmop {
 int launch_elem_2d_f64(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid) {
-  return launch_dispatch<2, double>(p, Q, metric, op, lp, s, grid);
+  if (metric == 14 || metric == 77 || metric == 98) return launch_elem_2d_f64_b(p, Q, metric, op, lp, s, grid);
+  return launch_dispatch<2, double, 0>(p, Q, metric, op, lp, s, grid);
 }
 }  // namespace tmop

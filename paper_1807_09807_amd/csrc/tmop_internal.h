@@ -8,9 +8,9 @@
 
 namespace tmop {
 
-// Element operations: F and min det A (eq. 2.4), dF/dx, (d^2F/dx^2) v, and
-// F, min det A and dF/dx in one pass.
-enum { OP_ENERGY = 0, OP_GRAD = 1, OP_HESS = 2, OP_EG = 3 };
+// Element operations: F and min det A (eq. 2.4), dF/dx, (d^2F/dx^2) v,
+// F, min det A and dF/dx in one pass, and the diagonal of d^2F/dx^2.
+enum { OP_ENERGY = 0, OP_GRAD = 1, OP_HESS = 2, OP_EG = 3, OP_DIAG = 4 };
 
 constexpr int MAXP = 5;   // nodes per direction (order p <= 4)
 constexpr int MAXQ = 6;   // quadrature points per direction
@@ -46,6 +46,8 @@ struct LaunchParams {
 // lp.part[0, grid) and lp.part_min[0, grid) (OP_ENERGY, OP_EG).
 int launch_elem_2d_f64(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
 int launch_elem_2d_f32(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
+int launch_elem_2d_f64_b(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
+int launch_elem_2d_f32_b(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
 int launch_elem_3d_f64(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
 int launch_elem_3d_f32(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
 bool elem_supported(int dim, int p, int Q);
@@ -61,6 +63,13 @@ constexpr int FIN_BLOCKS = 256;
 hipError_t finalize_sum_min(const double* part, int n, int moff, double* scratch, double* res, hipStream_t s);
 // res[0] = x . y   (scratch: >= RED_BLOCKS doubles)
 hipError_t dot(const double* x, const double* y, int64_t n, double* scratch, double* res, hipStream_t s);
+// res[0] = x . y, res[1] = x . z   (scratch: >= 2 RED_BLOCKS doubles)
+hipError_t dot2(const double* x, const double* y, const double* z, int64_t n, double* scratch, double* res,
+                hipStream_t s);
+hipError_t mul(const double* a, const double* x, double* y, int64_t n, hipStream_t s);    // y = a .* x
+hipError_t jacobi_inv(const double* m, double* d, int64_t n, hipStream_t s);              // d = m && d ? 1/|d| : 1
+hipError_t minres_w(const double* v, double a, double* w, double b, const double* u, double sc, int64_t n,
+                    hipStream_t s);                                                        // w = (v - a w - b u) sc
 hipError_t axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);          // y += a x
 hipError_t xpay(const double* x, double a, double* y, int64_t n, hipStream_t s);          // y = x + a y
 hipError_t waxpy(const double* x, double a, const double* d, double* w, int64_t n, hipStream_t s);  // w = x + a d
@@ -86,7 +95,7 @@ struct tmop_ctx {
   double* d_mask = nullptr;            // [n_dof], 1 = free DOF
   bool has_fixed = false;
   double* d_part = nullptr;            // [2 * n_elem] energy partials
-  double* d_scratch = nullptr;         // [RED_BLOCKS] dot partials
+  double* d_scratch = nullptr;         // [2 * RED_BLOCKS] dot partials
   double* d_res = nullptr;             // [4] reduction results
   double* h_res = nullptr;             // [4] pinned mirror
   double* d_work = nullptr;            // Newton work vectors, allocated on first use
@@ -95,6 +104,6 @@ struct tmop_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev_free;
   std::vector<TimedLaunch> ev_pending;
-  double t_ms[4] = {0.0, 0.0, 0.0, 0.0};      // per op: energy, gradient, Hessian action, energy+gradient
-  int64_t t_launches[4] = {0, 0, 0, 0};
+  double t_ms[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // per op: energy, gradient, Hessian action, energy+gradient,
+  int64_t t_launches[5] = {0, 0, 0, 0, 0};       // Hessian diagonal
 };

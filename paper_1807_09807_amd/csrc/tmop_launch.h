@@ -11,7 +11,7 @@ namespace tmop {
 template <int DIM, int P, int Q, int METRIC, typename R, int OP, bool ISO>
 static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   using C = Cfg<DIM, P, Q, R>;
-  ElemArgs<P, Q, R> a;
+  DiagArgs<P, Q, R> a;   // the element kernels take its ElemArgs part
   a.x = lp.x; a.v = lp.v; a.out = lp.out;
   a.elem_node = lp.elem_node; a.list = lp.list; a.first = lp.first; a.part = lp.part; a.part_min = lp.part_min; a.scale = lp.scale;
   a.n_node = lp.n_node; a.n_list = lp.n_list;
@@ -30,8 +30,22 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   const int g = (lp.n_list + C::EPB - 1) / C::EPB;
   *grid = g;
   if (g == 0) return 0;
-  if constexpr (DIM == 3) hipLaunchKernelGGL((elem_kernel_3d<P, Q, METRIC, R, OP, ISO>), dim3(g), dim3(C::BLOCK), 0, s, a);
-  else hipLaunchKernelGGL((elem_kernel_2d<P, Q, METRIC, R, OP, ISO>), dim3(g), dim3(C::BLOCK), 0, s, a);
+  if constexpr (OP == OP_DIAG) {
+    // products of the 1D tables for the squared gradients of the diagonal
+    for (int q = 0; q < Q; ++q)
+      for (int i = 0; i < P; ++i) {
+        const double b = lp.B[q][i], gg = lp.G[q][i] * gs;
+        a.BB[q][i] = (R)(b * b);
+        a.BG[q][i] = (R)(b * gg);
+        a.GG[q][i] = (R)(gg * gg);
+      }
+    if constexpr (DIM == 3) hipLaunchKernelGGL((diag_kernel_3d<P, Q, METRIC, R, ISO>), dim3(g), dim3(C::BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((diag_kernel_2d<P, Q, METRIC, R, ISO>), dim3(g), dim3(C::BLOCK), 0, s, a);
+  } else {
+    const ElemArgs<P, Q, R>& ea = a;
+    if constexpr (DIM == 3) hipLaunchKernelGGL((elem_kernel_3d<P, Q, METRIC, R, OP, ISO>), dim3(g), dim3(C::BLOCK), 0, s, ea);
+    else hipLaunchKernelGGL((elem_kernel_2d<P, Q, METRIC, R, OP, ISO>), dim3(g), dim3(C::BLOCK), 0, s, ea);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -41,26 +55,50 @@ static int launch_op(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
   if (op == OP_GRAD) return launch_one<DIM, P, Q, M, R, OP_GRAD, ISO>(lp, s, grid);
   if (op == OP_HESS) return launch_one<DIM, P, Q, M, R, OP_HESS, ISO>(lp, s, grid);
   if (op == OP_EG) return launch_one<DIM, P, Q, M, R, OP_EG, ISO>(lp, s, grid);
+  if (op == OP_DIAG) return launch_one<DIM, P, Q, M, R, OP_DIAG, ISO>(lp, s, grid);
   return -1;
 }
 
-template <int DIM, int P, int Q, typename R>
+template <int DIM, int P, int Q, int M, typename R>
+static int launch_metric(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
+  return lp.iso ? launch_op<DIM, P, Q, M, R, true>(op, lp, s, grid) : launch_op<DIM, P, Q, M, R, false>(op, lp, s, grid);
+}
+
+// The metrics of each dimension (Table 3.1, Sections 3.2 and 4.3; mu_302 in
+// 3D).  The 2D metrics come in two groups, instantiated by separate
+// translation units so that they compile in parallel.
+template <int DIM, int GROUP, int P, int Q, typename R>
 static int launch_pq(int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid) {
-  constexpr int M0 = DIM == 2 ? 2 : 302;
-  constexpr int M1 = DIM == 2 ? 7 : 303;
-  if (metric == M0)
-    return lp.iso ? launch_op<DIM, P, Q, M0, R, true>(op, lp, s, grid) : launch_op<DIM, P, Q, M0, R, false>(op, lp, s, grid);
-  if (metric == M1)
-    return lp.iso ? launch_op<DIM, P, Q, M1, R, true>(op, lp, s, grid) : launch_op<DIM, P, Q, M1, R, false>(op, lp, s, grid);
-  return -1;
+  if constexpr (DIM == 2 && GROUP == 0) {
+    switch (metric) {
+      case 1: return launch_metric<2, P, Q, 1, R>(op, lp, s, grid);
+      case 2: return launch_metric<2, P, Q, 2, R>(op, lp, s, grid);
+      case 7: return launch_metric<2, P, Q, 7, R>(op, lp, s, grid);
+      case 9: return launch_metric<2, P, Q, 9, R>(op, lp, s, grid);
+      default: return -1;
+    }
+  } else if constexpr (DIM == 2) {
+    switch (metric) {
+      case 14: return launch_metric<2, P, Q, 14, R>(op, lp, s, grid);
+      case 77: return launch_metric<2, P, Q, 77, R>(op, lp, s, grid);
+      case 98: return launch_metric<2, P, Q, 98, R>(op, lp, s, grid);
+      default: return -1;
+    }
+  } else {
+    switch (metric) {
+      case 302: return launch_metric<3, P, Q, 302, R>(op, lp, s, grid);
+      case 303: return launch_metric<3, P, Q, 303, R>(op, lp, s, grid);
+      default: return -1;
+    }
+  }
 }
 
 // Orders p = 1..4 with Q = p+1 (the minimum of Section 3.3) and Q = p+2.
-template <int DIM, typename R>
+template <int DIM, typename R, int GROUP = 0>
 static int launch_dispatch(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid) {
   const int P = p + 1;
 #define TMOP_PQ(P_, Q_) \
-  if (P == P_ && Q == Q_) return launch_pq<DIM, P_, Q_, R>(metric, op, lp, s, grid);
+  if (P == P_ && Q == Q_) return launch_pq<DIM, GROUP, P_, Q_, R>(metric, op, lp, s, grid);
   TMOP_PQ(2, 2) TMOP_PQ(2, 3)
   TMOP_PQ(3, 3) TMOP_PQ(3, 4)
   TMOP_PQ(4, 4) TMOP_PQ(4, 5)

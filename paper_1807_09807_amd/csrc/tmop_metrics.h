@@ -2,16 +2,18 @@
 //
 // Section 3.2 / Table 3.1 define the metrics; Section 3.4 recommends writing
 // them through matrix invariants so that first and second derivatives are
-// easy to form.  Every metric here is mu = f(I1, I2, tau) with
+// easy to form.  Every metric here is mu = f(I1, I2, tau, J) with
 //   I1 = |T|^2, tau = det T, C = cof T = d tau / dT, I2 = |C|^2 (3D only),
+//   J = tr T (the metrics measured against T = I, dJ/dT = Id),
 // and the derivatives follow from the chain rule:
-//   P  = dmu/dT = 2 f1 T + f2 dI2 + ft C,            dI2 = 2 (I1 T - T T^t T)
+//   P  = dmu/dT = 2 f1 T + f2 dI2 + ft C + fJ Id,    dI2 = 2 (I1 T - T T^t T)
 //   dP = d/de P(T + e E)
 //      = 2 f1 E + f2 ddI2[E] + ft dC[E]
 //        + 2T (f11 a1 + f12 a2 + f1t at) + dI2 (f12 a1 + f22 a2 + f2t at)
-//        + C (f1t a1 + f2t a2 + ftt at),
-//   a1 = 2 T:E, a2 = dI2:E, at = C:E,
-//   ddI2[E] = 2 (2 (T:E) T + I1 E - E T^t T - T E^t T - T T^t E).
+//        + C (f1t a1 + f2t a2 + ftt at + fJt aJ) + Id fJt at,
+//   a1 = 2 T:E, a2 = dI2:E, at = C:E, aJ = tr E,
+//   ddI2[E] = 2 (2 (T:E) T + I1 E - E T^t T - T E^t T - T T^t E)
+// (f11 = f22 = f1J = fJJ = 0 for every metric here).
 // Metric values avoid the cancellation of "... - 1" where an exact identity
 // allows it (2D: |T|^2 - 2 det T = (T00 - T11)^2 + (T01 + T10)^2).
 #pragma once
@@ -87,18 +89,42 @@ __device__ __forceinline__ R det(const R T[D][D]) {
 
 // Partial derivatives of f(I1, I2, tau).  Flags tell which ones are
 // identically zero so the compiler drops their terms.
-template <typename R> struct Partials { R f1, f2, ft, f11, f12, f1t, f22, f2t, ftt; };
+template <typename R> struct Partials { R f1, f2, ft, fJ, f11, f12, f1t, f22, f2t, ftt, fJt; };
 
+// dim, whether f depends on I2, whether it depends on J = tr T
 template <int METRIC> struct MetricInfo;
-template <> struct MetricInfo<2>   { static constexpr int dim = 2; static constexpr bool i2 = false; };
-template <> struct MetricInfo<7>   { static constexpr int dim = 2; static constexpr bool i2 = false; };
-template <> struct MetricInfo<302> { static constexpr int dim = 3; static constexpr bool i2 = true; };
-template <> struct MetricInfo<303> { static constexpr int dim = 3; static constexpr bool i2 = false; };
+template <> struct MetricInfo<1>   { static constexpr int dim = 2; static constexpr bool i2 = false, tr = false; };
+template <> struct MetricInfo<2>   { static constexpr int dim = 2; static constexpr bool i2 = false, tr = false; };
+template <> struct MetricInfo<7>   { static constexpr int dim = 2; static constexpr bool i2 = false, tr = false; };
+template <> struct MetricInfo<9>   { static constexpr int dim = 2; static constexpr bool i2 = false, tr = false; };
+template <> struct MetricInfo<14>  { static constexpr int dim = 2; static constexpr bool i2 = false, tr = true; };
+template <> struct MetricInfo<77>  { static constexpr int dim = 2; static constexpr bool i2 = false, tr = false; };
+template <> struct MetricInfo<98>  { static constexpr int dim = 2; static constexpr bool i2 = false, tr = true; };
+template <> struct MetricInfo<302> { static constexpr int dim = 3; static constexpr bool i2 = true, tr = false; };
+template <> struct MetricInfo<303> { static constexpr int dim = 3; static constexpr bool i2 = false, tr = false; };
 
 template <int METRIC, typename R>
-__device__ __forceinline__ Partials<R> partials(R I1, R I2, R tau) {
+__device__ __forceinline__ Partials<R> partials(R I1, R I2, R tau, R J = R(0)) {
   Partials<R> p{};
-  if constexpr (METRIC == 2) {            // f = I1 / (2 tau) - 1
+  if constexpr (METRIC == 1) {            // f = I1
+    p.f1 = R(1);
+  } else if constexpr (METRIC == 9) {     // f = tau I1 + I1 / tau - 4 tau  (tau |T - T^-t|^2 in 2D)
+    const R rt = rcp(tau);
+    const R rt2 = rt * rt;
+    p.f1 = tau + rt;  p.ft = I1 - I1 * rt2 - R(4);
+    p.f1t = R(1) - rt2;  p.ftt = R(2) * I1 * rt2 * rt;
+  } else if constexpr (METRIC == 77) {    // f = (tau - 1/tau)^2 / 2
+    const R rt = rcp(tau);
+    const R rt2 = rt * rt;
+    p.ft = (tau - rt) * (R(1) + rt2);  p.ftt = R(1) + R(3) * rt2 * rt2;
+  } else if constexpr (METRIC == 14) {    // f = I1 - 2 J + 2  (|T - I|^2)
+    p.f1 = R(1);  p.fJ = R(-2);
+  } else if constexpr (METRIC == 98) {    // f = (I1 - 2 J + 2) / tau  (|T - I|^2 / tau)
+    const R rt = rcp(tau);
+    const R n = I1 - R(2) * J + R(2);
+    p.f1 = rt;  p.fJ = R(-2) * rt;  p.ft = -n * rt * rt;
+    p.f1t = -rt * rt;  p.fJt = R(2) * rt * rt;  p.ftt = R(2) * n * rt * rt * rt;
+  } else if constexpr (METRIC == 2) {     // f = I1 / (2 tau) - 1
     const R rt = rcp(tau);
     const R rt2 = rt * rt;
     p.f1 = R(0.5) * rt;  p.ft = R(-0.5) * I1 * rt2;
@@ -130,12 +156,23 @@ __device__ __forceinline__ Partials<R> partials(R I1, R I2, R tau) {
 template <int METRIC, typename R>
 __device__ __forceinline__ R mu_value(const R (&T)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim], R tau) {
   constexpr int D = MetricInfo<METRIC>::dim;
-  if constexpr (METRIC == 2 || METRIC == 7) {
+  if constexpr (METRIC == 2 || METRIC == 7 || METRIC == 9) {
     const R u = T[0][0] - T[1][1], w = T[0][1] + T[1][0];
     const R dev = u * u + w * w;                 // |T|^2 - 2 tau >= 0
     const R rt = rcp(tau);
     if constexpr (METRIC == 2) return R(0.5) * dev * rt;
-    else return dev * (R(1) + rt * rt) + R(2) * (tau - R(1)) * (tau - R(1)) * rt;
+    else if constexpr (METRIC == 7) return dev * (R(1) + rt * rt) + R(2) * (tau - R(1)) * (tau - R(1)) * rt;
+    else return dev * (tau + rt) + R(2) * (tau - R(1)) * (tau - R(1));
+  } else if constexpr (METRIC == 1) {
+    return T[0][0] * T[0][0] + T[0][1] * T[0][1] + T[1][0] * T[1][0] + T[1][1] * T[1][1];
+  } else if constexpr (METRIC == 77) {
+    const R s = tau - rcp(tau);
+    return R(0.5) * s * s;
+  } else if constexpr (METRIC == 14 || METRIC == 98) {
+    const R a = T[0][0] - R(1), b = T[1][1] - R(1);
+    const R n = a * a + b * b + T[0][1] * T[0][1] + T[1][0] * T[1][0];
+    if constexpr (METRIC == 14) return n;
+    else return n * rcp(tau);
   } else {
     R I1 = 0;
 #pragma unroll
@@ -197,14 +234,18 @@ __device__ __forceinline__ void mu_first(const R (&T)[MetricInfo<METRIC>::dim][M
     for (int j = 0; j < D; ++j) I1 += T[i][j] * T[i][j];
 #pragma unroll
   for (int j = 0; j < D; ++j) tau += T[0][j] * C[0][j];
-  R I2 = 0;
+  R I2 = 0, J = 0;
   if constexpr (MetricInfo<METRIC>::i2) {
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int j = 0; j < D; ++j) I2 += C[i][j] * C[i][j];
   }
-  const Partials<R> f = partials<METRIC, R>(I1, I2, tau);
+  if constexpr (MetricInfo<METRIC>::tr) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) J += T[i][i];
+  }
+  const Partials<R> f = partials<METRIC, R>(I1, I2, tau, J);
   const R k1 = R(2) * k * f.f1, kt = k * f.ft;
   if constexpr (MetricInfo<METRIC>::i2) {
     R dI2[D][D];
@@ -219,6 +260,11 @@ __device__ __forceinline__ void mu_first(const R (&T)[MetricInfo<METRIC>::dim][M
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int j = 0; j < D; ++j) P[i][j] = k1 * T[i][j] + kt * C[i][j];
+  }
+  if constexpr (MetricInfo<METRIC>::tr) {
+    const R kJ = k * f.fJ;
+#pragma unroll
+    for (int i = 0; i < D; ++i) P[i][i] += kJ;
   }
 }
 
@@ -243,16 +289,27 @@ __device__ __forceinline__ void mu_second(const R (&T)[MetricInfo<METRIC>::dim][
 #pragma unroll
   for (int j = 0; j < D; ++j) tau += T[0][j] * C[0][j];
   if constexpr (!MetricInfo<METRIC>::i2) {
-    const Partials<R> f = partials<METRIC, R>(I1, R(0), tau);
+    R J = 0, aJ = 0;
+    if constexpr (MetricInfo<METRIC>::tr) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) { J += T[i][i]; aJ += E[i][i]; }
+    }
+    const Partials<R> f = partials<METRIC, R>(I1, R(0), tau, J);
     const R a1 = R(2) * TE, at = CE;
     const R kE = R(2) * k * f.f1, kd = k * f.ft;
     const R sT = R(2) * k * (f.f1t * at);         // f11 = 0 for these metrics
-    const R sC = k * (f.f1t * a1 + f.ftt * at);
+    R sC = k * (f.f1t * a1 + f.ftt * at);
+    if constexpr (MetricInfo<METRIC>::tr) sC += k * f.fJt * aJ;
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int j = 0; j < D; ++j)
         dP[i][j] = kE * E[i][j] + kd * dC[i][j] + sT * T[i][j] + sC * C[i][j];
+    if constexpr (MetricInfo<METRIC>::tr) {
+      const R sI = k * f.fJt * at;
+#pragma unroll
+      for (int i = 0; i < D; ++i) dP[i][i] += sI;
+    }
   } else {
     R I2 = 0;
 #pragma unroll
@@ -315,6 +372,93 @@ __device__ __forceinline__ void mu_second(const R (&T)[MetricInfo<METRIC>::dim][
         dP[i][j] = kE * E[i][j] + k2 * ddI2 + kd * dC[i][j]
                  + sT * T[i][j] + sI * dI2[i][j] + sC * C[i][j];
       }
+  }
+}
+
+// Diagonal row blocks of the second derivative:
+//   K[c][l][m] = k d^2 mu / (dT_cl dT_cm),
+// the part of mu'' that a rank-one direction E = e_c g^T (one row of T
+// moves) sees: E : mu''[E] = g^T K[c] g.  With E = e_c e_l^T and
+// E' = e_c e_m^T the chain rule above gives, since det T is linear in each
+// row (dC[E] : E' = 0) and
+//   ddI2[E] : E' = 2 (T_cl T_cm + (I1 - |row c of T|^2) delta_lm - (T^t T)_lm),
+//   K[c][l][m] = k (2 f1 delta_lm + f2 ddI2[E] : E' + sum_ab f_ab a_a(c,l) a_b(c,m)),
+// a(c,l) = (2 T_cl, dI2_cl, C_cl, delta_cl) for (I1, I2, tau, J).
+// K[c] is symmetric; its unique entries go to K6[c][pr] in the pair order
+// (0,0), (1,1), (0,1) (2D) or (0,0), (1,1), (2,2), (0,1), (0,2), (1,2) (3D).
+template <int D> struct SymPairs;
+template <> struct SymPairs<2> {
+  static constexpr int N = 3;
+  static constexpr int l[3] = {0, 1, 0}, m[3] = {0, 1, 1};
+};
+template <> struct SymPairs<3> {
+  static constexpr int N = 6;
+  static constexpr int l[6] = {0, 1, 2, 0, 0, 1}, m[6] = {0, 1, 2, 1, 2, 2};
+};
+
+template <int METRIC, typename R>
+__device__ __forceinline__ void mu_second_rows(const R (&T)[MetricInfo<METRIC>::dim][MetricInfo<METRIC>::dim], R k,
+                                               R (&K6)[MetricInfo<METRIC>::dim][SymPairs<MetricInfo<METRIC>::dim>::N]) {
+  constexpr int D = MetricInfo<METRIC>::dim;
+  using SP = SymPairs<D>;
+  R C[D][D];
+  cofactor<D, R>(T, C);
+  R I1 = 0, tau = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) I1 += T[i][j] * T[i][j];
+#pragma unroll
+  for (int j = 0; j < D; ++j) tau += T[0][j] * C[0][j];
+  if constexpr (!MetricInfo<METRIC>::i2) {
+    R J = 0;
+    if constexpr (MetricInfo<METRIC>::tr) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) J += T[i][i];
+    }
+    const Partials<R> f = partials<METRIC, R>(I1, R(0), tau, J);
+    const R kE = R(2) * k * f.f1, k1t = R(2) * k * f.f1t, ktt = k * f.ftt, kJt = k * f.fJt;
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+      for (int pr = 0; pr < SP::N; ++pr) {
+        const int l = SP::l[pr], m = SP::m[pr];
+        K6[c][pr] = (l == m ? kE : R(0)) + k1t * (T[c][l] * C[c][m] + C[c][l] * T[c][m]) + ktt * C[c][l] * C[c][m];
+        // d J / dT_cl = delta_cl
+        if constexpr (MetricInfo<METRIC>::tr)
+          K6[c][pr] += kJt * ((c == l ? C[c][m] : R(0)) + (c == m ? C[c][l] : R(0)));
+      }
+  } else {
+    R I2 = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) I2 += C[i][j] * C[i][j];
+    const Partials<R> f = partials<METRIC, R>(I1, I2, tau);
+    R dI2[D][D], rowsq[D];
+    dI2_of<D, R>(T, I1, dI2);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      R r = 0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) r += T[i][j] * T[i][j];
+      rowsq[i] = r;
+    }
+    const R kE = R(2) * k * f.f1, k2 = R(2) * k * f.f2;
+    const R k12 = R(2) * k * f.f12, k1t = R(2) * k * f.f1t, k2t = k * f.f2t, ktt = k * f.ftt;
+#pragma unroll
+    for (int pr = 0; pr < SP::N; ++pr) {
+      const int l = SP::l[pr], m = SP::m[pr];
+      R tlm = 0;                                   // (T^t T)_lm
+#pragma unroll
+      for (int q = 0; q < D; ++q) tlm += T[q][l] * T[q][m];
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        K6[c][pr] = (l == m ? kE + k2 * (I1 - rowsq[c]) : R(0)) + k2 * (T[c][l] * T[c][m] - tlm) +
+                    k12 * (T[c][l] * dI2[c][m] + dI2[c][l] * T[c][m]) +
+                    k1t * (T[c][l] * C[c][m] + C[c][l] * T[c][m]) +
+                    k2t * (dI2[c][l] * C[c][m] + C[c][l] * dI2[c][m]) + ktt * C[c][l] * C[c][m];
+    }
   }
 }
 

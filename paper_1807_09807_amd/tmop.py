@@ -3,7 +3,7 @@ step of the computation runs in the library's HIP kernels.
 
 The functions carry the names of the C ABI (include/tmop.h):
 tmop_setup, tmop_energy, tmop_gradient, tmop_energy_gradient, tmop_hessian_apply,
-tmop_newton_solve, tmop_destroy.  Device arrays are torch tensors of shape
+tmop_hessian_diagonal, tmop_newton_solve, tmop_destroy.  Device arrays are torch tensors of shape
 (dim, n_node), float64, contiguous, on a HIP device; the work is enqueued
 on torch's current stream of that device.
 """
@@ -21,14 +21,17 @@ LIB_PATH = os.path.join(_PKG, "libtmop.so")
 
 TMOP_OK, TMOP_W_INVERTED, TMOP_W_MAXIT, TMOP_W_LSFAIL = 0, 1, 2, 3
 TMOP_E_ARG, TMOP_E_TARGET, TMOP_E_NOMEM, TMOP_E_HIP, TMOP_E_UNSUPPORTED = -1, -2, -3, -4, -5
-TMOP_MU2, TMOP_MU7, TMOP_MU302, TMOP_MU303 = 2, 7, 302, 303
+TMOP_MU1, TMOP_MU2, TMOP_MU7, TMOP_MU9, TMOP_MU14, TMOP_MU77, TMOP_MU98 = 1, 2, 7, 9, 14, 77, 98
+TMOP_MU302, TMOP_MU303 = 302, 303
 TMOP_GAUSS_LEGENDRE, TMOP_GAUSS_LOBATTO = 0, 1
 TMOP_FP64, TMOP_MIXED_FP32 = 0, 1
 TMOP_TGT_CONST = 0
+TMOP_INNER_CG, TMOP_INNER_MINRES = 0, 1
+TMOP_PREC_NONE, TMOP_PREC_JACOBI = 0, 1
 
 EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_gradient_scaled", "tmop_hessian_apply",
            "tmop_newton_solve", "tmop_destroy", "tmop_strerror", "tmop_newton_default_opts",
-           "tmop_timing_enable", "tmop_timing_read", "tmop_energy_gradient")
+           "tmop_timing_enable", "tmop_timing_read", "tmop_energy_gradient", "tmop_hessian_diagonal")
 
 
 class TMOPError(RuntimeError):
@@ -57,7 +60,8 @@ class tmop_newton_opts(ctypes.Structure):
                 ("ls_max", ctypes.c_int32), ("f_growth", ctypes.c_double), ("g_growth", ctypes.c_double),
                 ("hist_F", ctypes.POINTER(ctypes.c_double)), ("hist_gnorm", ctypes.POINTER(ctypes.c_double)),
                 ("hist_cg", ctypes.POINTER(ctypes.c_int32)), ("ftarget", ctypes.c_double),
-                ("cg_forcing", ctypes.c_int32), ("hist_time", ctypes.POINTER(ctypes.c_double))]
+                ("cg_forcing", ctypes.c_int32), ("hist_time", ctypes.POINTER(ctypes.c_double)),
+                ("inner", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class tmop_newton_report(ctypes.Structure):
@@ -89,6 +93,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tmop_gradient_scaled.restype = ctypes.c_int
     lib.tmop_hessian_apply.argtypes = [P, P, P, P, P]
     lib.tmop_hessian_apply.restype = ctypes.c_int
+    lib.tmop_hessian_diagonal.argtypes = [P, P, P, P]
+    lib.tmop_hessian_diagonal.restype = ctypes.c_int
     lib.tmop_newton_solve.argtypes = [P, P, ctypes.POINTER(tmop_newton_opts),
                                       ctypes.POINTER(tmop_newton_report), P]
     lib.tmop_newton_solve.restype = ctypes.c_int
@@ -227,6 +233,18 @@ class Context:
             raise TMOPError(st, "tmop_hessian_apply")
         return out
 
+    def hessian_diagonal(self, x, out=None):
+        """diag(d^2F/dx^2) over all DOFs, shape (dim, n_node)."""
+        import torch
+        _check_field(x, self.dim, self.n_node, "x")
+        out = torch.empty_like(x) if out is None else out
+        _check_field(out, self.dim, self.n_node, "out")
+        st = self._lib.tmop_hessian_diagonal(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                             _stream(x))
+        if st < 0:
+            raise TMOPError(st, "tmop_hessian_diagonal")
+        return out
+
     def timing_enable(self, on: bool = True):
         """Clears the per-launch kernel timing totals and turns timing on/off."""
         st = self._lib.tmop_timing_enable(self._h, int(bool(on)))
@@ -236,7 +254,7 @@ class Context:
     def timing_read(self, op: int):
         """(summed device ms, launch count) of the element kernels of one
         operation (0 energy, 1 gradient, 2 Hessian action, 3 energy +
-        gradient) since the last timing_enable."""
+        gradient, 4 Hessian diagonal) since the last timing_enable."""
         ms, n = ctypes.c_double(), ctypes.c_int64()
         st = self._lib.tmop_timing_read(self._h, int(op), ctypes.byref(ms), ctypes.byref(n))
         if st < 0:
@@ -294,6 +312,10 @@ def tmop_energy_gradient(ctx: Context, x, g=None):
 
 def tmop_hessian_apply(ctx: Context, x, v, Hv=None):
     return ctx.hessian_apply(x, v, Hv)
+
+
+def tmop_hessian_diagonal(ctx: Context, x, diag=None):
+    return ctx.hessian_diagonal(x, diag)
 
 
 def tmop_newton_solve(ctx: Context, x, **opts):

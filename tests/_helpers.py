@@ -51,6 +51,12 @@ def small_cases():
         C("lobatto_3d_mu303", 3, 3, 2, 4, 303, 0.10, seed=19, rule="gll"),
         C("aniso_W_2d_mu2", 2, 6, 2, 4, 2, 0.10, seed=20, W0=((1.0, 0.4), (0.1, 1.3))),
         C("aniso_W_3d_mu302", 3, 3, 2, 4, 302, 0.05, seed=21, W0=((1.0, 0.2, 0.0), (0.0, 1.1, 0.3), (0.1, 0.0, 0.9))),
+        # the other 2D metrics of Table 3.1 and Sections 3.2 / 4.3
+        C("p2_q4_2d_mu1", 2, 6, 2, 4, 1, 0.10, seed=30),
+        C("p3_q5_2d_mu9", 2, 5, 3, 5, 9, 0.08, seed=31, W0=((1.0, 0.3), (-0.2, 1.1))),
+        C("p2_q3_2d_mu14", 2, 7, 2, 3, 14, 0.10, seed=32),
+        C("p1_q2_2d_mu77", 2, 9, 1, 2, 77, 0.15, seed=33),
+        C("p4_q5_2d_mu98_lobatto", 2, 3, 4, 5, 98, 0.03, seed=34, rule="gll"),
     ]
 
 

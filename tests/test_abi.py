@@ -78,6 +78,7 @@ def test_newton_default_opts():
     lib.tmop_newton_default_opts(ctypes.byref(o))
     assert o.rtol == 1e-12 and o.f_growth == 1.2 and o.g_growth == 1.2 and o.ls_shrink == 0.5
     assert o.max_it == 50 and o.ls_max == 30 and not o.hist_F
+    assert o.inner == T.TMOP_INNER_CG and o.precond == T.TMOP_PREC_NONE
 
 
 def test_null_arguments():
@@ -85,6 +86,7 @@ def test_null_arguments():
     assert lib.tmop_energy(None, None, None, None, None) == T.TMOP_E_ARG
     assert lib.tmop_gradient(None, None, None, None) == T.TMOP_E_ARG
     assert lib.tmop_hessian_apply(None, None, None, None, None) == T.TMOP_E_ARG
+    assert lib.tmop_hessian_diagonal(None, None, None, None) == T.TMOP_E_ARG
     assert lib.tmop_newton_solve(None, None, None, None, None) == T.TMOP_E_ARG
     lib.tmop_destroy(None)
     assert lib.tmop_energy_gradient(None, None, None, None, None, None) == T.TMOP_E_ARG

@@ -1,0 +1,41 @@
+"""Newton with the other 2D metrics of the paper (Table 3.1: mu_1, mu_9;
+Section 3.2: mu_14; Section 4.3: mu_98) on the GPU, against the oracle's
+implementation of the same rules.  With W = h I the unperturbed grid is the
+minimizer of each (T = I there: mu_9, mu_14, mu_98 vanish only at
+T = I up to rotation; mu_1 = |T|^2 is the Dirichlet energy of the map, whose
+minimizer with the box boundary fixed is the identity, which the Q_p space
+holds).  Element-wise parity of these metrics' energy, gradient, Hessian
+action and diagonal runs with the other cases in test_parity_gpu and
+test_solvers_gpu."""
+import numpy as np
+import pytest
+
+from oracle import tmop_oracle as O
+from paper_1807_09807_amd import meshgen
+from tests._helpers import say, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("metric", [1, 9, 14, 98])
+def test_newton_other_metrics(metric):
+    from paper_1807_09807_amd import tmop as T
+    say(f"[newton] 2D Q2 6x6 mu_{metric}")
+    mesh = meshgen.box_mesh(2, 6, 2)
+    W = mesh.h * np.eye(2)
+    prob = O.Problem(2, 2, 4, mesh.elem_node, metric, W)
+    x0 = meshgen.perturb(mesh, 0.1, 40 + metric, bad_elements=prob.bad_elements)
+    xo, rep_o = O.newton_solve(prob, x0, mesh.fixed, O.NewtonOptions(max_it=30, cg_rtol=1e-10))
+    ctx = T.Context(2, 2, mesh.elem_node, mesh.n_node, 4, metric, W, fixed=mesh.fixed)
+    xd = to_dev(x0)
+    st, rep = ctx.newton_solve(xd, max_it=30, cg_rtol=1e-10)
+    F_o = [h[0] for h in rep_o.history]
+    F_g = rep["history_F"]
+    say(f"  oracle {rep_o.iters} it, F {F_o[0]:.6e} -> {F_o[-1]:.3e}; gpu {rep['iters']} it, F -> {F_g[-1]:.3e}")
+    assert st == T.TMOP_OK and rep_o.stop == O.STOP_CONVERGED
+    assert abs(F_g[0] - F_o[0]) <= 1e-12 * abs(F_o[0])
+    assert abs(F_g[1] - F_o[1]) <= 1e-8 * abs(F_o[1]) + 1e-14 * abs(F_o[0])
+    x = xd.cpu().numpy()
+    assert np.max(np.abs(x - mesh.x_grid)) < 1e-8 * mesh.h
+    assert np.max(np.abs(xo - mesh.x_grid)) < 1e-8 * mesh.h
