@@ -90,7 +90,10 @@ enum { TMOP_PREC_NONE = 0, TMOP_PREC_JACOBI = 1 };
 
 /* Target matrices W (Section 3.1). */
 enum {
-  TMOP_TGT_CONST = 0       /* one dim x dim matrix for every point */
+  TMOP_TGT_CONST = 0,      /* one dim x dim matrix for every point */
+  TMOP_TGT_ISO_PER_QP = 1  /* W_q = s_q I, one size s_q > 0 per quadrature
+                              point: the targets W_2 scaled by a
+                              space-dependent factor and W_3 of Section 3.1 */
 };
 
 typedef struct {
@@ -113,8 +116,12 @@ typedef struct {
 } tmop_quadrature;
 
 typedef struct {
-  int32_t kind;               /* TMOP_TGT_CONST */
-  const double *W;            /* HOST, row-major dim x dim, det W > 0 */
+  int32_t kind;               /* TMOP_TGT_CONST or TMOP_TGT_ISO_PER_QP */
+  const double *W;            /* HOST.  TMOP_TGT_CONST: row-major dim x dim,
+                                 det W > 0.  TMOP_TGT_ISO_PER_QP: the sizes
+                                 [n_elem][n1d^dim], all > 0, point index
+                                 q0 + n1d q1 (+ n1d^2 q2) (first reference
+                                 coordinate fastest) */
 } tmop_target;
 
 typedef struct {
@@ -199,6 +206,20 @@ int tmop_gradient_scaled(tmop_ctx *ctx, const double *x, const double *scale, do
 int tmop_hessian_apply(tmop_ctx *ctx, const double *x, const double *v,
                        double *Hv, void *stream);
 
+/* The sizes of the target W_3 = (det A(x0))^(1/dim) I of Section 3.1 at
+ * every quadrature point of the mesh x0: sizes[e][q] = (det A)^(1/dim)
+ * (same layout as the TMOP_TGT_ISO_PER_QP sizes; the real root, so NaN in
+ * 2D and negative in 3D where det A < 0).  Works on any context.  x0:
+ * device [dim][n_node]; sizes: device [n_elem][n1d^dim], caller-owned.
+ * Returns TMOP_W_INVERTED when det A <= 0 at some point.  Syncs. */
+int tmop_target_sizes_w3(tmop_ctx *ctx, const double *x0, double *sizes, void *stream);
+
+/* Replaces the per-point target sizes of a TMOP_TGT_ISO_PER_QP context by
+ * the device array sizes [n_elem][n1d^dim] (copied).  TMOP_E_ARG for other
+ * contexts; TMOP_E_TARGET (context unchanged) unless every size is finite
+ * and > 0 (Section 3.1).  Syncs. */
+int tmop_set_target_sizes(tmop_ctx *ctx, const double *sizes, void *stream);
+
 /* diag = the diagonal of d^2F/dx^2 (Section 3.4) over all DOFs: entry
  * (c, I) is the Hessian action on the unit vector of DOF (c, I), read at
  * (c, I), i.e. sum over the elements E holding I of
@@ -281,10 +302,10 @@ int tmop_mlp_propose(tmop_ctx *ctx, tmop_mlp *mlp, const double *x, double *x_ou
  * two HIP events on the caller's stream; tmop_timing_read waits for them and
  * returns the summed device time in milliseconds and the number of launches
  * for one operation: 0 energy, 1 gradient, 2 Hessian action, 3 energy +
- * gradient (tmop_energy_gradient), 4 Hessian diagonal.
+ * gradient (tmop_energy_gradient), 4 Hessian diagonal, 5 target sizes.
  * tmop_timing_enable(ctx, on) clears the totals and turns timing on (1) or
  * off (0).  Both return TMOP_OK, TMOP_E_ARG (NULL ctx / out pointers, op
- * outside 0..4) or TMOP_E_HIP. */
+ * outside 0..5) or TMOP_E_HIP. */
 int tmop_timing_enable(tmop_ctx *ctx, int enable);
 int tmop_timing_read(tmop_ctx *ctx, int op, double *ms_total, int64_t *launches);
 

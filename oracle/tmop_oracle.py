@@ -386,6 +386,14 @@ class Problem:
             return F, float(np.min(detA.real))
         return math.fsum(c.ravel()), float(np.min(detA))
 
+    def point_sizes(self, x):
+        """(det A)^(1/d) at every quadrature point, shape (n_elem, nq): the
+        sizes of the target W_3 = (det A(x_0))^(1/d) I of Section 3.1 when
+        x is the initial mesh (real root: negative where det A < 0 in 3D,
+        NaN in 2D)."""
+        _, detA = self.pointwise(x)
+        return np.sqrt(detA) if self.dim == 2 else np.cbrt(detA)
+
     def max_condition(self, x, elems=None):
         """max over quadrature points of (|T|^2/d)^(d/2) / det T: 1 for a
         scaled rotation, large for nearly degenerate points.  It bounds how

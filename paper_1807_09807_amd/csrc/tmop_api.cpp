@@ -2,6 +2,8 @@
 // truncated-CG driver (arXiv:1807.09807, Sections 2-3).  Host code only;
 // every step of the computation runs in the HIP kernels of this library.
 #include <math.h>
+
+#include <cmath>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -148,9 +150,10 @@ namespace {
 // d_part[part_off + b] (sums) and d_part[n_elem + part_off + b] (minima).
 int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* out, const int32_t* conn,
                 const int32_t* list, int64_t n_list, hipStream_t s, int* grid, const double* scale = nullptr,
-                int64_t part_off = 0, const uint32_t* first = nullptr) {
+                int64_t part_off = 0, const uint32_t* first = nullptr, const double* tsize = nullptr) {
   LaunchParams lp = c->base;
   lp.first = first;
+  lp.tsize = tsize;
   lp.scale = scale;
   lp.x = x; lp.v = v; lp.out = out;
   lp.elem_node = conn;
@@ -221,7 +224,8 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
     if (n == 0) continue;
     int grid = 0;
     const int r = elem_launch(c, op, x, v, out, c->d_elem_node_col + c->color_off[k] * c->npe, nullptr, n, s,
-                              &grid, scale, off, c->d_first + c->color_off[k] * c->first_words);
+                              &grid, scale, off, c->d_first + c->color_off[k] * c->first_words,
+                              c->d_tsize_col ? c->d_tsize_col + c->color_off[k] * c->nq : nullptr);
     if (r != TMOP_OK) return r;
     off += grid;
   }
@@ -232,7 +236,8 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
 // Enqueue F and min det A into c->d_res[0..1].
 int energy_async(tmop_ctx* c, const double* x, hipStream_t s) {
   int grid = 0;
-  const int r = elem_launch(c, OP_ENERGY, x, nullptr, nullptr, c->d_elem_node, nullptr, c->n_elem, s, &grid);
+  const int r = elem_launch(c, OP_ENERGY, x, nullptr, nullptr, c->d_elem_node, nullptr, c->n_elem, s, &grid,
+                            nullptr, 0, nullptr, c->d_tsize);
   if (r != TMOP_OK) return r;
   HIP_TRY(finalize_sum_min(c->d_part, grid, (int)c->n_elem, c->d_scratch, c->d_res, s));
   return TMOP_OK;
@@ -289,6 +294,8 @@ void free_ctx(tmop_ctx* c) {
   (void)hipFree(c->d_elem_node_col);
   (void)hipFree(c->d_first);
   (void)hipFree(c->d_mask);
+  (void)hipFree(c->d_tsize);
+  (void)hipFree(c->d_tsize_col);
   (void)hipFree(c->d_part);
   (void)hipFree(c->d_scratch);
   (void)hipFree(c->d_res);
@@ -545,11 +552,19 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
     return TMOP_E_ARG;
   if (d == 3 && metric != TMOP_MU302 && metric != TMOP_MU303) return TMOP_E_ARG;
   if (precision != TMOP_FP64 && precision != TMOP_MIXED_FP32) return TMOP_E_ARG;
-  if (target->kind != TMOP_TGT_CONST || !target->W) return TMOP_E_ARG;
+  if ((target->kind != TMOP_TGT_CONST && target->kind != TMOP_TGT_ISO_PER_QP) || !target->W) return TMOP_E_ARG;
   const int npe = d == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
+  const int nq = d == 2 ? Q * Q : Q * Q * Q;
   for (int64_t k = 0; k < mesh->n_elem * npe; ++k)
     if (mesh->elem_node[k] < 0 || mesh->elem_node[k] >= mesh->n_node) return TMOP_E_ARG;
-  const double detW = det3(target->W, d);
+  const bool per_qp = target->kind == TMOP_TGT_ISO_PER_QP;
+  static const double eye2[4] = {1, 0, 0, 1}, eye3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  const double* Wc = per_qp ? (d == 2 ? eye2 : eye3) : target->W;
+  if (per_qp) {                                          // Section 3.1: det W = s^d > 0
+    for (int64_t k = 0; k < mesh->n_elem * nq; ++k)
+      if (!(target->W[k] > 0.0)) return TMOP_E_TARGET;
+  }
+  const double detW = det3(Wc, d);
   if (!(detW > 0.0)) return TMOP_E_TARGET;               // Section 3.1: det W > 0
   if (!elem_supported(d, p, Q)) return TMOP_E_UNSUPPORTED;
 
@@ -569,12 +584,13 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
     lagrange_at(p + 1, xi, s[q], c->base.B[q], c->base.G[q]);
     c->base.w[q] = w[q];
   }
-  inv3(target->W, d, c->base.Winv);
+  inv3(Wc, d, c->base.Winv);
   c->base.iso = true;
   for (int i = 0; i < d; ++i)
     for (int j = 0; j < d; ++j)
-      if (target->W[i * d + j] != (i == j ? target->W[0] : 0.0)) c->base.iso = false;
-  c->base.s_inv = 1.0 / target->W[0];
+      if (Wc[i * d + j] != (i == j ? Wc[0] : 0.0)) c->base.iso = false;
+  c->base.s_inv = 1.0 / Wc[0];
+  c->nq = nq;
   c->base.detW = detW;
   c->base.detWinv = 1.0 / detW;
 
@@ -618,6 +634,14 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
       if (hipMalloc(&c->d_first, fb) != hipSuccess) { st = TMOP_E_NOMEM; break; }
       if (hipMemcpy(c->d_first, first.data(), fb, hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
     }
+    if (per_qp) {   // per-point sizes, element order and colour order
+      const size_t tb = (size_t)mesh->n_elem * nq * sizeof(double);
+      if (hipMalloc(&c->d_tsize, tb) != hipSuccess) { c->d_tsize = nullptr; st = TMOP_E_NOMEM; break; }
+      if (hipMalloc(&c->d_tsize_col, tb) != hipSuccess) { c->d_tsize_col = nullptr; st = TMOP_E_NOMEM; break; }
+      if (hipMemcpy(c->d_tsize, target->W, tb, hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
+      if (gather_rows(c->d_tsize, c->d_colors, mesh->n_elem, nq, c->d_tsize_col, nullptr) != hipSuccess ||
+          hipDeviceSynchronize() != hipSuccess) { st = TMOP_E_HIP; break; }
+    }
     std::vector<double> mask(c->n_dof, 1.0);
     if (mesh->fixed)
       for (int64_t k = 0; k < c->n_dof; ++k)
@@ -638,7 +662,7 @@ int tmop_timing_enable(tmop_ctx* c, int enable) {
   const int st = collect_timing(c);
   (void)hipSetDevice(cur);
   c->timing = enable != 0;
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < 6; ++k) {
     c->t_ms[k] = 0.0;
     c->t_launches[k] = 0;
   }
@@ -646,7 +670,7 @@ int tmop_timing_enable(tmop_ctx* c, int enable) {
 }
 
 int tmop_timing_read(tmop_ctx* c, int op, double* ms_total, int64_t* launches) {
-  if (!c || op < 0 || op > 4 || !ms_total || !launches) return TMOP_E_ARG;
+  if (!c || op < 0 || op > 5 || !ms_total || !launches) return TMOP_E_ARG;
   const int st = collect_timing(c);
   *ms_total = c->t_ms[op];
   *launches = c->t_launches[op];
@@ -688,6 +712,37 @@ int tmop_energy_gradient(tmop_ctx* c, const double* x, double* F, double* min_de
 int tmop_hessian_apply(tmop_ctx* c, const double* x, const double* v, double* Hv, void* stream) {
   if (!c || !x || !v || !Hv || Hv == x || Hv == v) return TMOP_E_ARG;
   return assemble(c, OP_HESS, x, v, Hv, (hipStream_t)stream);
+}
+
+int tmop_target_sizes_w3(tmop_ctx* c, const double* x0, double* sizes, void* stream) {
+  if (!c || !x0 || !sizes || sizes == x0) return TMOP_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  int grid = 0;
+  const int r = elem_launch(c, OP_SIZE, x0, nullptr, sizes, c->d_elem_node, nullptr, c->n_elem, s, &grid, nullptr, 0,
+                            nullptr, c->d_tsize);
+  if (r != TMOP_OK) return r;
+  HIP_TRY(finalize_sum_min(c->d_part, grid, (int)c->n_elem, c->d_scratch, c->d_res, s));
+  double F = 0, m = 0;
+  const int st = read_res(c, s, &F, &m);
+  if (st != TMOP_OK) return st;
+  return m > 0.0 ? TMOP_OK : TMOP_W_INVERTED;
+}
+
+int tmop_set_target_sizes(tmop_ctx* c, const double* sizes, void* stream) {
+  if (!c || !sizes) return TMOP_E_ARG;
+  if (!c->d_tsize) return TMOP_E_ARG;                    // not a per-point target context
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = c->n_elem * c->nq;
+  if (n > INT32_MAX) return TMOP_E_ARG;
+  // Section 3.1: det W = s^d > 0 at every point, checked before anything changes
+  HIP_TRY(finalize_sum_min(sizes, (int)n, 0, c->d_scratch, c->d_res, s));
+  double sum = 0, m = 0;
+  const int st = read_res(c, s, &sum, &m);
+  if (st != TMOP_OK) return st;
+  if (!(m > 0.0) || !std::isfinite(sum)) return TMOP_E_TARGET;
+  HIP_TRY(hipMemcpyAsync(c->d_tsize, sizes, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(gather_rows(c->d_tsize, c->d_colors, c->n_elem, c->nq, c->d_tsize_col, s));
+  return TMOP_OK;
 }
 
 int tmop_hessian_diagonal(tmop_ctx* c, const double* x, double* diag, void* stream) {

@@ -61,6 +61,15 @@ __global__ void __launch_bounds__(VB) k_minres_w(const double* __restrict__ v, d
     w[i] = (v[i] - a * w[i] - b * u[i]) * s;
 }
 
+__global__ void __launch_bounds__(VB) k_gather_rows(const double* __restrict__ src, const int32_t* __restrict__ rows,
+                                                    int64_t n, int w, double* __restrict__ dst) {
+  const int64_t total = n * w;
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < total; i += (int64_t)gridDim.x * VB) {
+    const int64_t j = i / w;
+    dst[i] = src[(int64_t)rows[j] * w + (i - j * w)];
+  }
+}
+
 // Fixed-order tree reduction of one value per thread in a RED_THREADS block.
 __device__ __forceinline__ double block_sum(double s, double* red) {
 #pragma unroll
@@ -221,6 +230,11 @@ hipError_t waxpy(const double* x, double a, const double* d, double* w, int64_t 
 
 hipError_t scale_copy(double a, const double* x, double* y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_copy, dim3(vgrid(n)), dim3(VB), 0, s, a, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t gather_rows(const double* src, const int32_t* rows, int64_t n, int w, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_rows, dim3(vgrid(n * w)), dim3(VB), 0, s, src, rows, n, w, dst);
   return hipGetLastError();
 }
 

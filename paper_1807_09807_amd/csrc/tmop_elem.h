@@ -6,6 +6,12 @@
 //   OP_HESS    (d^2F/dx^2) v scattered to the nodes      (Section 3.4)
 //   OP_EG      OP_ENERGY and OP_GRAD in one pass (the line search needs both
 //              at every trial point)
+//   OP_SIZE    (det A)^(1/d) at every quadrature point: the size of the
+//              target W_3 = (det A(x_0))^(1/d) I of Section 3.1
+//
+// Targets (template parameter TGT): a constant general W (TGT_GEN), a
+// constant isotropic W = s I (TGT_ISO), or an isotropic W_q = s_q I given
+// per quadrature point (TGT_QPS, Section 3.1: W may differ at every point).
 //
 // The Jacobian A = sum_i x_i (grad w_i)^T (eq. 2.2) of a tensor-product
 // element is computed by sum factorization: one 1D contraction per
@@ -59,6 +65,8 @@ struct ElemArgs {
   double* __restrict__ part;             // OP_ENERGY, OP_EG: [gridDim.x] block sums of the energy
   double* __restrict__ part_min;         // OP_ENERGY, OP_EG: [gridDim.x] block minima of det A
   const double* __restrict__ scale;      // OP_GRAD: optional device scalar multiplying g (nullptr = 1)
+  const double* __restrict__ tsize;      // TGT_QPS: [n_list][Q^dim] target sizes s_q (W_q = s_q I), point
+                                         // index q0 + Q q1 (+ Q^2 q2), in the order of elem_node
   int64_t n_node;
   int32_t n_list;
   R B[Q][P];
@@ -205,12 +213,18 @@ __device__ __forceinline__ void stress(const R (&M)[D][D], const R (&Wi)[3][3], 
     }
 }
 
-// Per-point kernel of the three operations.  Given A (and dA), adds the
-// energy contribution (OP_ENERGY) or fills Y (OP_GRAD / OP_HESS).
+enum { TGT_GEN = 0, TGT_ISO = 1, TGT_QPS = 2 };
+
+// Per-point kernel of the operations.  Given A (and dA) -- already divided
+// by s for isotropic targets, i.e. T -- adds the energy contribution
+// wdet mu(T) (OP_ENERGY, OP_EG), fills Y (OP_GRAD / OP_HESS) with the weight
+// kY folded into the metric's coefficients, or returns det A (OP_SIZE).
+// detWq: det W at this point.
 template <int D, int METRIC, typename R, int OP, bool ISO, int P, int Q>
 __device__ __forceinline__ void point_op(const ElemArgs<P, Q, R>& a, const R (&A)[D][D], const R (&dA)[D][D],
-                                         double wdet, double& acc, double& mind, R (&Y)[D][D]) {
-  if constexpr (OP == OP_ENERGY || OP == OP_EG) {
+                                         double wdet, double detWq, double kY, double& acc, double& mind,
+                                         R (&Y)[D][D], double& detA_out) {
+  if constexpr (OP == OP_ENERGY || OP == OP_EG || OP == OP_SIZE) {
     // The energy value, det A and their sums are FP64 in both paths: the
     // FP32 path promotes its contracted A (mu's "... - 1" would otherwise
     // leave an FP32 rounding floor under F).
@@ -223,30 +237,55 @@ __device__ __forceinline__ void point_op(const ElemArgs<P, Q, R>& a, const R (&A
     if constexpr (ISO) {          // the contraction gave T; det A = det T det W
       right_mul<D, double, true>(Ad, a.Winvd, Td);
       tau = det<D, double>(Td);
-      detA = tau * a.detW;
+      detA = tau * detWq;
     } else {
       detA = det<D, double>(Ad);
       right_mul<D, double, false>(Ad, a.Winvd, Td);
       tau = det<D, double>(Td);
     }
-    acc += wdet * mu_value<METRIC, double>(Td, tau);
+    if constexpr (OP != OP_SIZE) acc += wdet * mu_value<METRIC, double>(Td, tau);
     mind = fmin(mind, detA);
+    detA_out = detA;
   }
-  if constexpr (OP != OP_ENERGY) {
-    // the weight w det W is folded into the metric's scalar coefficients
+  if constexpr (OP == OP_GRAD || OP == OP_EG || OP == OP_HESS) {
+    // the weight is folded into the metric's scalar coefficients
     R T[D][D];
     right_mul<D, R, ISO>(A, a.Winv, T);
     if constexpr (OP == OP_GRAD || OP == OP_EG) {
       R Pm[D][D];
-      mu_first<METRIC, R>(T, (R)wdet, Pm);
+      mu_first<METRIC, R>(T, (R)kY, Pm);
       stress<D, R, ISO>(Pm, a.Winv, Y);
     } else {
       R dT[D][D], dP[D][D];
       right_mul<D, R, ISO>(dA, a.Winv, dT);
-      mu_second<METRIC, R>(T, dT, (R)wdet, dP);
+      mu_second<METRIC, R>(T, dT, (R)kY, dP);
       stress<D, R, ISO>(dP, a.Winv, Y);
     }
   }
+}
+
+// (det A)^(1/d) with the real roots (NaN for det A < 0 in 2D, negative in 3D)
+template <int D>
+__device__ __forceinline__ double size_of(double detA) {
+  if constexpr (D == 2) return sqrt(detA);
+  else return cbrt(detA);
+}
+
+// Per-point target scaling (TGT_QPS): A, dA <- A / s, dA / s, and the
+// weights: w det W = w s^d for the energy, w s^(d-1) for Y (W^{-t} = I / s
+// is not in the G table then).
+template <int D, typename R>
+__device__ __forceinline__ void qp_scale(double s, R (&A)[D][D], R (&dA)[D][D], double& wdet, double& detWq,
+                                         double& kY) {
+  const double rs = 1.0 / s;
+  const R r = (R)rs;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) { A[i][j] *= r; dA[i][j] *= r; }
+  detWq = D == 2 ? s * s : s * s * s;
+  wdet *= detWq;
+  kY = wdet * rs;
 }
 
 // Both paths contract the field relative to the element: A only depends on
@@ -408,11 +447,13 @@ __device__ __forceinline__ void fwd_3d_areas(const ElemArgs<P, Q, R>& a, const R
   }
 }
 
-template <int P, int Q, int METRIC, typename R, int OP, bool ISO>
+template <int P, int Q, int METRIC, typename R, int OP, int TGT>
 __global__ void __launch_bounds__((Cfg<3, P, Q, R>::BLOCK))
 elem_kernel_3d(const ElemArgs<P, Q, R> a) {
   using C = Cfg<3, P, Q, R>;
   using L = Lds3<P, Q>;
+  constexpr bool ISO = TGT != TGT_GEN;
+  constexpr bool ENERGY_LIKE = OP == OP_ENERGY || OP == OP_SIZE;   // no transposed passes
   constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P * P;
   constexpr bool AFFINE = sizeof(R) == 4;   // FP32 contracts the deviation from the vertex-affine map
   constexpr int NE = OP == OP_HESS ? C::NEH : C::NE;
@@ -476,7 +517,13 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
       for (int i0 = 0; i0 < P; ++i0) Racc[tt][c][i0] = 0;
 
   if (tb < Q) {
-    const double w12 = a.w[ta] * a.w[tb] * a.detW * (a.scale ? *a.scale : 1.0);
+    const double w12 = a.w[ta] * a.w[tb] * (TGT == TGT_QPS ? 1.0 : a.detW) * (a.scale ? *a.scale : 1.0);
+    double sq[Q];   // this lane's row of target sizes (q0 = 0..Q-1)
+    if constexpr (TGT == TGT_QPS) {
+      const double* ts = a.tsize + (int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb;
+#pragma unroll
+      for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
+    }
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[3][3], dA[3][3];
@@ -504,8 +551,13 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
         }
       }
       R Y[3][3];
-      point_op<3, METRIC, R, OP, ISO>(a, A, dA, w12 * a.w[q0], acc, mind, Y);
-      if constexpr (OP != OP_ENERGY) {
+      double wdet = w12 * a.w[q0], detWq = a.detW, kY = wdet, detA = 0.0;
+      if constexpr (TGT == TGT_QPS) qp_scale<3, R>(sq[q0], A, dA, wdet, detWq, kY);
+      point_op<3, METRIC, R, OP, ISO>(a, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
+      if constexpr (OP == OP_SIZE) {
+        if (active) a.out[(int64_t)e * (Q * Q * Q) + q0 + Q * ta + Q * Q * tb] = size_of<3>(detA);
+      }
+      if constexpr (!ENERGY_LIKE) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -518,11 +570,11 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
     }
   }
 
-  if constexpr (OP == OP_ENERGY || OP == OP_EG) {
+  if constexpr (OP == OP_ENERGY || OP == OP_EG || OP == OP_SIZE) {
     if (!active) { acc = 0.0; mind = __builtin_huge_val(); }
     block_reduce_sum_min<C::BLOCK>(acc, mind, red, a.part + blk, a.part_min + blk);
   }
-  if constexpr (OP != OP_ENERGY) {
+  if constexpr (!ENERGY_LIKE) {
     // the scatter's old values, loaded now so the passes below hide latency
     double old[3][P];
     if (active && p1) {
@@ -701,10 +753,12 @@ __device__ __forceinline__ void fwd_2d(const ElemArgs<P, Q, R>& a, const R (&X)[
   }
 }
 
-template <int P, int Q, int METRIC, typename R, int OP, bool ISO>
+template <int P, int Q, int METRIC, typename R, int OP, int TGT>
 __global__ void __launch_bounds__((Cfg<2, P, Q, R>::BLOCK))
 elem_kernel_2d(const ElemArgs<P, Q, R> a) {
   using C = Cfg<2, P, Q, R>;
+  constexpr bool ISO = TGT != TGT_GEN;
+  constexpr bool ENERGY_LIKE = OP == OP_ENERGY || OP == OP_SIZE;
   constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P;
   constexpr bool AFFINE = sizeof(R) == 4;
   constexpr int NE = OP == OP_HESS ? C::NEH : C::NE;
@@ -748,7 +802,13 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
       for (int i0 = 0; i0 < P; ++i0) Racc[tt][c][i0] = 0;
 
   if (ta < Q) {   // lane q1 = ta
-    const double w1 = a.w[ta] * a.detW * (a.scale ? *a.scale : 1.0);
+    const double w1 = a.w[ta] * (TGT == TGT_QPS ? 1.0 : a.detW) * (a.scale ? *a.scale : 1.0);
+    double sq[Q];   // this lane's row of target sizes
+    if constexpr (TGT == TGT_QPS) {
+      const double* ts = a.tsize + (int64_t)e * (Q * Q) + Q * ta;
+#pragma unroll
+      for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
+    }
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[2][2], dA[2][2];
@@ -768,8 +828,13 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
         }
       }
       R Y[2][2];
-      point_op<2, METRIC, R, OP, ISO>(a, A, dA, w1 * a.w[q0], acc, mind, Y);
-      if constexpr (OP != OP_ENERGY) {
+      double wdet = w1 * a.w[q0], detWq = a.detW, kY = wdet, detA = 0.0;
+      if constexpr (TGT == TGT_QPS) qp_scale<2, R>(sq[q0], A, dA, wdet, detWq, kY);
+      point_op<2, METRIC, R, OP, ISO>(a, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
+      if constexpr (OP == OP_SIZE) {
+        if (active) a.out[(int64_t)e * (Q * Q) + q0 + Q * ta] = size_of<2>(detA);
+      }
+      if constexpr (!ENERGY_LIKE) {
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -781,11 +846,11 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
     }
   }
 
-  if constexpr (OP == OP_ENERGY || OP == OP_EG) {
+  if constexpr (OP == OP_ENERGY || OP == OP_EG || OP == OP_SIZE) {
     if (!active) { acc = 0.0; mind = __builtin_huge_val(); }
     block_reduce_sum_min<C::BLOCK>(acc, mind, red, a.part + blk, a.part_min + blk);
   }
-  if constexpr (OP != OP_ENERGY) {
+  if constexpr (!ENERGY_LIKE) {
     double old[2][P];
     if (active && p1) {
 #pragma unroll
@@ -894,9 +959,10 @@ __device__ __forceinline__ void target_congruence(const R (&Wi)[3][3], R (&K6)[D
   }
 }
 
-template <int P, int Q, int METRIC, typename R, bool ISO>
+template <int P, int Q, int METRIC, typename R, int TGT>
 __global__ void __launch_bounds__((Cfg<3, P, Q, R>::BLOCK))
 diag_kernel_3d(const DiagArgs<P, Q, R> a) {
+  constexpr bool ISO = TGT != TGT_GEN;
   using C = Cfg<3, P, Q, R>;
   using LD = LdsDiag3<P, Q>;
   constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P * P;
@@ -947,7 +1013,13 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
 #pragma unroll
       for (int i0 = 0; i0 < P; ++i0) Rd[pr][c][i0] = 0;
   if (tb < Q) {
-    const double w12 = a.w[ta] * a.w[tb] * a.detW;
+    const double w12 = a.w[ta] * a.w[tb] * (TGT == TGT_QPS ? 1.0 : a.detW);
+    double sq[Q];
+    if constexpr (TGT == TGT_QPS) {
+      const double* ts = a.tsize + (int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb;
+#pragma unroll
+      for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
+    }
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[3][3];
@@ -964,8 +1036,17 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
         A[c][0] = s0; A[c][1] = s1; A[c][2] = s2;
       }
       R T[3][3], K[3][6];
+      double kK = w12 * a.w[q0];
+      if constexpr (TGT == TGT_QPS) {   // T = A / s; W^{-1} K W^{-t} = K / s^2, det W = s^3
+        const R r = (R)(1.0 / sq[q0]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) A[i][j] *= r;
+        kK *= sq[q0];
+      }
       right_mul<3, R, ISO>(A, a.Winv, T);
-      mu_second_rows<METRIC, R>(T, (R)(w12 * a.w[q0]), K);
+      mu_second_rows<METRIC, R>(T, (R)kK, K);
       if constexpr (!ISO) target_congruence<3, R>(a.Winv, K);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1047,9 +1128,10 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
 
 // 2D pairs (l, m): 0 (0,0), 1 (1,1), 2 (0,1); x tables GG BB BG, y tables
 // BB GG BG.  LDS: the forward U, then the x-transposed sums [pair][c][q1][i0].
-template <int P, int Q, int METRIC, typename R, bool ISO>
+template <int P, int Q, int METRIC, typename R, int TGT>
 __global__ void __launch_bounds__((Cfg<2, P, Q, R>::BLOCK))
 diag_kernel_2d(const DiagArgs<P, Q, R> a) {
+  constexpr bool ISO = TGT != TGT_GEN;
   using C = Cfg<2, P, Q, R>;
   constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P;
   constexpr bool AFFINE = sizeof(R) == 4;
@@ -1086,7 +1168,13 @@ diag_kernel_2d(const DiagArgs<P, Q, R> a) {
 #pragma unroll
       for (int i0 = 0; i0 < P; ++i0) Rd[pr][c][i0] = 0;
   if (ta < Q) {   // lane q1 = ta
-    const double w1 = a.w[ta] * a.detW;
+    const double w1 = a.w[ta] * (TGT == TGT_QPS ? 1.0 : a.detW);
+    double sq[Q];
+    if constexpr (TGT == TGT_QPS) {
+      const double* ts = a.tsize + (int64_t)e * (Q * Q) + Q * ta;
+#pragma unroll
+      for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
+    }
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[2][2];
@@ -1099,8 +1187,16 @@ diag_kernel_2d(const DiagArgs<P, Q, R> a) {
         A[c][0] = s0; A[c][1] = s1;
       }
       R T[2][2], K[2][3];
+      double kK = w1 * a.w[q0];
+      if constexpr (TGT == TGT_QPS) {   // T = A / s; W^{-1} K W^{-t} = K / s^2, det W = s^2
+        const R r = (R)(1.0 / sq[q0]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) A[i][j] *= r;
+      }
       right_mul<2, R, ISO>(A, a.Winv, T);
-      mu_second_rows<METRIC, R>(T, (R)(w1 * a.w[q0]), K);
+      mu_second_rows<METRIC, R>(T, (R)kK, K);
       if constexpr (!ISO) target_congruence<2, R>(a.Winv, K);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {

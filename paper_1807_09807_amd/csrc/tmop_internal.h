@@ -9,8 +9,9 @@
 namespace tmop {
 
 // Element operations: F and min det A (eq. 2.4), dF/dx, (d^2F/dx^2) v,
-// F, min det A and dF/dx in one pass, and the diagonal of d^2F/dx^2.
-enum { OP_ENERGY = 0, OP_GRAD = 1, OP_HESS = 2, OP_EG = 3, OP_DIAG = 4 };
+// F, min det A and dF/dx in one pass, the diagonal of d^2F/dx^2, and the
+// per-point sizes (det A)^(1/d) (with min det A).
+enum { OP_ENERGY = 0, OP_GRAD = 1, OP_HESS = 2, OP_EG = 3, OP_DIAG = 4, OP_SIZE = 5 };
 
 constexpr int MAXP = 5;   // nodes per direction (order p <= 4)
 constexpr int MAXQ = 6;   // quadrature points per direction
@@ -28,6 +29,7 @@ struct LaunchParams {
   double* part;            // energy partials: sums (one per block)
   double* part_min;        // energy partials: minima of det A
   const double* scale;     // gradient: optional device scalar factor
+  const double* tsize;     // per-point isotropic target sizes (in the order of elem_node), or nullptr
   double B[MAXQ][MAXP];
   double G[MAXQ][MAXP];
   double w[MAXQ];
@@ -75,6 +77,8 @@ hipError_t xpay(const double* x, double a, double* y, int64_t n, hipStream_t s);
 hipError_t waxpy(const double* x, double a, const double* d, double* w, int64_t n, hipStream_t s);  // w = x + a d
 hipError_t scale_copy(double a, const double* x, double* y, int64_t n, hipStream_t s);    // y = a x
 hipError_t mask_mul(const double* m, double* y, int64_t n, hipStream_t s);                // y *= m
+// dst[j][0..w) = src[rows[j]][0..w) for j < n
+hipError_t gather_rows(const double* src, const int32_t* rows, int64_t n, int w, double* dst, hipStream_t s);
 
 }  // namespace tmop
 
@@ -92,6 +96,9 @@ struct tmop_ctx {
   bool all_touched = false;            // every node belongs to an element: the colour launches initialize out
   int npe = 0;                         // nodes per element
   std::vector<int64_t> color_off;      // colour c = d_colors[color_off[c] .. color_off[c+1])
+  int nq = 0;                          // quadrature points per element, Q^dim
+  double* d_tsize = nullptr;           // TMOP_TGT_ISO_PER_QP: [n_elem][nq] sizes s_q, element order
+  double* d_tsize_col = nullptr;       // the same in colour order
   double* d_mask = nullptr;            // [n_dof], 1 = free DOF
   bool has_fixed = false;
   double* d_part = nullptr;            // [2 * n_elem] energy partials
@@ -104,6 +111,6 @@ struct tmop_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev_free;
   std::vector<TimedLaunch> ev_pending;
-  double t_ms[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // per op: energy, gradient, Hessian action, energy+gradient,
-  int64_t t_launches[5] = {0, 0, 0, 0, 0};       // Hessian diagonal
+  double t_ms[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // per op: energy, gradient, Hessian action,
+  int64_t t_launches[6] = {0, 0, 0, 0, 0, 0};         // energy+gradient, Hessian diagonal, target sizes
 };

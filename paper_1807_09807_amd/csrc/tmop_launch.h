@@ -8,14 +8,15 @@
 
 namespace tmop {
 
-template <int DIM, int P, int Q, int METRIC, typename R, int OP, bool ISO>
+template <int DIM, int P, int Q, int METRIC, typename R, int OP, int TGT>
 static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   using C = Cfg<DIM, P, Q, R>;
   DiagArgs<P, Q, R> a;   // the element kernels take its ElemArgs part
   a.x = lp.x; a.v = lp.v; a.out = lp.out;
   a.elem_node = lp.elem_node; a.list = lp.list; a.first = lp.first; a.part = lp.part; a.part_min = lp.part_min; a.scale = lp.scale;
   a.n_node = lp.n_node; a.n_list = lp.n_list;
-  const double gs = ISO ? lp.s_inv : 1.0;   // isotropic target: G carries 1/s
+  a.tsize = lp.tsize;
+  const double gs = TGT == TGT_ISO ? lp.s_inv : 1.0;   // constant isotropic target: G carries 1/s
   for (int q = 0; q < Q; ++q) {
     a.w[q] = lp.w[q];
     for (int i = 0; i < P; ++i) { a.B[q][i] = (R)lp.B[q][i]; a.G[q][i] = (R)(lp.G[q][i] * gs); }
@@ -39,29 +40,34 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
         a.BG[q][i] = (R)(b * gg);
         a.GG[q][i] = (R)(gg * gg);
       }
-    if constexpr (DIM == 3) hipLaunchKernelGGL((diag_kernel_3d<P, Q, METRIC, R, ISO>), dim3(g), dim3(C::BLOCK), 0, s, a);
-    else hipLaunchKernelGGL((diag_kernel_2d<P, Q, METRIC, R, ISO>), dim3(g), dim3(C::BLOCK), 0, s, a);
+    if constexpr (DIM == 3) hipLaunchKernelGGL((diag_kernel_3d<P, Q, METRIC, R, TGT>), dim3(g), dim3(C::BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((diag_kernel_2d<P, Q, METRIC, R, TGT>), dim3(g), dim3(C::BLOCK), 0, s, a);
   } else {
     const ElemArgs<P, Q, R>& ea = a;
-    if constexpr (DIM == 3) hipLaunchKernelGGL((elem_kernel_3d<P, Q, METRIC, R, OP, ISO>), dim3(g), dim3(C::BLOCK), 0, s, ea);
-    else hipLaunchKernelGGL((elem_kernel_2d<P, Q, METRIC, R, OP, ISO>), dim3(g), dim3(C::BLOCK), 0, s, ea);
+    if constexpr (DIM == 3) hipLaunchKernelGGL((elem_kernel_3d<P, Q, METRIC, R, OP, TGT>), dim3(g), dim3(C::BLOCK), 0, s, ea);
+    else hipLaunchKernelGGL((elem_kernel_2d<P, Q, METRIC, R, OP, TGT>), dim3(g), dim3(C::BLOCK), 0, s, ea);
   }
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-template <int DIM, int P, int Q, int M, typename R, bool ISO>
+// OP_SIZE does not depend on the metric: it is instantiated for the first
+// metric of each dimension only (the caller routes it there).
+template <int DIM, int P, int Q, int M, typename R, int TGT>
 static int launch_op(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
-  if (op == OP_ENERGY) return launch_one<DIM, P, Q, M, R, OP_ENERGY, ISO>(lp, s, grid);
-  if (op == OP_GRAD) return launch_one<DIM, P, Q, M, R, OP_GRAD, ISO>(lp, s, grid);
-  if (op == OP_HESS) return launch_one<DIM, P, Q, M, R, OP_HESS, ISO>(lp, s, grid);
-  if (op == OP_EG) return launch_one<DIM, P, Q, M, R, OP_EG, ISO>(lp, s, grid);
-  if (op == OP_DIAG) return launch_one<DIM, P, Q, M, R, OP_DIAG, ISO>(lp, s, grid);
+  if (op == OP_ENERGY) return launch_one<DIM, P, Q, M, R, OP_ENERGY, TGT>(lp, s, grid);
+  if (op == OP_GRAD) return launch_one<DIM, P, Q, M, R, OP_GRAD, TGT>(lp, s, grid);
+  if (op == OP_HESS) return launch_one<DIM, P, Q, M, R, OP_HESS, TGT>(lp, s, grid);
+  if (op == OP_EG) return launch_one<DIM, P, Q, M, R, OP_EG, TGT>(lp, s, grid);
+  if (op == OP_DIAG) return launch_one<DIM, P, Q, M, R, OP_DIAG, TGT>(lp, s, grid);
+  if constexpr (M == (DIM == 2 ? 1 : 302))
+    if (op == OP_SIZE) return launch_one<DIM, P, Q, M, R, OP_SIZE, TGT>(lp, s, grid);
   return -1;
 }
 
 template <int DIM, int P, int Q, int M, typename R>
 static int launch_metric(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
-  return lp.iso ? launch_op<DIM, P, Q, M, R, true>(op, lp, s, grid) : launch_op<DIM, P, Q, M, R, false>(op, lp, s, grid);
+  if (lp.tsize) return launch_op<DIM, P, Q, M, R, TGT_QPS>(op, lp, s, grid);
+  return lp.iso ? launch_op<DIM, P, Q, M, R, TGT_ISO>(op, lp, s, grid) : launch_op<DIM, P, Q, M, R, TGT_GEN>(op, lp, s, grid);
 }
 
 // The metrics of each dimension (Table 3.1, Sections 3.2 and 4.3; mu_302 in
@@ -69,6 +75,7 @@ static int launch_metric(int op, const LaunchParams& lp, hipStream_t s, int* gri
 // translation units so that they compile in parallel.
 template <int DIM, int GROUP, int P, int Q, typename R>
 static int launch_pq(int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid) {
+  if (op == OP_SIZE) metric = DIM == 2 ? 1 : 302;
   if constexpr (DIM == 2 && GROUP == 0) {
     switch (metric) {
       case 1: return launch_metric<2, P, Q, 1, R>(op, lp, s, grid);

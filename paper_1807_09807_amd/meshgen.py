@@ -75,8 +75,13 @@ class BoxMesh:
         return self.dim * self.n_node
 
 
-def box_mesh(dim: int, n: int, order: int) -> BoxMesh:
-    """Structured mesh of the unit square/cube with n^dim Q_order elements."""
+def box_mesh(dim: int, n: int, order: int, slide: bool = False) -> BoxMesh:
+    """Structured mesh of the unit square/cube with n^dim Q_order elements.
+
+    fixed: every component of every boundary node (slide=False), or, for
+    motion along the axis-parallel boundary (slide=True), only the
+    component normal to each boundary face the node lies on (edge and corner
+    nodes of several faces keep several components)."""
     if dim not in (2, 3):
         raise ValueError("dim must be 2 or 3")
     p = order
@@ -99,7 +104,9 @@ def box_mesh(dim: int, n: int, order: int) -> BoxMesh:
         x_grid = np.stack([g0.ravel(), g1.ravel()])
         J = np.arange(m)
         on_bnd_1d = (J == 0) | (J == m - 1)
-        bnd = (on_bnd_1d[None, :] | on_bnd_1d[:, None]).ravel()
+        # on_face[c]: nodes on a face with normal c (grid index j_c at an end)
+        on_face = [np.broadcast_to(on_bnd_1d[None, :], (m, m)).ravel(),
+                   np.broadcast_to(on_bnd_1d[:, None], (m, m)).ravel()]
     else:
         e = eidx
         j0 = e[None, None, :, None, None, None] * p + loc[None, None, None, None, None, :]
@@ -111,8 +118,14 @@ def box_mesh(dim: int, n: int, order: int) -> BoxMesh:
         x_grid = np.stack([g0.ravel(), g1.ravel(), g2.ravel()])
         J = np.arange(m)
         b = (J == 0) | (J == m - 1)
-        bnd = (b[None, None, :] | b[None, :, None] | b[:, None, None]).ravel()
-    fixed = np.repeat(bnd[None, :].astype(np.uint8), dim, axis=0)
+        on_face = [np.broadcast_to(b[None, None, :], (m, m, m)).ravel(),
+                   np.broadcast_to(b[None, :, None], (m, m, m)).ravel(),
+                   np.broadcast_to(b[:, None, None], (m, m, m)).ravel()]
+    if slide:
+        fixed = np.stack([f.astype(np.uint8) for f in on_face])
+    else:
+        bnd = np.logical_or.reduce(on_face)
+        fixed = np.repeat(bnd[None, :].astype(np.uint8), dim, axis=0)
     return BoxMesh(dim=dim, order=p, n=n,
                    elem_node=np.ascontiguousarray(elem_node, dtype=np.int32),
                    x_grid=np.ascontiguousarray(x_grid, dtype=np.float64),

@@ -25,13 +25,14 @@ TMOP_MU1, TMOP_MU2, TMOP_MU7, TMOP_MU9, TMOP_MU14, TMOP_MU77, TMOP_MU98 = 1, 2, 
 TMOP_MU302, TMOP_MU303 = 302, 303
 TMOP_GAUSS_LEGENDRE, TMOP_GAUSS_LOBATTO = 0, 1
 TMOP_FP64, TMOP_MIXED_FP32 = 0, 1
-TMOP_TGT_CONST = 0
+TMOP_TGT_CONST, TMOP_TGT_ISO_PER_QP = 0, 1
 TMOP_INNER_CG, TMOP_INNER_MINRES = 0, 1
 TMOP_PREC_NONE, TMOP_PREC_JACOBI = 0, 1
 
 EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_gradient_scaled", "tmop_hessian_apply",
            "tmop_newton_solve", "tmop_destroy", "tmop_strerror", "tmop_newton_default_opts",
-           "tmop_timing_enable", "tmop_timing_read", "tmop_energy_gradient", "tmop_hessian_diagonal")
+           "tmop_timing_enable", "tmop_timing_read", "tmop_energy_gradient", "tmop_hessian_diagonal",
+           "tmop_target_sizes_w3", "tmop_set_target_sizes")
 
 
 class TMOPError(RuntimeError):
@@ -95,6 +96,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tmop_hessian_apply.restype = ctypes.c_int
     lib.tmop_hessian_diagonal.argtypes = [P, P, P, P]
     lib.tmop_hessian_diagonal.restype = ctypes.c_int
+    lib.tmop_target_sizes_w3.argtypes = [P, P, P, P]
+    lib.tmop_target_sizes_w3.restype = ctypes.c_int
+    lib.tmop_set_target_sizes.argtypes = [P, P, P]
+    lib.tmop_set_target_sizes.restype = ctypes.c_int
     lib.tmop_newton_solve.argtypes = [P, P, ctypes.POINTER(tmop_newton_opts),
                                       ctypes.POINTER(tmop_newton_report), P]
     lib.tmop_newton_solve.restype = ctypes.c_int
@@ -132,11 +137,13 @@ def _check_field(t, dim, n_node, name):
 
 
 class Context:
-    """Owns one tmop_ctx (tmop_setup ... tmop_destroy)."""
+    """Owns one tmop_ctx (tmop_setup ... tmop_destroy).  The target is the
+    constant matrix W, or, when `target_sizes` ([n_elem][n_q1d^dim] host
+    array) is given, the per-point isotropic targets W_q = s_q I."""
 
     def __init__(self, dim: int, order: int, elem_node: np.ndarray, n_node: int, n_q1d: int, metric: int,
                  W, fixed: Optional[np.ndarray] = None, precision: int = TMOP_FP64,
-                 rule: int = TMOP_GAUSS_LEGENDRE):
+                 rule: int = TMOP_GAUSS_LEGENDRE, target_sizes: Optional[np.ndarray] = None):
         lib = load()
         self._lib = lib
         self.dim, self.order, self.n_node, self.metric, self.precision = dim, order, int(n_node), metric, precision
@@ -148,9 +155,16 @@ class Context:
             if fx.shape != (dim, n_node):
                 raise ValueError("fixed must have shape (dim, n_node)")
             m.fixed = fx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
-        Wa = np.ascontiguousarray(np.asarray(W, dtype=np.float64).reshape(dim, dim))
         q = tmop_quadrature(rule, n_q1d)
-        t = tmop_target(TMOP_TGT_CONST, Wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        self.nq = n_q1d ** dim
+        if target_sizes is not None:
+            Wa = np.ascontiguousarray(target_sizes, dtype=np.float64)
+            if Wa.shape != (self.n_elem, self.nq):
+                raise ValueError(f"target_sizes must have shape ({self.n_elem}, {self.nq})")
+            t = tmop_target(TMOP_TGT_ISO_PER_QP, Wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        else:
+            Wa = np.ascontiguousarray(np.asarray(W, dtype=np.float64).reshape(dim, dim))
+            t = tmop_target(TMOP_TGT_CONST, Wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         h = ctypes.c_void_p()
         st = lib.tmop_setup(ctypes.byref(m), ctypes.byref(q), ctypes.byref(t), metric, precision, ctypes.byref(h))
         if st < 0:
@@ -245,6 +259,31 @@ class Context:
             raise TMOPError(st, "tmop_hessian_diagonal")
         return out
 
+    def target_sizes_w3(self, x0, out=None):
+        """(sizes, status): (det A(x0))^(1/dim) at every quadrature point,
+        a float64 device tensor [n_elem][n_q1d^dim]; status TMOP_OK or
+        TMOP_W_INVERTED."""
+        import torch
+        _check_field(x0, self.dim, self.n_node, "x0")
+        out = torch.empty((self.n_elem, self.nq), dtype=torch.float64, device=x0.device) if out is None else out
+        if tuple(out.shape) != (self.n_elem, self.nq) or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of shape (n_elem, n_q1d^dim)")
+        st = self._lib.tmop_target_sizes_w3(self._h, ctypes.c_void_p(x0.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                            _stream(x0))
+        if st < 0:
+            raise TMOPError(st, "tmop_target_sizes_w3")
+        return out, st
+
+    def set_target_sizes(self, sizes):
+        """Replaces the per-point target sizes (device tensor [n_elem][n_q1d^dim])."""
+        import torch
+        if not (isinstance(sizes, torch.Tensor) and sizes.dtype == torch.float64 and sizes.is_cuda
+                and tuple(sizes.shape) == (self.n_elem, self.nq) and sizes.is_contiguous()):
+            raise ValueError("sizes must be a contiguous float64 device tensor of shape (n_elem, n_q1d^dim)")
+        st = self._lib.tmop_set_target_sizes(self._h, ctypes.c_void_p(sizes.data_ptr()), _stream(sizes))
+        if st < 0:
+            raise TMOPError(st, "tmop_set_target_sizes")
+
     def timing_enable(self, on: bool = True):
         """Clears the per-launch kernel timing totals and turns timing on/off."""
         st = self._lib.tmop_timing_enable(self._h, int(bool(on)))
@@ -254,7 +293,8 @@ class Context:
     def timing_read(self, op: int):
         """(summed device ms, launch count) of the element kernels of one
         operation (0 energy, 1 gradient, 2 Hessian action, 3 energy +
-        gradient, 4 Hessian diagonal) since the last timing_enable."""
+        gradient, 4 Hessian diagonal, 5 target sizes) since the last
+        timing_enable."""
         ms, n = ctypes.c_double(), ctypes.c_int64()
         st = self._lib.tmop_timing_read(self._h, int(op), ctypes.byref(ms), ctypes.byref(n))
         if st < 0:

@@ -72,3 +72,21 @@ def test_training_mesh_valid():
     tm = meshgen.training_mesh(8, 1000, bad_elements=prob.bad_elements)
     assert prob.bad_elements(tm.x).size == 0
     assert 1 <= tm.info["kx"] <= 4 and 1 <= tm.info["ky"] <= 4
+
+
+def test_sliding_boundary_mask():
+    """slide=True fixes only the component normal to each boundary face a
+    node lies on (Section 4.1, axis-parallel boundaries); interior nodes are
+    free and the perturbation leaves the boundary alone."""
+    for dim in (2, 3):
+        m = meshgen.box_mesh(dim, 3, 2, slide=True)
+        full = meshgen.box_mesh(dim, 3, 2)
+        x = m.x_grid
+        for c in range(dim):
+            on = (np.abs(x[c]) < 1e-15) | (np.abs(x[c] - 1.0) < 1e-15)
+            np.testing.assert_array_equal(m.fixed[c].astype(bool), on)
+        # a node is fixed in some component exactly when it is on the boundary
+        np.testing.assert_array_equal(m.fixed.any(axis=0), full.fixed.any(axis=0))
+        xp = meshgen.perturb(m, 0.1, 1)
+        bnd = full.fixed.any(axis=0)
+        np.testing.assert_array_equal(xp[:, bnd], x[:, bnd])

@@ -39,3 +39,28 @@ def test_newton_other_metrics(metric):
     x = xd.cpu().numpy()
     assert np.max(np.abs(x - mesh.x_grid)) < 1e-8 * mesh.h
     assert np.max(np.abs(xo - mesh.x_grid)) < 1e-8 * mesh.h
+
+
+def test_newton_sliding_boundary():
+    """Axis-parallel boundaries with only the normal components fixed
+    (Section 4.1): boundary nodes moved along their faces slide back to the
+    grid on the GPU as in the oracle, and no node leaves its face."""
+    from paper_1807_09807_amd import tmop as T
+    mesh = meshgen.box_mesh(2, 6, 2, slide=True)
+    W = mesh.h * np.eye(2)
+    prob = O.Problem(2, 2, 4, mesh.elem_node, 2, W)
+    x0 = meshgen.perturb(mesh, 0.1, 8, bad_elements=prob.bad_elements)
+    rng = np.random.default_rng(9)
+    for c in range(2):
+        on = mesh.fixed[1 - c].astype(bool) & ~mesh.fixed[c].astype(bool)
+        x0[c, on] += rng.uniform(-0.15, 0.15, on.sum()) * mesh.h
+    xo, rep_o = O.newton_solve(prob, x0, mesh.fixed, O.NewtonOptions(max_it=40, cg_rtol=1e-10))
+    ctx = T.Context(2, 2, mesh.elem_node, mesh.n_node, 4, 2, W, fixed=mesh.fixed)
+    xd = to_dev(x0)
+    st, rep = ctx.newton_solve(xd, max_it=40, cg_rtol=1e-10)
+    assert st == T.TMOP_OK and rep_o.stop == O.STOP_CONVERGED
+    assert abs(rep["history_F"][1] - rep_o.history[1][0]) <= 1e-9 * rep_o.history[1][0]
+    x = xd.cpu().numpy()
+    assert np.max(np.abs(x - mesh.x_grid)) < 1e-9 * mesh.h
+    fx = mesh.fixed.astype(bool)
+    np.testing.assert_array_equal(x[fx], x0[fx])

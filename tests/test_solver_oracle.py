@@ -155,3 +155,56 @@ def test_newton_rejects_unknown_solver():
         O.newton_solve(prob, x, mesh.fixed, O.NewtonOptions(inner="gmres"))
     with pytest.raises(ValueError):
         O.newton_solve(prob, x, mesh.fixed, O.NewtonOptions(precond="ilu"))
+
+
+def test_w3_sizes_affine_mesh():
+    """On x = M x_grid every point has A = M h-scaled: det A = det M h^d, so
+    the W_3 sizes are (det M)^(1/d) h exactly."""
+    for dim, M in ((2, np.array([[1.2, 0.3], [-0.1, 0.9]])),
+                   (3, np.array([[1.1, 0.2, 0.0], [0.0, 0.9, 0.1], [0.2, 0.0, 1.3]]))):
+        mesh = meshgen.box_mesh(dim, 2, 2)
+        prob = O.Problem(dim, 2, 3, mesh.elem_node, 303 if dim == 3 else 2, mesh.h * np.eye(dim))
+        s = prob.point_sizes(M @ mesh.x_grid)
+        np.testing.assert_allclose(s, np.linalg.det(M) ** (1.0 / dim) * mesh.h, rtol=1e-14)
+
+
+@pytest.mark.parametrize("dim,metric", [(2, 77), (2, 9)])
+def test_w3_target_reproduces_initial_sizes(dim, metric):
+    """With the W_3 target of the initial mesh, det T = 1 at every point of
+    that mesh: the size metric mu_77 = (tau - 1/tau)^2 / 2 and its gradient
+    vanish there; for mu_9 the targets make F equal to the sum of
+    w_q det A(x0) mu_9(A / s_q)."""
+    mesh = meshgen.box_mesh(dim, 3, 2)
+    prob0 = O.Problem(dim, 2, 4, mesh.elem_node, metric, mesh.h * np.eye(dim))
+    x0 = meshgen.perturb(mesh, 0.15, 3, bad_elements=prob0.bad_elements)
+    s = prob0.point_sizes(x0)
+    W = s[:, :, None, None] * np.eye(dim)
+    prob = O.Problem(dim, 2, 4, mesh.elem_node, metric, W)
+    F, _ = prob.energy(x0)
+    if metric == 77:
+        assert abs(F) < 1e-28
+        assert np.max(np.abs(prob.gradient(x0))) < 1e-14
+    else:
+        A = np.concatenate([prob._jac(x0, e0, e1) for e0, e1 in prob._chunks()])
+        detA = np.linalg.det(A)
+        ref = math.fsum((prob.wq[None, :] * detA * O.mu(9, A / s[:, :, None, None])).ravel())
+        assert F == pytest.approx(ref, rel=1e-13)
+
+
+def test_newton_sliding_boundary_returns_to_grid():
+    """Boundary nodes moved along their (axis-parallel) face slide back:
+    Newton with only the normal components fixed returns to the grid, and no
+    node leaves its face (Section 4.1)."""
+    mesh = meshgen.box_mesh(2, 4, 2, slide=True)
+    prob = O.Problem(2, 2, 4, mesh.elem_node, 2, mesh.h * np.eye(2))
+    x0 = meshgen.perturb(mesh, 0.1, 8, bad_elements=prob.bad_elements)
+    rng = np.random.default_rng(9)
+    for c in range(2):   # tangential moves of the nodes on the faces with normal 1 - c
+        on = mesh.fixed[1 - c].astype(bool) & ~mesh.fixed[c].astype(bool)
+        x0[c, on] += rng.uniform(-0.15, 0.15, on.sum()) * mesh.h
+    assert prob.element_min_det(x0).min() > 0
+    x, rep = O.newton_solve(prob, x0, mesh.fixed, O.NewtonOptions(max_it=40, cg_rtol=1e-10))
+    assert rep.stop == O.STOP_CONVERGED
+    assert np.max(np.abs(x - mesh.x_grid)) < 1e-9 * mesh.h
+    fx = mesh.fixed.astype(bool)
+    np.testing.assert_array_equal(x[fx], x0[fx])
