@@ -113,6 +113,8 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-initial-guess pipeline")
     ap.add_argument("--train-meshes", type=int, default=2000)
     ap.add_argument("--eval-seeds", type=int, default=4)
+    ap.add_argument("--other-workloads", default="q3_square_256,q3_cube_48,q2_square_512",
+                    help="further workloads whose element operations are timed and reported (comma list)")
     return ap.parse_args()
 
 
@@ -169,6 +171,114 @@ def cpu_baseline(w, mesh, x, v, n_elem_sample):
                        f"{mesh.n_elem} elements ({dt:.1f} s), scaled by the element fraction")
 
 
+def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
+    """Builds the named workload and times its element operations in FP64
+    and mixed FP32: seconds per step (energy + gradient, then the Hessian
+    action), per-operation device time (HIP events on the library's stream)
+    and per-launch kernel time.  With gpu_repair, inverted elements of the
+    seeded mesh are redrawn using the library's own det A (the W_3 sizes
+    kernel), as the test suite does with the oracle's."""
+    w = meshgen.WORKLOADS[name]
+    W = None
+    bad = None
+    if gpu_repair:
+        topo = meshgen.box_mesh(w["dim"], w["n"], w["p"])
+        W = topo.h * np.eye(w["dim"])
+        cctx = T.Context(w["dim"], w["p"], topo.elem_node, topo.n_node, w["Q"], w["metric"], W)
+        floor = w["tau_min"] * topo.h ** w["dim"]
+
+        def bad(xh, elems):
+            s_q, _ = cctx.target_sizes_w3(torch.from_numpy(xh).to(dev))
+            detA = s_q.cpu().numpy() ** w["dim"]
+            worst = np.where(np.isnan(detA), -np.inf, detA).min(axis=1)
+            worst = worst if elems is None else worst[np.asarray(elems)]
+            return np.flatnonzero(worst <= floor)
+    mesh = meshgen.make_workload(name, bad_elements=bad)
+    if W is None:
+        W = mesh.h * np.eye(w["dim"])
+    x = torch.from_numpy(mesh.x).to(dev)
+    v = torch.from_numpy(meshgen.random_direction(mesh, w["seed"] + 100)).to(dev)
+    log(f"# workload {name}: {mesh.n_elem} elements, {mesh.n_dof} DOFs, repair rounds "
+        f"{mesh.info.get('repair_rounds', 0)}")
+    results = {}
+    for prec, pname in ((T.TMOP_FP64, "f64"), (T.TMOP_MIXED_FP32, "mixed")):
+        ctx = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W,
+                        fixed=mesh.fixed, precision=prec)
+        F, md, st = ctx.energy(x)
+        if st != 0 or not md > 0:
+            raise SystemExit(f"{name}: inverted input mesh (min det A = {md})")
+        g = torch.empty_like(x)
+        Hv = torch.empty_like(x)
+
+        def step():
+            ctx.energy_gradient(x, g)
+            ctx.hessian_apply(x, v, Hv)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+
+        # per-operation device time, HIP events on the stream the library uses
+        stream = torch.cuda.current_stream()
+        ops = {}
+        for oname, fn in (("energy", lambda: ctx.energy(x)), ("gradient", lambda: ctx.gradient(x, g)),
+                          ("energy_gradient", lambda: ctx.energy_gradient(x, g)),
+                          ("hessian", lambda: ctx.hessian_apply(x, v, Hv)),
+                          ("hessian_diagonal", lambda: ctx.hessian_diagonal(x, Hv))):
+            ts = []
+            for _ in range(max(steps, 5)):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+            ops[oname] = float(np.median(ts))
+        # per-launch device time of the element kernels over K steps
+        ctx.timing_enable(True)
+        for _ in range(steps):
+            ctx.energy(x)
+            ctx.gradient(x, g)
+            ctx.hessian_diagonal(x, Hv)
+            step()
+        launch = {}
+        for op, oname in enumerate(("energy", "gradient", "hessian", "energy_gradient", "hessian_diagonal")):
+            tot_ms, n = ctx.timing_read(op)
+            launch[oname] = dict(launches=n, us_per_launch=tot_ms * 1e3 / n, us_per_op=tot_ms * 1e3 / steps)
+        ctx.timing_enable(False)
+        results[pname] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), ops=ops, F=F, ctx=ctx,
+                              launch=launch)
+        log(f"# {pname}: {ms:.3f} ms/step, E {ops['energy']*1e6:.1f} us, G {ops['gradient']*1e6:.1f} us, "
+            f"E+G {ops['energy_gradient']*1e6:.1f} us, Hv {ops['hessian']*1e6:.1f} us, "
+            f"diag {ops['hessian_diagonal']*1e6:.1f} us; per launch "
+            + ", ".join(f"{k} {v['us_per_launch']:.1f}" for k, v in launch.items()))
+    return w, mesh, x, v, W, results
+
+
+def workload_summary(w, mesh, results):
+    """Per-operation rates of one workload against the FP64 VALU and HBM
+    peaks (algorithmic flops and unique L-vector bytes per element)."""
+    flops, nbytes = algorithmic(w)
+    out = {"elements": mesh.n_elem, "dofs": mesh.n_dof}
+    for pname, r in results.items():
+        d = {"ms_per_step": round(r["ms_per_step"], 4), "dof_iterations_per_s": r["value"]}
+        for k, (op, key) in enumerate((("energy", "energy"), ("gradient", "gradient"), ("hessian", "hessian"))):
+            t = r["ops"][op]
+            d[key] = {"us": round(t * 1e6, 2),
+                      "tflops": round(flops[k] * mesh.n_elem / t / 1e12, 3),
+                      "frac_fp64_peak": round(flops[k] * mesh.n_elem / t / FP64_PEAK, 4),
+                      "algorithmic_GBps": round(nbytes[k] * mesh.n_elem / t / 1e9, 1),
+                      "frac_hbm_peak": round(nbytes[k] * mesh.n_elem / t / HBM_PEAK, 4)}
+        out[pname] = d
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -183,74 +293,11 @@ def main():
     torch.cuda.set_device(dev)
     if args.calibrate_copy:
         copy_calibration(torch, dev)
-    w = meshgen.WORKLOADS[args.workload]
-    mesh = meshgen.make_workload(args.workload)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    w, mesh, x, v, W, results = time_workload(T, torch, dev, args.workload, args.steps, args.warmup, log)
     x_np = mesh.x
-    v_np = meshgen.random_direction(mesh, w["seed"] + 100)
-    x = torch.from_numpy(x_np).to(dev)
-    v = torch.from_numpy(v_np).to(dev)
-    W = mesh.h * np.eye(w["dim"])
-    print(f"# workload {args.workload}: {mesh.n_elem} elements, {mesh.n_dof} DOFs", file=sys.stderr, flush=True)
-
+    v_np = v.cpu().numpy()
     flops, nbytes = algorithmic(w)
-    results = {}
-    for prec, pname in ((T.TMOP_FP64, "f64"), (T.TMOP_MIXED_FP32, "mixed")):
-        ctx = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W,
-                        fixed=mesh.fixed, precision=prec)
-        F, md, st = ctx.energy(x)
-        if st != 0 or not md > 0:
-            raise SystemExit(f"{args.workload}: inverted input mesh (min det A = {md}); "
-                             "this workload needs the repaired mesh of the test suite")
-        g = torch.empty_like(x)
-        Hv = torch.empty_like(x)
-
-        def step():
-            ctx.energy_gradient(x, g)
-            ctx.hessian_apply(x, v, Hv)
-
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
-
-        # per-operation device time, HIP events on the stream the library uses
-        stream = torch.cuda.current_stream()
-        ops = {}
-        for name, fn in (("energy", lambda: ctx.energy(x)), ("gradient", lambda: ctx.gradient(x, g)),
-                         ("energy_gradient", lambda: ctx.energy_gradient(x, g)),
-                         ("hessian", lambda: ctx.hessian_apply(x, v, Hv)),
-                         ("hessian_diagonal", lambda: ctx.hessian_diagonal(x, Hv))):
-            ts = []
-            for _ in range(max(args.steps, 5)):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                fn()
-                e1.record(stream)
-                e1.synchronize()
-                ts.append(e0.elapsed_time(e1) * 1e-3)
-            ops[name] = float(np.median(ts))
-        # per-launch device time of the element kernels over K steps
-        ctx.timing_enable(True)
-        for _ in range(args.steps):
-            ctx.energy(x)
-            ctx.gradient(x, g)
-            ctx.hessian_diagonal(x, Hv)
-            step()
-        launch = {}
-        for op, name in enumerate(("energy", "gradient", "hessian", "energy_gradient", "hessian_diagonal")):
-            tot_ms, n = ctx.timing_read(op)
-            launch[name] = dict(launches=n, us_per_launch=tot_ms * 1e3 / n, us_per_op=tot_ms * 1e3 / args.steps)
-        ctx.timing_enable(False)
-        results[pname] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), ops=ops, F=F, ctx=ctx,
-                              launch=launch)
-        print(f"# {pname}: {ms:.3f} ms/step, E {ops['energy']*1e6:.1f} us, G {ops['gradient']*1e6:.1f} us, "
-              f"E+G {ops['energy_gradient']*1e6:.1f} us, Hv {ops['hessian']*1e6:.1f} us, diag {ops['hessian_diagonal']*1e6:.1f} us; per launch "
-              + ", ".join(f"{k} {v['us_per_launch']:.1f}" for k, v in launch.items()), file=sys.stderr, flush=True)
 
     # Newton wall time to F_tol = F_ref + 1e-8 F0 (F_ref: final F of FP64 Newton)
     newton = None
@@ -288,6 +335,14 @@ def main():
     learned = None
     if not args.no_learned:
         learned = learned_guess(args, lambda m: print(m, file=sys.stderr, flush=True))
+
+    others = {}
+    for name in [n for n in args.other_workloads.split(",") if n and n != args.workload]:
+        wo, mo, xo, vo, Wo, ro = time_workload(T, torch, dev, name, args.steps, args.warmup, log, gpu_repair=True)
+        others[name] = workload_summary(wo, mo, ro)
+        for r in ro.values():
+            r["ctx"].close()
+        del xo, vo
 
     cpu = None
     if not args.no_cpu:
@@ -328,6 +383,7 @@ def main():
         "ops_us": {k: round(t * 1e6, 2) for k, t in r64["ops"].items()},
         "mixed_fp32": {"value": results["mixed"]["value"], "ms_per_step": results["mixed"]["ms_per_step"],
                        "ops_us": {k: round(t * 1e6, 2) for k, t in results["mixed"]["ops"].items()}},
+        "workloads": {args.workload: workload_summary(w, mesh, {k: r for k, r in results.items()}), **others},
         "newton": newton,
         "learned_guess": learned,
         "cpu_baseline": cpu,
