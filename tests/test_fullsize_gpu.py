@@ -7,7 +7,7 @@ import pytest
 
 from oracle import tmop_oracle as O
 from paper_1807_09807_amd import meshgen
-from tests._helpers import EPS32, say, to_dev
+from tests._helpers import EPS32, MIXED_C, say, to_dev
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -39,7 +39,7 @@ def full(request):
 def test_full_size(full, precision):
     from paper_1807_09807_amd import tmop as T
     name, w, mesh, W, x, v, ref = full
-    tol = 1e-12 if precision == 0 else max(1e-5, 4.0 * EPS32 * ref["kappa"])
+    tol = 1e-12 if precision == 0 else max(1e-5, MIXED_C * EPS32 * ref["kappa"])
     ctx = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W,
                     fixed=mesh.fixed, precision=precision)
     xd, vd = to_dev(x), to_dev(v)

@@ -1,6 +1,6 @@
 """Parity of the HIP path with the FP64 oracle (energy, gradient, Hessian
 action), element by element, on seeded meshes: FP64 within 1e-12
-relative, the mixed FP32 path within 1e-5 relative (4 eps32 kappa on
+relative, the mixed FP32 path within 1e-5 relative (6 eps32 kappa on
 meshes with nearly degenerate points, see tests/_helpers.mixed_tol)."""
 import numpy as np
 import pytest
