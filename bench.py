@@ -64,7 +64,7 @@ POINT_FLOPS = {2: (15, 31, 72), 7: (21, 32, 74), 303: (40, 87, 232), 302: (85, 2
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ("tmop_elem.h", "tmop_metrics.h", "tmop_launch.h")
 MEASURED_TRAFFIC = {
-    "q2_cube_64": dict(src_sha256="4a3e38bff605c811b77f699a76c88a5c56d6a24ed44475eff994e182ce198935",
+    "q2_cube_64": dict(src_sha256="6d9a3df1ed4d218a66115d5fbe6e9536a652ce0983accf5659dc7026ae52c39f",
                        fetch_kib=41951.0, write_kib=27965.4),
 }
 
