@@ -64,8 +64,8 @@ POINT_FLOPS = {2: (15, 31, 72), 7: (21, 32, 74), 303: (40, 87, 232), 302: (85, 2
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ("tmop_elem.h", "tmop_metrics.h", "tmop_launch.h")
 MEASURED_TRAFFIC = {
-    "q2_cube_64": dict(src_sha256="6d9a3df1ed4d218a66115d5fbe6e9536a652ce0983accf5659dc7026ae52c39f",
-                       fetch_kib=41951.0, write_kib=27965.4),
+    "q2_cube_64": dict(src_sha256="fba2402802df71329ad15a1491690afe75b4f321eab4868af7c3e6348a6682ea",
+                       fetch_kib=41951.0, write_kib=27965.2),
 }
 
 
@@ -166,9 +166,16 @@ def cpu_baseline(w, mesh, x, v, n_elem_sample):
         prob.hessian_apply(x, v)
         dt = time.perf_counter() - t0
     frac = n_elem_sample / mesh.n_elem
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return dict(value=mesh.n_dof * frac / dt, unit="DOF-iterations/s", cores=1, kind="oracle",
                 sample=f"energy+gradient+Hessian action of the FP64 oracle on {n_elem_sample} of "
-                       f"{mesh.n_elem} elements ({dt:.1f} s), scaled by the element fraction")
+                       f"{mesh.n_elem} elements ({dt:.1f} s), scaled by the element fraction; "
+                       f"one thread of {os.cpu_count()} on {cpu}")
 
 
 def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
@@ -258,6 +265,48 @@ def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
             f"E+G {ops['energy_gradient']*1e6:.1f} us, Hv {ops['hessian']*1e6:.1f} us, "
             f"diag {ops['hessian_diagonal']*1e6:.1f} us; per launch "
             + ", ".join(f"{k} {v['us_per_launch']:.1f}" for k, v in launch.items()))
+    # "cold" operation times: a 512 MiB buffer is rewritten before each call,
+    # evicting x, v and the outputs from the 256 MB Infinity Cache and the L2s
+    flush = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    for pname in ("f64", "mixed"):
+        ctx = results[pname]["ctx"]
+        cold = {}
+        g = torch.empty_like(x)
+        Hv = torch.empty_like(x)
+        for oname, fn in (("energy_gradient", lambda: ctx.energy_gradient(x, g)),
+                          ("hessian", lambda: ctx.hessian_apply(x, v, Hv))):
+            ts = []
+            for _ in range(max(steps // 2, 3)):
+                flush.fill_(1.0)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+            cold[oname] = float(np.median(ts))
+        results[pname]["cold"] = cold
+        log(f"# {pname} cold (caches flushed before each call): E+G {cold['energy_gradient']*1e6:.1f} us, "
+            f"Hv {cold['hessian']*1e6:.1f} us")
+    del flush
+    # error of the mixed path against the FP64 path (itself within 1e-12 of
+    # the FP64 oracle in the parity tests), per result
+    vals = {}
+    for pname in ("f64", "mixed"):
+        ctx = results[pname]["ctx"]
+        F, _, _, g = ctx.energy_gradient(x)
+        vals[pname] = (F, g, ctx.hessian_apply(x, v))
+    (F64, g64, h64), (F32, g32, h32) = vals["f64"], vals["mixed"]
+    gn64 = float(torch.linalg.vector_norm(g64))
+    results["mixed"]["rel_err_vs_f64"] = {
+        "F": abs(F32 - F64) / abs(F64),
+        "grad_norm": abs(float(torch.linalg.vector_norm(g32)) - gn64) / gn64,
+        "grad_max": float((g32 - g64).abs().max() / g64.abs().max()),
+        "hessian_action_max": float((h32 - h64).abs().max() / h64.abs().max())}
+    log(f"# mixed vs f64: " + ", ".join(f"{k} {e:.2e}" for k, e in results["mixed"]["rel_err_vs_f64"].items()))
+    del vals, g64, g32, h64, h32
     return w, mesh, x, v, W, results
 
 
@@ -275,6 +324,8 @@ def workload_summary(w, mesh, results):
                       "frac_fp64_peak": round(flops[k] * mesh.n_elem / t / FP64_PEAK, 4),
                       "algorithmic_GBps": round(nbytes[k] * mesh.n_elem / t / 1e9, 1),
                       "frac_hbm_peak": round(nbytes[k] * mesh.n_elem / t / HBM_PEAK, 4)}
+        if "rel_err_vs_f64" in r:
+            d["rel_err_vs_f64"] = r["rel_err_vs_f64"]
         out[pname] = d
     return out
 
@@ -381,8 +432,10 @@ def main():
         "launch_us": {p: {k: round(v["us_per_launch"], 2) for k, v in results[p]["launch"].items()}
                       for p in ("f64", "mixed")},
         "ops_us": {k: round(t * 1e6, 2) for k, t in r64["ops"].items()},
+        "cold_ops_us": {p: {k: round(t * 1e6, 2) for k, t in results[p]["cold"].items()} for p in ("f64", "mixed")},
         "mixed_fp32": {"value": results["mixed"]["value"], "ms_per_step": results["mixed"]["ms_per_step"],
-                       "ops_us": {k: round(t * 1e6, 2) for k, t in results["mixed"]["ops"].items()}},
+                       "ops_us": {k: round(t * 1e6, 2) for k, t in results["mixed"]["ops"].items()},
+                       "rel_err_vs_f64": results["mixed"]["rel_err_vs_f64"]},
         "workloads": {args.workload: workload_summary(w, mesh, {k: r for k, r in results.items()}), **others},
         "newton": newton,
         "learned_guess": learned,
