@@ -266,16 +266,6 @@ int energy_sync(tmop_ctx* c, const double* x, hipStream_t s, double* F, double* 
   return read_res(c, s, F, mind);
 }
 
-// out[0] = x . y, out[1] = x . z with one host synchronization.
-int dot2_sync(tmop_ctx* c, const double* x, const double* y, const double* z, hipStream_t s, double* out) {
-  HIP_TRY(dot2(x, y, z, c->n_dof, c->d_scratch, c->d_res + 2, s));
-  HIP_TRY(hipMemcpyAsync(c->h_res + 2, c->d_res + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  out[0] = c->h_res[2];
-  out[1] = c->h_res[3];
-  return TMOP_OK;
-}
-
 int dot_sync(tmop_ctx* c, const double* a, const double* b, hipStream_t s, double* out) {
   HIP_TRY(dot(a, b, c->n_dof, c->d_scratch, c->d_res + 2, s));
   HIP_TRY(hipMemcpyAsync(c->h_res + 2, c->d_res + 2, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -372,10 +362,11 @@ int inner_tcg(tmop_ctx* c, const double* x, const double* g, double gn, double t
   double* p = w.v[1];
   double* Hp = w.v[2];
   double* z = minv ? w.v[3] : r;
+  const double* mask = c->has_fixed ? c->d_mask : nullptr;
   int st;
   HIP_TRY(fill(w.d, 0.0, N, s));
   HIP_TRY(scale_copy(-1.0, g, r, N, s));
-  double rz, rr;
+  double rz;
   if (minv) {
     HIP_TRY(mul(minv, r, z, N, s));
     if ((st = dot_sync(c, r, z, s, &rz)) != TMOP_OK) return st;
@@ -387,7 +378,9 @@ int inner_tcg(tmop_ctx* c, const double* x, const double* g, double gn, double t
   *neg = false;
   for (int j = 0; j < max_it; ++j) {
     ++*ncg;
-    if ((st = masked_hessian(c, x, p, Hp, s)) != TMOP_OK) return st;
+    // H p over all DOFs; p vanishes on the fixed DOFs, so p . Hp equals
+    // p . (m .* Hp), and the update below applies the mask to Hp
+    if ((st = assemble(c, OP_HESS, x, p, Hp, s)) != TMOP_OK) return st;
     double pHp;
     if ((st = dot_sync(c, p, Hp, s, &pHp)) != TMOP_OK) return st;
     if (!(pHp > 0.0)) {                      // non-positive curvature
@@ -396,19 +389,12 @@ int inner_tcg(tmop_ctx* c, const double* x, const double* g, double gn, double t
       break;
     }
     const double alpha = rz / pHp;
-    HIP_TRY(axpy(alpha, p, w.d, N, s));
-    HIP_TRY(axpy(-alpha, Hp, r, N, s));
-    double rz_new;
-    if (minv) {
-      HIP_TRY(mul(minv, r, z, N, s));
-      double two[2];
-      if ((st = dot2_sync(c, r, r, z, s, two)) != TMOP_OK) return st;
-      rr = two[0];
-      rz_new = two[1];
-    } else {
-      if ((st = dot_sync(c, r, r, s, &rr)) != TMOP_OK) return st;
-      rz_new = rr;
-    }
+    // d += alpha p, r -= alpha m .* Hp, z = M^{-1} r, r . r and r . z in one pass
+    HIP_TRY(cg_step(alpha, p, Hp, mask, minv, w.d, r, z, N, c->d_scratch, c->d_res + 2, s));
+    HIP_TRY(hipMemcpyAsync(c->h_res + 2, c->d_res + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double rr = c->h_res[2];
+    const double rz_new = minv ? c->h_res[3] : rr;
     if (sqrt(rr) <= tol * gn) break;
     HIP_TRY(xpay(z, rz_new / rz, p, N, s));
     rz = rz_new;

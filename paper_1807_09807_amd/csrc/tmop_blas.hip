@@ -106,23 +106,35 @@ __global__ void __launch_bounds__(RED_THREADS) k_dot_part(const double* __restri
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// Stage 1 of two dot products sharing x: x . y into part[b], x . z into
-// part[RED_BLOCKS + b].
-__global__ void __launch_bounds__(RED_THREADS) k_dot2_part(const double* __restrict__ x, const double* __restrict__ y,
-                                                           const double* __restrict__ z, int64_t n,
-                                                           double* __restrict__ part) {
+// One truncated-CG update, fused: d += a p; r -= a (m .* Hp) (m = nullptr:
+// no fixed DOF); z = minv .* r (minv = nullptr: z is r); and the block
+// partial sums of r . r into part[b] and, with minv, of r . z into
+// part[RED_BLOCKS + b].  Same grid and summation order as k_dot_part.
+__global__ void __launch_bounds__(RED_THREADS) k_cg_step(double a, const double* __restrict__ p,
+                                                         const double* __restrict__ Hp, const double* __restrict__ m,
+                                                         const double* __restrict__ minv, double* __restrict__ d,
+                                                         double* __restrict__ r, double* __restrict__ z, int64_t n,
+                                                         double* __restrict__ part) {
   __shared__ double red[2][RED_THREADS / 64];
-  double s = 0.0, t = 0.0;
+  double srr = 0.0, srz = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)RED_BLOCKS * RED_THREADS) {
-    const double xi = x[i];
-    s += xi * y[i];
-    t += xi * z[i];
+    const double pi = p[i];
+    const double hi = m ? Hp[i] * m[i] : Hp[i];
+    d[i] += a * pi;
+    const double ri = r[i] - a * hi;
+    r[i] = ri;
+    srr += ri * ri;
+    if (minv) {
+      const double zi = minv[i] * ri;
+      z[i] = zi;
+      srz += ri * zi;
+    }
   }
-  const double ts = block_sum(s, red[0]);
-  const double tt = block_sum(t, red[1]);
+  const double trr = block_sum(srr, red[0]);
+  const double trz = block_sum(srz, red[1]);
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = ts;
-    part[RED_BLOCKS + blockIdx.x] = tt;
+    part[blockIdx.x] = trr;
+    part[RED_BLOCKS + blockIdx.x] = trz;
   }
 }
 
@@ -189,11 +201,11 @@ hipError_t dot(const double* x, const double* y, int64_t n, double* scratch, dou
   return hipGetLastError();
 }
 
-hipError_t dot2(const double* x, const double* y, const double* z, int64_t n, double* scratch, double* res,
-                hipStream_t s) {
-  hipLaunchKernelGGL(k_dot2_part, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, x, y, z, n, scratch);
+hipError_t cg_step(double a, const double* p, const double* Hp, const double* m, const double* minv, double* d,
+                   double* r, double* z, int64_t n, double* scratch, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_step, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, a, p, Hp, m, minv, d, r, z, n, scratch);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch, RED_BLOCKS, 0, 0, res);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch + RED_BLOCKS, RED_BLOCKS, 0, 0, res + 1);
+  if (minv) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch + RED_BLOCKS, RED_BLOCKS, 0, 0, res + 1);
   return hipGetLastError();
 }
 

@@ -65,10 +65,11 @@ constexpr int FIN_BLOCKS = 256;
 hipError_t finalize_sum_min(const double* part, int n, int moff, double* scratch, double* res, hipStream_t s);
 // res[0] = x . y   (scratch: >= RED_BLOCKS doubles)
 hipError_t dot(const double* x, const double* y, int64_t n, double* scratch, double* res, hipStream_t s);
-// res[0] = x . y, res[1] = x . z   (scratch: >= 2 RED_BLOCKS doubles)
-hipError_t dot2(const double* x, const double* y, const double* z, int64_t n, double* scratch, double* res,
-                hipStream_t s);
 hipError_t mul(const double* a, const double* x, double* y, int64_t n, hipStream_t s);    // y = a .* x
+// Fused truncated-CG update: d += a p; r -= a (m .* Hp); z = minv .* r; res[0] = r . r, res[1] = r . z
+// (m, minv may be nullptr: no mask, no preconditioner; then z is not written and res[1] is not set).
+hipError_t cg_step(double a, const double* p, const double* Hp, const double* m, const double* minv, double* d,
+                   double* r, double* z, int64_t n, double* scratch, double* res, hipStream_t s);
 hipError_t jacobi_inv(const double* m, double* d, int64_t n, hipStream_t s);              // d = m && d ? 1/|d| : 1
 hipError_t minres_w(const double* v, double a, double* w, double b, const double* u, double sc, int64_t n,
                     hipStream_t s);                                                        // w = (v - a w - b u) sc
