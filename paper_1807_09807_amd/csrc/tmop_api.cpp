@@ -342,15 +342,6 @@ struct Inner {
   double* v[7];
 };
 
-// Hp = m .* H(x) p: the Hessian restricted to the free DOFs (p is zero on
-// the fixed ones).
-int masked_hessian(tmop_ctx* c, const double* x, const double* p, double* Hp, hipStream_t s) {
-  const int st = assemble(c, OP_HESS, x, p, Hp, s);
-  if (st != TMOP_OK) return st;
-  if (c->has_fixed) HIP_TRY(mask_mul(c->d_mask, Hp, c->n_dof, s));
-  return TMOP_OK;
-}
-
 // Steihaug's truncated CG for H d = -g from d = 0, optionally with the
 // diagonal preconditioner minv = 1 / diag M.  Non-positive curvature at the
 // first step returns -M^{-1} g (the steepest-descent direction, -g without
@@ -419,6 +410,7 @@ int inner_minres(tmop_ctx* c, const double* x, const double* g, double tol, int 
   double* ybuf = w.v[4];
   double* w_prev = w.v[5];
   double* w_cur = w.v[6];
+  const double* mask = c->has_fixed ? c->d_mask : nullptr;
   int st;
   HIP_TRY(fill(w.d, 0.0, N, s));
   HIP_TRY(scale_copy(-1.0, g, r_cur, N, s));
@@ -435,24 +427,21 @@ int inner_minres(tmop_ctx* c, const double* x, const double* g, double tol, int 
   if (!(beta1 > 0.0)) return TMOP_OK;
   HIP_TRY(fill(w_prev, 0.0, N, s));
   HIP_TRY(fill(w_cur, 0.0, N, s));
+  HIP_TRY(scale_copy(1.0 / beta, y, vbuf, N, s));          // Lanczos vector v_1
   double beta_prev = 0.0, cs = -1.0, sn = 0.0, dbar = 0.0, eps = 0.0, phibar = beta1;
   for (int k = 1; k <= max_it; ++k) {
     ++*nit;
-    HIP_TRY(scale_copy(1.0 / beta, y, vbuf, N, s));          // Lanczos vector v_k
-    if ((st = masked_hessian(c, x, vbuf, hbuf, s)) != TMOP_OK) return st;
+    // H v over all DOFs; v vanishes on the fixed DOFs, so v . Hv = v . (m .* Hv)
+    if ((st = assemble(c, OP_HESS, x, vbuf, hbuf, s)) != TMOP_OK) return st;
     double alpha;
     if ((st = dot_sync(c, vbuf, hbuf, s, &alpha)) != TMOP_OK) return st;
-    HIP_TRY(axpy(-alpha / beta, r_cur, hbuf, N, s));
-    if (k > 1) HIP_TRY(axpy(-beta / beta_prev, r_prev, hbuf, N, s));
-    // hbuf now holds r_{k+1}
-    y = hbuf;
-    if (minv) {
-      HIP_TRY(mul(minv, hbuf, ybuf, N, s));
-      y = ybuf;
-    }
-    double beta_next;
-    if ((st = dot_sync(c, hbuf, y, s, &beta_next)) != TMOP_OK) return st;
-    beta_next = sqrt(std::max(beta_next, 0.0));
+    // r_{k+1} = m .* H v_k - (alpha / beta_k) r_k - (beta_k / beta_{k-1}) r_{k-1}, y = M^{-1} r_{k+1}
+    HIP_TRY(minres_r(hbuf, mask, -alpha / beta, r_cur, k > 1 ? -beta / beta_prev : 0.0, k > 1 ? r_prev : nullptr,
+                     minv, ybuf, N, c->d_scratch, c->d_res + 2, s));
+    HIP_TRY(hipMemcpyAsync(c->h_res + 2, c->d_res + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double beta_next = sqrt(std::max(c->h_res[2], 0.0));
+    y = minv ? ybuf : hbuf;
     // previous rotation on this column and on the next column's beta
     const double eps_k = eps;
     const double delta = cs * dbar + sn * alpha;
@@ -466,10 +455,12 @@ int inner_minres(tmop_ctx* c, const double* x, const double* g, double tol, int 
     sn = beta_next / gamma;
     const double phi = cs * phibar;
     phibar = sn * phibar;
-    // w_k = (v_k - eps_k w_{k-2} - delta w_{k-1}) / gamma, into w_prev's storage
-    HIP_TRY(minres_w(vbuf, eps_k, w_prev, delta, w_cur, 1.0 / gamma, N, s));
+    const bool done = fabs(phibar) <= tol * beta1 || !(beta_next > 0.0) || k == max_it;
+    // w_k = (v_k - eps_k w_{k-2} - delta w_{k-1}) / gamma (into w_prev's storage), d += phi w_k, and the next
+    // Lanczos vector v_{k+1} = y / beta_{k+1}
+    HIP_TRY(minres_wd(vbuf, eps_k, w_prev, delta, w_cur, 1.0 / gamma, phi, w.d, done ? nullptr : y,
+                      done ? 0.0 : 1.0 / beta_next, N, s));
     std::swap(w_prev, w_cur);
-    HIP_TRY(axpy(phi, w_cur, w.d, N, s));
     // r_{k-1} <- r_k <- r_{k+1}; the oldest buffer takes the next H v
     double* spare = r_prev;
     r_prev = r_cur;
@@ -477,7 +468,7 @@ int inner_minres(tmop_ctx* c, const double* x, const double* g, double tol, int 
     hbuf = spare;
     beta_prev = beta;
     beta = beta_next;
-    if (fabs(phibar) <= tol * beta1 || !(beta > 0.0)) break;
+    if (done) break;
   }
   return TMOP_OK;
 }

@@ -54,13 +54,6 @@ __global__ void __launch_bounds__(VB) k_jacobi_inv(const double* __restrict__ m,
   }
 }
 
-// MINRES direction update w <- (v - a w - b u) s (w updated in place).
-__global__ void __launch_bounds__(VB) k_minres_w(const double* __restrict__ v, double a, double* __restrict__ w,
-                                                 double b, const double* __restrict__ u, double s, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB)
-    w[i] = (v[i] - a * w[i] - b * u[i]) * s;
-}
-
 __global__ void __launch_bounds__(VB) k_gather_rows(const double* __restrict__ src, const int32_t* __restrict__ rows,
                                                     int64_t n, int w, double* __restrict__ dst) {
   const int64_t total = n * w;
@@ -138,6 +131,48 @@ __global__ void __launch_bounds__(RED_THREADS) k_cg_step(double a, const double*
   }
 }
 
+// MINRES, fused: r_next = m .* Hv - a1 r_cur - a2 r_prev (r_prev = nullptr:
+// no such term), written over Hv; y = minv .* r_next (minv = nullptr: y is
+// r_next, not written); block partial sums of r_next . y into part[b].
+__global__ void __launch_bounds__(RED_THREADS) k_minres_r(double* __restrict__ Hv, const double* __restrict__ m,
+                                                          double a1, const double* __restrict__ r_cur, double a2,
+                                                          const double* __restrict__ r_prev,
+                                                          const double* __restrict__ minv, double* __restrict__ y,
+                                                          int64_t n, double* __restrict__ part) {
+  __shared__ double red[RED_THREADS / 64];
+  double sum = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)RED_BLOCKS * RED_THREADS) {
+    double t = m ? Hv[i] * m[i] : Hv[i];
+    t += a1 * r_cur[i];
+    if (r_prev) t += a2 * r_prev[i];
+    Hv[i] = t;
+    if (minv) {
+      const double yi = minv[i] * t;
+      y[i] = yi;
+      sum += t * yi;
+    } else {
+      sum += t * t;
+    }
+  }
+  const double ts = block_sum(sum, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = ts;
+}
+
+// MINRES, fused: w_prev <- (v - e w_prev - dl w_cur) sg (the new direction,
+// in w_prev's storage); d += phi w_prev; and, when bnext > 0, the next
+// Lanczos vector v <- y / bnext.
+__global__ void __launch_bounds__(VB) k_minres_wd(double* __restrict__ v, double e, double* __restrict__ w_prev,
+                                                  double dl, const double* __restrict__ w_cur, double sg, double phi,
+                                                  double* __restrict__ d, const double* __restrict__ y, double rb,
+                                                  int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+    const double wn = (v[i] - e * w_prev[i] - dl * w_cur[i]) * sg;
+    w_prev[i] = wn;
+    d[i] += phi * wn;
+    if (y) v[i] = rb * y[i];
+  }
+}
+
 // Stage 2: one block folds n partial sums part[0, n) (and, optionally, n
 // minima part[moff, moff + n)).
 __global__ void __launch_bounds__(RED_THREADS) k_finalize(const double* __restrict__ part, int n, int moff,
@@ -209,6 +244,20 @@ hipError_t cg_step(double a, const double* p, const double* Hp, const double* m,
   return hipGetLastError();
 }
 
+hipError_t minres_r(double* Hv, const double* m, double a1, const double* r_cur, double a2, const double* r_prev,
+                    const double* minv, double* y, int64_t n, double* scratch, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(k_minres_r, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, Hv, m, a1, r_cur, a2, r_prev, minv, y, n,
+                     scratch);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch, RED_BLOCKS, 0, 0, res);
+  return hipGetLastError();
+}
+
+hipError_t minres_wd(double* v, double e, double* w_prev, double dl, const double* w_cur, double sg, double phi,
+                     double* d, const double* y, double rb, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_minres_wd, dim3(vgrid(n)), dim3(VB), 0, s, v, e, w_prev, dl, w_cur, sg, phi, d, y, rb, n);
+  return hipGetLastError();
+}
+
 hipError_t mul(const double* a, const double* x, double* y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_mul, dim3(vgrid(n)), dim3(VB), 0, s, a, x, y, n);
   return hipGetLastError();
@@ -216,12 +265,6 @@ hipError_t mul(const double* a, const double* x, double* y, int64_t n, hipStream
 
 hipError_t jacobi_inv(const double* m, double* d, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_jacobi_inv, dim3(vgrid(n)), dim3(VB), 0, s, m, d, n);
-  return hipGetLastError();
-}
-
-hipError_t minres_w(const double* v, double a, double* w, double b, const double* u, double sc, int64_t n,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(k_minres_w, dim3(vgrid(n)), dim3(VB), 0, s, v, a, w, b, u, sc, n);
   return hipGetLastError();
 }
 

@@ -71,8 +71,13 @@ hipError_t mul(const double* a, const double* x, double* y, int64_t n, hipStream
 hipError_t cg_step(double a, const double* p, const double* Hp, const double* m, const double* minv, double* d,
                    double* r, double* z, int64_t n, double* scratch, double* res, hipStream_t s);
 hipError_t jacobi_inv(const double* m, double* d, int64_t n, hipStream_t s);              // d = m && d ? 1/|d| : 1
-hipError_t minres_w(const double* v, double a, double* w, double b, const double* u, double sc, int64_t n,
-                    hipStream_t s);                                                        // w = (v - a w - b u) sc
+// MINRES: Hv <- r_next = m .* Hv - a1 r_cur - a2 r_prev, y = minv .* r_next, res[0] = r_next . y
+// (m, r_prev, minv may be nullptr: no mask, no r_prev term, y is r_next)
+hipError_t minres_r(double* Hv, const double* m, double a1, const double* r_cur, double a2, const double* r_prev,
+                    const double* minv, double* y, int64_t n, double* scratch, double* res, hipStream_t s);
+// MINRES: w_prev <- (v - e w_prev - dl w_cur) sg; d += phi w_prev; v <- rb y (y may be nullptr: v kept)
+hipError_t minres_wd(double* v, double e, double* w_prev, double dl, const double* w_cur, double sg, double phi,
+                     double* d, const double* y, double rb, int64_t n, hipStream_t s);
 hipError_t axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);          // y += a x
 hipError_t xpay(const double* x, double a, double* y, int64_t n, hipStream_t s);          // y = x + a y
 hipError_t waxpy(const double* x, double a, const double* d, double* w, int64_t n, hipStream_t s);  // w = x + a d
