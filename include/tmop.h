@@ -283,8 +283,9 @@ int tmop_mlp_backward(tmop_mlp *mlp, const float *X, const float *dY, int64_t n,
  * Syncs when loss != NULL. */
 int tmop_mlp_train_step(tmop_mlp *mlp, const float *X, const float *L, int64_t n, float lr,
                         double *loss, void *stream);
-/* Element features of x (ctx: dim 2, order 2, isotropic target) into X
- * [n_elem][18].  Async. */
+/* Element features of x (ctx: dim 2, order 2, constant isotropic target
+ * W = h I; other contexts return TMOP_E_UNSUPPORTED, as do the two calls
+ * below) into X [n_elem][18].  Async. */
 int tmop_mlp_features(tmop_ctx *ctx, const double *x, float *X, void *stream);
 /* Training labels: ((x* - x) on the element minus its element mean) / h
  * into L [n_elem][18].  Async. */

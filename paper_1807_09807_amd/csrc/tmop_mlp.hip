@@ -530,9 +530,11 @@ int tmop_mlp_train_step(tmop_mlp* m, const float* X, const float* L, int64_t n, 
   return TMOP_OK;
 }
 
+// The network works in units of the constant isotropic target's size h
+// (W = h I): per-point targets give no single h.
 static int mlp_ctx_ok(const tmop_ctx* c) {
   if (!c) return TMOP_E_ARG;
-  if (c->dim != 2 || c->p != 2 || !c->base.iso) return TMOP_E_UNSUPPORTED;
+  if (c->dim != 2 || c->p != 2 || !c->base.iso || c->d_tsize) return TMOP_E_UNSUPPORTED;
   return TMOP_OK;
 }
 

@@ -139,3 +139,15 @@ def test_newton_mu9_w3_target():
     x = xd.cpu().numpy()
     assert np.max(np.abs(x - xo)) < 1e-6 * mesh.h
     assert F_g[-1] < F_g[0]
+
+
+def test_learned_guess_needs_a_constant_target():
+    """The MLP works in units of a constant target size h; a context with
+    per-point targets is refused (TMOP_E_UNSUPPORTED), not run with h = 1."""
+    from paper_1807_09807_amd import mlp as ML
+    from paper_1807_09807_amd import tmop as T
+    mesh, prob, x, sizes = _case(*CASES[0])
+    ctx = T.Context(2, 2, mesh.elem_node, mesh.n_node, 4, 2, None, fixed=mesh.fixed, target_sizes=sizes)
+    with pytest.raises(T.TMOPError) as ei:
+        ML.features(ctx, to_dev(x))
+    assert ei.value.status == T.TMOP_E_UNSUPPORTED
