@@ -20,7 +20,10 @@ names the passage it follows.  The oracle computes the plain definitions:
   element by element and scattered with numpy.add.at;
 * Newton's method with the positivity / 1.2-growth line search follows
   Section 3.4, with truncated CG (Steihaug) or MINRES (the inner solver of
-  Section 5) on the masked Hessian, optionally Jacobi preconditioned.
+  Section 5) on the masked Hessian, optionally Jacobi preconditioned;
+* the Section 4 objectives: a second weighted metric term (eq. 4.1), the
+  replication composite of Section 4.3.2 and the displacement penalty of
+  eq. 4.2, whose field values x(q) come from a dense basis-value table.
 
 Readings where the paper is silent: reference element [0,1]^d; nodal basis =
 Lagrange polynomials at the Gauss-Lobatto-Legendre points; Gauss-Legendre
@@ -123,6 +126,21 @@ def dense_tables(dim: int, p: int, Q: int, rule: str = "gl"):
     D[..., 2] = L[None, None, :, None, None, :] * L[None, :, None, None, :, None] * G[:, None, None, :, None, None]
     wq = (w1[:, None, None] * w1[None, :, None] * w1[None, None, :]).ravel()
     return D.reshape(Q ** 3, P1 ** 3, 3), wq
+
+
+def basis_table(dim: int, p: int, Q: int, rule: str = "gl"):
+    """Dense table Bv[q, i] = w_i(s_q): the nodal basis functions of eq. 2.1
+    at the quadrature points, with the index orders of dense_tables."""
+    s, _ = gauss_legendre(Q) if rule == "gl" else gauss_lobatto(Q)
+    L, _ = lagrange(gll_nodes(p), s)
+    P1 = p + 1
+    if dim == 2:
+        # axes: q1, q0, i1, i0
+        return (L[None, :, None, :] * L[:, None, :, None]).reshape(Q * Q, P1 * P1)
+    # axes: q2, q1, q0, i2, i1, i0
+    Bv = (L[None, None, :, None, None, :] * L[None, :, None, None, :, None]
+          * L[:, None, None, :, None, None])
+    return Bv.reshape(Q ** 3, P1 ** 3)
 
 
 # ---------------------------------------------------------------------------
@@ -324,6 +342,13 @@ class Problem:
     W: None (identity), a (d, d) matrix, per-element (n_elem, d, d) or
        per-quadrature-point (n_elem, Q^d, d, d) targets; det W > 0
        (Section 3.1).
+
+    Section 4 adds to F_V (each optional, see set_combo, set_replication and
+    set_restriction):
+      a weight eta_1 on the term above and a second term
+      sum_E sum_q w_q omega_q mu_2(A W_2^{-1})  (eq. 4.1 with two metrics,
+      or the replication composite of Section 4.3.2), and
+      sum_E sum_q w_q det W delta |x(q) - x_init(q)|^2  (eq. 4.2).
     """
 
     def __init__(self, dim, order, n_q1d, elem_node, metric, W=None, rule="gl", chunk=4096):
@@ -341,6 +366,88 @@ class Problem:
         self.Winv = np.linalg.inv(W)
         self.detW = detW
         self.chunk = chunk
+        self.Bv = basis_table(dim, order, n_q1d, rule)
+        self.eta1 = 1.0
+        self.second = None       # dict(metric, Winv (n_elem, nq, d, d), omega (n_elem, nq))
+        self.delta = 0.0
+        self.x_init = None
+
+    # ------------------------------------------------------------ Section 4
+    def _primary_detW(self):
+        """det W of the primary target at every point, shape (n_elem, nq)."""
+        _, dW = self._targets(0, self.n_elem)
+        return np.broadcast_to(dW, (self.n_elem, self.nq)).astype(np.float64)
+
+    def set_combo(self, metric2, W2, eta1=1.0, eta2=None):
+        """Composite metric of eq. 4.1 with two terms: eta_1 mu(T) with the
+        primary target plus eta_2 mu_2(A W_2^{-1}), each integrated over its
+        own target element (as in the combined objective of Section 5.2.4),
+        so the second term's weight is omega_q = eta_2(q) det W_2.  W2: a
+        (d, d) matrix or (n_elem, nq, d, d); eta2: None (1), a scalar or
+        (n_elem, nq) per-point weights."""
+        ok = METRICS_2D if self.dim == 2 else METRICS_3D
+        if metric2 not in ok:
+            raise ValueError("metric/dimension mismatch")
+        W2 = np.asarray(W2, dtype=np.float64)
+        W2 = np.broadcast_to(W2, (self.n_elem, self.nq, self.dim, self.dim))
+        d2 = np.linalg.det(W2)
+        if np.any(d2 <= 0):
+            raise ValueError("target matrices need det W > 0 (Section 3.1)")
+        eta2 = 1.0 if eta2 is None else np.asarray(eta2, dtype=np.float64)
+        self.eta1 = float(eta1)
+        self.second = dict(metric=metric2, Winv=np.linalg.inv(W2),
+                           omega=np.broadcast_to(eta2, (self.n_elem, self.nq)) * d2)
+
+    def set_replication(self, gamma, x_init):
+        """Second restricted node movement algorithm (Section 4.3.2): the
+        metric (1 - gamma) mu_98(T_0) + gamma mu(T) with T_0 = A W_0^{-1} and
+        W_0 = A(x_init) at every point.  The composite metric is integrated
+        over the primary target element (weight det W for both parts)."""
+        if not (0.0 <= gamma <= 1.0):
+            raise ValueError("gamma must lie in [0, 1]")
+        if self.dim != 2:
+            raise ValueError("mu_98 is a 2D metric here")
+        A0 = self._jac(np.asarray(x_init, dtype=np.float64), 0, self.n_elem)
+        if np.any(_det(A0) <= 0):
+            raise ValueError("the initial mesh is inverted: W_0 = A_init needs det > 0")
+        self.eta1 = float(gamma)
+        self.second = dict(metric=98, Winv=np.linalg.inv(A0), omega=(1.0 - gamma) * self._primary_detW())
+
+    def set_restriction(self, delta, x_init=None):
+        """First restricted node movement algorithm (Section 4.3.1, eq. 4.2):
+        adds delta |x - x_init|^2 integrated over the target elements, i.e.
+        sum_E sum_q w_q det W delta |x(q) - x_init(q)|^2 with x(q) the
+        finite element field of eq. 2.1 at the point.  delta = 0 removes it."""
+        if not (delta >= 0.0 and math.isfinite(delta)):
+            raise ValueError("delta must be finite and >= 0")
+        self.delta = float(delta)
+        self.x_init = None if delta == 0.0 else np.array(x_init, dtype=np.float64)
+
+    def _terms(self, e0, e1):
+        """(metric, W^{-1}, per-point weight) of every metric term on a chunk,
+        W^{-1} broadcastable to (ne, nq, d, d), weight to (ne, nq)."""
+        Wi, dW = self._targets(e0, e1)
+        out = [(self.metric, Wi, self.eta1 * self.wq[None, :] * dW)]
+        if self.second is not None:
+            s = self.second
+            out.append((s["metric"], s["Winv"][e0:e1], self.wq[None, :] * s["omega"][e0:e1]))
+        return out
+
+    def _penalty_weight(self, e0, e1):
+        """2 delta w_q det W per point (the weight of the eq. 4.2 term's
+        derivatives), shape broadcastable to (ne, nq)."""
+        _, dW = self._targets(e0, e1)
+        return 2.0 * self.delta * self.wq[None, :] * dW
+
+    def _field_at_points(self, f, e0, e1):
+        """f(q)[e, q, c] = sum_i f_{node(e,i), c} w_i(s_q) (eq. 2.1)."""
+        return np.einsum("cei,qi->eqc", f[:, self.elem_node[e0:e1]], self.Bv, optimize=True)
+
+    def _assemble_values(self, m, e0, e1, out):
+        """out[c, node(e,i)] += sum_q m[e,q,c] w_i(s_q)."""
+        G = np.einsum("eqc,qi->cei", m, self.Bv, optimize=True)
+        for c in range(self.dim):
+            np.add.at(out[c], self.elem_node[e0:e1], G[c])
 
     # per-chunk target data broadcast to (ne, nq, d, d) / (ne, nq)
     def _targets(self, e0, e1):
@@ -367,13 +474,18 @@ class Problem:
             yield e0, min(e0 + self.chunk, self.n_elem)
 
     def pointwise(self, x):
-        """Per point contributions w_q det W mu(T) and det A, shape (n_elem, nq)."""
+        """Per point contributions w_q det W mu(T) (plus the Section 4 terms
+        that are set) and det A, shape (n_elem, nq)."""
         contrib, detA = [], []
         for e0, e1 in self._chunks():
             A = self._jac(x, e0, e1)
-            Wi, dW = self._targets(e0, e1)
-            T = _mm(A, Wi)
-            contrib.append(self.wq[None, :] * dW * mu(self.metric, T))
+            c = 0.0
+            for metric, Wi, wt in self._terms(e0, e1):
+                c = c + wt * mu(metric, _mm(A, Wi))
+            if self.delta > 0.0:
+                u = self._field_at_points(x - self.x_init, e0, e1)
+                c = c + 0.5 * self._penalty_weight(e0, e1) * np.sum(u * u, axis=-1)
+            contrib.append(c)
             detA.append(_det(A))
         return np.concatenate(contrib), np.concatenate(detA)
 
@@ -444,10 +556,12 @@ class Problem:
         g = np.zeros(x.shape, dtype=np.result_type(x, np.float64))
         for e0, e1 in self._chunks():
             A = self._jac(x, e0, e1)
-            Wi, dW = self._targets(e0, e1)
-            P = dmu(self.metric, _mm(A, Wi))
-            Y = (self.wq[None, :] * dW)[..., None, None] * _mm(P, _tr(Wi))
-            self._assemble(Y, e0, e1, g)
+            for metric, Wi, wt in self._terms(e0, e1):
+                P = dmu(metric, _mm(A, Wi))
+                self._assemble(wt[..., None, None] * _mm(P, _tr(Wi)), e0, e1, g)
+            if self.delta > 0.0:
+                u = self._field_at_points(x - self.x_init, e0, e1)
+                self._assemble_values(self._penalty_weight(e0, e1)[..., None] * u, e0, e1, g)
         return g
 
     def _elements_touching(self, nodes):
@@ -472,6 +586,8 @@ class Problem:
         sub.n_elem = elems.size
         if self.Winv.ndim > 2:
             sub.Winv, sub.detW = self.Winv[elems], self.detW[elems]
+        if self.second is not None:
+            sub.second = dict(self.second, Winv=self.second["Winv"][elems], omega=self.second["omega"][elems])
         out = sub.gradient(x) if v is None else sub.hessian_apply(x, v)
         return out[:, nodes]
 
@@ -482,10 +598,12 @@ class Problem:
         for e0, e1 in self._chunks():
             A = self._jac(x, e0, e1)
             dA = self._jac(v, e0, e1)
-            Wi, dW = self._targets(e0, e1)
-            dP = d2mu(self.metric, _mm(A, Wi), _mm(dA, Wi))
-            Y = (self.wq[None, :] * dW)[..., None, None] * _mm(dP, _tr(Wi))
-            self._assemble(Y, e0, e1, Hv)
+            for metric, Wi, wt in self._terms(e0, e1):
+                dP = d2mu(metric, _mm(A, Wi), _mm(dA, Wi))
+                self._assemble(wt[..., None, None] * _mm(dP, _tr(Wi)), e0, e1, Hv)
+            if self.delta > 0.0:
+                vq = self._field_at_points(v, e0, e1)
+                self._assemble_values(self._penalty_weight(e0, e1)[..., None] * vq, e0, e1, Hv)
         return Hv
 
     def hessian_diagonal(self, x):
@@ -498,17 +616,21 @@ class Problem:
         d = self.dim
         for e0, e1 in self._chunks():
             A = self._jac(x, e0, e1)
-            Wi, dW = self._targets(e0, e1)
-            T = _mm(A, Wi)
             ne = e1 - e0
             share = np.zeros((d, ne, self.D.shape[1]), dtype=Dg.dtype)
-            for i in range(self.D.shape[1]):
-                for c in range(d):
-                    dA = np.zeros((ne, self.nq, d, d), dtype=Dg.dtype)
-                    dA[:, :, c, :] = self.D[None, :, i, :]
-                    dT = _mm(dA, Wi)
-                    q = _ddot(dT, d2mu(self.metric, T, dT))
-                    share[c, :, i] = np.sum(self.wq[None, :] * dW * q, axis=1)
+            for metric, Wi, wt in self._terms(e0, e1):
+                T = _mm(A, Wi)
+                for i in range(self.D.shape[1]):
+                    for c in range(d):
+                        dA = np.zeros((ne, self.nq, d, d), dtype=Dg.dtype)
+                        dA[:, :, c, :] = self.D[None, :, i, :]
+                        dT = _mm(dA, Wi)
+                        q = _ddot(dT, d2mu(metric, T, dT))
+                        share[c, :, i] += np.sum(wt * q, axis=1)
+            if self.delta > 0.0:
+                # the unit vector's field at the points is w_i(s_q) in component c
+                pw = np.broadcast_to(self._penalty_weight(e0, e1), (ne, self.nq))
+                share += (pw @ (self.Bv * self.Bv))[None]
             for c in range(d):
                 np.add.at(Dg[c], self.elem_node[e0:e1], share[c])
         return Dg
