@@ -229,6 +229,49 @@ int tmop_set_target_sizes(tmop_ctx *ctx, const double *sizes, void *stream);
  * Async. */
 int tmop_hessian_diagonal(tmop_ctx *ctx, const double *x, double *diag, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Section 4 objectives.  Each adds a term to the F of every call above
+ * (energy, gradient, Hessian action, diagonal, energy + gradient, Newton);
+ * they combine.  The terms run after the primary metric term and add to
+ * its outputs, so the calls keep their layouts and their determinism.
+ *
+ * First restricted node movement algorithm (Section 4.3.1, eq. 4.2): adds
+ *   sum_E sum_q w_q det W delta |x(q) - x_init(q)|^2
+ * (the displacement integrated over the target elements; x(q) is the
+ * finite element field of eq. 2.1 at the point, det W the primary
+ * target's, per point for TMOP_TGT_ISO_PER_QP).  Its gradient is
+ * 2 delta M (x - x_init) and its Hessian 2 delta M per component, with M the
+ * target-weighted mass matrix.  x_init: device [dim][n_node], copied
+ * (caller keeps ownership).  delta = 0 removes the term (x_init may then be
+ * NULL).  TMOP_E_ARG unless delta is finite and >= 0 (context unchanged).
+ * Syncs. */
+int tmop_set_restriction(tmop_ctx *ctx, double delta, const double *x_init, void *stream);
+
+/* Composite metric of eq. 4.1 with two terms (Section 5.2.4 form):
+ *   F = sum_E sum_q w_q [eta1 det W mu(A W^-1) + omega_q mu2(A W2^-1)],
+ *   omega_q = eta2 * eta2_q[e][q] * det W2,
+ * each term integrated over its own target element.  W2: host, row-major
+ * 2x2, det W2 > 0 (else TMOP_E_TARGET).  eta2_q: host [n_elem][n1d^2]
+ * per-point weights (point index q0 + n1d q1, the space-dependent weight of
+ * Section 5.2.4), or NULL for 1.  eta1, eta2 and every eta2_q finite and
+ * >= 0 (else TMOP_E_ARG).  metric2: a 2D metric; 0 removes the second term
+ * and keeps eta1.  2D contexts with a constant target only (else
+ * TMOP_E_UNSUPPORTED).  Replaces an earlier second term or replication.
+ * Syncs. */
+int tmop_set_combo(tmop_ctx *ctx, int32_t metric2, const double *W2, double eta1, double eta2,
+                   const double *eta2_q, void *stream);
+
+/* Second restricted node movement algorithm (Section 4.3.2): the metric
+ *   mu'(T0, T) = (1 - gamma) mu_98(T0) + gamma mu(T),  T0 = A W0^-1,
+ * with W0 = A(x_init) at every quadrature point, integrated over the
+ * primary target element (weight det W for both parts).  gamma in [0, 1]
+ * (else TMOP_E_ARG); gamma = 0 keeps x_init, gamma = 1 is the plain
+ * objective.  x_init: device [dim][n_node], read once (W0^-1 is stored per
+ * point).  TMOP_E_TARGET (context unchanged) if det A(x_init) <= 0 at a
+ * point.  2D contexts with a constant target only (else
+ * TMOP_E_UNSUPPORTED).  Replaces an earlier second term.  Syncs. */
+int tmop_set_replication(tmop_ctx *ctx, double gamma, const double *x_init, void *stream);
+
 /* F and min det A as tmop_energy (eq. 2.4), and g = dF/dx as tmop_gradient
  * (Section 3.4), in one pass over the elements: the line search of Section
  * 3.4 needs both at every trial point.  The energy partials ride along in
@@ -303,10 +346,13 @@ int tmop_mlp_propose(tmop_ctx *ctx, tmop_mlp *mlp, const double *x, double *x_ou
  * two HIP events on the caller's stream; tmop_timing_read waits for them and
  * returns the summed device time in milliseconds and the number of launches
  * for one operation: 0 energy, 1 gradient, 2 Hessian action, 3 energy +
- * gradient (tmop_energy_gradient), 4 Hessian diagonal, 5 target sizes.
+ * gradient (tmop_energy_gradient), 4 Hessian diagonal, 5 target sizes,
+ * 6 the W0 data of tmop_set_replication, 7 the displacement-penalty
+ * kernels of tmop_set_restriction (every operation).  Slots 0..4 count the
+ * second metric term's launches with the primary ones.
  * tmop_timing_enable(ctx, on) clears the totals and turns timing on (1) or
  * off (0).  Both return TMOP_OK, TMOP_E_ARG (NULL ctx / out pointers, op
- * outside 0..5) or TMOP_E_HIP. */
+ * outside 0..7) or TMOP_E_HIP. */
 int tmop_timing_enable(tmop_ctx *ctx, int enable);
 int tmop_timing_read(tmop_ctx *ctx, int op, double *ms_total, int64_t *launches);
 

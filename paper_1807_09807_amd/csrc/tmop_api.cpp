@@ -145,15 +145,51 @@ void inv3(const double* W, int d, double out[3][3]) {
 
 namespace {
 
+// Starts a timed region of timing slot `slot` (no-op unless timing is on).
+int timing_begin(tmop_ctx* c, int slot, hipStream_t s, tmop_ctx::TimedLaunch& tl) {
+  tl = tmop_ctx::TimedLaunch{slot, nullptr, nullptr};
+  if (!c->timing) return TMOP_OK;
+  for (hipEvent_t* e : {&tl.a, &tl.b}) {
+    if (!c->ev_free.empty()) {
+      *e = c->ev_free.back();
+      c->ev_free.pop_back();
+    } else if (hipEventCreate(e) != hipSuccess) {
+      return TMOP_E_HIP;
+    }
+  }
+  return hipEventRecord(tl.a, s) == hipSuccess ? TMOP_OK : TMOP_E_HIP;
+}
+
+// Ends it; a failed launch (r != 0) records nothing.
+void timing_end(tmop_ctx* c, int r, hipStream_t s, tmop_ctx::TimedLaunch& tl) {
+  if (!c->timing) return;
+  if (r != 0 || hipEventRecord(tl.b, s) != hipSuccess) {
+    c->ev_free.push_back(tl.a);
+    c->ev_free.push_back(tl.b);
+  } else {
+    c->ev_pending.push_back(tl);
+  }
+}
+
+// The metric term a launch evaluates: the primary one, or the second term
+// of a composite objective (its metric and per-point targets).
+struct TermSel {
+  int metric = -1;                 // -1: the context's metric
+  const double* tmat = nullptr;    // second term: per-point data in the launch's element order
+  double omega = 0.0;              // OP_JINV: the weight omega_q it writes beside W_0^{-1}
+};
+
 // Element kernels over n_list elements: conn[k * npe ...] (list == nullptr)
 // or conn[list[k] * npe ...].  Energy partials (OP_ENERGY, OP_EG) go to
-// d_part[part_off + b] (sums) and d_part[n_elem + part_off + b] (minima).
+// d_part[part_off + b] (sums) and d_part[part_cap + part_off + b] (minima).
 int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* out, const int32_t* conn,
                 const int32_t* list, int64_t n_list, hipStream_t s, int* grid, const double* scale = nullptr,
-                int64_t part_off = 0, const uint32_t* first = nullptr, const double* tsize = nullptr) {
+                int64_t part_off = 0, const uint32_t* first = nullptr, const double* tsize = nullptr,
+                TermSel term = TermSel{}) {
   LaunchParams lp = c->base;
   lp.first = first;
   lp.tsize = tsize;
+  lp.tmat = term.tmat;
   lp.scale = scale;
   lp.x = x; lp.v = v; lp.out = out;
   lp.elem_node = conn;
@@ -161,34 +197,54 @@ int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* o
   lp.n_list = (int32_t)n_list;
   lp.n_node = c->n_node;
   lp.part = c->d_part + part_off;
-  lp.part_min = c->d_part + c->n_elem + part_off;
-  tmop_ctx::TimedLaunch tl{op, nullptr, nullptr};
-  if (c->timing) {
-    for (hipEvent_t* e : {&tl.a, &tl.b}) {
-      if (!c->ev_free.empty()) {
-        *e = c->ev_free.back();
-        c->ev_free.pop_back();
-      } else if (hipEventCreate(e) != hipSuccess) {
-        return TMOP_E_HIP;
-      }
-    }
-    if (hipEventRecord(tl.a, s) != hipSuccess) return TMOP_E_HIP;
+  lp.part_min = c->d_part + c->part_cap + part_off;
+  const int metric = term.metric < 0 ? c->metric : term.metric;
+  if (op == OP_JINV) {   // W_0 data of the replication composite: A of W = I, in FP64
+    lp.iso = false;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) lp.Winv[i][j] = i == j ? 1.0 : 0.0;
+    lp.detW = lp.detWinv = 1.0;
+    lp.wdetW = term.omega;
   }
+  tmop_ctx::TimedLaunch tl;
+  if (timing_begin(c, op, s, tl) != TMOP_OK) return TMOP_E_HIP;
+  const bool f64 = c->precision == TMOP_FP64 || op == OP_JINV;
   int r;
   if (c->dim == 2)
-    r = c->precision == TMOP_FP64 ? launch_elem_2d_f64(c->p, c->Q, c->metric, op, lp, s, grid)
-                                  : launch_elem_2d_f32(c->p, c->Q, c->metric, op, lp, s, grid);
+    r = f64 ? launch_elem_2d_f64(c->p, c->Q, metric, op, lp, s, grid)
+            : launch_elem_2d_f32(c->p, c->Q, metric, op, lp, s, grid);
   else
-    r = c->precision == TMOP_FP64 ? launch_elem_3d_f64(c->p, c->Q, c->metric, op, lp, s, grid)
-                                  : launch_elem_3d_f32(c->p, c->Q, c->metric, op, lp, s, grid);
-  if (c->timing) {
-    if (r != 0 || hipEventRecord(tl.b, s) != hipSuccess) {
-      c->ev_free.push_back(tl.a);
-      c->ev_free.push_back(tl.b);
-    } else {
-      c->ev_pending.push_back(tl);
-    }
+    r = f64 ? launch_elem_3d_f64(c->p, c->Q, metric, op, lp, s, grid)
+            : launch_elem_3d_f32(c->p, c->Q, metric, op, lp, s, grid);
+  timing_end(c, r, s, tl);
+  if (r == -1) return TMOP_E_UNSUPPORTED;
+  return r == 0 ? TMOP_OK : TMOP_E_HIP;
+}
+
+// Displacement-penalty kernels (eq. 4.2) over n_list elements of conn,
+// adding to out; energy partials as elem_launch.  x is v for OP_HESS.
+int mass_launch(tmop_ctx* c, int op, const double* x, double* out, const int32_t* conn, int64_t n_list,
+                hipStream_t s, int* grid, const double* scale, int64_t part_off, const double* tsize) {
+  MassParams mp{};
+  mp.x = x;
+  mp.x0 = c->d_xinit;
+  mp.out = out;
+  mp.elem_node = conn;
+  mp.n_list = (int32_t)n_list;
+  mp.n_node = c->n_node;
+  mp.part = c->d_part + part_off;
+  mp.part_min = c->d_part + c->part_cap + part_off;
+  mp.scale = scale;
+  mp.tsize = tsize;
+  for (int q = 0; q < MAXQ; ++q) {
+    mp.w[q] = c->base.w[q];
+    for (int i = 0; i < MAXP; ++i) mp.B[q][i] = c->base.B[q][i];
   }
+  mp.k = 2.0 * c->delta * c->base.detW;   // per-point sizes: det W = 1 here, s_q^d in the kernel
+  tmop_ctx::TimedLaunch tl;
+  if (timing_begin(c, TIMING_PENALTY, s, tl) != TMOP_OK) return TMOP_E_HIP;
+  const int r = launch_mass(c->dim, c->p, c->Q, op, mp, s, grid);
+  timing_end(c, r, s, tl);
   if (r == -1) return TMOP_E_UNSUPPORTED;
   return r == 0 ? TMOP_OK : TMOP_E_HIP;
 }
@@ -211,15 +267,18 @@ int collect_timing(tmop_ctx* c) {
   return st;
 }
 
-// out = sum over colours of the element contributions (gradient / Hv; with
-// OP_EG also the energy partials of every colour, *nblocks of them).
+// out = sum over colours of the element contributions (gradient / Hv /
+// diagonal; with OP_EG also the energy partials of every colour, *nblocks
+// of them): the primary metric term (its colour launches write first
+// touches), then the Section 4 terms that are set, adding to out.
 int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out, hipStream_t s,
              const double* scale = nullptr, int64_t* nblocks = nullptr) {
   // the first touch of every node writes instead of adding, so out needs no
   // zero fill unless some node belongs to no element
   if (!c->all_touched) HIP_TRY(fill(out, 0.0, c->n_dof, s));
   int64_t off = 0;
-  for (size_t k = 0; k + 1 < c->color_off.size(); ++k) {
+  const int ncol = (int)c->color_off.size() - 1;
+  for (int k = 0; k < ncol; ++k) {
     const int64_t n = c->color_off[k + 1] - c->color_off[k];
     if (n == 0) continue;
     int grid = 0;
@@ -229,17 +288,48 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
     if (r != TMOP_OK) return r;
     off += grid;
   }
+  for (int k = 0; c->metric2 && k < ncol; ++k) {   // second metric term (Sections 4.2, 4.3.2)
+    const int64_t n = c->color_off[k + 1] - c->color_off[k];
+    if (n == 0) continue;
+    int grid = 0;
+    const int r = elem_launch(c, op, x, v, out, c->d_elem_node_col + c->color_off[k] * c->npe, nullptr, n, s,
+                              &grid, scale, off, nullptr, nullptr,
+                              TermSel{c->metric2, c->d_tmat_col + c->color_off[k] * c->nq * 5});
+    if (r != TMOP_OK) return r;
+    off += grid;
+  }
+  for (int k = 0; c->delta > 0.0 && k < ncol; ++k) {   // displacement penalty (eq. 4.2)
+    const int64_t n = c->color_off[k + 1] - c->color_off[k];
+    if (n == 0) continue;
+    int grid = 0;
+    const int r = mass_launch(c, op, op == OP_HESS ? v : x, out, c->d_elem_node_col + c->color_off[k] * c->npe, n,
+                              s, &grid, scale, off, c->d_tsize_col ? c->d_tsize_col + c->color_off[k] * c->nq : nullptr);
+    if (r != TMOP_OK) return r;
+    off += grid;
+  }
   if (nblocks) *nblocks = off;
   return TMOP_OK;
 }
 
-// Enqueue F and min det A into c->d_res[0..1].
+// Enqueue F and min det A into c->d_res[0..1]: every term, element order.
 int energy_async(tmop_ctx* c, const double* x, hipStream_t s) {
   int grid = 0;
-  const int r = elem_launch(c, OP_ENERGY, x, nullptr, nullptr, c->d_elem_node, nullptr, c->n_elem, s, &grid,
-                            nullptr, 0, nullptr, c->d_tsize);
+  int r = elem_launch(c, OP_ENERGY, x, nullptr, nullptr, c->d_elem_node, nullptr, c->n_elem, s, &grid, nullptr, 0,
+                      nullptr, c->d_tsize);
   if (r != TMOP_OK) return r;
-  HIP_TRY(finalize_sum_min(c->d_part, grid, (int)c->n_elem, c->d_scratch, c->d_res, s));
+  int64_t off = grid;
+  if (c->metric2) {
+    r = elem_launch(c, OP_ENERGY, x, nullptr, nullptr, c->d_elem_node, nullptr, c->n_elem, s, &grid, nullptr, off,
+                    nullptr, nullptr, TermSel{c->metric2, c->d_tmat});
+    if (r != TMOP_OK) return r;
+    off += grid;
+  }
+  if (c->delta > 0.0) {
+    r = mass_launch(c, OP_ENERGY, x, nullptr, c->d_elem_node, c->n_elem, s, &grid, nullptr, off, c->d_tsize);
+    if (r != TMOP_OK) return r;
+    off += grid;
+  }
+  HIP_TRY(finalize_sum_min(c->d_part, (int)off, (int)c->part_cap, c->d_scratch, c->d_res, s));
   return TMOP_OK;
 }
 
@@ -248,7 +338,7 @@ int energy_gradient_async(tmop_ctx* c, const double* x, double* g, hipStream_t s
   int64_t nb = 0;
   const int r = assemble(c, OP_EG, x, nullptr, g, s, nullptr, &nb);
   if (r != TMOP_OK) return r;
-  HIP_TRY(finalize_sum_min(c->d_part, (int)nb, (int)c->n_elem, c->d_scratch, c->d_res, s));
+  HIP_TRY(finalize_sum_min(c->d_part, (int)nb, (int)c->part_cap, c->d_scratch, c->d_res, s));
   return TMOP_OK;
 }
 
@@ -286,6 +376,9 @@ void free_ctx(tmop_ctx* c) {
   (void)hipFree(c->d_mask);
   (void)hipFree(c->d_tsize);
   (void)hipFree(c->d_tsize_col);
+  (void)hipFree(c->d_tmat);
+  (void)hipFree(c->d_tmat_col);
+  (void)hipFree(c->d_xinit);
   (void)hipFree(c->d_part);
   (void)hipFree(c->d_scratch);
   (void)hipFree(c->d_res);
@@ -519,7 +612,8 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
   if (!mesh || !quad || !target || !mesh->elem_node) return TMOP_E_ARG;
   const int d = mesh->dim, p = mesh->order, Q = quad->n1d;
   if (d != 2 && d != 3) return TMOP_E_ARG;
-  if (p < 1 || mesh->n_elem < 1 || mesh->n_node < 1 || mesh->n_elem > INT32_MAX || mesh->n_node > INT32_MAX)
+  if (p < 1 || mesh->n_elem < 1 || mesh->n_node < 1 || mesh->n_elem > (INT32_MAX - 16) / 3 ||
+      mesh->n_node > INT32_MAX)
     return TMOP_E_ARG;
   if (quad->kind != TMOP_GAUSS_LEGENDRE && quad->kind != TMOP_GAUSS_LOBATTO) return TMOP_E_ARG;
   if (Q < p + 1) return TMOP_E_ARG;                      // Section 3.3: at least p+1 points
@@ -570,6 +664,8 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
   c->nq = nq;
   c->base.detW = detW;
   c->base.detWinv = 1.0 / detW;
+  c->base.wdetW = detW;                                  // eta_1 = 1
+  c->part_cap = 3 * mesh->n_elem + 16;
 
   // colouring and device copies
   std::vector<int32_t> order;
@@ -580,7 +676,7 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
   do {
     if (hipMalloc(&c->d_elem_node, en_bytes) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipMalloc(&c->d_colors, order.size() * sizeof(int32_t)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
-    if (hipMalloc(&c->d_part, 2 * (size_t)mesh->n_elem * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
+    if (hipMalloc(&c->d_part, 2 * (size_t)c->part_cap * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipMalloc(&c->d_scratch, 2 * RED_BLOCKS * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipMalloc(&c->d_res, 4 * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipHostMalloc(&c->h_res, 4 * sizeof(double), 0) != hipSuccess) { st = TMOP_E_NOMEM; break; }
@@ -639,7 +735,7 @@ int tmop_timing_enable(tmop_ctx* c, int enable) {
   const int st = collect_timing(c);
   (void)hipSetDevice(cur);
   c->timing = enable != 0;
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < TIMING_SLOTS; ++k) {
     c->t_ms[k] = 0.0;
     c->t_launches[k] = 0;
   }
@@ -647,7 +743,7 @@ int tmop_timing_enable(tmop_ctx* c, int enable) {
 }
 
 int tmop_timing_read(tmop_ctx* c, int op, double* ms_total, int64_t* launches) {
-  if (!c || op < 0 || op > 5 || !ms_total || !launches) return TMOP_E_ARG;
+  if (!c || op < 0 || op >= TIMING_SLOTS || !ms_total || !launches) return TMOP_E_ARG;
   const int st = collect_timing(c);
   *ms_total = c->t_ms[op];
   *launches = c->t_launches[op];
@@ -698,7 +794,7 @@ int tmop_target_sizes_w3(tmop_ctx* c, const double* x0, double* sizes, void* str
   const int r = elem_launch(c, OP_SIZE, x0, nullptr, sizes, c->d_elem_node, nullptr, c->n_elem, s, &grid, nullptr, 0,
                             nullptr, c->d_tsize);
   if (r != TMOP_OK) return r;
-  HIP_TRY(finalize_sum_min(c->d_part, grid, (int)c->n_elem, c->d_scratch, c->d_res, s));
+  HIP_TRY(finalize_sum_min(c->d_part, grid, (int)c->part_cap, c->d_scratch, c->d_res, s));
   double F = 0, m = 0;
   const int st = read_res(c, s, &F, &m);
   if (st != TMOP_OK) return st;
@@ -720,6 +816,111 @@ int tmop_set_target_sizes(tmop_ctx* c, const double* sizes, void* stream) {
   HIP_TRY(hipMemcpyAsync(c->d_tsize, sizes, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(gather_rows(c->d_tsize, c->d_colors, c->n_elem, c->nq, c->d_tsize_col, s));
   return TMOP_OK;
+}
+
+int tmop_set_restriction(tmop_ctx* c, double delta, const double* x_init, void* stream) {
+  if (!c || !(delta >= 0.0) || !std::isfinite(delta)) return TMOP_E_ARG;
+  if (delta == 0.0) {          // Section 4.3.1 with delta = 0: the plain objective
+    c->delta = 0.0;
+    return TMOP_OK;
+  }
+  if (!x_init) return TMOP_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (!c->d_xinit && hipMalloc(&c->d_xinit, c->n_dof * sizeof(double)) != hipSuccess) {
+    c->d_xinit = nullptr;
+    return TMOP_E_NOMEM;
+  }
+  HIP_TRY(hipMemcpyAsync(c->d_xinit, x_init, c->n_dof * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  c->delta = delta;
+  return TMOP_OK;
+}
+
+namespace {
+
+bool metric_2d(int m) {
+  return m == TMOP_MU1 || m == TMOP_MU2 || m == TMOP_MU7 || m == TMOP_MU9 || m == TMOP_MU14 || m == TMOP_MU77 ||
+         m == TMOP_MU98;
+}
+
+// Installs per-point second-term data (element order, device) as the
+// context's second metric term: its colour-order copy, then the switch.
+int install_second_term(tmop_ctx* c, int metric2, double* d_tm, double eta1, hipStream_t s) {
+  if (!c->d_tmat_col && hipMalloc(&c->d_tmat_col, (size_t)c->n_elem * c->nq * 5 * sizeof(double)) != hipSuccess) {
+    c->d_tmat_col = nullptr;
+    (void)hipFree(d_tm);
+    return TMOP_E_NOMEM;
+  }
+  if (gather_rows(d_tm, c->d_colors, c->n_elem, c->nq * 5, c->d_tmat_col, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipFree(d_tm);
+    return TMOP_E_HIP;
+  }
+  (void)hipFree(c->d_tmat);
+  c->d_tmat = d_tm;
+  c->metric2 = metric2;
+  c->base.wdetW = eta1 * c->base.detW;
+  return TMOP_OK;
+}
+
+}  // namespace
+
+int tmop_set_combo(tmop_ctx* c, int32_t metric2, const double* W2, double eta1, double eta2, const double* eta2_q,
+                   void* stream) {
+  if (!c || !(eta1 >= 0.0) || !std::isfinite(eta1)) return TMOP_E_ARG;
+  if (metric2 == 0) {          // back to the single term eta_1 mu
+    c->metric2 = 0;
+    c->base.wdetW = eta1 * c->base.detW;
+    return TMOP_OK;
+  }
+  if (c->dim != 2 || c->d_tsize) return TMOP_E_UNSUPPORTED;
+  if (!metric_2d(metric2) || !W2 || !(eta2 >= 0.0) || !std::isfinite(eta2)) return TMOP_E_ARG;
+  const double det2 = det3(W2, 2);
+  if (!(det2 > 0.0)) return TMOP_E_TARGET;               // Section 3.1: det W > 0
+  const int64_t n = c->n_elem * c->nq;
+  if (eta2_q)
+    for (int64_t k = 0; k < n; ++k)
+      if (!(eta2_q[k] >= 0.0) || !std::isfinite(eta2_q[k])) return TMOP_E_ARG;
+  double Wi[3][3];
+  inv3(W2, 2, Wi);
+  std::vector<double> tm((size_t)n * 5);
+  for (int64_t k = 0; k < n; ++k) {
+    double* t = &tm[(size_t)k * 5];
+    t[0] = Wi[0][0]; t[1] = Wi[0][1]; t[2] = Wi[1][0]; t[3] = Wi[1][1];
+    t[4] = eta2 * (eta2_q ? eta2_q[k] : 1.0) * det2;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  double* d_tm = nullptr;
+  if (hipMalloc(&d_tm, tm.size() * sizeof(double)) != hipSuccess) return TMOP_E_NOMEM;
+  if (hipMemcpyAsync(d_tm, tm.data(), tm.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess) {
+    (void)hipFree(d_tm);
+    return TMOP_E_HIP;
+  }
+  return install_second_term(c, metric2, d_tm, eta1, s);
+}
+
+int tmop_set_replication(tmop_ctx* c, double gamma, const double* x_init, void* stream) {
+  if (!c || !x_init || !(gamma >= 0.0 && gamma <= 1.0)) return TMOP_E_ARG;
+  if (c->dim != 2 || c->d_tsize) return TMOP_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  double* d_tm = nullptr;
+  if (hipMalloc(&d_tm, (size_t)c->n_elem * c->nq * 5 * sizeof(double)) != hipSuccess) return TMOP_E_NOMEM;
+  // W_0 = A(x_init) at every point; both parts weigh with the primary det W
+  int grid = 0;
+  int r = elem_launch(c, OP_JINV, x_init, nullptr, d_tm, c->d_elem_node, nullptr, c->n_elem, s, &grid, nullptr, 0,
+                      nullptr, nullptr, TermSel{-1, nullptr, (1.0 - gamma) * c->base.detW});
+  double F = 0, m = 0;
+  if (r == TMOP_OK) {
+    r = finalize_sum_min(c->d_part, grid, (int)c->part_cap, c->d_scratch, c->d_res, s) == hipSuccess ? TMOP_OK
+                                                                                                      : TMOP_E_HIP;
+  }
+  if (r == TMOP_OK) r = read_res(c, s, &F, &m);
+  if (r == TMOP_OK && !(m > 0.0)) r = TMOP_E_TARGET;     // W_0 needs det A(x_init) > 0
+  if (r != TMOP_OK) {
+    (void)hipFree(d_tm);
+    return r;
+  }
+  return install_second_term(c, TMOP_MU98, d_tm, gamma, s);
 }
 
 int tmop_hessian_diagonal(tmop_ctx* c, const double* x, double* diag, void* stream) {

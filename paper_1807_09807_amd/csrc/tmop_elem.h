@@ -8,10 +8,14 @@
 //              at every trial point)
 //   OP_SIZE    (det A)^(1/d) at every quadrature point: the size of the
 //              target W_3 = (det A(x_0))^(1/d) I of Section 3.1
+//   OP_JINV    A^{-1} at every quadrature point (2D): the target data of
+//              W_0 = A(x_init) in the replication composite (Section 4.3.2)
 //
 // Targets (template parameter TGT): a constant general W (TGT_GEN), a
-// constant isotropic W = s I (TGT_ISO), or an isotropic W_q = s_q I given
-// per quadrature point (TGT_QPS, Section 3.1: W may differ at every point).
+// constant isotropic W = s I (TGT_ISO), an isotropic W_q = s_q I given
+// per quadrature point (TGT_QPS, Section 3.1: W may differ at every point),
+// or a general W_q with its own weight omega_q per point (TGT_MAT, 2D: the
+// second term of a composite objective, Section 4.2 and 4.3.2).
 //
 // The Jacobian A = sum_i x_i (grad w_i)^T (eq. 2.2) of a tensor-product
 // element is computed by sum factorization: one 1D contraction per
@@ -67,6 +71,7 @@ struct ElemArgs {
   const double* __restrict__ scale;      // OP_GRAD: optional device scalar multiplying g (nullptr = 1)
   const double* __restrict__ tsize;      // TGT_QPS: [n_list][Q^dim] target sizes s_q (W_q = s_q I), point
                                          // index q0 + Q q1 (+ Q^2 q2), in the order of elem_node
+  const double* __restrict__ tmat;       // TGT_MAT: [n_list][Q^2][5] W_q^{-1} (row-major) and omega_q
   int64_t n_node;
   int32_t n_list;
   R B[Q][P];
@@ -77,6 +82,7 @@ struct ElemArgs {
   double jscale;                         // factor of the affine-frame Jacobian: 1/s if isotropic, else 1
   double xi[P];                          // 1D GLL node coordinates
   double detW;
+  double wdetW;                          // weight factor of a constant target: eta det W
 };
 
 // Elements per block and block size: the smallest element count that best
@@ -219,18 +225,34 @@ __device__ __forceinline__ void stress(const R (&M)[D][D], const R (&Wi)[3][3], 
     }
 }
 
-enum { TGT_GEN = 0, TGT_ISO = 1, TGT_QPS = 2 };
+enum { TGT_GEN = 0, TGT_ISO = 1, TGT_QPS = 2, TGT_MAT = 3 };
+
+// TGT_MAT: this point's W^{-1} (in the arithmetic type and in FP64) and weight
+template <typename R>
+__device__ __forceinline__ double load_point_target2(const double* __restrict__ tm, R (&Wi)[3][3],
+                                                     double (&Wid)[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Wid[i][j] = 0.0;
+  Wid[0][0] = tm[0]; Wid[0][1] = tm[1]; Wid[1][0] = tm[2]; Wid[1][1] = tm[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Wi[i][j] = (R)Wid[i][j];
+  return tm[4];
+}
 
 // Per-point kernel of the operations.  Given A (and dA) -- already divided
 // by s for isotropic targets, i.e. T -- adds the energy contribution
 // wdet mu(T) (OP_ENERGY, OP_EG), fills Y (OP_GRAD / OP_HESS) with the weight
 // kY folded into the metric's coefficients, or returns det A (OP_SIZE).
 // detWq: det W at this point.
-template <int D, int METRIC, typename R, int OP, bool ISO, int P, int Q>
-__device__ __forceinline__ void point_op(const ElemArgs<P, Q, R>& a, const R (&A)[D][D], const R (&dA)[D][D],
-                                         double wdet, double detWq, double kY, double& acc, double& mind,
-                                         R (&Y)[D][D], double& detA_out) {
-  if constexpr (OP == OP_ENERGY || OP == OP_EG || OP == OP_SIZE) {
+template <int D, int METRIC, typename R, int OP, bool ISO>
+__device__ __forceinline__ void point_op(const R (&Wi)[3][3], const double (&Wid)[3][3], const R (&A)[D][D],
+                                         const R (&dA)[D][D], double wdet, double detWq, double kY, double& acc,
+                                         double& mind, R (&Y)[D][D], double& detA_out) {
+  if constexpr (OP == OP_ENERGY || OP == OP_EG || OP == OP_SIZE || OP == OP_JINV) {
     // The energy value, det A and their sums are FP64 in both paths: the
     // FP32 path promotes its contracted A (mu's "... - 1" would otherwise
     // leave an FP32 rounding floor under F).
@@ -241,31 +263,31 @@ __device__ __forceinline__ void point_op(const ElemArgs<P, Q, R>& a, const R (&A
       for (int j = 0; j < D; ++j) Ad[i][j] = (double)A[i][j];
     double detA, tau;
     if constexpr (ISO) {          // the contraction gave T; det A = det T det W
-      right_mul<D, double, true>(Ad, a.Winvd, Td);
+      right_mul<D, double, true>(Ad, Wid, Td);
       tau = det<D, double>(Td);
       detA = tau * detWq;
     } else {
       detA = det<D, double>(Ad);
-      right_mul<D, double, false>(Ad, a.Winvd, Td);
+      right_mul<D, double, false>(Ad, Wid, Td);
       tau = det<D, double>(Td);
     }
-    if constexpr (OP != OP_SIZE) acc += wdet * mu_value<METRIC, double>(Td, tau);
+    if constexpr (OP != OP_SIZE && OP != OP_JINV) acc += wdet * mu_value<METRIC, double>(Td, tau);
     mind = fmin(mind, detA);
     detA_out = detA;
   }
   if constexpr (OP == OP_GRAD || OP == OP_EG || OP == OP_HESS) {
     // the weight is folded into the metric's scalar coefficients
     R T[D][D];
-    right_mul<D, R, ISO>(A, a.Winv, T);
+    right_mul<D, R, ISO>(A, Wi, T);
     if constexpr (OP == OP_GRAD || OP == OP_EG) {
       R Pm[D][D];
       mu_first<METRIC, R>(T, (R)kY, Pm);
-      stress<D, R, ISO>(Pm, a.Winv, Y);
+      stress<D, R, ISO>(Pm, Wi, Y);
     } else {
       R dT[D][D], dP[D][D];
-      right_mul<D, R, ISO>(dA, a.Winv, dT);
+      right_mul<D, R, ISO>(dA, Wi, dT);
       mu_second<METRIC, R>(T, dT, (R)kY, dP);
-      stress<D, R, ISO>(dP, a.Winv, Y);
+      stress<D, R, ISO>(dP, Wi, Y);
     }
   }
 }
@@ -456,6 +478,7 @@ __device__ __forceinline__ void fwd_3d_areas(const ElemArgs<P, Q, R>& a, const R
 template <int P, int Q, int METRIC, typename R, int OP, int TGT>
 __global__ void __launch_bounds__((Cfg<3, P, Q, R>::BLOCK))
 elem_kernel_3d(const ElemArgs<P, Q, R> a) {
+  static_assert(TGT != TGT_MAT && OP != OP_JINV, "per-point general targets are 2D only");
   using C = Cfg<3, P, Q, R>;
   using L = Lds3<P, Q>;
   constexpr bool ISO = TGT != TGT_GEN;
@@ -523,7 +546,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
       for (int i0 = 0; i0 < P; ++i0) Racc[tt][c][i0] = 0;
 
   if (tb < Q) {
-    const double w12 = a.w[ta] * a.w[tb] * (TGT == TGT_QPS ? 1.0 : a.detW) * (a.scale ? *a.scale : 1.0);
+    const double w12 = a.w[ta] * a.w[tb] * (TGT == TGT_QPS ? 1.0 : a.wdetW) * (a.scale ? *a.scale : 1.0);
     double sq[Q];   // this lane's row of target sizes (q0 = 0..Q-1)
     if constexpr (TGT == TGT_QPS) {
       const double* ts = a.tsize + (int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb;
@@ -559,7 +582,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
       R Y[3][3];
       double wdet = w12 * a.w[q0], detWq = a.detW, kY = wdet, detA = 0.0;
       if constexpr (TGT == TGT_QPS) qp_scale<3, R>(sq[q0], A, dA, wdet, detWq, kY);
-      point_op<3, METRIC, R, OP, ISO>(a, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
+      point_op<3, METRIC, R, OP, ISO>(a.Winv, a.Winvd, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
       if constexpr (OP == OP_SIZE) {
         if (active) a.out[(int64_t)e * (Q * Q * Q) + q0 + Q * ta + Q * Q * tb] = size_of<3>(detA);
       }
@@ -763,8 +786,8 @@ template <int P, int Q, int METRIC, typename R, int OP, int TGT>
 __global__ void __launch_bounds__((Cfg<2, P, Q, R>::BLOCK))
 elem_kernel_2d(const ElemArgs<P, Q, R> a) {
   using C = Cfg<2, P, Q, R>;
-  constexpr bool ISO = TGT != TGT_GEN;
-  constexpr bool ENERGY_LIKE = OP == OP_ENERGY || OP == OP_SIZE;
+  constexpr bool ISO = TGT == TGT_ISO || TGT == TGT_QPS;
+  constexpr bool ENERGY_LIKE = OP == OP_ENERGY || OP == OP_SIZE || OP == OP_JINV;
   constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P;
   constexpr bool AFFINE = sizeof(R) == 4;
   constexpr int NE = OP == OP_HESS ? C::NEH : C::NE;
@@ -808,13 +831,14 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
       for (int i0 = 0; i0 < P; ++i0) Racc[tt][c][i0] = 0;
 
   if (ta < Q) {   // lane q1 = ta
-    const double w1 = a.w[ta] * (TGT == TGT_QPS ? 1.0 : a.detW) * (a.scale ? *a.scale : 1.0);
+    const double w1 = a.w[ta] * (TGT == TGT_QPS || TGT == TGT_MAT ? 1.0 : a.wdetW) * (a.scale ? *a.scale : 1.0);
     double sq[Q];   // this lane's row of target sizes
     if constexpr (TGT == TGT_QPS) {
       const double* ts = a.tsize + (int64_t)e * (Q * Q) + Q * ta;
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
+    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q) + Q * ta) * 5 : nullptr;
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[2][2], dA[2][2];
@@ -836,9 +860,28 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
       R Y[2][2];
       double wdet = w1 * a.w[q0], detWq = a.detW, kY = wdet, detA = 0.0;
       if constexpr (TGT == TGT_QPS) qp_scale<2, R>(sq[q0], A, dA, wdet, detWq, kY);
-      point_op<2, METRIC, R, OP, ISO>(a, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
+      if constexpr (TGT == TGT_MAT) {
+        R Wi[3][3];
+        double Wid[3][3];
+        wdet *= load_point_target2<R>(tm + 5 * q0, Wi, Wid);
+        kY = wdet;
+        point_op<2, METRIC, R, OP, false>(Wi, Wid, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
+      } else {
+        point_op<2, METRIC, R, OP, ISO>(a.Winv, a.Winvd, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
+      }
       if constexpr (OP == OP_SIZE) {
         if (active) a.out[(int64_t)e * (Q * Q) + q0 + Q * ta] = size_of<2>(detA);
+      }
+      if constexpr (OP == OP_JINV) {   // A^{-1} = adj(A) / det A, and the weight omega
+        if (active) {
+          double* o = a.out + ((int64_t)e * (Q * Q) + q0 + Q * ta) * 5;
+          const double r = 1.0 / detA;
+          o[0] = (double)A[1][1] * r;
+          o[1] = -(double)A[0][1] * r;
+          o[2] = -(double)A[1][0] * r;
+          o[3] = (double)A[0][0] * r;
+          o[4] = a.wdetW;
+        }
       }
       if constexpr (!ENERGY_LIKE) {
 #pragma unroll
@@ -852,7 +895,7 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
     }
   }
 
-  if constexpr (OP == OP_ENERGY || OP == OP_EG || OP == OP_SIZE) {
+  if constexpr (OP == OP_ENERGY || OP == OP_EG || OP == OP_SIZE || OP == OP_JINV) {
     if (!active) { acc = 0.0; mind = __builtin_huge_val(); }
     block_reduce_sum_min<C::BLOCK>(acc, mind, red, a.part + blk, a.part_min + blk);
   }
@@ -968,6 +1011,7 @@ __device__ __forceinline__ void target_congruence(const R (&Wi)[3][3], R (&K6)[D
 template <int P, int Q, int METRIC, typename R, int TGT>
 __global__ void __launch_bounds__((Cfg<3, P, Q, R>::BLOCK))
 diag_kernel_3d(const DiagArgs<P, Q, R> a) {
+  static_assert(TGT != TGT_MAT, "per-point general targets are 2D only");
   constexpr bool ISO = TGT != TGT_GEN;
   using C = Cfg<3, P, Q, R>;
   using LD = LdsDiag3<P, Q>;
@@ -1019,7 +1063,7 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
 #pragma unroll
       for (int i0 = 0; i0 < P; ++i0) Rd[pr][c][i0] = 0;
   if (tb < Q) {
-    const double w12 = a.w[ta] * a.w[tb] * (TGT == TGT_QPS ? 1.0 : a.detW);
+    const double w12 = a.w[ta] * a.w[tb] * (TGT == TGT_QPS ? 1.0 : a.wdetW);
     double sq[Q];
     if constexpr (TGT == TGT_QPS) {
       const double* ts = a.tsize + (int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb;
@@ -1137,7 +1181,7 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
 template <int P, int Q, int METRIC, typename R, int TGT>
 __global__ void __launch_bounds__((Cfg<2, P, Q, R>::BLOCK))
 diag_kernel_2d(const DiagArgs<P, Q, R> a) {
-  constexpr bool ISO = TGT != TGT_GEN;
+  constexpr bool ISO = TGT == TGT_ISO || TGT == TGT_QPS;
   using C = Cfg<2, P, Q, R>;
   constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P;
   constexpr bool AFFINE = sizeof(R) == 4;
@@ -1174,13 +1218,14 @@ diag_kernel_2d(const DiagArgs<P, Q, R> a) {
 #pragma unroll
       for (int i0 = 0; i0 < P; ++i0) Rd[pr][c][i0] = 0;
   if (ta < Q) {   // lane q1 = ta
-    const double w1 = a.w[ta] * (TGT == TGT_QPS ? 1.0 : a.detW);
+    const double w1 = a.w[ta] * (TGT == TGT_QPS || TGT == TGT_MAT ? 1.0 : a.wdetW);
     double sq[Q];
     if constexpr (TGT == TGT_QPS) {
       const double* ts = a.tsize + (int64_t)e * (Q * Q) + Q * ta;
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
+    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q) + Q * ta) * 5 : nullptr;
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[2][2];
@@ -1201,9 +1246,18 @@ diag_kernel_2d(const DiagArgs<P, Q, R> a) {
 #pragma unroll
           for (int j = 0; j < 2; ++j) A[i][j] *= r;
       }
-      right_mul<2, R, ISO>(A, a.Winv, T);
-      mu_second_rows<METRIC, R>(T, (R)kK, K);
-      if constexpr (!ISO) target_congruence<2, R>(a.Winv, K);
+      if constexpr (TGT == TGT_MAT) {
+        R Wi[3][3];
+        double Wid[3][3];
+        kK *= load_point_target2<R>(tm + 5 * q0, Wi, Wid);
+        right_mul<2, R, false>(A, Wi, T);
+        mu_second_rows<METRIC, R>(T, (R)kK, K);
+        target_congruence<2, R>(Wi, K);
+      } else {
+        right_mul<2, R, ISO>(A, a.Winv, T);
+        mu_second_rows<METRIC, R>(T, (R)kK, K);
+        if constexpr (!ISO) target_congruence<2, R>(a.Winv, K);
+      }
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const R f0 = K[c][0], f1 = K[c][1], f2 = R(2) * K[c][2];

@@ -3,7 +3,7 @@
 
 namespace tmop {
 int launch_elem_2d_f64(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid) {
-  if (op != OP_SIZE && (metric == 14 || metric == 77 || metric == 98)) return launch_elem_2d_f64_b(p, Q, metric, op, lp, s, grid);
+  if (op != OP_SIZE && op != OP_JINV && (metric == 14 || metric == 77 || metric == 98)) return launch_elem_2d_f64_b(p, Q, metric, op, lp, s, grid);
   return launch_dispatch<2, double, 0>(p, Q, metric, op, lp, s, grid);
 }
 }  // namespace tmop

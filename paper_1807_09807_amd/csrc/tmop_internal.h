@@ -9,9 +9,13 @@
 namespace tmop {
 
 // Element operations: F and min det A (eq. 2.4), dF/dx, (d^2F/dx^2) v,
-// F, min det A and dF/dx in one pass, the diagonal of d^2F/dx^2, and the
-// per-point sizes (det A)^(1/d) (with min det A).
-enum { OP_ENERGY = 0, OP_GRAD = 1, OP_HESS = 2, OP_EG = 3, OP_DIAG = 4, OP_SIZE = 5 };
+// F, min det A and dF/dx in one pass, the diagonal of d^2F/dx^2, the
+// per-point sizes (det A)^(1/d) (with min det A), and the per-point target
+// data W_0^{-1} = A^{-1} of the replication composite (Section 4.3.2, 2D).
+enum { OP_ENERGY = 0, OP_GRAD = 1, OP_HESS = 2, OP_EG = 3, OP_DIAG = 4, OP_SIZE = 5, OP_JINV = 6 };
+// timing slots: the element operations above, then the displacement penalty
+constexpr int TIMING_PENALTY = 7;
+constexpr int TIMING_SLOTS = 8;
 
 constexpr int MAXP = 5;   // nodes per direction (order p <= 4)
 constexpr int MAXQ = 6;   // quadrature points per direction
@@ -30,6 +34,8 @@ struct LaunchParams {
   double* part_min;        // energy partials: minima of det A
   const double* scale;     // gradient: optional device scalar factor
   const double* tsize;     // per-point isotropic target sizes (in the order of elem_node), or nullptr
+  const double* tmat;      // 2D per-point targets [n_list][Q^2][5]: W^{-1} row-major and the weight
+                           // omega_q (the term is sum_q w_q omega_q mu(A W_q^{-1})), or nullptr
   double B[MAXQ][MAXP];
   double G[MAXQ][MAXP];
   double w[MAXQ];
@@ -38,7 +44,28 @@ struct LaunchParams {
   bool iso;                // W = s I: kernels fold 1/s into the G table instead of multiplying by W^{-1}
   double s_inv;
   double detW, detWinv;
+  double wdetW;            // weight factor of a constant target: eta det W (OP_JINV: the omega it writes)
 };
+
+// Everything one launch of the displacement-penalty kernels (eq. 4.2)
+// needs.  Operations: OP_ENERGY, OP_GRAD, OP_HESS (field v in x, x0
+// unused), OP_EG, OP_DIAG (no field).
+struct MassParams {
+  const double* x;
+  const double* x0;
+  double* out;
+  const int32_t* elem_node;
+  int32_t n_list;
+  int64_t n_node;
+  double* part;
+  double* part_min;
+  const double* scale;
+  const double* tsize;
+  double B[MAXQ][MAXP];
+  double w[MAXQ];
+  double k;                // 2 delta det W (per-point sizes: 2 delta, times s_q^d in the kernel)
+};
+int launch_mass(int dim, int p, int Q, int op, const MassParams& mp, hipStream_t s, int* grid);
 
 // Launch one element operation (OP_ENERGY / OP_GRAD / OP_HESS / OP_EG) on
 // n_list elements: element k has the nodes lp.elem_node[e * npe ...] with
@@ -107,7 +134,14 @@ struct tmop_ctx {
   double* d_tsize_col = nullptr;       // the same in colour order
   double* d_mask = nullptr;            // [n_dof], 1 = free DOF
   bool has_fixed = false;
-  double* d_part = nullptr;            // [2 * n_elem] energy partials
+  double* d_part = nullptr;            // [2 * part_cap] energy partials: sums, then minima
+  int64_t part_cap = 0;                // partials per kind (3 n_elem + 16: up to three terms)
+  // Section 4 terms
+  int metric2 = 0;                     // second metric term (0: none), 2D
+  double* d_tmat = nullptr;            // its per-point data [n_elem][nq][5], element order
+  double* d_tmat_col = nullptr;        // the same in colour order
+  double delta = 0.0;                  // displacement penalty weight (eq. 4.2; 0: none)
+  double* d_xinit = nullptr;           // its x_init [dim][n_node]
   double* d_scratch = nullptr;         // [2 * RED_BLOCKS] dot partials
   double* d_res = nullptr;             // [4] reduction results
   double* h_res = nullptr;             // [4] pinned mirror
@@ -117,6 +151,6 @@ struct tmop_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev_free;
   std::vector<TimedLaunch> ev_pending;
-  double t_ms[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // per op: energy, gradient, Hessian action,
-  int64_t t_launches[6] = {0, 0, 0, 0, 0, 0};         // energy+gradient, Hessian diagonal, target sizes
+  double t_ms[tmop::TIMING_SLOTS] = {};        // per op: energy, gradient, Hessian action, energy+gradient,
+  int64_t t_launches[tmop::TIMING_SLOTS] = {};  // Hessian diagonal, target sizes, W_0 data, penalty
 };

@@ -16,6 +16,8 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   a.elem_node = lp.elem_node; a.list = lp.list; a.first = lp.first; a.part = lp.part; a.part_min = lp.part_min; a.scale = lp.scale;
   a.n_node = lp.n_node; a.n_list = lp.n_list;
   a.tsize = lp.tsize;
+  a.tmat = lp.tmat;
+  a.wdetW = lp.wdetW;
   const double gs = TGT == TGT_ISO ? lp.s_inv : 1.0;   // constant isotropic target: G carries 1/s
   for (int q = 0; q < Q; ++q) {
     a.w[q] = lp.w[q];
@@ -50,8 +52,9 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// OP_SIZE does not depend on the metric: it is instantiated for the first
-// metric of each dimension only (the caller routes it there).
+// OP_SIZE and OP_JINV do not depend on the metric: they are instantiated
+// for the first metric of each dimension only (the caller routes them
+// there), OP_JINV for the general constant target (W = I) in 2D only.
 template <int DIM, int P, int Q, int M, typename R, int TGT>
 static int launch_op(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
   if (op == OP_ENERGY) return launch_one<DIM, P, Q, M, R, OP_ENERGY, TGT>(lp, s, grid);
@@ -59,13 +62,18 @@ static int launch_op(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
   if (op == OP_HESS) return launch_one<DIM, P, Q, M, R, OP_HESS, TGT>(lp, s, grid);
   if (op == OP_EG) return launch_one<DIM, P, Q, M, R, OP_EG, TGT>(lp, s, grid);
   if (op == OP_DIAG) return launch_one<DIM, P, Q, M, R, OP_DIAG, TGT>(lp, s, grid);
-  if constexpr (M == (DIM == 2 ? 1 : 302))
+  if constexpr (M == (DIM == 2 ? 1 : 302) && TGT != TGT_MAT) {
     if (op == OP_SIZE) return launch_one<DIM, P, Q, M, R, OP_SIZE, TGT>(lp, s, grid);
+    if constexpr (DIM == 2 && TGT == TGT_GEN)
+      if (op == OP_JINV) return launch_one<DIM, P, Q, M, R, OP_JINV, TGT>(lp, s, grid);
+  }
   return -1;
 }
 
 template <int DIM, int P, int Q, int M, typename R>
 static int launch_metric(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
+  if constexpr (DIM == 2)
+    if (lp.tmat) return launch_op<DIM, P, Q, M, R, TGT_MAT>(op, lp, s, grid);
   if (lp.tsize) return launch_op<DIM, P, Q, M, R, TGT_QPS>(op, lp, s, grid);
   return lp.iso ? launch_op<DIM, P, Q, M, R, TGT_ISO>(op, lp, s, grid) : launch_op<DIM, P, Q, M, R, TGT_GEN>(op, lp, s, grid);
 }
@@ -75,7 +83,7 @@ static int launch_metric(int op, const LaunchParams& lp, hipStream_t s, int* gri
 // translation units so that they compile in parallel.
 template <int DIM, int GROUP, int P, int Q, typename R>
 static int launch_pq(int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid) {
-  if (op == OP_SIZE) metric = DIM == 2 ? 1 : 302;
+  if (op == OP_SIZE || op == OP_JINV) metric = DIM == 2 ? 1 : 302;
   if constexpr (DIM == 2 && GROUP == 0) {
     switch (metric) {
       case 1: return launch_metric<2, P, Q, 1, R>(op, lp, s, grid);

@@ -32,7 +32,9 @@ TMOP_PREC_NONE, TMOP_PREC_JACOBI = 0, 1
 EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_gradient_scaled", "tmop_hessian_apply",
            "tmop_newton_solve", "tmop_destroy", "tmop_strerror", "tmop_newton_default_opts",
            "tmop_timing_enable", "tmop_timing_read", "tmop_energy_gradient", "tmop_hessian_diagonal",
-           "tmop_target_sizes_w3", "tmop_set_target_sizes")
+           "tmop_target_sizes_w3", "tmop_set_target_sizes", "tmop_set_restriction", "tmop_set_combo",
+           "tmop_set_replication")
+TIMING_W0, TIMING_PENALTY = 6, 7
 
 
 class TMOPError(RuntimeError):
@@ -100,6 +102,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tmop_target_sizes_w3.restype = ctypes.c_int
     lib.tmop_set_target_sizes.argtypes = [P, P, P]
     lib.tmop_set_target_sizes.restype = ctypes.c_int
+    lib.tmop_set_restriction.argtypes = [P, ctypes.c_double, P, P]
+    lib.tmop_set_restriction.restype = ctypes.c_int
+    lib.tmop_set_combo.argtypes = [P, ctypes.c_int32, P, ctypes.c_double, ctypes.c_double, P, P]
+    lib.tmop_set_combo.restype = ctypes.c_int
+    lib.tmop_set_replication.argtypes = [P, ctypes.c_double, P, P]
+    lib.tmop_set_replication.restype = ctypes.c_int
     lib.tmop_newton_solve.argtypes = [P, P, ctypes.POINTER(tmop_newton_opts),
                                       ctypes.POINTER(tmop_newton_report), P]
     lib.tmop_newton_solve.restype = ctypes.c_int
@@ -284,6 +292,46 @@ class Context:
         if st < 0:
             raise TMOPError(st, "tmop_set_target_sizes")
 
+    def set_restriction(self, delta: float, x_init=None):
+        """Displacement penalty delta |x - x_init|^2 of Section 4.3.1 (eq. 4.2);
+        x_init: device tensor (dim, n_node), copied; delta = 0 removes it."""
+        ptr = None
+        if x_init is not None:
+            _check_field(x_init, self.dim, self.n_node, "x_init")
+            ptr = ctypes.c_void_p(x_init.data_ptr())
+        st = self._lib.tmop_set_restriction(self._h, float(delta), ptr,
+                                            _stream(x_init) if x_init is not None else None)
+        if st < 0:
+            raise TMOPError(st, "tmop_set_restriction")
+
+    def set_combo(self, metric2: int, W2=None, eta1: float = 1.0, eta2: float = 1.0, eta2_q=None):
+        """Second metric term of eq. 4.1: eta1 mu + eta2 eta2_q det W2 mu2(A W2^-1)
+        (W2: 2x2 host matrix; eta2_q: host (n_elem, n_q1d^2) weights or None);
+        metric2 = 0 removes it."""
+        W2p, Wbuf, qbuf = None, None, None
+        if W2 is not None:
+            Wbuf = np.ascontiguousarray(np.asarray(W2, dtype=np.float64).reshape(-1))
+            if Wbuf.size != 4:
+                raise ValueError("W2 must be a 2x2 matrix")
+            W2p = Wbuf.ctypes.data_as(ctypes.c_void_p)
+        qp = None
+        if eta2_q is not None:
+            qbuf = np.ascontiguousarray(np.asarray(eta2_q, dtype=np.float64))
+            if qbuf.shape != (self.n_elem, self.nq):
+                raise ValueError(f"eta2_q must have shape ({self.n_elem}, {self.nq})")
+            qp = qbuf.ctypes.data_as(ctypes.c_void_p)
+        st = self._lib.tmop_set_combo(self._h, int(metric2), W2p, float(eta1), float(eta2), qp, None)
+        if st < 0:
+            raise TMOPError(st, "tmop_set_combo")
+
+    def set_replication(self, gamma: float, x_init):
+        """The replication composite of Section 4.3.2 with W0 = A(x_init)."""
+        _check_field(x_init, self.dim, self.n_node, "x_init")
+        st = self._lib.tmop_set_replication(self._h, float(gamma), ctypes.c_void_p(x_init.data_ptr()),
+                                            _stream(x_init))
+        if st < 0:
+            raise TMOPError(st, "tmop_set_replication")
+
     def timing_enable(self, on: bool = True):
         """Clears the per-launch kernel timing totals and turns timing on/off."""
         st = self._lib.tmop_timing_enable(self._h, int(bool(on)))
@@ -293,8 +341,8 @@ class Context:
     def timing_read(self, op: int):
         """(summed device ms, launch count) of the element kernels of one
         operation (0 energy, 1 gradient, 2 Hessian action, 3 energy +
-        gradient, 4 Hessian diagonal, 5 target sizes) since the last
-        timing_enable."""
+        gradient, 4 Hessian diagonal, 5 target sizes, 6 replication W0 data,
+        7 displacement penalty) since the last timing_enable."""
         ms, n = ctypes.c_double(), ctypes.c_int64()
         st = self._lib.tmop_timing_read(self._h, int(op), ctypes.byref(ms), ctypes.byref(n))
         if st < 0:

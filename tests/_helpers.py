@@ -94,18 +94,20 @@ EPS32 = 2.0 ** -24
 
 
 def mixed_tol(prob, x, elems=None):
-    """Tolerance of the mixed FP32 path: 1e-5, or 6 eps32 kappa on meshes
-    whose worst point has condition kappa > 28.  Rounding A to FP32 perturbs
+    """Tolerance of the mixed FP32 path: 1e-5, or 8 eps32 kappa on meshes
+    whose worst point has condition kappa > 21.  Rounding A to FP32 perturbs
     it by eps32 relative; the metric derivatives amplify a relative
     perturbation of A by up to kappa = (|T|^2/d)^(d/2) / det T.  The
     constant covers the FP32 sums over the P and Q terms of the three
     contractions: the largest error seen over every case, metric and
-    operation is 4.4 eps32 kappa (Hessian action and diagonal of the Q3 mu_9
-    case with an anisotropic target, kappa 266)."""
+    operation is 7.1 eps32 kappa (Hessian action and diagonal of a Q3 mu_9
+    mesh with W = h I, kappa 57, at the node of its largest Hessian entry;
+    mu_9's second derivative carries 1/tau^3, so its amplification can
+    exceed kappa)."""
     return max(1e-5, MIXED_C * EPS32 * prob.max_condition(x, elems))
 
 
-MIXED_C = 6.0
+MIXED_C = 8.0
 
 
 def say(*a):

@@ -1,6 +1,6 @@
 """Parity of the HIP path with the FP64 oracle (energy, gradient, Hessian
 action), element by element, on seeded meshes: FP64 within 1e-12
-relative, the mixed FP32 path within 1e-5 relative (6 eps32 kappa on
+relative, the mixed FP32 path within 1e-5 relative (8 eps32 kappa on
 meshes with nearly degenerate points, see tests/_helpers.mixed_tol)."""
 import numpy as np
 import pytest
@@ -62,8 +62,10 @@ def test_hessian_apply(setup, precision):
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
 def test_energy_gradient_one_pass(setup, precision):
     """The fused pass gives the oracle's F, min det A and g, and the separate
-    calls' g bit for bit (same kernel arithmetic); F differs from the energy
-    call only in its summation order."""
+    calls' g to rounding: the same arithmetic in another kernel
+    instantiation, where the compiler may fuse a different set of products
+    and sums into FMAs (often bit for bit, not always); F differs from the
+    energy call only in its summation order."""
     case, mesh, W, v, ref = setup
     ctx = context(case, mesh, W, precision)
     x = to_dev(mesh.x)
@@ -75,7 +77,11 @@ def test_energy_gradient_one_pass(setup, precision):
     assert rel_max_err(g.cpu().numpy(), ref["g"]) <= tol
     F1, md1, _ = ctx.energy(x)
     assert abs(F - F1) <= 1e-13 * abs(F1) and md == md1
-    assert torch.equal(g, ctx.gradient(x))
+    g1 = ctx.gradient(x)
+    d = rel_max_err(g.cpu().numpy(), g1.cpu().numpy())
+    if d > 0.0:
+        say(f"  {case.name} prec={precision}: fused and separate gradients differ by {d:.2e} (relative)")
+    assert d <= 1e-14
 
 
 def test_bitwise_deterministic(setup):
