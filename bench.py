@@ -10,7 +10,9 @@ step), inputs resident in HBM.  Printed as one JSON line.  The FP64 path is the 
 value; the mixed FP32 path, per-operation times, the roofline of the
 Hessian-action kernel, Newton wall time to the F tolerance (truncated CG
 with a fixed or an inexact-Newton inner tolerance, Jacobi preconditioned or
-not, and Jacobi-preconditioned MINRES) and the CPU oracle baseline are
+not, and Jacobi-preconditioned MINRES), the Section 4 objectives
+(displacement penalty, second metric term, replication composite: their
+kernels' cost and Newton with the penalty) and the CPU oracle baseline are
 reported alongside.
 """
 from __future__ import annotations
@@ -64,8 +66,8 @@ POINT_FLOPS = {2: (15, 31, 72), 7: (21, 32, 74), 303: (40, 87, 232), 302: (85, 2
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ("tmop_elem.h", "tmop_metrics.h", "tmop_launch.h")
 MEASURED_TRAFFIC = {
-    "q2_cube_64": dict(src_sha256="fba2402802df71329ad15a1491690afe75b4f321eab4868af7c3e6348a6682ea",
-                       fetch_kib=41951.0, write_kib=27965.2),
+    "q2_cube_64": dict(src_sha256="639116ba950e00d0950094c144084a6dabd61294ef8839e5d64eda90ab50e2a1",
+                       fetch_kib=41951.5, write_kib=27967.5),
 }
 
 
@@ -115,6 +117,9 @@ def parse():
     ap.add_argument("--eval-seeds", type=int, default=4)
     ap.add_argument("--other-workloads", default="q3_square_256,q3_cube_48,q2_square_512",
                     help="further workloads whose element operations are timed and reported (comma list)")
+    ap.add_argument("--no-section4", action="store_true", help="skip the Section 4 objectives")
+    ap.add_argument("--section4-2d", default="q3_square_256",
+                    help="2D workload for the second metric term and the replication composite")
     return ap.parse_args()
 
 
@@ -178,13 +183,11 @@ def cpu_baseline(w, mesh, x, v, n_elem_sample):
                        f"one thread of {os.cpu_count()} on {cpu}")
 
 
-def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
-    """Builds the named workload and times its element operations in FP64
-    and mixed FP32: seconds per step (energy + gradient, then the Hessian
-    action), per-operation device time (HIP events on the library's stream)
-    and per-launch kernel time.  With gpu_repair, inverted elements of the
-    seeded mesh are redrawn using the library's own det A (the W_3 sizes
-    kernel), as the test suite does with the oracle's."""
+def build_mesh(T, torch, dev, name, gpu_repair=False):
+    """The named workload's seeded mesh and its target W = h I.  With
+    gpu_repair, inverted elements of the seeded mesh are redrawn using the
+    library's own det A (the W_3 sizes kernel), as the test suite does with
+    the oracle's."""
     w = meshgen.WORKLOADS[name]
     W = None
     bad = None
@@ -203,6 +206,15 @@ def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
     mesh = meshgen.make_workload(name, bad_elements=bad)
     if W is None:
         W = mesh.h * np.eye(w["dim"])
+    return w, mesh, W
+
+
+def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
+    """Builds the named workload and times its element operations in FP64
+    and mixed FP32: seconds per step (energy + gradient, then the Hessian
+    action), per-operation device time (HIP events on the library's stream)
+    and per-launch kernel time."""
+    w, mesh, W = build_mesh(T, torch, dev, name, gpu_repair)
     x = torch.from_numpy(mesh.x).to(dev)
     v = torch.from_numpy(meshgen.random_direction(mesh, w["seed"] + 100)).to(dev)
     log(f"# workload {name}: {mesh.n_elem} elements, {mesh.n_dof} DOFs, repair rounds "
@@ -310,6 +322,96 @@ def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
     return w, mesh, x, v, W, results
 
 
+def op_times(torch, ctx, x, v, reps):
+    """Median device time (s) of energy, energy + gradient, Hessian action
+    and Hessian diagonal: HIP events on the stream the library uses."""
+    stream = torch.cuda.current_stream()
+    g, Hv = torch.empty_like(x), torch.empty_like(x)
+    out = {}
+    for oname, fn in (("energy", lambda: ctx.energy(x)), ("energy_gradient", lambda: ctx.energy_gradient(x, g)),
+                      ("hessian", lambda: ctx.hessian_apply(x, v, Hv)),
+                      ("hessian_diagonal", lambda: ctx.hessian_diagonal(x, Hv))):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        out[oname] = float(np.median(ts))
+    return out
+
+
+def section4(T, torch, dev, args, w, mesh, x, v, W, log):
+    """Cost of the Section 4 objectives.  Displacement penalty (eq. 4.2) on
+    the main workload: operation times with and without it, the penalty
+    kernels' per-launch time in the Hessian action against the HBM peak
+    (they move 3 fields per unique node: v in, out read and written), and
+    Newton with the penalty.  Second metric term (eq. 4.1, mu_77 with
+    W_2 = 0.7 h I and per-point weights) and replication composite (Section
+    4.3.2, gamma = 1/2) on a 2D workload: operation times."""
+    reps = max(args.steps, 5)
+    us = lambda d: {k: round(t * 1e6, 2) for k, t in d.items()}
+    out = {}
+    ctx = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=mesh.fixed)
+    plain = op_times(torch, ctx, x, v, reps)
+    delta = 1.0e3
+    ctx.set_restriction(delta, x)
+    pen = op_times(torch, ctx, x, v, reps)
+    Hv = torch.empty_like(x)
+    ctx.timing_enable(True)
+    for _ in range(reps):
+        ctx.hessian_apply(x, v, Hv)
+    ms, n = ctx.timing_read(T.TIMING_PENALTY)
+    ctx.timing_enable(False)
+    per_op = n / reps
+    t_l = ms * 1e-3 / n
+    _, nbytes = algorithmic(w)
+    gbps = nbytes[2] * mesh.n_elem / per_op / t_l / 1e9
+    newton = {}
+    for key, d in (("plain", 0.0), ("penalty", delta)):
+        ctx.set_restriction(d, x)
+        xn = x.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, rep = ctx.newton_solve(xn, max_it=50, cg_forcing=1)
+        torch.cuda.synchronize()
+        newton[key] = dict(status=st, iters=rep["iters"], cg_iters=rep["cg_iters"],
+                           wall_s=round(time.perf_counter() - t0, 4), F0=rep["F0"], F=rep["F"],
+                           max_displacement_over_h=float((xn - x).abs().max()) / mesh.h)
+        log(f"# section 4 newton {key}: {rep['iters']} it, {rep['cg_iters']} CG, {newton[key]['wall_s']} s, "
+            f"F {rep['F0']:.4e} -> {rep['F']:.4e}, max |x - x_init| / h {newton[key]['max_displacement_over_h']:.3e}")
+    ctx.close()
+    out["penalty"] = {"workload": args.workload, "delta": delta, "ops_us_plain": us(plain), "ops_us_penalty": us(pen),
+                      "hessian_penalty_launch_us": round(t_l * 1e6, 2), "launches_per_op": per_op,
+                      "algorithmic_bytes_per_element": nbytes[2], "algorithmic_GBps": round(gbps, 1),
+                      "frac_hbm_peak": round(gbps * 1e9 / HBM_PEAK, 4), "newton_inexact_f64": newton}
+    log(f"# section 4 penalty on {args.workload}: Hv {plain['hessian']*1e6:.1f} -> {pen['hessian']*1e6:.1f} us, "
+        f"E+G {plain['energy_gradient']*1e6:.1f} -> {pen['energy_gradient']*1e6:.1f} us; penalty launch "
+        f"{t_l*1e6:.2f} us, {gbps:.0f} GB/s algorithmic")
+    # 2D: second metric term and replication composite
+    name2 = args.section4_2d
+    w2, mesh2, W2 = build_mesh(T, torch, dev, name2, gpu_repair=True)
+    x2 = torch.from_numpy(mesh2.x).to(dev)
+    v2 = torch.from_numpy(meshgen.random_direction(mesh2, w2["seed"] + 100)).to(dev)
+    c2 = T.Context(2, w2["p"], mesh2.elem_node, mesh2.n_node, w2["Q"], w2["metric"], W2, fixed=mesh2.fixed)
+    p2 = op_times(torch, c2, x2, v2, reps)
+    eta_q = np.random.default_rng(7).uniform(0.2, 1.2, (mesh2.n_elem, w2["Q"] ** 2))
+    c2.set_combo(77, 0.7 * mesh2.h * np.eye(2), 1.0, 1.0, eta_q)
+    cb = op_times(torch, c2, x2, v2, reps)
+    c2.set_replication(0.5, x2)
+    rp = op_times(torch, c2, x2, v2, reps)
+    c2.close()
+    out["second_term"] = {"workload": name2, "elements": mesh2.n_elem, "ops_us_plain": us(p2),
+                          "ops_us_combo_mu77": us(cb), "ops_us_replication": us(rp)}
+    log(f"# section 4 on {name2}: Hv plain {p2['hessian']*1e6:.1f}, + mu_77 term {cb['hessian']*1e6:.1f}, "
+        f"replication {rp['hessian']*1e6:.1f} us")
+    return out
+
+
 def workload_summary(w, mesh, results):
     """Per-operation rates of one workload against the FP64 VALU and HBM
     peaks (algorithmic flops and unique L-vector bytes per element)."""
@@ -383,6 +485,10 @@ def main():
             print(f"# newton {key}: status {st}, {rep['iters']} it, {rep['cg_iters']} CG, "
                   f"{rep['wall_s']:.2f} s, F {rep['F0']:.4e} -> {rep['F']:.4e}", file=sys.stderr, flush=True)
 
+    sec4 = None
+    if not args.no_section4:
+        sec4 = section4(T, torch, dev, args, w, mesh, x, v, W, lambda m: print(m, file=sys.stderr, flush=True))
+
     learned = None
     if not args.no_learned:
         learned = learned_guess(args, lambda m: print(m, file=sys.stderr, flush=True))
@@ -438,6 +544,7 @@ def main():
                        "rel_err_vs_f64": results["mixed"]["rel_err_vs_f64"]},
         "workloads": {args.workload: workload_summary(w, mesh, {k: r for k, r in results.items()}), **others},
         "newton": newton,
+        "section4": sec4,
         "learned_guess": learned,
         "cpu_baseline": cpu,
     }
