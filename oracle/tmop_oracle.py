@@ -473,9 +473,25 @@ class Problem:
         for e0 in range(0, self.n_elem, self.chunk):
             yield e0, min(e0 + self.chunk, self.n_elem)
 
-    def pointwise(self, x):
+    def subset(self, elems):
+        """The same objective restricted to the given elements."""
+        elems = np.asarray(elems, dtype=np.int64)
+        sub = Problem.__new__(Problem)
+        sub.__dict__.update(self.__dict__)
+        sub.elem_node = self.elem_node[elems]
+        sub.n_elem = elems.size
+        if self.Winv.ndim > 2:
+            sub.Winv, sub.detW = self.Winv[elems], self.detW[elems]
+        if self.second is not None:
+            sub.second = dict(self.second, Winv=self.second["Winv"][elems], omega=self.second["omega"][elems])
+        return sub
+
+    def pointwise(self, x, elems=None):
         """Per point contributions w_q det W mu(T) (plus the Section 4 terms
-        that are set) and det A, shape (n_elem, nq)."""
+        that are set) and det A, shape (n_elem, nq); with elems, of those
+        elements only."""
+        if elems is not None:
+            return self.subset(elems).pointwise(x)
         contrib, detA = [], []
         for e0, e1 in self._chunks():
             A = self._jac(x, e0, e1)
@@ -579,15 +595,7 @@ class Problem:
 
     def _restricted(self, x, v, nodes):
         nodes = np.asarray(nodes, dtype=np.int64)
-        elems = self._elements_touching(nodes)
-        sub = Problem.__new__(Problem)
-        sub.__dict__.update(self.__dict__)
-        sub.elem_node = self.elem_node[elems]
-        sub.n_elem = elems.size
-        if self.Winv.ndim > 2:
-            sub.Winv, sub.detW = self.Winv[elems], self.detW[elems]
-        if self.second is not None:
-            sub.second = dict(self.second, Winv=self.second["Winv"][elems], omega=self.second["omega"][elems])
+        sub = self.subset(self._elements_touching(nodes))
         out = sub.gradient(x) if v is None else sub.hessian_apply(x, v)
         return out[:, nodes]
 
