@@ -294,6 +294,52 @@ int tmop_newton_solve(tmop_ctx *ctx, double *x, const tmop_newton_opts *opts,
                       tmop_newton_report *report, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Derivative-free solver (Section 3.4, eq. 3.3, variational form): every
+ * node in turn moves to the position that minimizes its patch quality
+ *   Q(x_i) = sum over the elements E holding node i of sum_q w_q det W mu(T),
+ * by the Nelder-Mead simplex method over its free components; sweeps stop
+ * when no node moved more than t (max norm) in a sweep.  Nodes are visited
+ * by colour (greedy in node order: a node takes the smallest colour not
+ * used by a node it shares an element with); the nodes of one colour have
+ * disjoint patches and move at once, which gives the same result as
+ * visiting them one after the other.  Nelder-Mead after Lagarias, Reeds,
+ * Wright and Wright (1998): reflection 1, expansion 2, contraction 1/2,
+ * shrink 1/2; initial simplex x_i, x_i + s e_k with s = step (det W)^(1/d);
+ * a node stops when every vertex lies within xtol of the best one or after
+ * max_evals evaluations.  Q = +inf where det A <= 0 at a patch point, so a
+ * valid mesh stays valid.  FP64 in every precision mode.  Contexts with a
+ * constant target and no Section 4 term only (else TMOP_E_UNSUPPORTED). */
+typedef struct {
+  double t;                   /* sweep tolerance (Section 3.4: 1e-5 for unit volume) */
+  int32_t max_sweeps;         /* default 100 */
+  double step;                /* initial simplex edge / target size, default 0.1 */
+  double xtol;                /* Nelder-Mead simplex size at which a node stops, default 1e-6 */
+  int32_t max_evals;          /* Nelder-Mead evaluations per node and sweep, default 200 */
+} tmop_dfo_opts;
+
+typedef struct {
+  int32_t sweeps;             /* sweeps done */
+  int32_t converged;          /* 1 when the last sweep moved no node by t or more */
+  double F0, F;               /* F_V at the start and at the end */
+  double max_move;            /* largest node move of the last sweep */
+} tmop_dfo_report;
+
+void tmop_dfo_default_opts(tmop_dfo_opts *opts);
+
+/* One sweep over all nodes.  x: device [dim][n_node], updated in place
+ * (fixed components keep their value).  opts: host, NULL = defaults.
+ * *max_move: the largest max-norm move of a node.  TMOP_E_ARG for invalid
+ * options (step <= 0, xtol < 0, max_evals < 1).  The first call builds the
+ * node colouring on the host.  Syncs. */
+int tmop_dfo_sweep(tmop_ctx *ctx, double *x, const tmop_dfo_opts *opts, double *max_move, void *stream);
+
+/* Sweeps until the largest move of a sweep is below t (TMOP_OK) or
+ * max_sweeps (TMOP_W_MAXIT); TMOP_W_INVERTED (x untouched) if the input
+ * mesh is inverted.  report: host, may be NULL.  Syncs. */
+int tmop_dfo_solve(tmop_ctx *ctx, double *x, const tmop_dfo_opts *opts, tmop_dfo_report *report,
+                   void *stream);
+
+/* ------------------------------------------------------------------------
  * Learned initial guess for the Newton method of Section 3.4 (a layer on
  * top of the paper's method): a per-element MLP on 2D Q2 meshes that maps
  * an element's 9 nodes, relative to its centroid and divided by the target

@@ -379,6 +379,10 @@ void free_ctx(tmop_ctx* c) {
   (void)hipFree(c->d_tmat);
   (void)hipFree(c->d_tmat_col);
   (void)hipFree(c->d_xinit);
+  (void)hipFree(c->d_dfo_nodes);
+  (void)hipFree(c->d_ne_off);
+  (void)hipFree(c->d_ne);
+  (void)hipFree(c->d_dfo_move);
   (void)hipFree(c->d_part);
   (void)hipFree(c->d_scratch);
   (void)hipFree(c->d_res);
@@ -921,6 +925,160 @@ int tmop_set_replication(tmop_ctx* c, double gamma, const double* x_init, void* 
     return r;
   }
   return install_second_term(c, TMOP_MU98, d_tm, gamma, s);
+}
+
+namespace {
+
+// Node colouring and node -> element adjacency of the derivative-free
+// solver.  Greedy in node order: node I takes the smallest colour not used
+// by a node that shares an element with it.
+int dfo_prepare(tmop_ctx* c) {
+  if (c->dfo_ready) return TMOP_OK;
+  const int npe = c->npe;
+  const int64_t ne_tot = c->n_elem * npe;
+  std::vector<int32_t> en((size_t)ne_tot);
+  HIP_TRY(hipMemcpy(en.data(), c->d_elem_node, ne_tot * sizeof(int32_t), hipMemcpyDeviceToHost));
+  std::vector<int32_t> off(c->n_node + 1, 0), code((size_t)ne_tot);
+  for (int64_t k = 0; k < ne_tot; ++k) off[en[k] + 1]++;
+  for (int64_t I = 0; I < c->n_node; ++I) off[I + 1] += off[I];
+  {
+    std::vector<int32_t> pos(off.begin(), off.end() - 1);
+    for (int64_t e = 0; e < c->n_elem; ++e)   // ascending element ids per node
+      for (int l = 0; l < npe; ++l) code[pos[en[e * npe + l]]++] = (int32_t)(e * npe + l);
+  }
+  std::vector<int32_t> colour(c->n_node, -1), mark;
+  int ncol = 0;
+  for (int64_t I = 0; I < c->n_node; ++I) {
+    for (int32_t k = off[I]; k < off[I + 1]; ++k) {
+      const int64_t e = code[k] / npe;
+      for (int l = 0; l < npe; ++l) {
+        const int32_t cj = colour[en[e * npe + l]];
+        if (cj >= 0) mark[cj] = (int32_t)I;
+      }
+    }
+    int col = 0;
+    while (col < (int)mark.size() && mark[col] == (int32_t)I) ++col;
+    if (col == (int)mark.size()) mark.push_back(-1);
+    colour[I] = col;
+    ncol = std::max(ncol, col + 1);
+  }
+  std::vector<int32_t> order;
+  order.reserve(c->n_node);
+  c->dfo_col_off.assign(1, 0);
+  {
+    std::vector<std::vector<int32_t>> by(ncol);
+    for (int64_t I = 0; I < c->n_node; ++I) by[colour[I]].push_back((int32_t)I);
+    for (auto& v : by) {
+      order.insert(order.end(), v.begin(), v.end());
+      c->dfo_col_off.push_back((int64_t)order.size());
+    }
+  }
+  if (hipMalloc(&c->d_dfo_nodes, order.size() * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&c->d_ne_off, off.size() * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&c->d_ne, code.size() * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&c->d_dfo_move, c->n_node * sizeof(double)) != hipSuccess)
+    return TMOP_E_NOMEM;
+  HIP_TRY(hipMemcpy(c->d_dfo_nodes, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_ne_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_ne, code.data(), code.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  c->dfo_ready = true;
+  return TMOP_OK;
+}
+
+bool dfo_opts_ok(const tmop_dfo_opts& o) {
+  return o.t >= 0.0 && std::isfinite(o.t) && o.max_sweeps >= 0 && o.step > 0.0 && std::isfinite(o.step) &&
+         o.xtol >= 0.0 && std::isfinite(o.xtol) && o.max_evals >= 1;
+}
+
+int dfo_sweep(tmop_ctx* c, double* x, const tmop_dfo_opts& o, hipStream_t s, double* max_move) {
+  int st = dfo_prepare(c);
+  if (st != TMOP_OK) return st;
+  DfoParams dp{};
+  dp.x = x;
+  dp.mask = c->d_mask;
+  dp.ne_off = c->d_ne_off;
+  dp.ne = c->d_ne;
+  dp.elem_node = c->d_elem_node;
+  dp.n_node = c->n_node;
+  dp.max_evals = o.max_evals;
+  for (int q = 0; q < MAXQ; ++q) {
+    dp.w[q] = c->base.w[q];
+    for (int i = 0; i < MAXP; ++i) { dp.B[q][i] = c->base.B[q][i]; dp.G[q][i] = c->base.G[q][i]; }
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) dp.Winv[i][j] = c->base.Winv[i][j];
+  dp.detW = c->base.detW;
+  dp.step = o.step * std::pow(c->base.detW, 1.0 / c->dim);   // in units of the target size
+  dp.xtol = o.xtol;
+  for (size_t k = 0; k + 1 < c->dfo_col_off.size(); ++k) {
+    const int64_t a = c->dfo_col_off[k], n = c->dfo_col_off[k + 1] - a;
+    dp.nodes = c->d_dfo_nodes + a;
+    dp.move = c->d_dfo_move + a;
+    dp.n_list = (int32_t)n;
+    const int r = launch_dfo(c->dim, c->p, c->Q, c->metric, dp, s);
+    if (r == -1) return TMOP_E_UNSUPPORTED;
+    if (r != 0) return TMOP_E_HIP;
+  }
+  HIP_TRY(finalize_sum_min(c->d_dfo_move, (int)c->n_node, 0, c->d_scratch, c->d_res, s));
+  double sum = 0, m = 0;
+  if ((st = read_res(c, s, &sum, &m)) != TMOP_OK) return st;
+  *max_move = -m;
+  return TMOP_OK;
+}
+
+}  // namespace
+
+void tmop_dfo_default_opts(tmop_dfo_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->t = 1e-5;
+  o->max_sweeps = 100;
+  o->step = 0.1;
+  o->xtol = 1e-6;
+  o->max_evals = 200;
+}
+
+int tmop_dfo_sweep(tmop_ctx* c, double* x, const tmop_dfo_opts* opts, double* max_move, void* stream) {
+  if (!c || !x || !max_move) return TMOP_E_ARG;
+  tmop_dfo_opts o;
+  if (opts) o = *opts;
+  else tmop_dfo_default_opts(&o);
+  if (!dfo_opts_ok(o)) return TMOP_E_ARG;
+  if (c->d_tsize || c->metric2 || c->delta > 0.0) return TMOP_E_UNSUPPORTED;
+  return dfo_sweep(c, x, o, (hipStream_t)stream, max_move);
+}
+
+int tmop_dfo_solve(tmop_ctx* c, double* x, const tmop_dfo_opts* opts, tmop_dfo_report* rep, void* stream) {
+  if (!c || !x) return TMOP_E_ARG;
+  tmop_dfo_opts o;
+  if (opts) o = *opts;
+  else tmop_dfo_default_opts(&o);
+  if (!dfo_opts_ok(o)) return TMOP_E_ARG;
+  if (c->d_tsize || c->metric2 || c->delta > 0.0) return TMOP_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  tmop_dfo_report r{};
+  double F = 0, m = 0;
+  int st = energy_sync(c, x, s, &F, &m);
+  if (st != TMOP_OK) return st;
+  r.F0 = r.F = F;
+  if (!(m > 0.0)) {
+    if (rep) *rep = r;
+    return TMOP_W_INVERTED;
+  }
+  for (int k = 0; k < o.max_sweeps; ++k) {
+    double mv = 0;
+    if ((st = dfo_sweep(c, x, o, s, &mv)) != TMOP_OK) return st;
+    r.sweeps = k + 1;
+    r.max_move = mv;
+    if (mv < o.t) {
+      r.converged = 1;
+      break;
+    }
+  }
+  if ((st = energy_sync(c, x, s, &F, &m)) != TMOP_OK) return st;
+  r.F = F;
+  if (rep) *rep = r;
+  return r.converged ? TMOP_OK : TMOP_W_MAXIT;
 }
 
 int tmop_hessian_diagonal(tmop_ctx* c, const double* x, double* diag, void* stream) {

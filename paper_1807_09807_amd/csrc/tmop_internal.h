@@ -67,6 +67,27 @@ struct MassParams {
 };
 int launch_mass(int dim, int p, int Q, int op, const MassParams& mp, hipStream_t s, int* grid);
 
+// One colour of a sweep of the derivative-free solver (Section 3.4): one
+// workgroup per node of `nodes`.
+struct DfoParams {
+  double* x;
+  const double* mask;
+  const int32_t* nodes;
+  const int32_t* ne_off;
+  const int32_t* ne;
+  const int32_t* elem_node;
+  double* move;
+  int64_t n_node;
+  int32_t n_list;
+  int32_t max_evals;
+  double B[MAXQ][MAXP];
+  double G[MAXQ][MAXP];
+  double w[MAXQ];
+  double Winv[3][3];
+  double detW, step, xtol;
+};
+int launch_dfo(int dim, int p, int Q, int metric, const DfoParams& dp, hipStream_t s);
+
 // Launch one element operation (OP_ENERGY / OP_GRAD / OP_HESS / OP_EG) on
 // n_list elements: element k has the nodes lp.elem_node[e * npe ...] with
 // e = lp.list[k] (or e = k without a list).  Returns 0, -1 if no kernel
@@ -142,6 +163,13 @@ struct tmop_ctx {
   double* d_tmat_col = nullptr;        // the same in colour order
   double delta = 0.0;                  // displacement penalty weight (eq. 4.2; 0: none)
   double* d_xinit = nullptr;           // its x_init [dim][n_node]
+  // derivative-free solver (Section 3.4), built on first use
+  bool dfo_ready = false;
+  int32_t* d_dfo_nodes = nullptr;      // nodes grouped by colour
+  std::vector<int64_t> dfo_col_off;    // colour c = d_dfo_nodes[dfo_col_off[c] .. dfo_col_off[c+1])
+  int32_t* d_ne_off = nullptr;         // node -> (element, local node) CSR offsets
+  int32_t* d_ne = nullptr;             // element * npe + local node
+  double* d_dfo_move = nullptr;        // [n_node] per-node moves of a sweep (negated)
   double* d_scratch = nullptr;         // [2 * RED_BLOCKS] dot partials
   double* d_res = nullptr;             // [4] reduction results
   double* h_res = nullptr;             // [4] pinned mirror

@@ -33,7 +33,7 @@ EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_gradient_scaled",
            "tmop_newton_solve", "tmop_destroy", "tmop_strerror", "tmop_newton_default_opts",
            "tmop_timing_enable", "tmop_timing_read", "tmop_energy_gradient", "tmop_hessian_diagonal",
            "tmop_target_sizes_w3", "tmop_set_target_sizes", "tmop_set_restriction", "tmop_set_combo",
-           "tmop_set_replication")
+           "tmop_set_replication", "tmop_dfo_default_opts", "tmop_dfo_sweep", "tmop_dfo_solve")
 TIMING_W0, TIMING_PENALTY = 6, 7
 
 
@@ -73,6 +73,16 @@ class tmop_newton_report(ctypes.Structure):
                 ("gnorm0", ctypes.c_double), ("gnorm", ctypes.c_double), ("min_detA", ctypes.c_double)]
 
 
+class tmop_dfo_opts(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("max_sweeps", ctypes.c_int32), ("step", ctypes.c_double),
+                ("xtol", ctypes.c_double), ("max_evals", ctypes.c_int32)]
+
+
+class tmop_dfo_report(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("converged", ctypes.c_int32), ("F0", ctypes.c_double),
+                ("F", ctypes.c_double), ("max_move", ctypes.c_double)]
+
+
 _lib: Optional[ctypes.CDLL] = None
 
 
@@ -108,6 +118,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tmop_set_combo.restype = ctypes.c_int
     lib.tmop_set_replication.argtypes = [P, ctypes.c_double, P, P]
     lib.tmop_set_replication.restype = ctypes.c_int
+    lib.tmop_dfo_default_opts.argtypes = [ctypes.POINTER(tmop_dfo_opts)]
+    lib.tmop_dfo_default_opts.restype = None
+    lib.tmop_dfo_sweep.argtypes = [P, P, ctypes.POINTER(tmop_dfo_opts), ctypes.POINTER(dbl), P]
+    lib.tmop_dfo_sweep.restype = ctypes.c_int
+    lib.tmop_dfo_solve.argtypes = [P, P, ctypes.POINTER(tmop_dfo_opts), ctypes.POINTER(tmop_dfo_report), P]
+    lib.tmop_dfo_solve.restype = ctypes.c_int
     lib.tmop_newton_solve.argtypes = [P, P, ctypes.POINTER(tmop_newton_opts),
                                       ctypes.POINTER(tmop_newton_report), P]
     lib.tmop_newton_solve.restype = ctypes.c_int
@@ -331,6 +347,38 @@ class Context:
                                             _stream(x_init))
         if st < 0:
             raise TMOPError(st, "tmop_set_replication")
+
+    def _dfo_opts(self, opts):
+        o = tmop_dfo_opts()
+        self._lib.tmop_dfo_default_opts(ctypes.byref(o))
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise ValueError(f"unknown derivative-free option {k}")
+            setattr(o, k, v)
+        return o
+
+    def dfo_sweep(self, x, **opts):
+        """One sweep of the derivative-free solver (Section 3.4) over x in
+        place; returns the largest node move.  Options: tmop_dfo_opts fields."""
+        _check_field(x, self.dim, self.n_node, "x")
+        o = self._dfo_opts(opts)
+        mv = ctypes.c_double()
+        st = self._lib.tmop_dfo_sweep(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.byref(o), ctypes.byref(mv),
+                                      _stream(x))
+        if st < 0:
+            raise TMOPError(st, "tmop_dfo_sweep")
+        return mv.value
+
+    def dfo_solve(self, x, **opts):
+        """Derivative-free solve of x in place; returns (status, report dict)."""
+        _check_field(x, self.dim, self.n_node, "x")
+        o = self._dfo_opts(opts)
+        rep = tmop_dfo_report()
+        st = self._lib.tmop_dfo_solve(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.byref(o), ctypes.byref(rep),
+                                      _stream(x))
+        if st < 0:
+            raise TMOPError(st, "tmop_dfo_solve")
+        return st, {k: getattr(rep, k) for k, _ in tmop_dfo_report._fields_}
 
     def timing_enable(self, on: bool = True):
         """Clears the per-launch kernel timing totals and turns timing on/off."""

@@ -1,0 +1,123 @@
+"""The derivative-free solver of Section 3.4 (eq. 3.3) in the HIP library
+against the oracle: one colour-ordered sweep of Nelder-Mead node moves
+(2D and 3D, constant isotropic and general targets, sliding boundaries)
+node by node, the full solve reaching Newton's minimizer, the FP64 path in
+every precision mode, and the argument checks."""
+import numpy as np
+import pytest
+
+from oracle import tmop_dfo as D
+from oracle import tmop_oracle as O
+from paper_1807_09807_amd import meshgen
+from tests._helpers import say, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+CASES = [  # dim, n, p, Q, metric, W0, noise, seed, slide
+    (2, 6, 2, 4, 2, None, 0.15, 200, False),
+    (2, 4, 3, 4, 9, ((1.0, 0.3), (-0.2, 1.1)), 0.08, 201, False),
+    (2, 7, 1, 2, 7, None, 0.2, 202, True),
+    (2, 5, 2, 3, 77, None, 0.12, 203, False),
+    (3, 2, 2, 3, 303, None, 0.1, 204, False),
+    (3, 2, 1, 2, 302, ((1.0, 0.2, 0.0), (0.0, 1.1, 0.3), (0.1, 0.0, 0.9)), 0.12, 205, True),
+]
+
+
+def _case(dim, n, p, Q, metric, W0, noise, seed, slide):
+    mesh = meshgen.box_mesh(dim, n, p, slide=slide)
+    W = mesh.h * (np.eye(dim) if W0 is None else np.asarray(W0))
+    prob = O.Problem(dim, p, Q, mesh.elem_node, metric, W)
+    x0 = meshgen.perturb(mesh, noise, seed, bad_elements=prob.bad_elements)
+    return mesh, W, prob, x0
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d_p{c[2]}_q{c[3]}_mu{c[4]}{'_slide' if c[8] else ''}")
+def test_sweep_matches_oracle(case):
+    from paper_1807_09807_amd import tmop as T
+    say(f"[dfo] sweep {case}")
+    mesh, W, prob, x0 = _case(*case)
+    opts = D.DfoOptions(step=0.1, xtol=1e-7, max_evals=300)
+    x_o = x0.copy()
+    colours = D.node_colouring(prob.elem_node, mesh.n_node)
+    move_o = D.dfo_sweep(prob, D.Patches(prob, mesh.n_node), x_o, 1 - mesh.fixed.astype(np.int64), colours, opts)
+    ctx = T.Context(mesh.dim, case[2], mesh.elem_node, mesh.n_node, case[3], case[4], W, fixed=mesh.fixed)
+    xd = to_dev(x0)
+    move_g = ctx.dfo_sweep(xd, step=0.1, xtol=1e-7, max_evals=300)
+    x_g = xd.cpu().numpy()
+    d = np.max(np.abs(x_g - x_o), axis=0)
+    off = np.flatnonzero(d > 1e-10 * mesh.h)
+    F_o, F_g = prob.energy(x_o)[0], prob.energy(x_g)[0]
+    say(f"  oracle move {move_o / mesh.h:.4e} h, gpu {move_g / mesh.h:.4e} h; max |x_gpu - x_oracle| = "
+        f"{d.max() / mesh.h:.2e} h; {off.size} of {mesh.n_node} nodes beyond 1e-10 h; F {prob.energy(x0)[0]:.6e} -> "
+        f"{F_o:.6e} (gpu {F_g:.6e})")
+    # Q is summed in another order on the GPU, so a Nelder-Mead comparison
+    # between nearly equal values can go the other way; that node then stops
+    # at another point of the same tolerance box (and its later neighbours
+    # see it there).  Such nodes must be rare and within 2 xtol; F then
+    # differs to first order in that move (a Nelder-Mead end point is not a
+    # stationary point: 6e-7 relative seen for a 4e-8 move on the 3D case).
+    assert off.size <= max(1, 0.02 * mesh.n_node)
+    assert d.max() <= 2 * opts.xtol
+    assert abs(move_g - move_o) <= 2 * opts.xtol
+    assert abs(F_g - F_o) <= (1e-13 if off.size == 0 else 1e-5) * F_o
+    np.testing.assert_array_equal(x_g[mesh.fixed.astype(bool)], x0[mesh.fixed.astype(bool)])
+    assert prob.energy(x_g)[0] <= prob.energy(x0)[0]
+
+
+def test_solve_reaches_the_newton_minimizer():
+    """Swept to t = 1e-8 the mesh is the minimizer Newton finds (here the
+    grid, F = 0), to within the Nelder-Mead tolerance."""
+    from paper_1807_09807_amd import tmop as T
+    say("[dfo] solve 5x5 Q2 mu_2")
+    mesh = meshgen.box_mesh(2, 5, 2)
+    W = mesh.h * np.eye(2)
+    prob = O.Problem(2, 2, 4, mesh.elem_node, 2, W)
+    x0 = meshgen.perturb(mesh, 0.15, 210, bad_elements=prob.bad_elements)
+    ctx = T.Context(2, 2, mesh.elem_node, mesh.n_node, 4, 2, W, fixed=mesh.fixed)
+    xd = to_dev(x0)
+    st, rep = ctx.dfo_solve(xd, t=1e-8, xtol=1e-10, max_evals=1000, max_sweeps=500)
+    say(f"  status {st}, {rep['sweeps']} sweeps, F {rep['F0']:.4e} -> {rep['F']:.4e}, last move {rep['max_move']:.2e}")
+    assert st == T.TMOP_OK and rep["converged"] == 1 and rep["max_move"] < 1e-8
+    assert np.max(np.abs(xd.cpu().numpy() - mesh.x_grid)) < 1e-6 * mesh.h
+    assert rep["F"] < 1e-10 * rep["F0"]
+    assert rep["F"] == pytest.approx(ctx.energy(xd)[0], rel=0, abs=1e-18)
+
+
+def test_fp64_in_every_precision_mode():
+    from paper_1807_09807_amd import tmop as T
+    mesh, W, prob, x0 = _case(*CASES[0])
+    a, b = to_dev(x0), to_dev(x0)
+    ma = T.Context(2, 2, mesh.elem_node, mesh.n_node, 4, 2, W, fixed=mesh.fixed).dfo_sweep(a)
+    mb = T.Context(2, 2, mesh.elem_node, mesh.n_node, 4, 2, W, fixed=mesh.fixed,
+                   precision=T.TMOP_MIXED_FP32).dfo_sweep(b)
+    assert ma == mb and torch.equal(a, b)
+
+
+def test_arguments_and_unsupported_contexts():
+    from paper_1807_09807_amd import tmop as T
+    mesh, W, prob, x0 = _case(*CASES[0])
+    ctx = T.Context(2, 2, mesh.elem_node, mesh.n_node, 4, 2, W, fixed=mesh.fixed)
+    xd = to_dev(x0)
+    for bad in (dict(step=0.0), dict(xtol=-1.0), dict(max_evals=0), dict(t=float("nan"))):
+        with pytest.raises(T.TMOPError) as ei:
+            ctx.dfo_sweep(xd, **bad)
+        assert ei.value.status == T.TMOP_E_ARG
+    assert torch.equal(xd, to_dev(x0))
+    # an inverted input mesh is reported and left alone
+    bad = x0.copy()
+    a = (mesh.n * 2 + 1) + 1
+    bad[:, [a, a + 1]] = bad[:, [a + 1, a]]
+    bd = to_dev(bad)
+    st, rep = ctx.dfo_solve(bd)
+    assert st == T.TMOP_W_INVERTED and torch.equal(bd, to_dev(bad))
+    # Section 4 terms and per-point targets are not part of the patch quality
+    ctx.set_restriction(1.0, xd)
+    with pytest.raises(T.TMOPError) as ei:
+        ctx.dfo_sweep(xd)
+    assert ei.value.status == T.TMOP_E_UNSUPPORTED
+    qps = T.Context(2, 2, mesh.elem_node, mesh.n_node, 4, 2, None, fixed=mesh.fixed,
+                    target_sizes=np.full((mesh.n_elem, 16), mesh.h))
+    with pytest.raises(T.TMOPError) as ei:
+        qps.dfo_solve(xd)
+    assert ei.value.status == T.TMOP_E_UNSUPPORTED
