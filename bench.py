@@ -118,6 +118,7 @@ def parse():
     ap.add_argument("--other-workloads", default="q3_square_256,q3_cube_48,q2_square_512",
                     help="further workloads whose element operations are timed and reported (comma list)")
     ap.add_argument("--no-section4", action="store_true", help="skip the Section 4 objectives")
+    ap.add_argument("--no-dfo", action="store_true", help="skip the derivative-free solver")
     ap.add_argument("--section4-2d", default="q3_square_256",
                     help="2D workload for the second metric term and the replication composite")
     return ap.parse_args()
@@ -412,6 +413,50 @@ def section4(T, torch, dev, args, w, mesh, x, v, W, log):
     return out
 
 
+def dfo(T, torch, dev, args, w, mesh, x, W, log):
+    """Derivative-free solver (Section 3.4): one sweep over the main
+    workload (node moves per second), and the full solve on the 8x8 Q2
+    workload against Newton's wall time to the same mesh."""
+    out = {}
+    ctx = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=mesh.fixed)
+    xs = x.clone()
+    ctx.dfo_sweep(xs.clone(), max_evals=4)                     # builds the node colouring
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mv = ctx.dfo_sweep(xs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    F0, F1 = ctx.energy(x)[0], ctx.energy(xs)[0]
+    ctx.close()
+    out["sweep"] = {"workload": args.workload, "nodes": mesh.n_node, "seconds": round(dt, 4),
+                    "node_moves_per_s": mesh.n_node / dt, "F0": F0, "F_after": F1, "max_move_over_h": mv / mesh.h}
+    log(f"# dfo: one sweep over {args.workload} in {dt:.3f} s ({mesh.n_node / dt:.3e} nodes/s), "
+        f"F {F0:.4e} -> {F1:.4e}")
+    w8, m8, W8 = build_mesh(T, torch, dev, "q2_square_8", gpu_repair=True)
+    c8 = T.Context(2, w8["p"], m8.elem_node, m8.n_node, w8["Q"], w8["metric"], W8, fixed=m8.fixed)
+    x8 = torch.from_numpy(m8.x).to(dev)
+    xd = x8.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, rep = c8.dfo_solve(xd)
+    torch.cuda.synchronize()
+    t_dfo = time.perf_counter() - t0
+    xn = x8.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_n, rn = c8.newton_solve(xn)
+    torch.cuda.synchronize()
+    t_newton = time.perf_counter() - t0
+    diff = float((xd - xn).abs().max()) / m8.h
+    c8.close()
+    out["solve_q2_square_8"] = {"status": st, "sweeps": rep["sweeps"], "seconds": round(t_dfo, 4), "F0": rep["F0"],
+                                "F": rep["F"], "newton_seconds": round(t_newton, 4), "newton_F": rn["F"],
+                                "max_diff_to_newton_over_h": diff}
+    log(f"# dfo: q2_square_8 solve {rep['sweeps']} sweeps {t_dfo:.3f} s, F {rep['F0']:.4e} -> {rep['F']:.4e}; "
+        f"Newton {t_newton:.3f} s, F {rn['F']:.4e}; max |x_dfo - x_newton| / h {diff:.2e}")
+    return out
+
+
 def workload_summary(w, mesh, results):
     """Per-operation rates of one workload against the FP64 VALU and HBM
     peaks (algorithmic flops and unique L-vector bytes per element)."""
@@ -489,6 +534,10 @@ def main():
     if not args.no_section4:
         sec4 = section4(T, torch, dev, args, w, mesh, x, v, W, lambda m: print(m, file=sys.stderr, flush=True))
 
+    dfo_res = None
+    if not args.no_dfo:
+        dfo_res = dfo(T, torch, dev, args, w, mesh, x, W, lambda m: print(m, file=sys.stderr, flush=True))
+
     learned = None
     if not args.no_learned:
         learned = learned_guess(args, lambda m: print(m, file=sys.stderr, flush=True))
@@ -545,6 +594,7 @@ def main():
         "workloads": {args.workload: workload_summary(w, mesh, {k: r for k, r in results.items()}), **others},
         "newton": newton,
         "section4": sec4,
+        "derivative_free": dfo_res,
         "learned_guess": learned,
         "cpu_baseline": cpu,
     }
