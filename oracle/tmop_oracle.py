@@ -172,7 +172,8 @@ def mu(metric: int, T: np.ndarray) -> np.ndarray:
     9:   tau |T - T^{-t}|^2                   (Table 3.1, shape+size, 2D)
     14:  |T - I|^2                            (Section 3.2, shape+size+alignment, 2D)
     77:  (tau - 1/tau)^2 / 2                  (Table 3.1, size, 2D)
-    98:  |T - I|^2 / tau                     (Section 4.3, shape+size+alignment, 2D)
+    98:  |T - I|^2 / tau                     (Section 4.3, shape+size+alignment; a primary
+         metric in 2D, and the replication metric in 2D and 3D)
     303: |T|^2 / (3 tau^{2/3}) - 1           (Table 3.1, shape, 3D)
     302: |T|^2 |T^{-1}|^2 / 9 - 1            (3D shape metric of the workloads)
     with tau = det T and |.| the Frobenius norm."""
@@ -246,9 +247,10 @@ def _tr(A):
     return np.swapaxes(A, -1, -2)
 
 
-def _partials(metric, I1, I2, tau, J=None):
+def _partials(metric, I1, I2, tau, J=None, d=2):
     """The nonzero partials among (f1, f2, ft, fJ, f11, f12, f1t, f22, f2t,
-    ftt, fJt) of mu = f(I1, I2, tau, J); the others are zero."""
+    ftt, fJt) of mu = f(I1, I2, tau, J) for d x d matrices; the others are
+    zero."""
     z = 0.0 * tau
     if metric == 1:          # f = I1
         return dict(f1=1.0 + z)
@@ -259,8 +261,8 @@ def _partials(metric, I1, I2, tau, J=None):
         return dict(ft=(tau - 1.0 / tau) * (1.0 + 1.0 / tau ** 2), ftt=1.0 + 3.0 / tau ** 4)
     if metric == 14:         # |T - I|^2 = I1 - 2 J + d
         return dict(f1=1.0 + z, fJ=-2.0 + z)
-    if metric == 98:         # (I1 - 2 J + 2) / tau  (2D)
-        n = I1 - 2.0 * J + 2.0
+    if metric == 98:         # (I1 - 2 J + d) / tau
+        n = I1 - 2.0 * J + d
         return dict(f1=1.0 / tau, fJ=-2.0 / tau, ft=-n / tau ** 2, f1t=-1.0 / tau ** 2,
                     fJt=2.0 / tau ** 2, ftt=2.0 * n / tau ** 3)
     if metric == 2:          # f = I1/(2 tau) - 1
@@ -293,8 +295,8 @@ def _inv(T):
 _PARTIAL_NAMES = ("f1", "f2", "ft", "fJ", "f11", "f12", "f1t", "f22", "f2t", "ftt", "fJt")
 
 
-def _all_partials(metric, I1, I2, tau, J):
-    f = _partials(metric, I1, I2, tau, J)
+def _all_partials(metric, I1, I2, tau, J, d=2):
+    f = _partials(metric, I1, I2, tau, J, d)
     z = 0.0 * tau
     return {k: f.get(k, z) for k in _PARTIAL_NAMES}
 
@@ -302,7 +304,7 @@ def _all_partials(metric, I1, I2, tau, J):
 def dmu(metric: int, T: np.ndarray) -> np.ndarray:
     """First derivative P = d mu / dT (the matrix of Section 3.4)."""
     I1, I2, tau, C, J = _inv(T)
-    f = _all_partials(metric, I1, I2, tau, J)
+    f = _all_partials(metric, I1, I2, tau, J, T.shape[-1])
     e = lambda s: s[..., None, None]
     dI2 = 2.0 * (e(I1) * T - _mm(_mm(T, _tr(T)), T))
     Id = np.eye(T.shape[-1])
@@ -314,7 +316,7 @@ def d2mu(metric: int, T: np.ndarray, E: np.ndarray) -> np.ndarray:
     at e = 0 (the Hessian ingredient of Section 3.4).  The partials f1J and
     fJJ vanish for every metric here."""
     I1, I2, tau, C, J = _inv(T)
-    f = _all_partials(metric, I1, I2, tau, J)
+    f = _all_partials(metric, I1, I2, tau, J, T.shape[-1])
     e = lambda s: s[..., None, None]
     TtT = _mm(_tr(T), T)
     dI2 = 2.0 * (e(I1) * T - _mm(T, TtT))
@@ -405,8 +407,6 @@ class Problem:
         over the primary target element (weight det W for both parts)."""
         if not (0.0 <= gamma <= 1.0):
             raise ValueError("gamma must lie in [0, 1]")
-        if self.dim != 2:
-            raise ValueError("mu_98 is a 2D metric here")
         A0 = self._jac(np.asarray(x_init, dtype=np.float64), 0, self.n_elem)
         if np.any(_det(A0) <= 0):
             raise ValueError("the initial mesh is inverted: W_0 = A_init needs det > 0")

@@ -236,22 +236,30 @@ def test_replication_gamma_zero_keeps_the_initial_mesh():
     assert rep.iters == 0 and np.array_equal(x, x0)
 
 
-@pytest.mark.parametrize("gamma", [0.0, 0.3, 0.8])
-def test_replication_linear_map_closed_form(gamma):
+@pytest.mark.parametrize("dim,metric,gamma", [(2, 9, 0.0), (2, 9, 0.3), (2, 9, 0.8), (3, 303, 0.0), (3, 302, 0.6)])
+def test_replication_linear_map_closed_form(dim, metric, gamma):
     """x = M x_init: T_0 = M at every point, so the mu_98 part is
-    (1 - gamma) |M - I|^2 / det M times the target volume n_elem h^2."""
-    mesh, W, prob, x0 = _mesh(2, 3, 2, 4, 9)
-    plain = _fresh(mesh, 2, 4, 9, W)
-    M = np.array([[1.1, 0.15], [-0.05, 0.95]])
+    (1 - gamma) |M - I|^2 / det M times the target volume n_elem h^d."""
+    mesh, W, prob, x0 = _mesh(dim, 3 if dim == 2 else 2, 2, 4 if dim == 2 else 3, metric)
+    plain = _fresh(mesh, 2, 4 if dim == 2 else 3, metric, W)
+    M = np.array([[1.1, 0.15, 0.05], [-0.05, 0.95, 0.1], [0.02, -0.1, 1.05]])[:dim, :dim]
     x = M @ x0
     prob.set_replication(gamma, x0)
     F = prob.energy(x)[0]
-    part98 = (1 - gamma) * float(np.sum((M - np.eye(2)) ** 2)) / np.linalg.det(M) * mesh.n_elem * mesh.h ** 2
+    part98 = (1 - gamma) * float(np.sum((M - np.eye(dim)) ** 2)) / np.linalg.det(M) * mesh.n_elem * mesh.h ** dim
     assert F == pytest.approx(gamma * plain.energy(x)[0] + part98, rel=1e-12)
 
 
-def test_replication_derivatives():
-    mesh, W, prob, x0 = _mesh(2, 2, 2, 3, 2)
+def test_replication_3d_gamma_zero_is_stationary():
+    mesh, W, prob, x0 = _mesh(3, 2, 2, 3, 303)
+    prob.set_replication(0.0, x0)
+    assert abs(prob.energy(x0)[0]) <= 1e-28
+    assert np.max(np.abs(prob.gradient(x0))) <= 1e-14
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_replication_derivatives(dim):
+    mesh, W, prob, x0 = _mesh(dim, 2 if dim == 2 else 1, 2, 3, 2 if dim == 2 else 302)
     x = meshgen.perturb(mesh, 0.05, 13, base=x0, bad_elements=prob.bad_elements)
     prob.set_replication(0.4, x0)
     _cs_checks(prob, x, 8)
