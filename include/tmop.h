@@ -251,13 +251,13 @@ int tmop_set_restriction(tmop_ctx *ctx, double delta, const double *x_init, void
  *   F = sum_E sum_q w_q [eta1 det W mu(A W^-1) + omega_q mu2(A W2^-1)],
  *   omega_q = eta2 * eta2_q[e][q] * det W2,
  * each term integrated over its own target element.  W2: host, row-major
- * 2x2, det W2 > 0 (else TMOP_E_TARGET).  eta2_q: host [n_elem][n1d^2]
- * per-point weights (point index q0 + n1d q1, the space-dependent weight of
- * Section 5.2.4), or NULL for 1.  eta1, eta2 and every eta2_q finite and
- * >= 0 (else TMOP_E_ARG).  metric2: a 2D metric; 0 removes the second term
- * and keeps eta1.  2D contexts with a constant target only (else
- * TMOP_E_UNSUPPORTED).  Replaces an earlier second term or replication.
- * Syncs. */
+ * dim x dim, det W2 > 0 (else TMOP_E_TARGET).  eta2_q: host
+ * [n_elem][n1d^dim] per-point weights (point index q0 + n1d q1 (+ n1d^2 q2),
+ * the space-dependent weight of Section 5.2.4), or NULL for 1.  eta1, eta2
+ * and every eta2_q finite and >= 0 (else TMOP_E_ARG).  metric2: a metric of
+ * the context's dimension; 0 removes the second term and keeps eta1.
+ * Contexts with a constant target only (else TMOP_E_UNSUPPORTED).  Replaces
+ * an earlier second term or replication.  Syncs. */
 int tmop_set_combo(tmop_ctx *ctx, int32_t metric2, const double *W2, double eta1, double eta2,
                    const double *eta2_q, void *stream);
 
@@ -268,8 +268,9 @@ int tmop_set_combo(tmop_ctx *ctx, int32_t metric2, const double *W2, double eta1
  * (else TMOP_E_ARG); gamma = 0 keeps x_init, gamma = 1 is the plain
  * objective.  x_init: device [dim][n_node], read once (W0^-1 is stored per
  * point).  TMOP_E_TARGET (context unchanged) if det A(x_init) <= 0 at a
- * point.  2D contexts with a constant target only (else
- * TMOP_E_UNSUPPORTED).  Replaces an earlier second term.  Syncs. */
+ * point.  mu_98 = |T - I|^2 / tau for the context's dimension.  Contexts
+ * with a constant target only (else TMOP_E_UNSUPPORTED).  Replaces an
+ * earlier second term.  Syncs. */
 int tmop_set_replication(tmop_ctx *ctx, double gamma, const double *x_init, void *stream);
 
 /* F and min det A as tmop_energy (eq. 2.4), and g = dF/dx as tmop_gradient

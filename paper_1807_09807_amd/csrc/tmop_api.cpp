@@ -171,6 +171,9 @@ void timing_end(tmop_ctx* c, int r, hipStream_t s, tmop_ctx::TimedLaunch& tl) {
   }
 }
 
+// Values per point of the second term's data: W^{-1} (row-major) and omega.
+int tmat_stride(const tmop_ctx* c) { return c->dim * c->dim + 1; }
+
 // The metric term a launch evaluates: the primary one, or the second term
 // of a composite objective (its metric and per-point targets).
 struct TermSel {
@@ -294,7 +297,7 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
     int grid = 0;
     const int r = elem_launch(c, op, x, v, out, c->d_elem_node_col + c->color_off[k] * c->npe, nullptr, n, s,
                               &grid, scale, off, nullptr, nullptr,
-                              TermSel{c->metric2, c->d_tmat_col + c->color_off[k] * c->nq * 5});
+                              TermSel{c->metric2, c->d_tmat_col + c->color_off[k] * c->nq * tmat_stride(c)});
     if (r != TMOP_OK) return r;
     off += grid;
   }
@@ -850,12 +853,13 @@ bool metric_2d(int m) {
 // Installs per-point second-term data (element order, device) as the
 // context's second metric term: its colour-order copy, then the switch.
 int install_second_term(tmop_ctx* c, int metric2, double* d_tm, double eta1, hipStream_t s) {
-  if (!c->d_tmat_col && hipMalloc(&c->d_tmat_col, (size_t)c->n_elem * c->nq * 5 * sizeof(double)) != hipSuccess) {
+  const int ts = tmat_stride(c);
+  if (!c->d_tmat_col && hipMalloc(&c->d_tmat_col, (size_t)c->n_elem * c->nq * ts * sizeof(double)) != hipSuccess) {
     c->d_tmat_col = nullptr;
     (void)hipFree(d_tm);
     return TMOP_E_NOMEM;
   }
-  if (gather_rows(d_tm, c->d_colors, c->n_elem, c->nq * 5, c->d_tmat_col, s) != hipSuccess ||
+  if (gather_rows(d_tm, c->d_colors, c->n_elem, c->nq * ts, c->d_tmat_col, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     (void)hipFree(d_tm);
     return TMOP_E_HIP;
@@ -877,21 +881,24 @@ int tmop_set_combo(tmop_ctx* c, int32_t metric2, const double* W2, double eta1, 
     c->base.wdetW = eta1 * c->base.detW;
     return TMOP_OK;
   }
-  if (c->dim != 2 || c->d_tsize) return TMOP_E_UNSUPPORTED;
-  if (!metric_2d(metric2) || !W2 || !(eta2 >= 0.0) || !std::isfinite(eta2)) return TMOP_E_ARG;
-  const double det2 = det3(W2, 2);
+  if (c->d_tsize) return TMOP_E_UNSUPPORTED;
+  const int d = c->dim, ts = tmat_stride(c);
+  const bool metric_ok = d == 2 ? metric_2d(metric2) : (metric2 == TMOP_MU302 || metric2 == TMOP_MU303);
+  if (!metric_ok || !W2 || !(eta2 >= 0.0) || !std::isfinite(eta2)) return TMOP_E_ARG;
+  const double det2 = det3(W2, d);
   if (!(det2 > 0.0)) return TMOP_E_TARGET;               // Section 3.1: det W > 0
   const int64_t n = c->n_elem * c->nq;
   if (eta2_q)
     for (int64_t k = 0; k < n; ++k)
       if (!(eta2_q[k] >= 0.0) || !std::isfinite(eta2_q[k])) return TMOP_E_ARG;
   double Wi[3][3];
-  inv3(W2, 2, Wi);
-  std::vector<double> tm((size_t)n * 5);
+  inv3(W2, d, Wi);
+  std::vector<double> tm((size_t)n * ts);
   for (int64_t k = 0; k < n; ++k) {
-    double* t = &tm[(size_t)k * 5];
-    t[0] = Wi[0][0]; t[1] = Wi[0][1]; t[2] = Wi[1][0]; t[3] = Wi[1][1];
-    t[4] = eta2 * (eta2_q ? eta2_q[k] : 1.0) * det2;
+    double* t = &tm[(size_t)k * ts];
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) t[d * i + j] = Wi[i][j];
+    t[d * d] = eta2 * (eta2_q ? eta2_q[k] : 1.0) * det2;
   }
   hipStream_t s = (hipStream_t)stream;
   double* d_tm = nullptr;
@@ -905,10 +912,11 @@ int tmop_set_combo(tmop_ctx* c, int32_t metric2, const double* W2, double eta1, 
 
 int tmop_set_replication(tmop_ctx* c, double gamma, const double* x_init, void* stream) {
   if (!c || !x_init || !(gamma >= 0.0 && gamma <= 1.0)) return TMOP_E_ARG;
-  if (c->dim != 2 || c->d_tsize) return TMOP_E_UNSUPPORTED;
+  if (c->d_tsize) return TMOP_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   double* d_tm = nullptr;
-  if (hipMalloc(&d_tm, (size_t)c->n_elem * c->nq * 5 * sizeof(double)) != hipSuccess) return TMOP_E_NOMEM;
+  if (hipMalloc(&d_tm, (size_t)c->n_elem * c->nq * tmat_stride(c) * sizeof(double)) != hipSuccess)
+    return TMOP_E_NOMEM;
   // W_0 = A(x_init) at every point; both parts weigh with the primary det W
   int grid = 0;
   int r = elem_launch(c, OP_JINV, x_init, nullptr, d_tm, c->d_elem_node, nullptr, c->n_elem, s, &grid, nullptr, 0,
@@ -924,7 +932,7 @@ int tmop_set_replication(tmop_ctx* c, double gamma, const double* x_init, void* 
     (void)hipFree(d_tm);
     return r;
   }
-  return install_second_term(c, TMOP_MU98, d_tm, gamma, s);
+  return install_second_term(c, c->dim == 2 ? TMOP_MU98 : MU98_3D, d_tm, gamma, s);
 }
 
 namespace {

@@ -8,13 +8,13 @@
 //              at every trial point)
 //   OP_SIZE    (det A)^(1/d) at every quadrature point: the size of the
 //              target W_3 = (det A(x_0))^(1/d) I of Section 3.1
-//   OP_JINV    A^{-1} at every quadrature point (2D): the target data of
+//   OP_JINV    A^{-1} at every quadrature point: the target data of
 //              W_0 = A(x_init) in the replication composite (Section 4.3.2)
 //
 // Targets (template parameter TGT): a constant general W (TGT_GEN), a
 // constant isotropic W = s I (TGT_ISO), an isotropic W_q = s_q I given
 // per quadrature point (TGT_QPS, Section 3.1: W may differ at every point),
-// or a general W_q with its own weight omega_q per point (TGT_MAT, 2D: the
+// or a general W_q with its own weight omega_q per point (TGT_MAT: the
 // second term of a composite objective, Section 4.2 and 4.3.2).
 //
 // The Jacobian A = sum_i x_i (grad w_i)^T (eq. 2.2) of a tensor-product
@@ -71,7 +71,7 @@ struct ElemArgs {
   const double* __restrict__ scale;      // OP_GRAD: optional device scalar multiplying g (nullptr = 1)
   const double* __restrict__ tsize;      // TGT_QPS: [n_list][Q^dim] target sizes s_q (W_q = s_q I), point
                                          // index q0 + Q q1 (+ Q^2 q2), in the order of elem_node
-  const double* __restrict__ tmat;       // TGT_MAT: [n_list][Q^2][5] W_q^{-1} (row-major) and omega_q
+  const double* __restrict__ tmat;       // TGT_MAT: [n_list][Q^dim][dim^2 + 1] W_q^{-1} (row-major) and omega_q
   int64_t n_node;
   int32_t n_list;
   R B[Q][P];
@@ -241,6 +241,19 @@ __device__ __forceinline__ double load_point_target2(const double* __restrict__ 
 #pragma unroll
     for (int j = 0; j < 3; ++j) Wi[i][j] = (R)Wid[i][j];
   return tm[4];
+}
+
+template <typename R>
+__device__ __forceinline__ double load_point_target3(const double* __restrict__ tm, R (&Wi)[3][3],
+                                                     double (&Wid)[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Wid[i][j] = tm[3 * i + j];
+      Wi[i][j] = (R)Wid[i][j];
+    }
+  return tm[9];
 }
 
 // Per-point kernel of the operations.  Given A (and dA) -- already divided
@@ -478,11 +491,10 @@ __device__ __forceinline__ void fwd_3d_areas(const ElemArgs<P, Q, R>& a, const R
 template <int P, int Q, int METRIC, typename R, int OP, int TGT>
 __global__ void __launch_bounds__((Cfg<3, P, Q, R>::BLOCK))
 elem_kernel_3d(const ElemArgs<P, Q, R> a) {
-  static_assert(TGT != TGT_MAT && OP != OP_JINV, "per-point general targets are 2D only");
   using C = Cfg<3, P, Q, R>;
   using L = Lds3<P, Q>;
-  constexpr bool ISO = TGT != TGT_GEN;
-  constexpr bool ENERGY_LIKE = OP == OP_ENERGY || OP == OP_SIZE;   // no transposed passes
+  constexpr bool ISO = TGT == TGT_ISO || TGT == TGT_QPS;
+  constexpr bool ENERGY_LIKE = OP == OP_ENERGY || OP == OP_SIZE || OP == OP_JINV;   // no transposed passes
   constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P * P;
   constexpr bool AFFINE = sizeof(R) == 4;   // FP32 contracts the deviation from the vertex-affine map
   constexpr int NE = OP == OP_HESS ? C::NEH : C::NE;
@@ -546,13 +558,15 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
       for (int i0 = 0; i0 < P; ++i0) Racc[tt][c][i0] = 0;
 
   if (tb < Q) {
-    const double w12 = a.w[ta] * a.w[tb] * (TGT == TGT_QPS ? 1.0 : a.wdetW) * (a.scale ? *a.scale : 1.0);
+    const double w12 =
+        a.w[ta] * a.w[tb] * (TGT == TGT_QPS || TGT == TGT_MAT ? 1.0 : a.wdetW) * (a.scale ? *a.scale : 1.0);
     double sq[Q];   // this lane's row of target sizes (q0 = 0..Q-1)
     if constexpr (TGT == TGT_QPS) {
       const double* ts = a.tsize + (int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb;
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
+    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb) * 10 : nullptr;
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[3][3], dA[3][3];
@@ -582,9 +596,34 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
       R Y[3][3];
       double wdet = w12 * a.w[q0], detWq = a.detW, kY = wdet, detA = 0.0;
       if constexpr (TGT == TGT_QPS) qp_scale<3, R>(sq[q0], A, dA, wdet, detWq, kY);
-      point_op<3, METRIC, R, OP, ISO>(a.Winv, a.Winvd, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
+      if constexpr (TGT == TGT_MAT) {
+        R Wi[3][3];
+        double Wid[3][3];
+        wdet *= load_point_target3<R>(tm + 10 * q0, Wi, Wid);
+        kY = wdet;
+        point_op<3, METRIC, R, OP, false>(Wi, Wid, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
+      } else {
+        point_op<3, METRIC, R, OP, ISO>(a.Winv, a.Winvd, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
+      }
       if constexpr (OP == OP_SIZE) {
         if (active) a.out[(int64_t)e * (Q * Q * Q) + q0 + Q * ta + Q * Q * tb] = size_of<3>(detA);
+      }
+      if constexpr (OP == OP_JINV) {   // A^{-1} = cof(A)^t / det A, and the weight omega
+        if (active) {
+          double Ad[3][3], Cd[3][3];
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Ad[i][j] = (double)A[i][j];
+          cofactor<3, double>(Ad, Cd);
+          double* o = a.out + ((int64_t)e * (Q * Q * Q) + q0 + Q * ta + Q * Q * tb) * 10;
+          const double r = 1.0 / detA;
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) o[3 * i + j] = Cd[j][i] * r;
+          o[9] = a.wdetW;
+        }
       }
       if constexpr (!ENERGY_LIKE) {
 #pragma unroll
@@ -599,7 +638,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
     }
   }
 
-  if constexpr (OP == OP_ENERGY || OP == OP_EG || OP == OP_SIZE) {
+  if constexpr (OP == OP_ENERGY || OP == OP_EG || OP == OP_SIZE || OP == OP_JINV) {
     if (!active) { acc = 0.0; mind = __builtin_huge_val(); }
     block_reduce_sum_min<C::BLOCK>(acc, mind, red, a.part + blk, a.part_min + blk);
   }
@@ -1011,8 +1050,7 @@ __device__ __forceinline__ void target_congruence(const R (&Wi)[3][3], R (&K6)[D
 template <int P, int Q, int METRIC, typename R, int TGT>
 __global__ void __launch_bounds__((Cfg<3, P, Q, R>::BLOCK))
 diag_kernel_3d(const DiagArgs<P, Q, R> a) {
-  static_assert(TGT != TGT_MAT, "per-point general targets are 2D only");
-  constexpr bool ISO = TGT != TGT_GEN;
+  constexpr bool ISO = TGT == TGT_ISO || TGT == TGT_QPS;
   using C = Cfg<3, P, Q, R>;
   using LD = LdsDiag3<P, Q>;
   constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P * P;
@@ -1063,13 +1101,14 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
 #pragma unroll
       for (int i0 = 0; i0 < P; ++i0) Rd[pr][c][i0] = 0;
   if (tb < Q) {
-    const double w12 = a.w[ta] * a.w[tb] * (TGT == TGT_QPS ? 1.0 : a.wdetW);
+    const double w12 = a.w[ta] * a.w[tb] * (TGT == TGT_QPS || TGT == TGT_MAT ? 1.0 : a.wdetW);
     double sq[Q];
     if constexpr (TGT == TGT_QPS) {
       const double* ts = a.tsize + (int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb;
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
+    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb) * 10 : nullptr;
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[3][3];
@@ -1095,9 +1134,18 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
           for (int j = 0; j < 3; ++j) A[i][j] *= r;
         kK *= sq[q0];
       }
-      right_mul<3, R, ISO>(A, a.Winv, T);
-      mu_second_rows<METRIC, R>(T, (R)kK, K);
-      if constexpr (!ISO) target_congruence<3, R>(a.Winv, K);
+      if constexpr (TGT == TGT_MAT) {
+        R Wi[3][3];
+        double Wid[3][3];
+        kK *= load_point_target3<R>(tm + 10 * q0, Wi, Wid);
+        right_mul<3, R, false>(A, Wi, T);
+        mu_second_rows<METRIC, R>(T, (R)kK, K);
+        target_congruence<3, R>(Wi, K);
+      } else {
+        right_mul<3, R, ISO>(A, a.Winv, T);
+        mu_second_rows<METRIC, R>(T, (R)kK, K);
+        if constexpr (!ISO) target_congruence<3, R>(a.Winv, K);
+      }
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const R f0 = K[c][0], f1 = K[c][1], f2 = K[c][2];

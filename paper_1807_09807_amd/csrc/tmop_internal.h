@@ -17,6 +17,10 @@ enum { OP_ENERGY = 0, OP_GRAD = 1, OP_HESS = 2, OP_EG = 3, OP_DIAG = 4, OP_SIZE 
 constexpr int TIMING_PENALTY = 7;
 constexpr int TIMING_SLOTS = 8;
 
+// mu_98 = |T - I|^2 / tau on 3x3 T (the replication metric of Section
+// 4.3.2 in 3D): an internal metric id of the 3D kernels
+constexpr int MU98_3D = 398;
+
 constexpr int MAXP = 5;   // nodes per direction (order p <= 4)
 constexpr int MAXQ = 6;   // quadrature points per direction
 
@@ -34,8 +38,8 @@ struct LaunchParams {
   double* part_min;        // energy partials: minima of det A
   const double* scale;     // gradient: optional device scalar factor
   const double* tsize;     // per-point isotropic target sizes (in the order of elem_node), or nullptr
-  const double* tmat;      // 2D per-point targets [n_list][Q^2][5]: W^{-1} row-major and the weight
-                           // omega_q (the term is sum_q w_q omega_q mu(A W_q^{-1})), or nullptr
+  const double* tmat;      // per-point targets [n_list][Q^dim][dim^2 + 1]: W^{-1} row-major and the
+                           // weight omega_q (the term is sum_q w_q omega_q mu(A W_q^{-1})), or nullptr
   double B[MAXQ][MAXP];
   double G[MAXQ][MAXP];
   double w[MAXQ];
@@ -158,8 +162,8 @@ struct tmop_ctx {
   double* d_part = nullptr;            // [2 * part_cap] energy partials: sums, then minima
   int64_t part_cap = 0;                // partials per kind (3 n_elem + 16: up to three terms)
   // Section 4 terms
-  int metric2 = 0;                     // second metric term (0: none), 2D
-  double* d_tmat = nullptr;            // its per-point data [n_elem][nq][5], element order
+  int metric2 = 0;                     // second metric term (0: none)
+  double* d_tmat = nullptr;            // its per-point data [n_elem][nq][dim^2 + 1], element order
   double* d_tmat_col = nullptr;        // the same in colour order
   double delta = 0.0;                  // displacement penalty weight (eq. 4.2; 0: none)
   double* d_xinit = nullptr;           // its x_init [dim][n_node]

@@ -54,7 +54,7 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
 
 // OP_SIZE and OP_JINV do not depend on the metric: they are instantiated
 // for the first metric of each dimension only (the caller routes them
-// there), OP_JINV for the general constant target (W = I) in 2D only.
+// there), OP_JINV for the general constant target (W = I) only.
 template <int DIM, int P, int Q, int M, typename R, int TGT>
 static int launch_op(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
   if (op == OP_ENERGY) return launch_one<DIM, P, Q, M, R, OP_ENERGY, TGT>(lp, s, grid);
@@ -64,7 +64,7 @@ static int launch_op(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
   if (op == OP_DIAG) return launch_one<DIM, P, Q, M, R, OP_DIAG, TGT>(lp, s, grid);
   if constexpr (M == (DIM == 2 ? 1 : 302) && TGT != TGT_MAT) {
     if (op == OP_SIZE) return launch_one<DIM, P, Q, M, R, OP_SIZE, TGT>(lp, s, grid);
-    if constexpr (DIM == 2 && TGT == TGT_GEN)
+    if constexpr (TGT == TGT_GEN)
       if (op == OP_JINV) return launch_one<DIM, P, Q, M, R, OP_JINV, TGT>(lp, s, grid);
   }
   return -1;
@@ -72,8 +72,7 @@ static int launch_op(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
 
 template <int DIM, int P, int Q, int M, typename R>
 static int launch_metric(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
-  if constexpr (DIM == 2)
-    if (lp.tmat) return launch_op<DIM, P, Q, M, R, TGT_MAT>(op, lp, s, grid);
+  if (lp.tmat) return launch_op<DIM, P, Q, M, R, TGT_MAT>(op, lp, s, grid);
   if (lp.tsize) return launch_op<DIM, P, Q, M, R, TGT_QPS>(op, lp, s, grid);
   return lp.iso ? launch_op<DIM, P, Q, M, R, TGT_ISO>(op, lp, s, grid) : launch_op<DIM, P, Q, M, R, TGT_GEN>(op, lp, s, grid);
 }
@@ -103,6 +102,7 @@ static int launch_pq(int metric, int op, const LaunchParams& lp, hipStream_t s, 
     switch (metric) {
       case 302: return launch_metric<3, P, Q, 302, R>(op, lp, s, grid);
       case 303: return launch_metric<3, P, Q, 303, R>(op, lp, s, grid);
+      case 398: return lp.tmat ? launch_op<3, P, Q, 398, R, TGT_MAT>(op, lp, s, grid) : -1;   // replication, 3D
       default: return -1;
     }
   }

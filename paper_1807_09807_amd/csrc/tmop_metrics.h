@@ -100,6 +100,9 @@ template <> struct MetricInfo<9>   { static constexpr int dim = 2; static conste
 template <> struct MetricInfo<14>  { static constexpr int dim = 2; static constexpr bool i2 = false, tr = true; };
 template <> struct MetricInfo<77>  { static constexpr int dim = 2; static constexpr bool i2 = false, tr = false; };
 template <> struct MetricInfo<98>  { static constexpr int dim = 2; static constexpr bool i2 = false, tr = true; };
+// mu_98 = |T - I|^2 / tau for 3x3 T: the replication metric of Section 4.3.2 in 3D (an internal id; the
+// 3D primary metrics are 302 and 303)
+template <> struct MetricInfo<398> { static constexpr int dim = 3; static constexpr bool i2 = false, tr = true; };
 template <> struct MetricInfo<302> { static constexpr int dim = 3; static constexpr bool i2 = true, tr = false; };
 template <> struct MetricInfo<303> { static constexpr int dim = 3; static constexpr bool i2 = false, tr = false; };
 
@@ -119,9 +122,9 @@ __device__ __forceinline__ Partials<R> partials(R I1, R I2, R tau, R J = R(0)) {
     p.ft = (tau - rt) * (R(1) + rt2);  p.ftt = R(1) + R(3) * rt2 * rt2;
   } else if constexpr (METRIC == 14) {    // f = I1 - 2 J + 2  (|T - I|^2)
     p.f1 = R(1);  p.fJ = R(-2);
-  } else if constexpr (METRIC == 98) {    // f = (I1 - 2 J + 2) / tau  (|T - I|^2 / tau)
+  } else if constexpr (METRIC == 98 || METRIC == 398) {   // f = (I1 - 2 J + d) / tau  (|T - I|^2 / tau)
     const R rt = rcp(tau);
-    const R n = I1 - R(2) * J + R(2);
+    const R n = I1 - R(2) * J + R(METRIC == 98 ? 2 : 3);
     p.f1 = rt;  p.fJ = R(-2) * rt;  p.ft = -n * rt * rt;
     p.f1t = -rt * rt;  p.fJt = R(2) * rt * rt;  p.ftt = R(2) * n * rt * rt * rt;
   } else if constexpr (METRIC == 2) {     // f = I1 / (2 tau) - 1
@@ -173,6 +176,16 @@ __device__ __forceinline__ R mu_value(const R (&T)[MetricInfo<METRIC>::dim][Metr
     const R n = a * a + b * b + T[0][1] * T[0][1] + T[1][0] * T[1][0];
     if constexpr (METRIC == 14) return n;
     else return n * rcp(tau);
+  } else if constexpr (METRIC == 398) {
+    R n = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const R t = T[i][j] - (i == j ? R(1) : R(0));
+        n += t * t;
+      }
+    return n * rcp(tau);
   } else {
     R I1 = 0;
 #pragma unroll

@@ -322,13 +322,13 @@ class Context:
 
     def set_combo(self, metric2: int, W2=None, eta1: float = 1.0, eta2: float = 1.0, eta2_q=None):
         """Second metric term of eq. 4.1: eta1 mu + eta2 eta2_q det W2 mu2(A W2^-1)
-        (W2: 2x2 host matrix; eta2_q: host (n_elem, n_q1d^2) weights or None);
-        metric2 = 0 removes it."""
+        (W2: dim x dim host matrix; eta2_q: host (n_elem, n_q1d^dim) weights or
+        None); metric2 = 0 removes it."""
         W2p, Wbuf, qbuf = None, None, None
         if W2 is not None:
             Wbuf = np.ascontiguousarray(np.asarray(W2, dtype=np.float64).reshape(-1))
-            if Wbuf.size != 4:
-                raise ValueError("W2 must be a 2x2 matrix")
+            if Wbuf.size != self.dim * self.dim:
+                raise ValueError(f"W2 must be a {self.dim}x{self.dim} matrix")
             W2p = Wbuf.ctypes.data_as(ctypes.c_void_p)
         qp = None
         if eta2_q is not None:

@@ -1,9 +1,9 @@
 """The Section 4 objectives in the HIP library against the oracle, element
 by element (FP64 within 1e-12 relative, mixed FP32 within the mixed
 tolerance of the worse-conditioned term): the displacement penalty of
-eq. 4.2 (2D and 3D, constant and per-point targets), the two-term composite
-metric of eq. 4.1 with per-point weights, the replication composite of
-Section 4.3.2, all of them together, argument checks, and Newton on each
+eq. 4.2, the two-term composite metric of eq. 4.1 with per-point weights
+and the replication composite of Section 4.3.2 (each in 2D and 3D, the
+penalty also with per-point targets), all of them together, argument checks, and Newton on each
 against the oracle's Newton."""
 import numpy as np
 import pytest
@@ -146,28 +146,30 @@ def test_newton_restricted_matches_oracle():
 
 # ----------------------------------------------------------------- eq. 4.1
 
-COMBO = [  # n, p, Q, metric, metric2, W2 / h, eta1, eta2, per-point eta2, seed
-    (6, 2, 4, 1, 77, ((0.7, 0.0), (0.0, 0.7)), 1.0, 0.5, True, 100),
-    (5, 3, 5, 2, 9, ((1.0, 0.3), (-0.2, 1.1)), 0.7, 2.0, False, 101),
-    (7, 1, 2, 7, 14, ((1.2, 0.0), (0.1, 0.9)), 1.3, 0.4, True, 102),
-    (4, 4, 5, 98, 2, ((0.9, 0.0), (0.0, 1.1)), 0.5, 1.0, True, 103),
+COMBO = [  # dim, n, p, Q, metric, metric2, W2 / h, eta1, eta2, per-point eta2, seed
+    (2, 6, 2, 4, 1, 77, ((0.7, 0.0), (0.0, 0.7)), 1.0, 0.5, True, 100),
+    (2, 5, 3, 5, 2, 9, ((1.0, 0.3), (-0.2, 1.1)), 0.7, 2.0, False, 101),
+    (2, 7, 1, 2, 7, 14, ((1.2, 0.0), (0.1, 0.9)), 1.3, 0.4, True, 102),
+    (2, 4, 4, 5, 98, 2, ((0.9, 0.0), (0.0, 1.1)), 0.5, 1.0, True, 103),
+    (3, 3, 2, 4, 303, 302, ((0.8, 0.1, 0.0), (0.0, 1.1, 0.2), (0.1, 0.0, 0.9)), 1.0, 0.6, True, 104),
+    (3, 2, 3, 4, 302, 303, ((0.7, 0.0, 0.0), (0.0, 0.7, 0.0), (0.0, 0.0, 0.7)), 0.8, 1.5, False, 105),
 ]
 
 
 def _combo(case):
-    n, p, Q, m1, m2, W2s, eta1, eta2, pp, seed = case
-    mesh, prob, x0, x, _ = _base(2, n, p, Q, m1, seed)
+    dim, n, p, Q, m1, m2, W2s, eta1, eta2, pp, seed = case
+    mesh, prob, x0, x, _ = _base(dim, n, p, Q, m1, seed)
     W2 = mesh.h * np.asarray(W2s)
-    eq = np.random.default_rng(seed + 5).uniform(0.2, 1.5, (mesh.n_elem, Q * Q)) if pp else None
+    eq = np.random.default_rng(seed + 5).uniform(0.2, 1.5, (mesh.n_elem, Q ** dim)) if pp else None
     prob.set_combo(m2, W2, eta1, eta2 * (eq if pp else 1.0))
-    tol2 = MIXED_C * EPS32 * O.Problem(2, p, Q, mesh.elem_node, m2, W2).max_condition(x)
+    tol2 = MIXED_C * EPS32 * O.Problem(dim, p, Q, mesh.elem_node, m2, W2).max_condition(x)
     return mesh, prob, x0, x, W2, eq, max(mixed_tol(prob, x), tol2)
 
 
-@pytest.mark.parametrize("case", COMBO, ids=lambda c: f"p{c[1]}_q{c[2]}_mu{c[3]}+mu{c[4]}")
+@pytest.mark.parametrize("case", COMBO, ids=lambda c: f"{c[0]}d_p{c[2]}_q{c[3]}_mu{c[4]}+mu{c[5]}")
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
 def test_combo_parity(case, precision):
-    n, p, Q, m1, m2, W2s, eta1, eta2, pp, seed = case
+    dim, n, p, Q, m1, m2, W2s, eta1, eta2, pp, seed = case
     say(f"[combo] case {case} precision {precision}")
     mesh, prob, x0, x, W2, eq, mtol = _combo(case)
     ctx = _ctx(mesh, p, Q, m1, None, precision)
@@ -199,11 +201,10 @@ def test_combo_arguments():
     m3 = meshgen.box_mesh(3, 2, 2)
     c3 = T.Context(3, 2, m3.elem_node, m3.n_node, 3, 303, m3.h * np.eye(3))
     with pytest.raises(T.TMOPError) as ei:
-        c3.set_combo(302, np.eye(2))
-    assert ei.value.status == T.TMOP_E_UNSUPPORTED
-    with pytest.raises(T.TMOPError) as ei:
-        c3.set_replication(0.5, to_dev(m3.x_grid))
-    assert ei.value.status == T.TMOP_E_UNSUPPORTED
+        c3.set_combo(77, np.eye(3))                    # a 2D metric
+    assert ei.value.status == T.TMOP_E_ARG
+    with pytest.raises(ValueError):
+        c3.set_combo(302, np.eye(2))                   # a 2x2 target
 
 
 def test_newton_combo_matches_oracle():
@@ -228,27 +229,42 @@ def test_newton_combo_matches_oracle():
 
 # ----------------------------------------------------------- Section 4.3.2
 
-REPL = [  # n, p, Q, metric, gamma, seed
-    (6, 2, 4, 2, 0.4, 130),
-    (5, 3, 5, 9, 0.7, 131),
-    (4, 4, 5, 1, 0.0, 132),
-    (7, 1, 2, 77, 1.0, 133),
+REPL = [  # dim, n, p, Q, metric, gamma, seed
+    (2, 6, 2, 4, 2, 0.4, 130),
+    (2, 5, 3, 5, 9, 0.7, 131),
+    (2, 4, 4, 5, 1, 0.0, 132),
+    (2, 7, 1, 2, 77, 1.0, 133),
+    (3, 3, 2, 4, 303, 0.5, 134),
+    (3, 2, 3, 4, 302, 0.3, 135),
+    (3, 3, 1, 2, 303, 0.0, 136),
 ]
 
 
-@pytest.mark.parametrize("case", REPL, ids=lambda c: f"p{c[1]}_q{c[2]}_mu{c[3]}_g{c[4]}")
+@pytest.mark.parametrize("case", REPL, ids=lambda c: f"{c[0]}d_p{c[2]}_q{c[3]}_mu{c[4]}_g{c[5]}")
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
 def test_replication_parity(case, precision):
-    n, p, Q, metric, gamma, seed = case
+    dim, n, p, Q, metric, gamma, seed = case
     say(f"[replication] case {case} precision {precision}")
-    mesh, prob, x0, x, _ = _base(2, n, p, Q, metric, seed)
+    mesh, prob, x0, x, _ = _base(dim, n, p, Q, metric, seed)
     prob.set_replication(gamma, x0)
     A0 = prob._jac(x0, 0, mesh.n_elem)
-    tol2 = MIXED_C * EPS32 * O.Problem(2, p, Q, mesh.elem_node, 98, A0).max_condition(x)
+    # mu_98's conditioning: the oracle's metric list has it in 2D only, so a
+    # 3D problem for the bound uses mu_302 (kappa only depends on T)
+    tol2 = MIXED_C * EPS32 * O.Problem(dim, p, Q, mesh.elem_node, 98 if dim == 2 else 302, A0).max_condition(x)
     ctx = _ctx(mesh, p, Q, metric, None, precision)
     ctx.set_replication(gamma, to_dev(x0))
     v = np.random.default_rng(seed + 7).uniform(-1, 1, x.shape)
     _compare(ctx, prob, x, v, 1e-12 if precision == 0 else max(mixed_tol(prob, x), tol2), "replication")
+
+
+def test_replication_3d_keeps_initial_mesh():
+    from paper_1807_09807_amd import tmop as T
+    mesh, prob, x0, x, _ = _base(3, 3, 2, 3, 303, 141)
+    ctx = _ctx(mesh, 2, 3, 303, None, 0)
+    x0d = to_dev(x0)
+    ctx.set_replication(0.0, x0d)
+    F, md, st = ctx.energy(x0d)
+    assert st == 0 and abs(F) <= 1e-26 and float(ctx.gradient(x0d).abs().max()) <= 1e-13
 
 
 def test_replication_keeps_initial_mesh_and_rejects_inverted():
@@ -294,16 +310,18 @@ def test_newton_replication_matches_oracle():
 
 # ------------------------------------------------------------- all together
 
+@pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
-def test_all_terms_together(precision):
-    """Replication composite and displacement penalty at once, 2D Q3."""
-    mesh, prob, x0, x, _ = _base(2, 5, 3, 5, 9, 160)
+def test_all_terms_together(dim, precision):
+    """Replication composite and displacement penalty at once (2D Q3, 3D Q2)."""
+    n, p, Q, metric = (5, 3, 5, 9) if dim == 2 else (3, 2, 3, 303)
+    mesh, prob, x0, x, _ = _base(dim, n, p, Q, metric, 160)
     prob.set_replication(0.6, x0)
     prob.set_restriction(20.0, x0)
-    ctx = _ctx(mesh, 3, 5, 9, None, precision)
+    ctx = _ctx(mesh, p, Q, metric, None, precision)
     ctx.set_replication(0.6, to_dev(x0))
     ctx.set_restriction(20.0, to_dev(x0))
     A0 = prob._jac(x0, 0, mesh.n_elem)
-    tol2 = MIXED_C * EPS32 * O.Problem(2, 3, 5, mesh.elem_node, 98, A0).max_condition(x)
+    tol2 = MIXED_C * EPS32 * O.Problem(dim, p, Q, mesh.elem_node, 98 if dim == 2 else 302, A0).max_condition(x)
     v = np.random.default_rng(161).uniform(-1, 1, x.shape)
     _compare(ctx, prob, x, v, 1e-12 if precision == 0 else max(mixed_tol(prob, x), tol2), "all")
