@@ -351,9 +351,10 @@ def section4(T, torch, dev, args, w, mesh, x, v, W, log):
     the main workload: operation times with and without it, the penalty
     kernels' per-launch time in the Hessian action against the HBM peak
     (they move 3 fields per unique node: v in, out read and written), and
-    Newton with the penalty.  Second metric term (eq. 4.1, mu_77 with
-    W_2 = 0.7 h I and per-point weights) and replication composite (Section
-    4.3.2, gamma = 1/2) on a 2D workload: operation times."""
+    Newton with the penalty; the replication composite (Section 4.3.2,
+    gamma = 1/2) on the main workload.  Second metric term (eq. 4.1, mu_77
+    with W_2 = 0.7 h I and per-point weights) and replication composite on a
+    2D workload: operation times."""
     reps = max(args.steps, 5)
     us = lambda d: {k: round(t * 1e6, 2) for k, t in d.items()}
     out = {}
@@ -385,7 +386,14 @@ def section4(T, torch, dev, args, w, mesh, x, v, W, log):
                            max_displacement_over_h=float((xn - x).abs().max()) / mesh.h)
         log(f"# section 4 newton {key}: {rep['iters']} it, {rep['cg_iters']} CG, {newton[key]['wall_s']} s, "
             f"F {rep['F0']:.4e} -> {rep['F']:.4e}, max |x - x_init| / h {newton[key]['max_displacement_over_h']:.3e}")
+    # replication composite on the main workload (W_0 = A(x) per point)
+    ctx.set_restriction(0.0)
+    ctx.set_replication(0.5, x)
+    repl = op_times(torch, ctx, x, v, reps)
     ctx.close()
+    out["replication_main"] = {"workload": args.workload, "ops_us_plain": us(plain), "ops_us_replication": us(repl)}
+    log(f"# section 4 replication on {args.workload}: Hv {plain['hessian']*1e6:.1f} -> {repl['hessian']*1e6:.1f} us, "
+        f"E+G {plain['energy_gradient']*1e6:.1f} -> {repl['energy_gradient']*1e6:.1f} us")
     out["penalty"] = {"workload": args.workload, "delta": delta, "ops_us_plain": us(plain), "ops_us_penalty": us(pen),
                       "hessian_penalty_launch_us": round(t_l * 1e6, 2), "launches_per_op": per_op,
                       "algorithmic_bytes_per_element": nbytes[2], "algorithmic_GBps": round(gbps, 1),
