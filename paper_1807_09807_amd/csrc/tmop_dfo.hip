@@ -81,11 +81,13 @@ __global__ void __launch_bounds__(DfoCfg<D>::BLOCK) dfo_kernel(const DfoArgs<P, 
   const int node = a.nodes[k];
   const int tid = threadIdx.x;
   // the free components (uniform)
-  int comp[3];
+  bool fr[D];
   int n = 0;
 #pragma unroll
-  for (int c = 0; c < D; ++c)
-    if (a.mask[c * a.n_node + node] > 0.5) comp[n++] = c;
+  for (int c = 0; c < D; ++c) {
+    fr[c] = a.mask[c * a.n_node + node] > 0.5;
+    n += fr[c] ? 1 : 0;
+  }
   if (n == 0) {
     if (tid == 0) a.move[k] = -0.0;
     return;
@@ -147,16 +149,15 @@ __global__ void __launch_bounds__(DfoCfg<D>::BLOCK) dfo_kernel(const DfoArgs<P, 
     }
   }
 
-  // Q at the trial position y (free components only), the same on every lane
-  auto quality = [&](const double (&y)[3]) -> double {
+  // Q at the trial position y, the same on every lane.  The simplex
+  // vertices are full d-vectors whose fixed components stay at x_i: every
+  // simplex operation works component by component, and with at most two
+  // free components the centroid of equal values is exact, so a fixed
+  // component never moves and contributes nothing to the size test.
+  auto quality = [&](const double (&y)[D]) -> double {
     double dy[D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) dy[c] = 0.0;
-    for (int t = 0; t < n; ++t) {
-#pragma unroll
-      for (int c = 0; c < D; ++c)
-        if (comp[t] == c) dy[c] = y[t] - xi[c];
-    }
+    for (int c = 0; c < D; ++c) dy[c] = y[c] - xi[c];
     double s = 0.0, m = __builtin_huge_val();
 #pragma unroll
     for (int r = 0; r < PPL; ++r) {
@@ -182,72 +183,128 @@ __global__ void __launch_bounds__(DfoCfg<D>::BLOCK) dfo_kernel(const DfoArgs<P, 
     return m > 0.0 ? s : __builtin_huge_val();
   };
 
-  // Nelder-Mead over the n free components
-  double V[4][3], fv[4];
-  for (int v = 0; v <= n; ++v)
-    for (int t = 0; t < 3; ++t) V[v][t] = t < n ? xi[comp[t]] : 0.0;
-  for (int t = 0; t < n; ++t) V[t + 1][t] += a.step;
-  for (int v = 0; v <= n; ++v) fv[v] = quality(V[v]);
+  // Nelder-Mead over the n free components: vertices 0..n of V (static
+  // indices with guards, so the state stays in registers)
+  double V[D + 1][D], fv[D + 1];
+#pragma unroll
+  for (int v = 0; v <= D; ++v) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) V[v][c] = xi[c];
+    fv[v] = __builtin_huge_val();
+  }
+  {   // vertex t + 1 moves the t-th free component by the step
+    int t = 0;
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+      if (fr[c]) {
+        ++t;
+#pragma unroll
+        for (int v = 1; v <= D; ++v)
+          if (v == t) V[v][c] += a.step;
+      }
+  }
+#pragma unroll
+  for (int v = 0; v <= D; ++v)
+    if (v <= n) fv[v] = quality(V[v]);
   int evals = n + 1;
   while (true) {
-    // stable insertion sort by value
-    for (int i = 1; i <= n; ++i) {
-      for (int j = i; j > 0 && fv[j] < fv[j - 1]; --j) {
-        const double tf = fv[j]; fv[j] = fv[j - 1]; fv[j - 1] = tf;
-        for (int t = 0; t < 3; ++t) { const double tv = V[j][t]; V[j][t] = V[j - 1][t]; V[j - 1][t] = tv; }
-      }
-    }
+    // stable sort of vertices 0..n by value (bubble passes: swap only on <)
+#pragma unroll
+    for (int pass = 0; pass < D; ++pass)
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        if (j + 1 <= n && fv[j + 1] < fv[j]) {
+          const double tf = fv[j]; fv[j] = fv[j + 1]; fv[j + 1] = tf;
+#pragma unroll
+          for (int c = 0; c < D; ++c) { const double tv = V[j][c]; V[j][c] = V[j + 1][c]; V[j + 1][c] = tv; }
+        }
     double size = 0.0;
-    for (int v = 1; v <= n; ++v)
-      for (int t = 0; t < n; ++t) size = fmax(size, fabs(V[v][t] - V[0][t]));
+#pragma unroll
+    for (int v = 1; v <= D; ++v)
+      if (v <= n)
+#pragma unroll
+        for (int c = 0; c < D; ++c) size = fmax(size, fabs(V[v][c] - V[0][c]));
     if (size <= a.xtol || evals >= a.max_evals) break;
-    double xb[3], xr[3];
-    for (int t = 0; t < 3; ++t) {
-      double s = V[0][t];
-      for (int v = 1; v < n; ++v) s += V[v][t];
-      xb[t] = s / n;
-      xr[t] = xb[t] + (xb[t] - V[n][t]);
+    // the worst vertex, its value and the second worst value
+    double Vw[D], fw = fv[0], fw2 = fv[0];
+#pragma unroll
+    for (int c = 0; c < D; ++c) Vw[c] = V[0][c];
+#pragma unroll
+    for (int v = 1; v <= D; ++v) {
+      if (v == n) {
+        fw = fv[v];
+#pragma unroll
+        for (int c = 0; c < D; ++c) Vw[c] = V[v][c];
+      }
+      if (v == n - 1) fw2 = fv[v];
     }
-    const double fr = quality(xr);
+    double xb[D], xr[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double sum = V[0][c];
+#pragma unroll
+      for (int v = 1; v < D; ++v)
+        if (v < n) sum += V[v][c];
+      xb[c] = sum / n;
+      xr[c] = xb[c] + (xb[c] - Vw[c]);
+    }
+    double fnew, Vnew[D];
+    bool replace = true;
+    const double frv = quality(xr);
     ++evals;
-    if (fv[0] <= fr && fr < fv[n - 1]) {
-      for (int t = 0; t < 3; ++t) V[n][t] = xr[t];
-      fv[n] = fr;
-      continue;
-    }
-    if (fr < fv[0]) {   // expansion
-      double xe[3];
-      for (int t = 0; t < 3; ++t) xe[t] = xb[t] + 2.0 * (xr[t] - xb[t]);
+    if (fv[0] <= frv && frv < fw2) {
+      fnew = frv;
+#pragma unroll
+      for (int c = 0; c < D; ++c) Vnew[c] = xr[c];
+    } else if (frv < fv[0]) {   // expansion
+      double xe[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) xe[c] = xb[c] + 2.0 * (xr[c] - xb[c]);
       const double fe = quality(xe);
       ++evals;
-      const bool take_e = fe < fr;
-      for (int t = 0; t < 3; ++t) V[n][t] = take_e ? xe[t] : xr[t];
-      fv[n] = take_e ? fe : fr;
+      const bool take_e = fe < frv;
+      fnew = take_e ? fe : frv;
+#pragma unroll
+      for (int c = 0; c < D; ++c) Vnew[c] = take_e ? xe[c] : xr[c];
+    } else {                    // contraction, outside or inside
+      const bool outside = frv < fw;
+      double xc[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) xc[c] = outside ? xb[c] + 0.5 * (xr[c] - xb[c]) : xb[c] + 0.5 * (Vw[c] - xb[c]);
+      const double fc = quality(xc);
+      ++evals;
+      replace = outside ? fc <= frv : fc < fw;
+      fnew = fc;
+#pragma unroll
+      for (int c = 0; c < D; ++c) Vnew[c] = xc[c];
+    }
+    if (replace) {
+#pragma unroll
+      for (int v = 1; v <= D; ++v)
+        if (v == n) {
+          fv[v] = fnew;
+#pragma unroll
+          for (int c = 0; c < D; ++c) V[v][c] = Vnew[c];
+        }
       continue;
     }
-    double xc[3];
-    const bool outside = fr < fv[n];
-    for (int t = 0; t < 3; ++t) xc[t] = outside ? xb[t] + 0.5 * (xr[t] - xb[t]) : xb[t] + 0.5 * (V[n][t] - xb[t]);
-    const double fc = quality(xc);
-    ++evals;
-    if (outside ? fc <= fr : fc < fv[n]) {
-      for (int t = 0; t < 3; ++t) V[n][t] = xc[t];
-      fv[n] = fc;
-      continue;
-    }
-    for (int v = 1; v <= n; ++v) {   // shrink towards the best vertex
-      for (int t = 0; t < 3; ++t) V[v][t] = V[0][t] + 0.5 * (V[v][t] - V[0][t]);
-      fv[v] = quality(V[v]);
-    }
+#pragma unroll
+    for (int v = 1; v <= D; ++v)   // shrink towards the best vertex
+      if (v <= n) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) V[v][c] = V[0][c] + 0.5 * (V[v][c] - V[0][c]);
+        fv[v] = quality(V[v]);
+      }
     evals += n;
   }
   if (tid == 0) {
     double mv = 0.0;
-    for (int t = 0; t < n; ++t) {
-      const int c = comp[t];
-      mv = fmax(mv, fabs(V[0][t] - xi[c]));
-      a.x[c * a.n_node + node] = V[0][t];
-    }
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+      if (fr[c]) {
+        mv = fmax(mv, fabs(V[0][c] - xi[c]));
+        a.x[c * a.n_node + node] = V[0][c];
+      }
     a.move[k] = -mv;
   }
 }
