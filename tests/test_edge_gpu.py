@@ -121,3 +121,54 @@ def test_kernel_timing_counts_launches():
     assert torch.equal(h0, h1)
     ctx.energy(x)
     assert ctx.timing_read(0) == (0.0, 0)
+
+
+@pytest.mark.parametrize("dim,p,Q,metric", [(2, 1, 2, 2), (2, 4, 5, 9), (3, 1, 2, 303), (3, 3, 4, 302)])
+def test_single_element_section4(dim, p, Q, metric):
+    """One element with every Section 4 term at once (the replication
+    composite and the displacement penalty), against the oracle."""
+    say(f"[edge] single element + Section 4 dim={dim} p={p}")
+    mesh = meshgen.box_mesh(dim, 1, p)
+    W = np.eye(dim)
+    prob = O.Problem(dim, p, Q, mesh.elem_node, metric, W)
+    rng = np.random.default_rng(5)
+    x0 = mesh.x_grid + rng.uniform(-0.05, 0.05, mesh.x_grid.shape)
+    x = x0 + rng.uniform(-0.03, 0.03, x0.shape)
+    v = rng.uniform(-1, 1, x.shape)
+    prob.set_replication(0.3, x0)
+    prob.set_restriction(7.0, x0)
+    ctx = _ctx(mesh, Q, metric, W)
+    ctx.set_replication(0.3, to_dev(x0))
+    ctx.set_restriction(7.0, to_dev(x0))
+    F, md, st = ctx.energy(to_dev(x))
+    assert st == 0 and abs(F - prob.energy(x)[0]) <= 1e-12 * abs(prob.energy(x)[0])
+    assert rel_max_err(ctx.gradient(to_dev(x)).cpu().numpy(), prob.gradient(x)) <= 1e-12
+    assert rel_max_err(ctx.hessian_apply(to_dev(x), to_dev(v)).cpu().numpy(), prob.hessian_apply(x, v)) <= 1e-12
+    assert rel_max_err(ctx.hessian_diagonal(to_dev(x)).cpu().numpy(), prob.hessian_diagonal(x)) <= 1e-12
+
+
+def test_unused_nodes_get_zero_with_penalty():
+    """The penalty kernels leave a node no element references at zero."""
+    mesh = meshgen.box_mesh(2, 3, 2)
+    n_node = mesh.n_node + 1
+    x = np.concatenate([mesh.x_grid, np.array([[5.0], [5.0]])], axis=1)
+    x[:, :mesh.n_node] += np.random.default_rng(1).uniform(-0.01, 0.01, mesh.x_grid.shape) * (1 - mesh.fixed)
+    from paper_1807_09807_amd import tmop as T
+    ctx = T.Context(2, 2, mesh.elem_node, n_node, 4, 2, mesh.h * np.eye(2))
+    ctx.set_restriction(3.0, to_dev(x + 0.01))
+    for out in (ctx.gradient(to_dev(x)), ctx.hessian_apply(to_dev(x), to_dev(np.ones_like(x))),
+                ctx.hessian_diagonal(to_dev(x))):
+        o = out.cpu().numpy()
+        assert o[0, -1] == 0.0 and o[1, -1] == 0.0 and np.all(np.isfinite(o))
+
+
+def test_dfo_with_every_node_fixed_moves_nothing():
+    mesh = meshgen.box_mesh(2, 1, 2)
+    from paper_1807_09807_amd import tmop as T
+    fixed = np.ones((2, mesh.n_node), dtype=np.uint8)
+    ctx = T.Context(2, 2, mesh.elem_node, mesh.n_node, 3, 2, mesh.h * np.eye(2), fixed=fixed)
+    x = to_dev(mesh.x_grid + 0.01)
+    x0 = x.clone()
+    assert ctx.dfo_sweep(x) == 0.0 and torch.equal(x, x0)
+    st, rep = ctx.dfo_solve(x)
+    assert st == T.TMOP_OK and rep["sweeps"] == 1 and rep["converged"] == 1
