@@ -876,12 +876,12 @@ int install_second_term(tmop_ctx* c, int metric2, double* d_tm, double eta1, hip
 int tmop_set_combo(tmop_ctx* c, int32_t metric2, const double* W2, double eta1, double eta2, const double* eta2_q,
                    void* stream) {
   if (!c || !(eta1 >= 0.0) || !std::isfinite(eta1)) return TMOP_E_ARG;
+  if (c->d_tsize) return TMOP_E_UNSUPPORTED;             // per-point targets carry their own weights
   if (metric2 == 0) {          // back to the single term eta_1 mu
     c->metric2 = 0;
     c->base.wdetW = eta1 * c->base.detW;
     return TMOP_OK;
   }
-  if (c->d_tsize) return TMOP_E_UNSUPPORTED;
   const int d = c->dim, ts = tmat_stride(c);
   const bool metric_ok = d == 2 ? metric_2d(metric2) : (metric2 == TMOP_MU302 || metric2 == TMOP_MU303);
   if (!metric_ok || !W2 || !(eta2 >= 0.0) || !std::isfinite(eta2)) return TMOP_E_ARG;
@@ -981,14 +981,25 @@ int dfo_prepare(tmop_ctx* c) {
       c->dfo_col_off.push_back((int64_t)order.size());
     }
   }
+  auto release = [c]() {
+    for (void** p : {(void**)&c->d_dfo_nodes, (void**)&c->d_ne_off, (void**)&c->d_ne, (void**)&c->d_dfo_move}) {
+      (void)hipFree(*p);
+      *p = nullptr;
+    }
+  };
   if (hipMalloc(&c->d_dfo_nodes, order.size() * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&c->d_ne_off, off.size() * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&c->d_ne, code.size() * sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&c->d_dfo_move, c->n_node * sizeof(double)) != hipSuccess)
+      hipMalloc(&c->d_dfo_move, c->n_node * sizeof(double)) != hipSuccess) {
+    release();
     return TMOP_E_NOMEM;
-  HIP_TRY(hipMemcpy(c->d_dfo_nodes, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(c->d_ne_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(c->d_ne, code.data(), code.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  if (hipMemcpy(c->d_dfo_nodes, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_ne_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_ne, code.data(), code.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+    release();
+    return TMOP_E_HIP;
+  }
   c->dfo_ready = true;
   return TMOP_OK;
 }
