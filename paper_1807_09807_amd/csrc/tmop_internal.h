@@ -49,6 +49,11 @@ struct LaunchParams {
   double s_inv;
   double detW, detWinv;
   double wdetW;            // weight factor of a constant target: eta det W (OP_JINV: the omega it writes)
+  // displacement penalty fused into the 3D FP64 constant-target kernels (eq. 4.2)
+  bool pen;
+  const double* x0;        // x_init
+  double M1[MAXP][MAXP];   // 1D mass matrix of the quadrature
+  double kpen;             // 2 delta det W
 };
 
 // Everything one launch of the displacement-penalty kernels (eq. 4.2)

@@ -3,12 +3,14 @@
 // the instantiations compile in parallel.
 #pragma once
 
+#include <type_traits>
+
 #include "tmop_elem.h"
 #include "tmop_internal.h"
 
 namespace tmop {
 
-template <int DIM, int P, int Q, int METRIC, typename R, int OP, int TGT>
+template <int DIM, int P, int Q, int METRIC, typename R, int OP, int TGT, bool PEN = false>
 static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   using C = Cfg<DIM, P, Q, R>;
   DiagArgs<P, Q, R> a;   // the element kernels take its ElemArgs part
@@ -18,6 +20,10 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   a.tsize = lp.tsize;
   a.tmat = lp.tmat;
   a.wdetW = lp.wdetW;
+  a.x0 = lp.x0;
+  a.kpen = lp.kpen;
+  for (int i = 0; i < P; ++i)
+    for (int j = 0; j < P; ++j) a.M1[i][j] = lp.M1[i][j];
   const double gs = TGT == TGT_ISO ? lp.s_inv : 1.0;   // constant isotropic target: G carries 1/s
   for (int q = 0; q < Q; ++q) {
     a.w[q] = lp.w[q];
@@ -46,7 +52,7 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
     else hipLaunchKernelGGL((diag_kernel_2d<P, Q, METRIC, R, TGT>), dim3(g), dim3(C::BLOCK), 0, s, a);
   } else {
     const ElemArgs<P, Q, R>& ea = a;
-    if constexpr (DIM == 3) hipLaunchKernelGGL((elem_kernel_3d<P, Q, METRIC, R, OP, TGT>), dim3(g), dim3(C::BLOCK), 0, s, ea);
+    if constexpr (DIM == 3) hipLaunchKernelGGL((elem_kernel_3d<P, Q, METRIC, R, OP, TGT, PEN>), dim3(g), dim3(C::BLOCK), 0, s, ea);
     else hipLaunchKernelGGL((elem_kernel_2d<P, Q, METRIC, R, OP, TGT>), dim3(g), dim3(C::BLOCK), 0, s, ea);
   }
   return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -57,6 +63,11 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
 // there), OP_JINV for the general constant target (W = I) only.
 template <int DIM, int P, int Q, int M, typename R, int TGT>
 static int launch_op(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
+  // the displacement penalty fused into the 3D FP64 constant-target Hessian action
+  if constexpr (DIM == 3 && std::is_same<R, double>::value && (TGT == TGT_ISO || TGT == TGT_GEN) && M != 398) {
+    if (lp.pen) return op == OP_HESS ? launch_one<DIM, P, Q, M, R, OP_HESS, TGT, true>(lp, s, grid) : -1;
+  }
+  if (lp.pen) return -1;
   if (op == OP_ENERGY) return launch_one<DIM, P, Q, M, R, OP_ENERGY, TGT>(lp, s, grid);
   if (op == OP_GRAD) return launch_one<DIM, P, Q, M, R, OP_GRAD, TGT>(lp, s, grid);
   if (op == OP_HESS) return launch_one<DIM, P, Q, M, R, OP_HESS, TGT>(lp, s, grid);
