@@ -325,3 +325,19 @@ def test_all_terms_together(dim, precision):
     tol2 = MIXED_C * EPS32 * O.Problem(dim, p, Q, mesh.elem_node, 98 if dim == 2 else 302, A0).max_condition(x)
     v = np.random.default_rng(161).uniform(-1, 1, x.shape)
     _compare(ctx, prob, x, v, 1e-12 if precision == 0 else max(mixed_tol(prob, x), tol2), "all")
+
+
+def test_restriction_general_target_3d():
+    """The penalty with a general constant target W in 3D (det W weights the
+    mass matrix; the FP64 Hessian action fuses it into the element kernel)."""
+    from paper_1807_09807_amd import tmop as T
+    mesh = meshgen.box_mesh(3, 3, 2)
+    W = mesh.h * np.array([[1.0, 0.2, 0.0], [0.0, 1.1, 0.3], [0.1, 0.0, 0.9]])
+    prob = O.Problem(3, 2, 4, mesh.elem_node, 302, W)
+    x0 = meshgen.perturb(mesh, 0.08, 170, bad_elements=prob.bad_elements)
+    x = meshgen.perturb(mesh, 0.03, 171, base=x0, bad_elements=prob.bad_elements)
+    v = np.random.default_rng(172).uniform(-1, 1, x.shape)
+    prob.set_restriction(60.0, x0)
+    ctx = T.Context(3, 2, mesh.elem_node, mesh.n_node, 4, 302, W, fixed=mesh.fixed)
+    ctx.set_restriction(60.0, to_dev(x0))
+    _compare(ctx, prob, x, v, 1e-12, "3D general W + penalty")
