@@ -206,10 +206,7 @@ int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* o
   lp.tsize = tsize;
   lp.tmat = term.tmat;
   lp.pen = term.pen;
-  if (term.pen) {
-    lp.x0 = c->d_xinit;
-    lp.kpen = 2.0 * c->delta * c->base.detW;
-  }
+  if (term.pen) lp.kpen = 2.0 * c->delta * c->base.detW;
   lp.scale = scale;
   lp.x = x; lp.v = v; lp.out = out;
   lp.elem_node = conn;

@@ -72,7 +72,6 @@ struct ElemArgs {
   const double* __restrict__ tsize;      // TGT_QPS: [n_list][Q^dim] target sizes s_q (W_q = s_q I), point
                                          // index q0 + Q q1 (+ Q^2 q2), in the order of elem_node
   const double* __restrict__ tmat;       // TGT_MAT: [n_list][Q^dim][dim^2 + 1] W_q^{-1} (row-major) and omega_q
-  const double* __restrict__ x0;         // PEN: x_init of the displacement penalty (eq. 4.2), [dim][n_node]
   int64_t n_node;
   int32_t n_list;
   R B[Q][P];
@@ -491,30 +490,25 @@ __device__ __forceinline__ void fwd_3d_areas(const ElemArgs<P, Q, R>& a, const R
   }
 }
 
-// Displacement penalty of eq. 4.2 fused into an element kernel (PEN, FP64,
-// constant target): with det W constant the target-weighted element mass
-// matrix is det W (M1 x M1 x M1), M1 the 1D mass matrix of the quadrature,
-// so M_E u is three P x P passes over the element's nodes.  Runs between the
-// point loop and the transposed passes, in the LDS the forward passes leave
-// free and while the point loop's registers are dead, on u = x - x_init
-// (energy, gradient) or v (Hessian action), re-read from global memory;
-// lane (i0, i1) gets w[c][i2] = (M1 x M1 x M1 u)[c][i0][i1][i2] and its share
-// of u . M1 x M1 x M1 u.
+// Displacement penalty of eq. 4.2 fused into the 3D Hessian action (PEN,
+// FP64, constant target): with det W constant the target-weighted element
+// mass matrix is det W (M1 x M1 x M1), M1 the 1D mass matrix of the
+// quadrature, so M_E v is three P x P passes over the element's nodes.  Runs
+// between the point loop and the transposed passes, in the LDS the forward
+// passes leave free and while the point loop's registers are dead, on v
+// re-read from global memory; lane (i0, i1) gets
+// w[c][i2] = (M1 x M1 x M1 v)[c][i0][i1][i2].
 template <int P, int Q>
-__device__ __forceinline__ double penalty_pass_3d(const ElemArgs<P, Q, double>& a, const double* __restrict__ f,
-                                                  const double* __restrict__ f0, const int (&node)[P], bool p1,
-                                                  int ta, int tb, double* __restrict__ s, double (&w)[3][P]) {
+__device__ __forceinline__ void penalty_pass_3d(const ElemArgs<P, Q, double>& a, const double* __restrict__ f,
+                                                const int (&node)[P], bool p1, int ta, int tb,
+                                                double* __restrict__ s, double (&w)[3][P]) {
   auto t = [](int c, int i0, int i1, int i2) { return ((c * P + i2) * P + i1) * P + i0; };
   double u[3][P];
-  double part = 0.0;
   if (p1) {   // z, lane (i0, i1)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int i2 = 0; i2 < P; ++i2) {
-        const int64_t j = c * a.n_node + node[i2];
-        u[c][i2] = f0 ? f[j] - f0[j] : f[j];
-      }
+      for (int i2 = 0; i2 < P; ++i2) u[c][i2] = f[c * a.n_node + node[i2]];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -554,19 +548,15 @@ __device__ __forceinline__ double penalty_pass_3d(const ElemArgs<P, Q, double>& 
 #pragma unroll
         for (int j0 = 0; j0 < P; ++j0) v += a.M1[ta][j0] * s[t(c, j0, tb, i2)];
         w[c][i2] = v;
-        part += u[c][i2] * v;
       }
   }
-  return part;
 }
 
 template <int P, int Q, int METRIC, typename R, int OP, int TGT, bool PEN = false>
 __global__ void __launch_bounds__((Cfg<3, P, Q, R>::BLOCK))
 elem_kernel_3d(const ElemArgs<P, Q, R> a) {
-  static_assert(!PEN || (sizeof(R) == 8 && (OP == OP_ENERGY || OP == OP_GRAD || OP == OP_HESS || OP == OP_EG) &&
-                         (TGT == TGT_ISO || TGT == TGT_GEN)),
-                "the fused penalty is FP64, constant-target, energy / gradient / Hessian action");
-  // (the host launches the fused form for the Hessian action only)
+  static_assert(!PEN || (sizeof(R) == 8 && OP == OP_HESS && (TGT == TGT_ISO || TGT == TGT_GEN)),
+                "the fused penalty is the FP64 constant-target Hessian action");
   using C = Cfg<3, P, Q, R>;
   using L = Lds3<P, Q>;
   constexpr bool ISO = TGT == TGT_ISO || TGT == TGT_QPS;
@@ -727,22 +717,17 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
       }
     }
   };
-  if constexpr (PEN) {
+  if constexpr (PEN) {   // the penalty's share 2 delta det W (M1 x M1 x M1 v) joins the old values
     __syncthreads();   // the forward data is dead
     double w[3][P];
-    const double part = penalty_pass_3d<P, Q>(a, OP == OP_HESS ? a.v : a.x, OP == OP_HESS ? nullptr : a.x0, node,
-                                              p1, ta, tb, s, w);
-    if constexpr (!ENERGY_LIKE) {
-      load_old();
-      const double kp = a.kpen * (OP == OP_GRAD && a.scale ? *a.scale : 1.0);
-      if (active && p1) {
+    penalty_pass_3d<P, Q>(a, a.v, node, p1, ta, tb, s, w);
+    load_old();
+    if (active && p1) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
-          for (int i2 = 0; i2 < P; ++i2) old[c][i2] += kp * w[c][i2];
-      }
+        for (int i2 = 0; i2 < P; ++i2) old[c][i2] += a.kpen * w[c][i2];
     }
-    if constexpr (OP == OP_ENERGY || OP == OP_EG) acc += 0.5 * a.kpen * part;
   }
   if constexpr (OP == OP_ENERGY || OP == OP_EG || OP == OP_SIZE || OP == OP_JINV) {
     if (!active) { acc = 0.0; mind = __builtin_huge_val(); }

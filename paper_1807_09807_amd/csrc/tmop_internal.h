@@ -49,9 +49,8 @@ struct LaunchParams {
   double s_inv;
   double detW, detWinv;
   double wdetW;            // weight factor of a constant target: eta det W (OP_JINV: the omega it writes)
-  // displacement penalty fused into the 3D FP64 constant-target kernels (eq. 4.2)
+  // displacement penalty fused into the 3D FP64 constant-target Hessian action (eq. 4.2)
   bool pen;
-  const double* x0;        // x_init
   double M1[MAXP][MAXP];   // 1D mass matrix of the quadrature
   double kpen;             // 2 delta det W
 };

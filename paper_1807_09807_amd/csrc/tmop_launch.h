@@ -20,7 +20,6 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   a.tsize = lp.tsize;
   a.tmat = lp.tmat;
   a.wdetW = lp.wdetW;
-  a.x0 = lp.x0;
   a.kpen = lp.kpen;
   for (int i = 0; i < P; ++i)
     for (int j = 0; j < P; ++j) a.M1[i][j] = lp.M1[i][j];
