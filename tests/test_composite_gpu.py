@@ -341,3 +341,18 @@ def test_restriction_general_target_3d():
     ctx = T.Context(3, 2, mesh.elem_node, mesh.n_node, 4, 302, W, fixed=mesh.fixed)
     ctx.set_restriction(60.0, to_dev(x0))
     _compare(ctx, prob, x, v, 1e-12, "3D general W + penalty")
+
+
+def test_fused_penalty_bitwise_deterministic():
+    """The FP64 3D Hessian action with the penalty fused into the element
+    kernel keeps the coloured scatter's bitwise reproducibility, and so do
+    the separate penalty kernels of the other operations."""
+    from paper_1807_09807_amd import tmop as T
+    mesh, prob, x0, x, _ = _base(3, 3, 2, 4, 303, 180)
+    ctx = _ctx(mesh, 2, 4, 303, None, T.TMOP_FP64)
+    ctx.set_restriction(40.0, to_dev(x0))
+    xd, vd = to_dev(x), to_dev(np.random.default_rng(181).uniform(-1, 1, x.shape))
+    assert torch.equal(ctx.hessian_apply(xd, vd), ctx.hessian_apply(xd, vd))
+    assert torch.equal(ctx.gradient(xd), ctx.gradient(xd))
+    assert torch.equal(ctx.hessian_diagonal(xd), ctx.hessian_diagonal(xd))
+    assert ctx.energy(xd) == ctx.energy(xd)
