@@ -496,7 +496,7 @@ def workload_summary(w, mesh, results):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU per process and has no multi-GPU path; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_1807_09807_amd import tmop as T
