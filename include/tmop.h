@@ -257,7 +257,10 @@ int tmop_set_restriction(tmop_ctx *ctx, double delta, const double *x_init, void
  * and every eta2_q finite and >= 0 (else TMOP_E_ARG).  metric2: a metric of
  * the context's dimension; 0 removes the second term and keeps eta1.
  * Contexts with a constant target only (else TMOP_E_UNSUPPORTED).  Replaces
- * an earlier second term or replication.  Syncs. */
+ * an earlier second term or replication; after TMOP_E_NOMEM or TMOP_E_HIP
+ * the earlier second term may be gone.  The device keeps omega_q per point (two
+ * copies, element and colour order) and W2^-1 in the kernel arguments.
+ * Syncs. */
 int tmop_set_combo(tmop_ctx *ctx, int32_t metric2, const double *W2, double eta1, double eta2,
                    const double *eta2_q, void *stream);
 
@@ -270,7 +273,8 @@ int tmop_set_combo(tmop_ctx *ctx, int32_t metric2, const double *W2, double eta1
  * point).  TMOP_E_TARGET (context unchanged) if det A(x_init) <= 0 at a
  * point.  mu_98 = |T - I|^2 / tau for the context's dimension.  Contexts
  * with a constant target only (else TMOP_E_UNSUPPORTED).  Replaces an
- * earlier second term.  Syncs. */
+ * earlier second term; after TMOP_E_NOMEM or TMOP_E_HIP the earlier second
+ * term may be gone.  Syncs. */
 int tmop_set_replication(tmop_ctx *ctx, double gamma, const double *x_init, void *stream);
 
 /* F and min det A as tmop_energy (eq. 2.4), and g = dF/dx as tmop_gradient

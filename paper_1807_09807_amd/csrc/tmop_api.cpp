@@ -171,8 +171,9 @@ void timing_end(tmop_ctx* c, int r, hipStream_t s, tmop_ctx::TimedLaunch& tl) {
   }
 }
 
-// Values per point of the second term's data: W^{-1} (row-major) and omega.
-int tmat_stride(const tmop_ctx* c) { return c->dim * c->dim + 1; }
+// Values per point of the second term's data: W^{-1} (row-major) and omega,
+// or omega alone when the term's target is constant.
+int tmat_stride(const tmop_ctx* c) { return c->tm_stride; }
 
 // The metric term a launch evaluates: the primary one, or the second term
 // of a composite objective (its metric and per-point targets).
@@ -205,6 +206,12 @@ int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* o
   lp.first = first;
   lp.tsize = tsize;
   lp.tmat = term.tmat;
+  if (term.tmat) {
+    lp.tms = c->tm_stride;
+    if (c->tm_stride == 1)   // constant second target: its W^{-1} rides in the kernel arguments
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) lp.Winv[i][j] = c->W2inv[i][j];
+  }
   lp.pen = term.pen;
   if (term.pen) lp.kpen = 2.0 * c->delta * c->base.detW;
   lp.scale = scale;
@@ -872,22 +879,34 @@ bool metric_2d(int m) {
          m == TMOP_MU98;
 }
 
-// Installs per-point second-term data (element order, device) as the
-// context's second metric term: its colour-order copy, then the switch.
-int install_second_term(tmop_ctx* c, int metric2, double* d_tm, double eta1, hipStream_t s) {
-  const int ts = tmat_stride(c);
+// Installs per-point second-term data (element order, device; ts values
+// per point) as the context's second metric term: its colour-order copy,
+// then the switch.
+int install_second_term(tmop_ctx* c, int metric2, double* d_tm, int ts, double eta1, hipStream_t s) {
+  if (c->d_tmat_col && ts != c->tm_stride) {   // the colour-order copy has another size
+    if (hipStreamSynchronize(s) != hipSuccess) {
+      (void)hipFree(d_tm);
+      return TMOP_E_HIP;
+    }
+    c->metric2 = 0;
+    (void)hipFree(c->d_tmat_col);
+    c->d_tmat_col = nullptr;
+  }
   if (!c->d_tmat_col && hipMalloc(&c->d_tmat_col, (size_t)c->n_elem * c->nq * ts * sizeof(double)) != hipSuccess) {
     c->d_tmat_col = nullptr;
+    c->metric2 = 0;
     (void)hipFree(d_tm);
     return TMOP_E_NOMEM;
   }
   if (gather_rows(d_tm, c->d_colors, c->n_elem, c->nq * ts, c->d_tmat_col, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
+    c->metric2 = 0;   // the colour-order copy may be half overwritten
     (void)hipFree(d_tm);
     return TMOP_E_HIP;
   }
   (void)hipFree(c->d_tmat);
   c->d_tmat = d_tm;
+  c->tm_stride = ts;
   c->metric2 = metric2;
   c->base.wdetW = eta1 * c->base.detW;
   return TMOP_OK;
@@ -904,7 +923,7 @@ int tmop_set_combo(tmop_ctx* c, int32_t metric2, const double* W2, double eta1, 
     c->base.wdetW = eta1 * c->base.detW;
     return TMOP_OK;
   }
-  const int d = c->dim, ts = tmat_stride(c);
+  const int d = c->dim;
   const bool metric_ok = d == 2 ? metric_2d(metric2) : (metric2 == TMOP_MU302 || metric2 == TMOP_MU303);
   if (!metric_ok || !W2 || !(eta2 >= 0.0) || !std::isfinite(eta2)) return TMOP_E_ARG;
   const double det2 = det3(W2, d);
@@ -913,15 +932,9 @@ int tmop_set_combo(tmop_ctx* c, int32_t metric2, const double* W2, double eta1, 
   if (eta2_q)
     for (int64_t k = 0; k < n; ++k)
       if (!(eta2_q[k] >= 0.0) || !std::isfinite(eta2_q[k])) return TMOP_E_ARG;
-  double Wi[3][3];
-  inv3(W2, d, Wi);
-  std::vector<double> tm((size_t)n * ts);
-  for (int64_t k = 0; k < n; ++k) {
-    double* t = &tm[(size_t)k * ts];
-    for (int i = 0; i < d; ++i)
-      for (int j = 0; j < d; ++j) t[d * i + j] = Wi[i][j];
-    t[d * d] = eta2 * (eta2_q ? eta2_q[k] : 1.0) * det2;
-  }
+  // W2 is constant: per point only its weight omega_q = eta_2 eta_2(q) det W2
+  std::vector<double> tm((size_t)n);
+  for (int64_t k = 0; k < n; ++k) tm[(size_t)k] = eta2 * (eta2_q ? eta2_q[k] : 1.0) * det2;
   hipStream_t s = (hipStream_t)stream;
   double* d_tm = nullptr;
   if (hipMalloc(&d_tm, tm.size() * sizeof(double)) != hipSuccess) return TMOP_E_NOMEM;
@@ -929,7 +942,14 @@ int tmop_set_combo(tmop_ctx* c, int32_t metric2, const double* W2, double eta1, 
     (void)hipFree(d_tm);
     return TMOP_E_HIP;
   }
-  return install_second_term(c, metric2, d_tm, eta1, s);
+  const int r = install_second_term(c, metric2, d_tm, 1, eta1, s);
+  if (r == TMOP_OK) {
+    double Wi[3][3];
+    inv3(W2, d, Wi);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) c->W2inv[i][j] = i < d && j < d ? Wi[i][j] : 0.0;
+  }
+  return r;
 }
 
 int tmop_set_replication(tmop_ctx* c, double gamma, const double* x_init, void* stream) {
@@ -937,8 +957,8 @@ int tmop_set_replication(tmop_ctx* c, double gamma, const double* x_init, void* 
   if (c->d_tsize) return TMOP_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   double* d_tm = nullptr;
-  if (hipMalloc(&d_tm, (size_t)c->n_elem * c->nq * tmat_stride(c) * sizeof(double)) != hipSuccess)
-    return TMOP_E_NOMEM;
+  const int ts = c->dim * c->dim + 1;
+  if (hipMalloc(&d_tm, (size_t)c->n_elem * c->nq * ts * sizeof(double)) != hipSuccess) return TMOP_E_NOMEM;
   // W_0 = A(x_init) at every point; both parts weigh with the primary det W
   int grid = 0;
   int r = elem_launch(c, OP_JINV, x_init, nullptr, d_tm, c->d_elem_node, nullptr, c->n_elem, s, &grid, nullptr, 0,
@@ -954,7 +974,7 @@ int tmop_set_replication(tmop_ctx* c, double gamma, const double* x_init, void* 
     (void)hipFree(d_tm);
     return r;
   }
-  return install_second_term(c, c->dim == 2 ? TMOP_MU98 : MU98_3D, d_tm, gamma, s);
+  return install_second_term(c, c->dim == 2 ? TMOP_MU98 : MU98_3D, d_tm, ts, gamma, s);
 }
 
 namespace {

@@ -71,7 +71,9 @@ struct ElemArgs {
   const double* __restrict__ scale;      // OP_GRAD: optional device scalar multiplying g (nullptr = 1)
   const double* __restrict__ tsize;      // TGT_QPS: [n_list][Q^dim] target sizes s_q (W_q = s_q I), point
                                          // index q0 + Q q1 (+ Q^2 q2), in the order of elem_node
-  const double* __restrict__ tmat;       // TGT_MAT: [n_list][Q^dim][dim^2 + 1] W_q^{-1} (row-major) and omega_q
+  const double* __restrict__ tmat;       // TGT_MAT: [n_list][Q^dim][tms] W_q^{-1} (row-major) and omega_q,
+                                         // or omega_q alone (tms = 1, W_q^{-1} = Winv for every point)
+  int tms;
   int64_t n_node;
   int32_t n_list;
   R B[Q][P];
@@ -229,33 +231,33 @@ __device__ __forceinline__ void stress(const R (&M)[D][D], const R (&Wi)[3][3], 
 
 enum { TGT_GEN = 0, TGT_ISO = 1, TGT_QPS = 2, TGT_MAT = 3 };
 
-// TGT_MAT: this point's W^{-1} (in the arithmetic type and in FP64) and weight
-template <typename R>
-__device__ __forceinline__ double load_point_target2(const double* __restrict__ tm, R (&Wi)[3][3],
-                                                     double (&Wid)[3][3]) {
+// TGT_MAT: point q0's W^{-1} (in the arithmetic type and in FP64) and its
+// weight, from the lane's row tm of per-point data: W^{-1} row-major and
+// omega (a.tms = D^2 + 1 values per point), or omega alone (a.tms = 1) with
+// the constant W^{-1} of the kernel arguments.
+template <int D, typename R, typename Args>
+__device__ __forceinline__ double load_point_target(const Args& a, const double* __restrict__ tm, int q0,
+                                                    R (&Wi)[3][3], double (&Wid)[3][3]) {
+  if (a.tms == 1) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        Wid[i][j] = a.Winvd[i][j];
+        Wi[i][j] = a.Winv[i][j];
+      }
+    return tm[q0];
+  }
+  const double* t = tm + (D * D + 1) * q0;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) Wid[i][j] = 0.0;
-  Wid[0][0] = tm[0]; Wid[0][1] = tm[1]; Wid[1][0] = tm[2]; Wid[1][1] = tm[3];
+    for (int j = 0; j < 3; ++j) Wid[i][j] = i < D && j < D ? t[D * i + j] : 0.0;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) Wi[i][j] = (R)Wid[i][j];
-  return tm[4];
-}
-
-template <typename R>
-__device__ __forceinline__ double load_point_target3(const double* __restrict__ tm, R (&Wi)[3][3],
-                                                     double (&Wid)[3][3]) {
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      Wid[i][j] = tm[3 * i + j];
-      Wi[i][j] = (R)Wid[i][j];
-    }
-  return tm[9];
+  return t[D * D];
 }
 
 // Per-point kernel of the operations.  Given A (and dA) -- already divided
@@ -632,7 +634,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
-    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb) * 10 : nullptr;
+    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb) * a.tms : nullptr;
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[3][3], dA[3][3];
@@ -665,7 +667,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
       if constexpr (TGT == TGT_MAT) {
         R Wi[3][3];
         double Wid[3][3];
-        wdet *= load_point_target3<R>(tm + 10 * q0, Wi, Wid);
+        wdet *= load_point_target<3, R>(a, tm, q0, Wi, Wid);
         kY = wdet;
         point_op<3, METRIC, R, OP, false>(Wi, Wid, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
       } else {
@@ -959,7 +961,7 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
-    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q) + Q * ta) * 5 : nullptr;
+    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q) + Q * ta) * a.tms : nullptr;
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[2][2], dA[2][2];
@@ -984,7 +986,7 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
       if constexpr (TGT == TGT_MAT) {
         R Wi[3][3];
         double Wid[3][3];
-        wdet *= load_point_target2<R>(tm + 5 * q0, Wi, Wid);
+        wdet *= load_point_target<2, R>(a, tm, q0, Wi, Wid);
         kY = wdet;
         point_op<2, METRIC, R, OP, false>(Wi, Wid, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
       } else {
@@ -1190,7 +1192,7 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
-    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb) * 10 : nullptr;
+    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb) * a.tms : nullptr;
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[3][3];
@@ -1219,7 +1221,7 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
       if constexpr (TGT == TGT_MAT) {
         R Wi[3][3];
         double Wid[3][3];
-        kK *= load_point_target3<R>(tm + 10 * q0, Wi, Wid);
+        kK *= load_point_target<3, R>(a, tm, q0, Wi, Wid);
         right_mul<3, R, false>(A, Wi, T);
         mu_second_rows<METRIC, R>(T, (R)kK, K);
         target_congruence<3, R>(Wi, K);
@@ -1355,7 +1357,7 @@ diag_kernel_2d(const DiagArgs<P, Q, R> a) {
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
-    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q) + Q * ta) * 5 : nullptr;
+    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q) + Q * ta) * a.tms : nullptr;
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[2][2];
@@ -1379,7 +1381,7 @@ diag_kernel_2d(const DiagArgs<P, Q, R> a) {
       if constexpr (TGT == TGT_MAT) {
         R Wi[3][3];
         double Wid[3][3];
-        kK *= load_point_target2<R>(tm + 5 * q0, Wi, Wid);
+        kK *= load_point_target<2, R>(a, tm, q0, Wi, Wid);
         right_mul<2, R, false>(A, Wi, T);
         mu_second_rows<METRIC, R>(T, (R)kK, K);
         target_congruence<2, R>(Wi, K);

@@ -38,8 +38,9 @@ struct LaunchParams {
   double* part_min;        // energy partials: minima of det A
   const double* scale;     // gradient: optional device scalar factor
   const double* tsize;     // per-point isotropic target sizes (in the order of elem_node), or nullptr
-  const double* tmat;      // per-point targets [n_list][Q^dim][dim^2 + 1]: W^{-1} row-major and the
-                           // weight omega_q (the term is sum_q w_q omega_q mu(A W_q^{-1})), or nullptr
+  const double* tmat;      // per-point targets [n_list][Q^dim][tms]: W^{-1} row-major and the weight
+                           // omega_q (the term is sum_q w_q omega_q mu(A W_q^{-1})), or nullptr
+  int tms;                 // values per point of tmat: dim^2 + 1, or 1 (omega_q alone, W^{-1} = Winv)
   double B[MAXQ][MAXP];
   double G[MAXQ][MAXP];
   double w[MAXQ];
@@ -167,7 +168,10 @@ struct tmop_ctx {
   int64_t part_cap = 0;                // partials per kind (3 n_elem + 16: up to three terms)
   // Section 4 terms
   int metric2 = 0;                     // second metric term (0: none)
-  double* d_tmat = nullptr;            // its per-point data [n_elem][nq][dim^2 + 1], element order
+  int tm_stride = 0;                   // values per point of that data: dim^2 + 1 (W_q^{-1}, omega_q),
+                                       // or 1 (omega_q alone, with the constant W2^{-1} below)
+  double W2inv[3][3] = {};
+  double* d_tmat = nullptr;            // its per-point data [n_elem][nq][tm_stride], element order
   double* d_tmat_col = nullptr;        // the same in colour order
   double delta = 0.0;                  // displacement penalty weight (eq. 4.2; 0: none)
   double* d_xinit = nullptr;           // its x_init [dim][n_node]

@@ -19,6 +19,7 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   a.n_node = lp.n_node; a.n_list = lp.n_list;
   a.tsize = lp.tsize;
   a.tmat = lp.tmat;
+  a.tms = lp.tms;
   a.wdetW = lp.wdetW;
   a.kpen = lp.kpen;
   for (int i = 0; i < P; ++i)

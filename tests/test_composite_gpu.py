@@ -356,3 +356,28 @@ def test_fused_penalty_bitwise_deterministic():
     assert torch.equal(ctx.gradient(xd), ctx.gradient(xd))
     assert torch.equal(ctx.hessian_diagonal(xd), ctx.hessian_diagonal(xd))
     assert ctx.energy(xd) == ctx.energy(xd)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_second_term_switches(dim):
+    """One context through combo -> replication -> combo -> none: the
+    combo keeps its weight per point (W2 constant), the replication
+    W_0^{-1} and its weight, so the library re-sizes its per-point data at
+    each switch; every state matches the oracle's."""
+    case = COMBO[0] if dim == 2 else COMBO[4]
+    d, n, p, Q, m1, m2, W2s, eta1, eta2, pp, seed = case
+    say(f"[combo] switches {dim}D")
+    mesh, prob, x0, x, W2, eq, _ = _combo(case)
+    ctx = _ctx(mesh, p, Q, m1, None, 0)
+    v = np.random.default_rng(seed + 7).uniform(-1, 1, x.shape)
+    ctx.set_combo(m2, W2, eta1, eta2, eq)
+    _compare(ctx, prob, x, v, 1e-12, "combo")
+    rep = O.Problem(dim, p, Q, mesh.elem_node, m1, mesh.h * np.eye(dim))
+    rep.set_replication(0.4, x0)
+    ctx.set_replication(0.4, to_dev(x0))
+    _compare(ctx, rep, x, v, 1e-12, "then replication")
+    ctx.set_combo(m2, W2, eta1, eta2, eq)
+    _compare(ctx, prob, x, v, 1e-12, "combo again")
+    ctx.set_combo(0, eta1=1.0)
+    plain = O.Problem(dim, p, Q, mesh.elem_node, m1, mesh.h * np.eye(dim))
+    _compare(ctx, plain, x, v, 1e-12, "none")
