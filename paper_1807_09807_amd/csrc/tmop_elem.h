@@ -14,8 +14,9 @@
 // Targets (template parameter TGT): a constant general W (TGT_GEN), a
 // constant isotropic W = s I (TGT_ISO), an isotropic W_q = s_q I given
 // per quadrature point (TGT_QPS, Section 3.1: W may differ at every point),
-// or a general W_q with its own weight omega_q per point (TGT_MAT: the
-// second term of a composite objective, Section 4.2 and 4.3.2).
+// a general W_q with its own weight omega_q per point (TGT_MAT: the
+// replication composite, Section 4.3.2), or a constant general W with a
+// weight omega_q per point (TGT_CW: the second term of eq. 4.1).
 //
 // The Jacobian A = sum_i x_i (grad w_i)^T (eq. 2.2) of a tensor-product
 // element is computed by sum factorization: one 1D contraction per
@@ -71,9 +72,8 @@ struct ElemArgs {
   const double* __restrict__ scale;      // OP_GRAD: optional device scalar multiplying g (nullptr = 1)
   const double* __restrict__ tsize;      // TGT_QPS: [n_list][Q^dim] target sizes s_q (W_q = s_q I), point
                                          // index q0 + Q q1 (+ Q^2 q2), in the order of elem_node
-  const double* __restrict__ tmat;       // TGT_MAT: [n_list][Q^dim][tms] W_q^{-1} (row-major) and omega_q,
-                                         // or omega_q alone (tms = 1, W_q^{-1} = Winv for every point)
-  int tms;
+  const double* __restrict__ tmat;       // TGT_MAT: [n_list][Q^dim][dim^2 + 1] W_q^{-1} (row-major) and omega_q;
+                                         // TGT_CW: [n_list][Q^dim] omega_q (W^{-1} = Winv)
   int64_t n_node;
   int32_t n_list;
   R B[Q][P];
@@ -229,35 +229,35 @@ __device__ __forceinline__ void stress(const R (&M)[D][D], const R (&Wi)[3][3], 
     }
 }
 
-enum { TGT_GEN = 0, TGT_ISO = 1, TGT_QPS = 2, TGT_MAT = 3 };
+enum { TGT_GEN = 0, TGT_ISO = 1, TGT_QPS = 2, TGT_MAT = 3, TGT_CW = 4 };
 
-// TGT_MAT: point q0's W^{-1} (in the arithmetic type and in FP64) and its
-// weight, from the lane's row tm of per-point data: W^{-1} row-major and
-// omega (a.tms = D^2 + 1 values per point), or omega alone (a.tms = 1) with
-// the constant W^{-1} of the kernel arguments.
-template <int D, typename R, typename Args>
-__device__ __forceinline__ double load_point_target(const Args& a, const double* __restrict__ tm, int q0,
-                                                    R (&Wi)[3][3], double (&Wid)[3][3]) {
-  if (a.tms == 1) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        Wid[i][j] = a.Winvd[i][j];
-        Wi[i][j] = a.Winv[i][j];
-      }
-    return tm[q0];
-  }
-  const double* t = tm + (D * D + 1) * q0;
+// TGT_MAT: this point's W^{-1} (in the arithmetic type and in FP64) and weight
+template <typename R>
+__device__ __forceinline__ double load_point_target2(const double* __restrict__ tm, R (&Wi)[3][3],
+                                                     double (&Wid)[3][3]) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) Wid[i][j] = i < D && j < D ? t[D * i + j] : 0.0;
+    for (int j = 0; j < 3; ++j) Wid[i][j] = 0.0;
+  Wid[0][0] = tm[0]; Wid[0][1] = tm[1]; Wid[1][0] = tm[2]; Wid[1][1] = tm[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) Wi[i][j] = (R)Wid[i][j];
-  return t[D * D];
+  return tm[4];
+}
+
+template <typename R>
+__device__ __forceinline__ double load_point_target3(const double* __restrict__ tm, R (&Wi)[3][3],
+                                                     double (&Wid)[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Wid[i][j] = tm[3 * i + j];
+      Wi[i][j] = (R)Wid[i][j];
+    }
+  return tm[9];
 }
 
 // Per-point kernel of the operations.  Given A (and dA) -- already divided
@@ -627,14 +627,16 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
 
   if (tb < Q) {
     const double w12 =
-        a.w[ta] * a.w[tb] * (TGT == TGT_QPS || TGT == TGT_MAT ? 1.0 : a.wdetW) * (a.scale ? *a.scale : 1.0);
+        a.w[ta] * a.w[tb] * (TGT >= TGT_QPS ? 1.0 : a.wdetW) * (a.scale ? *a.scale : 1.0);
     double sq[Q];   // this lane's row of target sizes (q0 = 0..Q-1)
     if constexpr (TGT == TGT_QPS) {
       const double* ts = a.tsize + (int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb;
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
-    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb) * a.tms : nullptr;
+    const double* tm = TGT == TGT_MAT || TGT == TGT_CW
+                           ? a.tmat + ((int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb) * (TGT == TGT_MAT ? 10 : 1)
+                           : nullptr;
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[3][3], dA[3][3];
@@ -667,10 +669,14 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
       if constexpr (TGT == TGT_MAT) {
         R Wi[3][3];
         double Wid[3][3];
-        wdet *= load_point_target<3, R>(a, tm, q0, Wi, Wid);
+        wdet *= load_point_target3<R>(tm + 10 * q0, Wi, Wid);
         kY = wdet;
         point_op<3, METRIC, R, OP, false>(Wi, Wid, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
       } else {
+        if constexpr (TGT == TGT_CW) {
+          wdet *= tm[q0];
+          kY = wdet;
+        }
         point_op<3, METRIC, R, OP, ISO>(a.Winv, a.Winvd, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
       }
       if constexpr (OP == OP_SIZE) {
@@ -954,14 +960,15 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
       for (int i0 = 0; i0 < P; ++i0) Racc[tt][c][i0] = 0;
 
   if (ta < Q) {   // lane q1 = ta
-    const double w1 = a.w[ta] * (TGT == TGT_QPS || TGT == TGT_MAT ? 1.0 : a.wdetW) * (a.scale ? *a.scale : 1.0);
+    const double w1 = a.w[ta] * (TGT >= TGT_QPS ? 1.0 : a.wdetW) * (a.scale ? *a.scale : 1.0);
     double sq[Q];   // this lane's row of target sizes
     if constexpr (TGT == TGT_QPS) {
       const double* ts = a.tsize + (int64_t)e * (Q * Q) + Q * ta;
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
-    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q) + Q * ta) * a.tms : nullptr;
+    const double* tm =
+        TGT == TGT_MAT || TGT == TGT_CW ? a.tmat + ((int64_t)e * (Q * Q) + Q * ta) * (TGT == TGT_MAT ? 5 : 1) : nullptr;
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[2][2], dA[2][2];
@@ -986,10 +993,14 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
       if constexpr (TGT == TGT_MAT) {
         R Wi[3][3];
         double Wid[3][3];
-        wdet *= load_point_target<2, R>(a, tm, q0, Wi, Wid);
+        wdet *= load_point_target2<R>(tm + 5 * q0, Wi, Wid);
         kY = wdet;
         point_op<2, METRIC, R, OP, false>(Wi, Wid, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
       } else {
+        if constexpr (TGT == TGT_CW) {
+          wdet *= tm[q0];
+          kY = wdet;
+        }
         point_op<2, METRIC, R, OP, ISO>(a.Winv, a.Winvd, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
       }
       if constexpr (OP == OP_SIZE) {
@@ -1185,14 +1196,16 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
 #pragma unroll
       for (int i0 = 0; i0 < P; ++i0) Rd[pr][c][i0] = 0;
   if (tb < Q) {
-    const double w12 = a.w[ta] * a.w[tb] * (TGT == TGT_QPS || TGT == TGT_MAT ? 1.0 : a.wdetW);
+    const double w12 = a.w[ta] * a.w[tb] * (TGT >= TGT_QPS ? 1.0 : a.wdetW);
     double sq[Q];
     if constexpr (TGT == TGT_QPS) {
       const double* ts = a.tsize + (int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb;
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
-    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb) * a.tms : nullptr;
+    const double* tm = TGT == TGT_MAT || TGT == TGT_CW
+                           ? a.tmat + ((int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb) * (TGT == TGT_MAT ? 10 : 1)
+                           : nullptr;
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[3][3];
@@ -1221,11 +1234,12 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
       if constexpr (TGT == TGT_MAT) {
         R Wi[3][3];
         double Wid[3][3];
-        kK *= load_point_target<3, R>(a, tm, q0, Wi, Wid);
+        kK *= load_point_target3<R>(tm + 10 * q0, Wi, Wid);
         right_mul<3, R, false>(A, Wi, T);
         mu_second_rows<METRIC, R>(T, (R)kK, K);
         target_congruence<3, R>(Wi, K);
       } else {
+        if constexpr (TGT == TGT_CW) kK *= tm[q0];
         right_mul<3, R, ISO>(A, a.Winv, T);
         mu_second_rows<METRIC, R>(T, (R)kK, K);
         if constexpr (!ISO) target_congruence<3, R>(a.Winv, K);
@@ -1350,14 +1364,15 @@ diag_kernel_2d(const DiagArgs<P, Q, R> a) {
 #pragma unroll
       for (int i0 = 0; i0 < P; ++i0) Rd[pr][c][i0] = 0;
   if (ta < Q) {   // lane q1 = ta
-    const double w1 = a.w[ta] * (TGT == TGT_QPS || TGT == TGT_MAT ? 1.0 : a.wdetW);
+    const double w1 = a.w[ta] * (TGT >= TGT_QPS ? 1.0 : a.wdetW);
     double sq[Q];
     if constexpr (TGT == TGT_QPS) {
       const double* ts = a.tsize + (int64_t)e * (Q * Q) + Q * ta;
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
-    const double* tm = TGT == TGT_MAT ? a.tmat + ((int64_t)e * (Q * Q) + Q * ta) * a.tms : nullptr;
+    const double* tm =
+        TGT == TGT_MAT || TGT == TGT_CW ? a.tmat + ((int64_t)e * (Q * Q) + Q * ta) * (TGT == TGT_MAT ? 5 : 1) : nullptr;
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[2][2];
@@ -1381,11 +1396,12 @@ diag_kernel_2d(const DiagArgs<P, Q, R> a) {
       if constexpr (TGT == TGT_MAT) {
         R Wi[3][3];
         double Wid[3][3];
-        kK *= load_point_target<2, R>(a, tm, q0, Wi, Wid);
+        kK *= load_point_target2<R>(tm + 5 * q0, Wi, Wid);
         right_mul<2, R, false>(A, Wi, T);
         mu_second_rows<METRIC, R>(T, (R)kK, K);
         target_congruence<2, R>(Wi, K);
       } else {
+        if constexpr (TGT == TGT_CW) kK *= tm[q0];
         right_mul<2, R, ISO>(A, a.Winv, T);
         mu_second_rows<METRIC, R>(T, (R)kK, K);
         if constexpr (!ISO) target_congruence<2, R>(a.Winv, K);

@@ -19,7 +19,6 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   a.n_node = lp.n_node; a.n_list = lp.n_list;
   a.tsize = lp.tsize;
   a.tmat = lp.tmat;
-  a.tms = lp.tms;
   a.wdetW = lp.wdetW;
   a.kpen = lp.kpen;
   for (int i = 0; i < P; ++i)
@@ -73,7 +72,7 @@ static int launch_op(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
   if (op == OP_HESS) return launch_one<DIM, P, Q, M, R, OP_HESS, TGT>(lp, s, grid);
   if (op == OP_EG) return launch_one<DIM, P, Q, M, R, OP_EG, TGT>(lp, s, grid);
   if (op == OP_DIAG) return launch_one<DIM, P, Q, M, R, OP_DIAG, TGT>(lp, s, grid);
-  if constexpr (M == (DIM == 2 ? 1 : 302) && TGT != TGT_MAT) {
+  if constexpr (M == (DIM == 2 ? 1 : 302) && TGT != TGT_MAT && TGT != TGT_CW) {
     if (op == OP_SIZE) return launch_one<DIM, P, Q, M, R, OP_SIZE, TGT>(lp, s, grid);
     if constexpr (TGT == TGT_GEN)
       if (op == OP_JINV) return launch_one<DIM, P, Q, M, R, OP_JINV, TGT>(lp, s, grid);
@@ -83,7 +82,10 @@ static int launch_op(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
 
 template <int DIM, int P, int Q, int M, typename R>
 static int launch_metric(int op, const LaunchParams& lp, hipStream_t s, int* grid) {
-  if (lp.tmat) return launch_op<DIM, P, Q, M, R, TGT_MAT>(op, lp, s, grid);
+  if (lp.tmat) {
+    if (lp.tms == 1) return launch_op<DIM, P, Q, M, R, TGT_CW>(op, lp, s, grid);
+    return launch_op<DIM, P, Q, M, R, TGT_MAT>(op, lp, s, grid);
+  }
   if (lp.tsize) return launch_op<DIM, P, Q, M, R, TGT_QPS>(op, lp, s, grid);
   return lp.iso ? launch_op<DIM, P, Q, M, R, TGT_ISO>(op, lp, s, grid) : launch_op<DIM, P, Q, M, R, TGT_GEN>(op, lp, s, grid);
 }
