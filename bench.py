@@ -118,6 +118,7 @@ def parse():
     ap.add_argument("--other-workloads", default="q3_square_256,q3_cube_48,q2_square_512",
                     help="further workloads whose element operations are timed and reported (comma list)")
     ap.add_argument("--no-section4", action="store_true", help="skip the Section 4 objectives")
+    ap.add_argument("--no-targets", action="store_true", help="skip the per-point target and sliding runs")
     ap.add_argument("--no-dfo", action="store_true", help="skip the derivative-free solver")
     ap.add_argument("--section4-2d", default="q3_square_256",
                     help="2D workload for the second metric term and the replication composite")
@@ -352,6 +353,61 @@ def op_times(torch, ctx, x, v, reps):
     return out
 
 
+def targets(T, torch, dev, args, w, mesh, x, v, W, log):
+    """Per-point targets and sliding boundaries on the main workload.
+    W_3 (Section 3.1: W_q = (det A(x_0))^(1/d) I at every point, from the
+    input mesh itself): FP64 operation times and the Hessian colour launch
+    against the constant target W = h I.  Sliding (Section 4.1: only the
+    normal component of a boundary node is fixed): Newton with the
+    inexact-Newton forcing from the same mesh, against the fixed
+    boundary."""
+    reps = max(args.steps, 5)
+    us = lambda d: {k: round(t * 1e6, 2) for k, t in d.items()}
+
+    def hess_launch(ctx):
+        Hv = torch.empty_like(x)
+        ctx.hessian_apply(x, v, Hv)
+        ctx.timing_enable(True)
+        for _ in range(reps):
+            ctx.hessian_apply(x, v, Hv)
+        ms, n = ctx.timing_read(T.TIMING_HESS)
+        ctx.timing_enable(False)
+        return ms * 1e3 / n
+
+    ctx = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=mesh.fixed)
+    const = op_times(torch, ctx, x, v, reps)
+    const_l = hess_launch(ctx)
+    sizes, st = ctx.target_sizes_w3(x)
+    ctx.close()
+    cq = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], None, fixed=mesh.fixed,
+                   target_sizes=sizes.cpu().numpy())
+    w3 = op_times(torch, cq, x, v, reps)
+    w3_l = hess_launch(cq)
+    cq.close()
+    log(f"# targets W_3 on {args.workload}: Hv {const['hessian']*1e6:.1f} -> {w3['hessian']*1e6:.1f} us "
+        f"(colour launch {const_l:.1f} -> {w3_l:.1f} us), E+G {const['energy_gradient']*1e6:.1f} -> "
+        f"{w3['energy_gradient']*1e6:.1f} us")
+    newton = {}
+    for key, slide in (("fixed", False), ("sliding", True)):
+        fixed = meshgen.box_mesh(w["dim"], w["n"], w["p"], slide=slide).fixed
+        cs = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=fixed)
+        xn = x.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, rep = cs.newton_solve(xn, max_it=50, cg_forcing=1)
+        torch.cuda.synchronize()
+        newton[key] = dict(status=st, iters=rep["iters"], cg_iters=rep["cg_iters"],
+                           wall_s=round(time.perf_counter() - t0, 4), F0=rep["F0"], F=rep["F"],
+                           free_dofs=int(fixed.size - np.count_nonzero(fixed)))
+        cs.close()
+        log(f"# targets newton {key} boundary: {rep['iters']} it, {rep['cg_iters']} CG, {newton[key]['wall_s']} s, "
+            f"F {rep['F0']:.4e} -> {rep['F']:.4e}, {newton[key]['free_dofs']} free DOFs")
+    return {"workload": args.workload,
+            "w3": {"ops_us_constant_W": us(const), "ops_us_w3": us(w3),
+                   "hessian_launch_us_constant_W": round(const_l, 2), "hessian_launch_us_w3": round(w3_l, 2)},
+            "newton_inexact_f64": newton}
+
+
 def section4(T, torch, dev, args, w, mesh, x, v, W, log):
     """Cost of the Section 4 objectives.  Displacement penalty (eq. 4.2) on
     the main workload: FP64 operation times with and without it (fused into
@@ -553,6 +609,10 @@ def main():
             print(f"# newton {key}: status {st}, {rep['iters']} it, {rep['cg_iters']} CG, "
                   f"{rep['wall_s']:.2f} s, F {rep['F0']:.4e} -> {rep['F']:.4e}", file=sys.stderr, flush=True)
 
+    tgt = None
+    if not args.no_targets:
+        tgt = targets(T, torch, dev, args, w, mesh, x, v, W, lambda m: print(m, file=sys.stderr, flush=True))
+
     sec4 = None
     if not args.no_section4:
         sec4 = section4(T, torch, dev, args, w, mesh, x, v, W, lambda m: print(m, file=sys.stderr, flush=True))
@@ -616,6 +676,7 @@ def main():
                        "rel_err_vs_f64": results["mixed"]["rel_err_vs_f64"]},
         "workloads": {args.workload: workload_summary(w, mesh, {k: r for k, r in results.items()}), **others},
         "newton": newton,
+        "targets": tgt,
         "section4": sec4,
         "derivative_free": dfo_res,
         "learned_guess": learned,

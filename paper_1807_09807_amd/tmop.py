@@ -34,6 +34,8 @@ EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_gradient_scaled",
            "tmop_timing_enable", "tmop_timing_read", "tmop_energy_gradient", "tmop_hessian_diagonal",
            "tmop_target_sizes_w3", "tmop_set_target_sizes", "tmop_set_restriction", "tmop_set_combo",
            "tmop_set_replication", "tmop_dfo_default_opts", "tmop_dfo_sweep", "tmop_dfo_solve")
+# timing slots: the element-kernel operations, then the W_0 data and the penalty kernels
+TIMING_ENERGY, TIMING_GRAD, TIMING_HESS, TIMING_EG, TIMING_DIAG, TIMING_SIZE = 0, 1, 2, 3, 4, 5
 TIMING_W0, TIMING_PENALTY = 6, 7
 
 
