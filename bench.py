@@ -115,7 +115,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-initial-guess pipeline")
     ap.add_argument("--train-meshes", type=int, default=2000)
     ap.add_argument("--eval-seeds", type=int, default=4)
-    ap.add_argument("--other-workloads", default="q3_square_256,q3_cube_48,q2_square_512",
+    ap.add_argument("--other-workloads", default="q3_square_256,q3_cube_48,q2_square_512,q2_cube_32",
                     help="further workloads whose element operations are timed and reported (comma list)")
     ap.add_argument("--no-section4", action="store_true", help="skip the Section 4 objectives")
     ap.add_argument("--no-targets", action="store_true", help="skip the per-point target and sliding runs")

@@ -217,6 +217,8 @@ WORKLOADS = {
     "q2_cube_64":     dict(dim=3, n=64,  p=2, Q=4, metric=303, noise=0.10, amp=0.0,  seed=2,     tau_min=0.0),
     "q3_cube_48":     dict(dim=3, n=48,  p=3, Q=5, metric=302, noise=0.05, amp=0.03, seed=3,     tau_min=0.0),
     "q2_square_512":  dict(dim=2, n=512, p=2, Q=4, metric=2,   noise=0.10, amp=0.0,  seed=10000, tau_min=0.0),
+    # one GPU's share of q2_cube_64 split over 8 GPUs (a 2 x 2 x 2 block decomposition), at its real shape
+    "q2_cube_32":     dict(dim=3, n=32,  p=2, Q=4, metric=303, noise=0.10, amp=0.0,  seed=20,    tau_min=0.0),
 }
 
 

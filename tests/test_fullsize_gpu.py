@@ -12,7 +12,7 @@ from tests._helpers import EPS32, MIXED_C, say, to_dev
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-WORKLOADS = ["q2_square_8", "q3_square_256", "q2_cube_64", "q3_cube_48", "q2_square_512"]
+WORKLOADS = ["q2_square_8", "q3_square_256", "q2_cube_64", "q3_cube_48", "q2_square_512", "q2_cube_32"]
 
 
 @pytest.fixture(scope="module", params=WORKLOADS)

@@ -8,7 +8,7 @@ from paper_1807_09807_amd import meshgen
 
 @pytest.mark.parametrize("name,dofs", [("q2_square_8", 578), ("q3_square_256", 1_182_722),
                                        ("q2_cube_64", 6_440_067), ("q3_cube_48", 9_145_875),
-                                       ("q2_square_512", 2_101_250)])
+                                       ("q2_square_512", 2_101_250), ("q2_cube_32", 3 * 65 ** 3)])
 def test_workload_sizes(name, dofs):
     w = meshgen.WORKLOADS[name]
     m = w["n"] * w["p"] + 1
