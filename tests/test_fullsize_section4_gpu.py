@@ -1,10 +1,11 @@
-"""The Section 4 objectives and the derivative-free solver at full workload
-sizes, with the calls the benchmark times: the displacement penalty on the
-64^3 Q2 hex workload and the second metric term and replication composite
-on the 256^2 Q3 workload (gradient and Hessian action at 64 seeded nodes
-against the oracle evaluated on the elements around those nodes), and one
-derivative-free sweep over the 64^3 workload checked by its properties (F
-does not rise, no point inverts, fixed nodes stay)."""
+"""The Section 4 objectives, per-point targets, sliding boundaries and the
+derivative-free solver at full workload sizes, with the calls the
+benchmark times: the displacement penalty, the replication composite and
+the W_3 target on the 64^3 Q2 hex workload and the second metric term and
+replication composite on the 256^2 Q3 workload (gradient and Hessian
+action at 64 seeded nodes against the oracle evaluated on the elements
+around those nodes); Newton with sliding boundaries and one derivative-free
+sweep over the 64^3 workload checked by their properties."""
 import numpy as np
 import pytest
 
@@ -92,4 +93,58 @@ def test_dfo_sweep_q2_cube_64():
     fixed = torch.from_numpy(mesh.fixed.astype(bool)).cuda()
     assert torch.equal(xd[fixed], x0[fixed])
     assert float((xd - x0).abs().max()) == pytest.approx(move, rel=0, abs=0)
+    ctx.close()
+
+
+def test_replication_q2_cube_64():
+    from paper_1807_09807_amd import tmop as T
+    say("[fullsize s4] replication on q2_cube_64")
+    w, mesh, W, prob = _workload("q2_cube_64")
+    x0 = mesh.x
+    x = meshgen.perturb(mesh, 0.02, 320, base=x0)
+    v = meshgen.random_direction(mesh, 321)
+    prob.set_replication(0.5, x0)
+    ctx = T.Context(3, w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=mesh.fixed)
+    ctx.set_replication(0.5, to_dev(x0))
+    nodes = np.random.default_rng(322).choice(mesh.n_node, 64, replace=False)
+    _sampled(ctx, prob, x, v, nodes, "q2_cube_64 + replication")
+    ctx.close()
+
+
+def test_w3_target_q2_cube_64():
+    """The W_3 target of the input mesh (sizes from the oracle's det A),
+    at a perturbed mesh."""
+    from paper_1807_09807_amd import tmop as T
+    say("[fullsize targets] W_3 on q2_cube_64")
+    w, mesh, W, prob0 = _workload("q2_cube_64")
+    x0 = mesh.x
+    sizes = prob0.point_sizes(x0)
+    prob = O.Problem(3, w["p"], w["Q"], mesh.elem_node, w["metric"], sizes[:, :, None, None] * np.eye(3))
+    x = meshgen.perturb(mesh, 0.02, 330, base=x0)
+    v = meshgen.random_direction(mesh, 331)
+    ctx = T.Context(3, w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], None, fixed=mesh.fixed,
+                    target_sizes=sizes)
+    nodes = np.random.default_rng(332).choice(mesh.n_node, 64, replace=False)
+    _sampled(ctx, prob, x, v, nodes, "q2_cube_64 + W_3")
+    ctx.close()
+
+
+def test_newton_sliding_q2_cube_64():
+    """Newton (inexact forcing) with only the normal components of boundary
+    nodes fixed, as the benchmark runs it: it converges to the grid (F = 0
+    is the minimum), every boundary node stays on its face."""
+    from paper_1807_09807_amd import tmop as T
+    say("[fullsize targets] Newton with sliding boundaries on q2_cube_64")
+    w = meshgen.WORKLOADS["q2_cube_64"]
+    mesh = meshgen.make_workload("q2_cube_64")
+    fixed = meshgen.box_mesh(3, w["n"], w["p"], slide=True).fixed
+    ctx = T.Context(3, w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], mesh.h * np.eye(3), fixed=fixed)
+    x0 = to_dev(mesh.x)
+    xd = x0.clone()
+    st, rep = ctx.newton_solve(xd, max_it=50, cg_forcing=1)
+    say(f"  status {st}, {rep['iters']} it, {rep['cg_iters']} CG, F {rep['F0']:.4e} -> {rep['F']:.4e}")
+    assert st == T.TMOP_OK and rep["F"] < 1e-12 * rep["F0"]
+    fx = torch.from_numpy(fixed.astype(bool)).cuda()
+    assert torch.equal(xd[fx], x0[fx])
+    assert float((xd - torch.from_numpy(mesh.x_grid).cuda()).abs().max()) < 1e-6 * mesh.h
     ctx.close()
