@@ -67,7 +67,7 @@ FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ("tmop_elem.h", "tmop_metrics.h", "tmop_launch.h")
 MEASURED_TRAFFIC = {
     "q2_cube_64": dict(src_sha256="2ccb2c2c070177213051be2d7677cef2b95f2b660cbf9f015a29f7911a1d3f6c",
-                       fetch_kib=41952.1, write_kib=27968.5),
+                       fetch_kib=41952.1, write_kib=27967.9),
 }
 
 
