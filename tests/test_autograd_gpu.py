@@ -94,11 +94,13 @@ def test_q3_cube_48_finite_differences_and_oracle(precision):
     assert e_or <= (1e-12 if precision == 0 else max(1e-5, 4 * EPS32 * prob.max_condition(mesh.x)))
 
 
+@pytest.mark.parametrize("kind", ["replication", "combo"])
 @pytest.mark.parametrize("dim", [2, 3])
-def test_backward_with_section4_terms(dim):
+def test_backward_with_section4_terms(dim, kind):
     """The autograd backward scales every term: the upstream gradient enters
     the displacement penalty's and the second metric term's kernels too
-    (eq. 4.2 and Section 4.3.2 objectives against the oracle gradient)."""
+    (eq. 4.2 with the Section 4.3.2 replication or the eq. 4.1 second term,
+    against the oracle gradient)."""
     from paper_1807_09807_amd import tmop as T
     from paper_1807_09807_amd.autograd import TMOPEnergy
     n, p, Q, metric = (4, 2, 4, 2) if dim == 2 else (2, 2, 3, 303)
@@ -107,10 +109,17 @@ def test_backward_with_section4_terms(dim):
     prob = O.Problem(dim, p, Q, mesh.elem_node, metric, W)
     x_init = meshgen.perturb(mesh, 0.1, 30 + dim, bad_elements=prob.bad_elements)
     x0 = meshgen.perturb(mesh, 0.03, 40 + dim, base=x_init, bad_elements=prob.bad_elements)
-    prob.set_replication(0.4, x_init)
-    prob.set_restriction(25.0, x_init)
     ctx = T.Context(dim, p, mesh.elem_node, mesh.n_node, Q, metric, W, fixed=mesh.fixed)
-    ctx.set_replication(0.4, to_dev(x_init))
+    if kind == "replication":
+        prob.set_replication(0.4, x_init)
+        ctx.set_replication(0.4, to_dev(x_init))
+    else:
+        m2 = 77 if dim == 2 else 302
+        W2 = 0.8 * W
+        eq = np.random.default_rng(50 + dim).uniform(0.5, 1.5, (mesh.n_elem, Q ** dim))
+        prob.set_combo(m2, W2, 1.0, 0.7 * eq)
+        ctx.set_combo(m2, W2, 1.0, 0.7, eq)
+    prob.set_restriction(25.0, x_init)
     ctx.set_restriction(25.0, to_dev(x_init))
     x = to_dev(x0).requires_grad_(True)
     (2.5 * TMOPEnergy.apply(x, ctx)).backward()
