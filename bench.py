@@ -114,7 +114,7 @@ def parse():
                     help="first copy a 256 MiB buffer, so a profile holds a kernel of known HBM traffic")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-initial-guess pipeline")
     ap.add_argument("--train-meshes", type=int, default=2000)
-    ap.add_argument("--eval-seeds", type=int, default=4)
+    ap.add_argument("--eval-seeds", type=int, default=8)
     ap.add_argument("--other-workloads", default="q3_square_256,q3_cube_48,q2_square_512,q2_cube_32",
                     help="further workloads whose element operations are timed and reported (comma list)")
     ap.add_argument("--no-section4", action="store_true", help="skip the Section 4 objectives")
@@ -138,11 +138,16 @@ def learned_guess(args, log):
     log(f"#   training {tinfo['seconds']:.1f} s, {tinfo['steps']} Adam steps of {tinfo['batch']} samples, "
         f"last-batch loss per epoch {[round(l, 6) for l in tinfo['loss_history']]}")
     rows = ML.evaluate(net, n=512, seeds=tuple(10000 + k for k in range(args.eval_seeds)), log=log)
-    sp = [r["plain"]["wall_s"] / r["learned"]["wall_s"] for r in rows]
+    # wall-time ratio over the seeds where both runs reached F_tol; losses (ratio < 1) included
+    both = [r for r in rows if r["plain"]["reached_F_tol"] and r["learned"]["reached_F_tol"]]
+    sp = [r["plain"]["wall_s"] / r["learned"]["wall_s"] for r in both]
     return dict(train_meshes=args.train_meshes, samples=int(data.X.shape[0]), data_s=data.info["seconds"],
                 train_s=tinfo["seconds"], train_samples_per_s=tinfo["steps"] * tinfo["batch"] / tinfo["seconds"],
                 loss_history=tinfo["loss_history"], eval=rows,
-                speedup_wall_median=float(np.median(sp)),
+                speedup_wall_per_seed=[round(x, 3) for x in sp],
+                speedup_wall_median=float(np.median(sp)) if sp else None,
+                seeds_learned_slower=[r["seed"] for r in both if r["learned"]["wall_s"] > r["plain"]["wall_s"]],
+                seeds_fallback=[r["seed"] for r in rows if not r["used_proposal"] or r["learned"]["fell_back_after_solve"]],
                 reference_converged=[r["reference"]["converged"] for r in rows],
                 proposal_F_over_F0=[r["F_proposal"] / r["F0"] for r in rows],
                 newton_iters_plain=[r["plain"]["iters"] for r in rows],
@@ -159,36 +164,62 @@ def copy_calibration(torch, dev):
     del a, b
 
 
-def cpu_baseline(w, mesh, x, v, n_elem_sample, chunk=4096):
-    """The FP64 oracle (energy + gradient + Hessian action) on the first
-    n_elem_sample elements, single-threaded, scaled to DOF-iterations/s.
-    The sample is fed to the oracle in element chunks (its dense per-point
-    tables would not fit in memory at once); the time is the sum over the
-    chunks of the three calls."""
+_CPU_JOB = {}
+
+
+def _oracle_chunk(e0, e1):
+    """Worker of the multi-process CPU baseline: energy + gradient + Hessian
+    action of the FP64 oracle on elements [e0, e1), one thread; returns
+    (F part, seconds).  The mesh arrays come from the parent by fork."""
     from threadpoolctl import threadpool_limits
     from oracle import tmop_oracle as O
-    dt = 0.0
+    j = _CPU_JOB
+    w = j["w"]
     with threadpool_limits(1):
-        for e0 in range(0, n_elem_sample, chunk):
-            en = mesh.elem_node[e0:min(e0 + chunk, n_elem_sample)]
-            prob = O.Problem(w["dim"], w["p"], w["Q"], en, w["metric"], mesh.h * np.eye(w["dim"]))
-            t0 = time.perf_counter()
-            prob.energy(x)
-            prob.gradient(x)
-            prob.hessian_apply(x, v)
-            dt += time.perf_counter() - t0
-            del prob
-    frac = n_elem_sample / mesh.n_elem
+        prob = O.Problem(w["dim"], w["p"], w["Q"], j["en"][e0:e1], w["metric"], j["h"] * np.eye(w["dim"]))
+        t0 = time.perf_counter()
+        F, _ = prob.energy(j["x"])
+        prob.gradient(j["x"])
+        prob.hessian_apply(j["x"], j["v"])
+        return F, time.perf_counter() - t0
+
+
+def cpu_baseline(w, mesh, x, v, n_elem_sample, chunk=4096, workers=None):
+    """The FP64 oracle (energy + gradient + Hessian action) on the first
+    n_elem_sample elements, scaled to DOF-iterations/s, (i) in one process
+    and thread and (ii) over a pool of worker processes (fork, one thread
+    each, at most 16: the host share of one GPU) on element chunks of the
+    whole mesh, merged with math.fsum.  The sample is fed to the oracle in
+    element chunks (its dense per-point tables would not fit in memory at
+    once)."""
+    import math
+    import multiprocessing as mp
     cpu = "unknown CPU"
     try:
         with open("/proc/cpuinfo") as f:
             cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
     except (OSError, StopIteration):
         pass
-    return dict(value=mesh.n_dof * frac / dt, unit="DOF-iterations/s", cores=1, kind="oracle",
-                sample=f"energy+gradient+Hessian action of the FP64 oracle on {n_elem_sample} of "
-                       f"{mesh.n_elem} elements ({dt:.1f} s), scaled by the element fraction; "
-                       f"one thread of {os.cpu_count()} on {cpu}")
+    _CPU_JOB.update(w=w, en=mesh.elem_node, h=mesh.h, x=x, v=v)
+    frac = n_elem_sample / mesh.n_elem
+    bounds = [(e0, min(e0 + chunk, n_elem_sample)) for e0 in range(0, n_elem_sample, chunk)]
+    dt = sum(_oracle_chunk(a, b)[1] for a, b in bounds)            # (i) one process, one thread
+    single = dict(value=mesh.n_dof * frac / dt, cores=1, seconds=round(dt, 2))
+    n_work = workers or min(16, os.cpu_count() or 1)
+    sample2 = min(mesh.n_elem, n_elem_sample * n_work)              # (ii) the same work per core
+    bounds2 = [(e0, min(e0 + chunk, sample2)) for e0 in range(0, sample2, chunk)]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(n_work) as pool:
+        parts = pool.starmap(_oracle_chunk, bounds2)
+    wall = time.perf_counter() - t0
+    math.fsum(p[0] for p in parts)
+    frac2 = sample2 / mesh.n_elem
+    return dict(value=mesh.n_dof * frac2 / wall, unit="DOF-iterations/s", cores=n_work, kind="oracle",
+                sample=f"energy+gradient+Hessian action of the FP64 oracle on {sample2} of {mesh.n_elem} elements "
+                       f"in chunks of {chunk} over {n_work} worker processes of one thread ({wall:.1f} s wall), "
+                       f"scaled by the element fraction; host {cpu}, {os.cpu_count()} CPUs visible",
+                single_thread=dict(single, sample=f"{n_elem_sample} elements in one thread"))
 
 
 def build_mesh(T, torch, dev, name, gpu_repair=False):
@@ -535,6 +566,37 @@ def dfo(T, torch, dev, args, w, mesh, x, W, log):
     return out
 
 
+def small_newton(T, torch, dev, log):
+    """The 8x8 Q2 mu_2 workload's setting, 10 Newton iterations with the
+    default inner solver (cg_rtol 1e-10): the library on the GPU against the
+    FP64 oracle's Newton (same rules) on the host."""
+    from oracle import tmop_oracle as O
+    w = meshgen.WORKLOADS["q2_square_8"]
+    mesh = meshgen.box_mesh(2, w["n"], w["p"])
+    W = mesh.h * np.eye(2)
+    prob = O.Problem(2, w["p"], w["Q"], mesh.elem_node, w["metric"], W)
+    x0 = meshgen.perturb(mesh, w["noise"], w["seed"], bad_elements=prob.bad_elements)
+    t0 = time.perf_counter()
+    xo, rep_o = O.newton_solve(prob, x0, mesh.fixed, O.NewtonOptions(max_it=10, cg_rtol=1e-10))
+    t_cpu = time.perf_counter() - t0
+    ctx = T.Context(2, w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=mesh.fixed)
+    xd = torch.from_numpy(x0).to(dev)
+    ctx.newton_solve(xd.clone(), max_it=10, cg_rtol=1e-10)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, rep = ctx.newton_solve(xd, max_it=10, cg_rtol=1e-10)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    ctx.close()
+    F_o = [h[0] for h in rep_o.history]
+    out = dict(iters=rep["iters"], gpu_s=round(t_gpu, 4), oracle_s=round(t_cpu, 3), F_gpu=rep["history_F"],
+               F_oracle=F_o, max_rel_F_diff=max(abs(a - b) / a for a, b in zip(F_o, rep["history_F"]) if a > 1e-8 * F_o[0]),
+               dist_to_grid_over_h=float(np.max(np.abs(xd.cpu().numpy() - mesh.x_grid)) / mesh.h))
+    log(f"# newton q2_square_8, 10 iterations: GPU {t_gpu:.4f} s, oracle {t_cpu:.2f} s, F {F_o[0]:.4e} -> "
+        f"{rep['F']:.4e} (oracle {rep_o.F:.4e})")
+    return out
+
+
 def workload_summary(w, mesh, results):
     """Per-operation rates of one workload against the FP64 VALU and HBM
     peaks (algorithmic flops and unique L-vector bytes per element)."""
@@ -595,19 +657,24 @@ def main():
         F_ref = c64.energy(torch.from_numpy(mesh.x_grid).to(dev))[0]
         F_tol = F_ref + 1e-8 * c64.energy(x)[0]
         newton["F_ref"], newton["F_tol"] = F_ref, F_tol
-        J, MR = T.TMOP_PREC_JACOBI, T.TMOP_INNER_MINRES
+        J, MR, TC = T.TMOP_PREC_JACOBI, T.TMOP_INNER_MINRES, T.TMOP_INNER_CG
+        # default: CG on the Hessian shifted to positive definiteness; truncated CG (Steihaug) and MINRES beside it
         variants = (("f64", "f64", dict()), ("f64_inexact", "f64", dict(cg_forcing=1)),
                     ("mixed", "mixed", dict()), ("mixed_inexact", "mixed", dict(cg_forcing=1)),
-                    ("f64_jacobi", "f64", dict(precond=J)), ("f64_inexact_jacobi", "f64", dict(cg_forcing=1, precond=J)),
+                    ("f64_jacobi", "f64", dict(precond=J)),
+                    ("f64_truncated_cg", "f64", dict(inner=TC)), ("f64_truncated_cg_inexact", "f64", dict(inner=TC, cg_forcing=1)),
+                    ("f64_minres_inexact", "f64", dict(inner=MR, cg_forcing=1)),
                     ("f64_minres_jacobi", "f64", dict(inner=MR, precond=J)))
         for key, pname, kw in variants:
             st, rep = solve(pname, ftarget=F_tol, **kw)
             reached = next((k for k, f in enumerate(rep["history_F"]) if f <= F_tol), None)
             newton[key] = dict(status=st, reached_F_tol=reached is not None,
                                wall_s_to_F_tol=rep["history_time"][reached] if reached is not None else None,
-                               iters=rep["iters"], cg_iters=rep["cg_iters"], F=rep["F"])
-            print(f"# newton {key}: status {st}, {rep['iters']} it, {rep['cg_iters']} CG, "
-                  f"{rep['wall_s']:.2f} s, F {rep['F0']:.4e} -> {rep['F']:.4e}", file=sys.stderr, flush=True)
+                               iters=rep["iters"], cg_iters=rep["cg_iters"], neg_curv=rep["neg_curv"], F=rep["F"])
+            print(f"# newton {key}: status {st}, {rep['iters']} it, {rep['cg_iters']} CG, {rep['neg_curv']} "
+                  f"negative-curvature exits or CG restarts, {rep['wall_s']:.2f} s, F {rep['F0']:.4e} -> "
+                  f"{rep['F']:.4e}", file=sys.stderr, flush=True)
+        newton["q2_square_8"] = small_newton(T, torch, dev, lambda m: print(m, file=sys.stderr, flush=True))
 
     tgt = None
     if not args.no_targets:

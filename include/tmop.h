@@ -78,22 +78,38 @@ enum { TMOP_GAUSS_LEGENDRE = 0, TMOP_GAUSS_LOBATTO = 1 };
  * return FP64 arrays. */
 enum { TMOP_FP64 = 0, TMOP_MIXED_FP32 = 1 };
 
-/* Inner linear solver of the Newton step (Section 3.4): Steihaug's truncated
- * conjugate gradients, or MINRES, the solver of the paper's results
- * (Section 5), which accepts the indefinite Hessians of the early
- * iterations. */
-enum { TMOP_INNER_CG = 0, TMOP_INNER_MINRES = 1 };
+/* Inner linear solver of the Newton step (Section 3.4).  The Hessian is
+ * indefinite away from the optimum (barrier metrics are not convex).
+ *  TMOP_INNER_SHIFTED_CG (default): conjugate gradients on H + tau I, the
+ *    added multiple of the identity of Nocedal and Wright (Numerical
+ *    Optimization, 2nd ed., Algorithm 3.3) with a CG run as the test of
+ *    positive definiteness: tau_0 = 0 if the free diagonal of H is
+ *    positive, else beta - min diag; while CG meets curvature
+ *    p.(H + tau I)p <= 0, tau <- max(2 tau, beta) and CG restarts;
+ *    beta = shift_beta * mean |diag H| over the free DOFs.  The direction
+ *    solves a positive definite system, so it always descends.
+ *  TMOP_INNER_CG: Steihaug's truncated CG: at non-positive curvature it
+ *    returns -M^{-1} g at the first step, else the current iterate.
+ *  TMOP_INNER_MINRES: MINRES, the solver of the paper's results (Section
+ *    5), which accepts indefinite systems.
+ * The scalar recurrences of all three run on the device; the host reads
+ * their state back after inner iterations 1, 2, 4, 8, 16, 24, ... only. */
+enum { TMOP_INNER_CG = 0, TMOP_INNER_MINRES = 1, TMOP_INNER_SHIFTED_CG = 2 };
 
 /* Preconditioner of the inner solver: none, or Jacobi, M = |diag H| on the
  * free DOFs, from tmop_hessian_diagonal at the current iterate. */
 enum { TMOP_PREC_NONE = 0, TMOP_PREC_JACOBI = 1 };
 
-/* Target matrices W (Section 3.1). */
+/* Target matrices W (Section 3.1: W may be chosen at every quadrature
+ * point; det W > 0). */
 enum {
   TMOP_TGT_CONST = 0,      /* one dim x dim matrix for every point */
-  TMOP_TGT_ISO_PER_QP = 1  /* W_q = s_q I, one size s_q > 0 per quadrature
+  TMOP_TGT_ISO_PER_QP = 1, /* W_q = s_q I, one size s_q > 0 per quadrature
                               point: the targets W_2 scaled by a
                               space-dependent factor and W_3 of Section 3.1 */
+  TMOP_TGT_PER_ELEM = 2,   /* one general dim x dim matrix per element */
+  TMOP_TGT_PER_QP = 3      /* one general dim x dim matrix per quadrature
+                              point */
 };
 
 typedef struct {
@@ -116,12 +132,20 @@ typedef struct {
 } tmop_quadrature;
 
 typedef struct {
-  int32_t kind;               /* TMOP_TGT_CONST or TMOP_TGT_ISO_PER_QP */
+  int32_t kind;               /* TMOP_TGT_CONST, TMOP_TGT_ISO_PER_QP,
+                                 TMOP_TGT_PER_ELEM or TMOP_TGT_PER_QP */
   const double *W;            /* HOST.  TMOP_TGT_CONST: row-major dim x dim,
                                  det W > 0.  TMOP_TGT_ISO_PER_QP: the sizes
                                  [n_elem][n1d^dim], all > 0, point index
                                  q0 + n1d q1 (+ n1d^2 q2) (first reference
-                                 coordinate fastest) */
+                                 coordinate fastest).  TMOP_TGT_PER_ELEM:
+                                 [n_elem][dim][dim] row-major matrices.
+                                 TMOP_TGT_PER_QP: [n_elem][n1d^dim][dim][dim]
+                                 in the point order above.  Every matrix
+                                 finite with det W > 0, else TMOP_E_TARGET.
+                                 The device keeps W^{-1} and det W of each
+                                 (d^2 + 1 doubles per element or per point,
+                                 twice: element and colour order) */
 } tmop_target;
 
 typedef struct {
@@ -146,12 +170,15 @@ typedef struct {
                                  sqrt(|g|/|g0|))) */
   double *hist_time;          /* optional HOST [max_it + 1]: seconds since the
                                  call started, at each accepted iterate */
-  int32_t inner;              /* TMOP_INNER_CG (default) or TMOP_INNER_MINRES;
-                                 MINRES stops when its residual estimate (the
-                                 M^{-1} norm with a preconditioner) falls
-                                 to the inner tolerance times its initial
-                                 value */
+  int32_t inner;              /* TMOP_INNER_SHIFTED_CG (default), TMOP_INNER_CG
+                                 or TMOP_INNER_MINRES; MINRES stops when its
+                                 residual estimate (the M^{-1} norm with a
+                                 preconditioner) falls to the inner
+                                 tolerance times its initial value */
   int32_t precond;            /* TMOP_PREC_NONE (default) or TMOP_PREC_JACOBI */
+  double shift_beta;          /* TMOP_INNER_SHIFTED_CG: the floor of tau
+                                 relative to the mean |diag H|; default 1e-3,
+                                 must be > 0 */
 } tmop_newton_opts;
 
 typedef struct {
@@ -159,7 +186,9 @@ typedef struct {
   int32_t cg_iters;           /* total inner iterations (Hessian actions), CG
                                  or MINRES */
   int32_t ls_shrinks;         /* rejected step lengths */
-  int32_t neg_curv;           /* inner solves ended by non-positive curvature */
+  int32_t neg_curv;           /* truncated CG: inner solves ended by
+                                 non-positive curvature; shifted CG: CG
+                                 restarts with a larger shift */
   double F0, F;               /* objective at the start and at the end */
   double gnorm0, gnorm;       /* |g| over the free DOFs, start and end */
   double min_detA;            /* smallest det A at the end */
@@ -167,7 +196,7 @@ typedef struct {
 
 /* Fills `opts` with the defaults: rtol 1e-12, atol 0, max_it 50, cg_rtol
  * 1e-8, cg_max_it 1000, ls_shrink 0.5, ls_max 30, growth factors 1.2, no
- * history, truncated CG without preconditioner. */
+ * history, shifted CG (shift_beta 1e-3) without preconditioner. */
 void tmop_newton_default_opts(tmop_newton_opts *opts);
 
 /* Builds a context on the current HIP device for the objective of eq. 2.4

@@ -660,7 +660,9 @@ class NewtonOptions:
     g_growth: float = 1.2        # |g(x+)| < 1.2 |g(x)|
     ftarget: float = -math.inf   # also stop once F <= ftarget
     cg_forcing: int = 0          # 1: inner tolerance max(cg_rtol, min(0.5, sqrt(|g|/|g0|)))
-    inner: str = "cg"            # "cg": truncated CG; "minres": MINRES, the solver of Section 5
+    inner: str = "shifted_cg"    # "shifted_cg": CG on H + tau I (see shifted_cg); "cg": truncated CG;
+                                 # "minres": MINRES, the solver of Section 5
+    shift_beta: float = 1e-3     # shifted_cg: the floor of tau relative to the mean |diag H| (free DOFs)
     precond: str = "none"        # "none" or "jacobi": M = |diag H| on the free DOFs
 
 
@@ -679,6 +681,7 @@ class NewtonReport:
     gnorm: float = 0.0
     min_detA: float = 0.0
     history: list = field(default_factory=list)   # per iteration: (F, |g|, alpha, cg_iters, neg_curv)
+                                                  # (neg_curv: a flag for "cg", the CG restarts for "shifted_cg")
 
 
 def truncated_cg(apply_H, g, rtol, max_it, minv=None):
@@ -709,6 +712,59 @@ def truncated_cg(apply_H, g, rtol, max_it, minv=None):
         p = z + (rz_new / rz) * p
         rz = rz_new
     return d, max_it, False
+
+
+def _cg_or_negative(apply_H, g, rtol, max_it, minv=None):
+    """Preconditioned CG for H d = -g from d = 0, stopped once |r|_2 <=
+    rtol |g|_2, or at the first non-positive curvature p.Hp <= 0.  Returns
+    (d, iterations, negative-curvature flag)."""
+    d = np.zeros_like(g)
+    r = -g
+    z = r if minv is None else minv * r
+    p = z.copy()
+    rz = float(np.dot(r, z))
+    gnorm = math.sqrt(float(np.dot(g, g)))
+    for j in range(max_it):
+        Hp = apply_H(p)
+        pHp = float(np.dot(p, Hp))
+        if not pHp > 0.0:
+            return d, j + 1, True
+        alpha = rz / pHp
+        d = d + alpha * p
+        r = r - alpha * Hp
+        if math.sqrt(float(np.dot(r, r))) <= rtol * gnorm:
+            return d, j + 1, False
+        z = r if minv is None else minv * r
+        rz_new = float(np.dot(r, z))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return d, max_it, False
+
+
+def shifted_cg(apply_H, g, rtol, max_it, diag, beta_rel=1e-3, minv=None, max_shifts=64):
+    """CG on the modified Hessian H + tau I: the added multiple of the
+    identity of Nocedal and Wright (Numerical Optimization, 2nd ed., Alg.
+    3.3), with a CG run standing in for their Cholesky factorization as the
+    test of positive definiteness.  beta = beta_rel times the mean |diag H|
+    (diag: the diagonal on the free DOFs, a scale of H); tau_0 = 0 if every
+    diagonal entry is positive, else -min diag + beta; while CG meets
+    curvature p.(H + tau I)p <= 0, tau <- max(2 tau, beta) and CG restarts
+    from d = 0.  The direction solves (H + tau I) d = -g to the CG tolerance
+    with H + tau I positive definite on the Krylov space, so it descends.
+    Returns (d, total CG iterations, number of restarts, tau)."""
+    diag = np.asarray(diag, dtype=np.float64)
+    beta = beta_rel * float(np.mean(np.abs(diag)))
+    dmin = float(np.min(diag))
+    tau = 0.0 if dmin > 0.0 else -dmin + beta
+    total = 0
+    for k in range(max_shifts):
+        op = apply_H if tau == 0.0 else (lambda p, t=tau: apply_H(p) + t * p)
+        d, it, neg = _cg_or_negative(op, g, rtol, max_it, minv)
+        total += it
+        if not neg:
+            return d, total, k, tau
+        tau = max(2.0 * tau, beta)
+    return -g if minv is None else -minv * g, total, max_shifts, tau
 
 
 def minres(apply_H, b, rtol, max_it, minv=None):
@@ -784,8 +840,9 @@ def newton_solve(prob: Problem, x0, fixed, opts: NewtonOptions = NewtonOptions()
     """Minimize F_V over the free DOFs (fixed[c, I] = 1 marks Dirichlet).
 
     Each iteration: masked gradient g, a direction from the masked Hessian
-    (truncated CG, or MINRES as in Section 5; optionally Jacobi
-    preconditioned), then alpha = 1, 1/2, ... until the new mesh has det A > 0 at
+    (CG on the Hessian plus a multiple of the identity where it is not
+    positive definite (shifted_cg), truncated CG, or MINRES as in Section 5;
+    optionally Jacobi preconditioned), then alpha = 1, 1/2, ... until the new mesh has det A > 0 at
     every quadrature point, F(x+) < 1.2 F(x) and |g(x+)| < 1.2 |g(x)|;
     stops when no alpha works (Section 3.4), when |g| <= rtol |g0|
     (Section 5), or after max_it iterations."""
@@ -816,7 +873,11 @@ def newton_solve(prob: Problem, x0, fixed, opts: NewtonOptions = NewtonOptions()
             minv = jacobi_inverse(prob.hessian_diagonal(x.reshape(shape)).ravel(), m)
         elif opts.precond != "none":
             raise ValueError(f"unknown preconditioner {opts.precond}")
-        if opts.inner == "cg":
+        if opts.inner == "shifted_cg":
+            diag = prob.hessian_diagonal(x.reshape(shape)).ravel()[m > 0]
+            dvec, ncg, nshift, _ = shifted_cg(Hm, g, cg_tol, opts.cg_max_it, diag, opts.shift_beta, minv)
+            neg = nshift
+        elif opts.inner == "cg":
             dvec, ncg, neg = truncated_cg(Hm, g, cg_tol, opts.cg_max_it, minv)
         elif opts.inner == "minres":
             dvec, ncg = minres(Hm, -g, cg_tol, opts.cg_max_it, minv)

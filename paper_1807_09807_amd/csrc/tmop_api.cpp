@@ -171,18 +171,58 @@ void timing_end(tmop_ctx* c, int r, hipStream_t s, tmop_ctx::TimedLaunch& tl) {
   }
 }
 
-// Values per point of the second term's data: W^{-1} (row-major) and omega,
-// or omega alone when the term's target is constant.
-int tmat_stride(const tmop_ctx* c) { return c->tm_stride; }
+// Where the energy partials and the final reduction of an energy call go:
+// the context's buffers (nullptr), or the allocation-free scratch.  With
+// dry set the launches only count their workgroups.
+struct RedDst {
+  double* part;        // sums at part[0, cap), minima at part[cap, 2 cap)
+  int64_t cap;
+  double* fin;         // >= 2 FIN_BLOCKS doubles of reduction scratch
+  double* res;         // F and min det A
+  bool dry;
+};
 
 // The metric term a launch evaluates: the primary one, or the second term
 // of a composite objective (its metric and per-point targets).
 struct TermSel {
   int metric = -1;                 // -1: the context's metric
-  const double* tmat = nullptr;    // second term: per-point data in the launch's element order
+  const double* tmat = nullptr;    // general targets: their data in the launch's element order
+  int tms = 0;                     // values per point (or element) of tmat: dim^2 + 1, or 1 (omega_q alone)
+  bool per_elem = false;           // tmat holds one target per element
   double omega = 0.0;              // OP_JINV: the weight omega_q it writes beside W_0^{-1}
   bool pen = false;                // the displacement penalty rides in this launch
 };
+
+// The primary metric term on elements [e0, ...) of the element order (col
+// false) or the colour order (col true): general targets per element or per
+// point (TMOP_TGT_PER_ELEM / TMOP_TGT_PER_QP) ride in tmat.
+TermSel primary_term(const tmop_ctx* c, bool col, int64_t e0, bool pen) {
+  TermSel t;
+  t.pen = pen;
+  if (c->d_ptgt) {
+    const int64_t per = (c->ptgt_elem ? 1 : c->nq) * (int64_t)c->ptgt_stride;
+    t.tmat = (col ? c->d_ptgt_col : c->d_ptgt) + e0 * per;
+    t.tms = c->ptgt_stride;
+    t.per_elem = c->ptgt_elem;
+  }
+  return t;
+}
+
+// The second metric term (Sections 4.2, 4.3.2) on elements [e0, ...).
+TermSel second_term(const tmop_ctx* c, bool col, int64_t e0) {
+  TermSel t;
+  t.metric = c->metric2;
+  t.tmat = (col ? c->d_tmat_col : c->d_tmat) + e0 * c->nq * c->tm_stride;
+  t.tms = c->tm_stride;
+  return t;
+}
+
+// Per-point sizes whose d-th powers are det W of the primary target, for the
+// displacement penalty (nullptr: a constant target).
+const double* penalty_sizes(const tmop_ctx* c, bool col, int64_t e0) {
+  const double* p = c->d_tsize ? (col ? c->d_tsize_col : c->d_tsize) : (col ? c->d_psize_col : c->d_psize);
+  return p ? p + e0 * c->nq : nullptr;
+}
 
 // Whether the displacement penalty (eq. 4.2) of op runs inside the primary
 // term's element kernels: the Hessian action, 3D, FP64, constant target.
@@ -192,7 +232,7 @@ struct TermSel {
 // (the fused gradient kernels lose a wave per SIMD to registers, and the
 // x_init gather stays), so they keep the separate kernels.
 bool fused_penalty(const tmop_ctx* c, int op) {
-  return c->delta > 0.0 && c->dim == 3 && c->precision == TMOP_FP64 && !c->d_tsize && op == OP_HESS;
+  return c->delta > 0.0 && c->dim == 3 && c->precision == TMOP_FP64 && !c->d_tsize && !c->d_ptgt && op == OP_HESS;
 }
 
 // Element kernels over n_list elements: conn[k * npe ...] (list == nullptr)
@@ -201,14 +241,16 @@ bool fused_penalty(const tmop_ctx* c, int op) {
 int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* out, const int32_t* conn,
                 const int32_t* list, int64_t n_list, hipStream_t s, int* grid, const double* scale = nullptr,
                 int64_t part_off = 0, const uint32_t* first = nullptr, const double* tsize = nullptr,
-                TermSel term = TermSel{}) {
+                TermSel term = TermSel{}, const RedDst* rd = nullptr) {
   LaunchParams lp = c->base;
   lp.first = first;
   lp.tsize = tsize;
   lp.tmat = term.tmat;
   if (term.tmat) {
-    lp.tms = c->tm_stride;
-    if (c->tm_stride == 1)   // constant second target: its W^{-1} rides in the kernel arguments
+    lp.tms = term.tms;
+    lp.tm_pt = term.per_elem ? 0 : term.tms;
+    lp.tm_el = term.per_elem ? term.tms : c->nq * term.tms;
+    if (term.tms == 1)   // constant second target: its W^{-1} rides in the kernel arguments
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) lp.Winv[i][j] = c->W2inv[i][j];
   }
@@ -220,8 +262,9 @@ int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* o
   lp.list = list;
   lp.n_list = (int32_t)n_list;
   lp.n_node = c->n_node;
-  lp.part = c->d_part + part_off;
-  lp.part_min = c->d_part + c->part_cap + part_off;
+  lp.part = (rd ? rd->part : c->d_part) + part_off;
+  lp.part_min = (rd ? rd->part + rd->cap : c->d_part + c->part_cap) + part_off;
+  lp.dry = rd && rd->dry;
   const int metric = term.metric < 0 ? c->metric : term.metric;
   if (op == OP_JINV) {   // W_0 data of the replication composite: A of W = I, in FP64
     lp.iso = false;
@@ -231,7 +274,8 @@ int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* o
     lp.wdetW = term.omega;
   }
   tmop_ctx::TimedLaunch tl;
-  if (timing_begin(c, op, s, tl) != TMOP_OK) return TMOP_E_HIP;
+  const bool timed = !rd;   // the allocation-free call creates no events
+  if (timed && timing_begin(c, op, s, tl) != TMOP_OK) return TMOP_E_HIP;
   const bool f64 = c->precision == TMOP_FP64 || op == OP_JINV;
   int r;
   if (c->dim == 2)
@@ -240,7 +284,7 @@ int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* o
   else
     r = f64 ? launch_elem_3d_f64(c->p, c->Q, metric, op, lp, s, grid)
             : launch_elem_3d_f32(c->p, c->Q, metric, op, lp, s, grid);
-  timing_end(c, r, s, tl);
+  if (timed) timing_end(c, r, s, tl);
   if (r == -1) return TMOP_E_UNSUPPORTED;
   return r == 0 ? TMOP_OK : TMOP_E_HIP;
 }
@@ -248,7 +292,8 @@ int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* o
 // Displacement-penalty kernels (eq. 4.2) over n_list elements of conn,
 // adding to out; energy partials as elem_launch.  x is v for OP_HESS.
 int mass_launch(tmop_ctx* c, int op, const double* x, double* out, const int32_t* conn, int64_t n_list,
-                hipStream_t s, int* grid, const double* scale, int64_t part_off, const double* tsize) {
+                hipStream_t s, int* grid, const double* scale, int64_t part_off, const double* tsize,
+                const RedDst* rd = nullptr) {
   MassParams mp{};
   mp.x = x;
   mp.x0 = c->d_xinit;
@@ -256,8 +301,9 @@ int mass_launch(tmop_ctx* c, int op, const double* x, double* out, const int32_t
   mp.elem_node = conn;
   mp.n_list = (int32_t)n_list;
   mp.n_node = c->n_node;
-  mp.part = c->d_part + part_off;
-  mp.part_min = c->d_part + c->part_cap + part_off;
+  mp.part = (rd ? rd->part : c->d_part) + part_off;
+  mp.part_min = (rd ? rd->part + rd->cap : c->d_part + c->part_cap) + part_off;
+  mp.dry = rd && rd->dry;
   mp.scale = scale;
   mp.tsize = tsize;
   for (int q = 0; q < MAXQ; ++q) {
@@ -266,9 +312,9 @@ int mass_launch(tmop_ctx* c, int op, const double* x, double* out, const int32_t
   }
   mp.k = 2.0 * c->delta * c->base.detW;   // per-point sizes: det W = 1 here, s_q^d in the kernel
   tmop_ctx::TimedLaunch tl;
-  if (timing_begin(c, TIMING_PENALTY, s, tl) != TMOP_OK) return TMOP_E_HIP;
+  if (!rd && timing_begin(c, TIMING_PENALTY, s, tl) != TMOP_OK) return TMOP_E_HIP;
   const int r = launch_mass(c->dim, c->p, c->Q, op, mp, s, grid);
-  timing_end(c, r, s, tl);
+  if (!rd) timing_end(c, r, s, tl);
   if (r == -1) return TMOP_E_UNSUPPORTED;
   return r == 0 ? TMOP_OK : TMOP_E_HIP;
 }
@@ -309,7 +355,7 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
     const int r = elem_launch(c, op, x, v, out, c->d_elem_node_col + c->color_off[k] * c->npe, nullptr, n, s,
                               &grid, scale, off, c->d_first + c->color_off[k] * c->first_words,
                               c->d_tsize_col ? c->d_tsize_col + c->color_off[k] * c->nq : nullptr,
-                              TermSel{-1, nullptr, 0.0, fused_penalty(c, op)});
+                              primary_term(c, true, c->color_off[k], fused_penalty(c, op)));
     if (r != TMOP_OK) return r;
     off += grid;
   }
@@ -318,8 +364,7 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
     if (n == 0) continue;
     int grid = 0;
     const int r = elem_launch(c, op, x, v, out, c->d_elem_node_col + c->color_off[k] * c->npe, nullptr, n, s,
-                              &grid, scale, off, nullptr, nullptr,
-                              TermSel{c->metric2, c->d_tmat_col + c->color_off[k] * c->nq * tmat_stride(c)});
+                              &grid, scale, off, nullptr, nullptr, second_term(c, true, c->color_off[k]));
     if (r != TMOP_OK) return r;
     off += grid;
   }
@@ -328,7 +373,7 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
     if (n == 0) continue;
     int grid = 0;
     const int r = mass_launch(c, op, op == OP_HESS ? v : x, out, c->d_elem_node_col + c->color_off[k] * c->npe, n,
-                              s, &grid, scale, off, c->d_tsize_col ? c->d_tsize_col + c->color_off[k] * c->nq : nullptr);
+                              s, &grid, scale, off, penalty_sizes(c, true, c->color_off[k]));
     if (r != TMOP_OK) return r;
     off += grid;
   }
@@ -336,25 +381,32 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
   return TMOP_OK;
 }
 
-// Enqueue F and min det A into c->d_res[0..1]: every term, element order.
-int energy_async(tmop_ctx* c, const double* x, hipStream_t s) {
+// Enqueue F and min det A into c->d_res[0..1] (rd: into rd->res, the
+// partials into rd->part; a dry rd only counts the workgroups into *nblocks):
+// every term, element order.
+int energy_async(tmop_ctx* c, const double* x, hipStream_t s, const RedDst* rd = nullptr,
+                 int64_t* nblocks = nullptr) {
   int grid = 0;
   int r = elem_launch(c, OP_ENERGY, x, nullptr, nullptr, c->d_elem_node, nullptr, c->n_elem, s, &grid, nullptr, 0,
-                      nullptr, c->d_tsize, TermSel{-1, nullptr, 0.0, fused_penalty(c, OP_ENERGY)});
+                      nullptr, c->d_tsize, primary_term(c, false, 0, fused_penalty(c, OP_ENERGY)), rd);
   if (r != TMOP_OK) return r;
   int64_t off = grid;
   if (c->metric2) {
     r = elem_launch(c, OP_ENERGY, x, nullptr, nullptr, c->d_elem_node, nullptr, c->n_elem, s, &grid, nullptr, off,
-                    nullptr, nullptr, TermSel{c->metric2, c->d_tmat});
+                    nullptr, nullptr, second_term(c, false, 0), rd);
     if (r != TMOP_OK) return r;
     off += grid;
   }
   if (c->delta > 0.0 && !fused_penalty(c, OP_ENERGY)) {
-    r = mass_launch(c, OP_ENERGY, x, nullptr, c->d_elem_node, c->n_elem, s, &grid, nullptr, off, c->d_tsize);
+    r = mass_launch(c, OP_ENERGY, x, nullptr, c->d_elem_node, c->n_elem, s, &grid, nullptr, off,
+                    penalty_sizes(c, false, 0), rd);
     if (r != TMOP_OK) return r;
     off += grid;
   }
-  HIP_TRY(finalize_sum_min(c->d_part, (int)off, (int)c->part_cap, c->d_scratch, c->d_res, s));
+  if (nblocks) *nblocks = off;
+  if (rd && rd->dry) return TMOP_OK;
+  if (rd) HIP_TRY(finalize_sum_min(rd->part, (int)off, (int)rd->cap, rd->fin, rd->res, s));
+  else HIP_TRY(finalize_sum_min(c->d_part, (int)off, (int)c->part_cap, c->d_scratch, c->d_res, s));
   return TMOP_OK;
 }
 
@@ -403,6 +455,10 @@ void free_ctx(tmop_ctx* c) {
   (void)hipFree(c->d_tsize_col);
   (void)hipFree(c->d_tmat);
   (void)hipFree(c->d_tmat_col);
+  (void)hipFree(c->d_ptgt);
+  (void)hipFree(c->d_ptgt_col);
+  (void)hipFree(c->d_psize);
+  (void)hipFree(c->d_psize_col);
   (void)hipFree(c->d_xinit);
   (void)hipFree(c->d_dfo_nodes);
   (void)hipFree(c->d_ne_off);
@@ -412,7 +468,9 @@ void free_ctx(tmop_ctx* c) {
   (void)hipFree(c->d_scratch);
   (void)hipFree(c->d_res);
   (void)hipFree(c->d_work);
+  (void)hipFree(c->d_sc);
   if (c->h_res) (void)hipHostFree(c->h_res);
+  if (c->h_sc) (void)hipHostFree(c->h_sc);
   (void)collect_timing(c);
   for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
   (void)hipSetDevice(cur);
@@ -464,12 +522,32 @@ struct Inner {
   double* v[7];
 };
 
-// Steihaug's truncated CG for H d = -g from d = 0, optionally with the
-// diagonal preconditioner minv = 1 / diag M.  Non-positive curvature at the
-// first step returns -M^{-1} g (the steepest-descent direction, -g without
-// M), later the current iterate; stops once |r|_2 <= tol |g|_2.
-int inner_tcg(tmop_ctx* c, const double* x, const double* g, double gn, double tol, int max_it,
-              const double* minv, Inner& w, hipStream_t s, int* ncg, bool* neg) {
+// The Krylov runs keep their scalars on the device (tmop_blas.hip) and the
+// host reads them back only at these iteration counts: 1, 2, 4, 8, then every 8.
+int next_check(int k) { return k < 8 ? 2 * k : k + 8; }
+
+// Copies the run state in h_sc to the device (before the first iteration).
+int sc_upload(tmop_ctx* c, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(c->d_sc, c->h_sc, SC_COUNT * sizeof(double), hipMemcpyHostToDevice, s));
+  return TMOP_OK;
+}
+
+// Reads the run state back into h_sc; returns whether the run is still active.
+int sc_read(tmop_ctx* c, hipStream_t s, bool* active) {
+  HIP_TRY(hipMemcpyAsync(c->h_sc, c->d_sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *active = c->h_sc[SC_ACTIVE] != 0.0;
+  return TMOP_OK;
+}
+
+// One preconditioned CG run on (m H m + tau I) d = -g from d = 0 (minv =
+// 1 / diag M or nullptr), until |r|_2 <= tol |g|_2, max_it Hessian
+// actions, or the first curvature p.(H + tau I)p <= 0 (*neg; d then holds
+// the iterate before that step).  *ncg: Hessian actions used.  r, p, Hp and
+// z are w.v[0..3]; p still holds the first direction -M^{-1} g when the run
+// ends at its first step.
+int cg_run(tmop_ctx* c, const double* x, const double* g, double gn, double tol, int max_it, const double* minv,
+           double tau, Inner& w, hipStream_t s, int* ncg, bool* neg) {
   const int64_t N = c->n_dof;
   double* r = w.v[0];
   double* p = w.v[1];
@@ -487,31 +565,76 @@ int inner_tcg(tmop_ctx* c, const double* x, const double* g, double gn, double t
     rz = gn * gn;
   }
   HIP_TRY(hipMemcpyAsync(p, z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-  *ncg = 0;
-  *neg = false;
-  for (int j = 0; j < max_it; ++j) {
-    ++*ncg;
+  for (int k = 0; k < SC_COUNT; ++k) c->h_sc[k] = 0.0;
+  c->h_sc[SC_ACTIVE] = 1.0;
+  c->h_sc[SC_MAXIT] = max_it;
+  c->h_sc[SC_RZ] = rz;
+  if ((st = sc_upload(c, s)) != TMOP_OK) return st;
+  bool active = true;
+  for (int j = 1, check = 1; j <= max_it; ++j) {
     // H p over all DOFs; p vanishes on the fixed DOFs, so p . Hp equals
-    // p . (m .* Hp), and the update below applies the mask to Hp
+    // p . (m .* Hp), and the update applies the mask to Hp
     if ((st = assemble(c, OP_HESS, x, p, Hp, s)) != TMOP_OK) return st;
-    double pHp;
-    if ((st = dot_sync(c, p, Hp, s, &pHp)) != TMOP_OK) return st;
-    if (!(pHp > 0.0)) {                      // non-positive curvature
-      *neg = true;
-      if (j == 0) HIP_TRY(hipMemcpyAsync(w.d, p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-      break;
+    HIP_TRY(cg_dev_curvature(p, Hp, tau, N, c->d_scratch, c->d_sc, s));
+    HIP_TRY(cg_dev_update(p, Hp, tau, mask, minv, w.d, r, z, N, tol * gn, c->d_scratch, c->d_sc, s));
+    if (j == check || j == max_it) {
+      if ((st = sc_read(c, s, &active)) != TMOP_OK) return st;
+      if (!active) break;
+      check = next_check(check);
     }
-    const double alpha = rz / pHp;
-    // d += alpha p, r -= alpha m .* Hp, z = M^{-1} r, r . r and r . z in one pass
-    HIP_TRY(cg_step(alpha, p, Hp, mask, minv, w.d, r, z, N, c->d_scratch, c->d_res + 2, s));
-    HIP_TRY(hipMemcpyAsync(c->h_res + 2, c->d_res + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const double rr = c->h_res[2];
-    const double rz_new = minv ? c->h_res[3] : rr;
-    if (sqrt(rr) <= tol * gn) break;
-    HIP_TRY(xpay(z, rz_new / rz, p, N, s));
-    rz = rz_new;
   }
+  if (active && (st = sc_read(c, s, &active)) != TMOP_OK) return st;
+  *ncg = (int)c->h_sc[SC_ITERS];
+  *neg = c->h_sc[SC_NEG] != 0.0;
+  return TMOP_OK;
+}
+
+// Steihaug's truncated CG for H d = -g from d = 0, optionally with the
+// diagonal preconditioner minv = 1 / diag M.  Non-positive curvature at the
+// first step returns -M^{-1} g (the steepest-descent direction, -g without
+// M), later the current iterate; stops once |r|_2 <= tol |g|_2.
+int inner_tcg(tmop_ctx* c, const double* x, const double* g, double gn, double tol, int max_it,
+              const double* minv, Inner& w, hipStream_t s, int* ncg, bool* neg) {
+  const int st = cg_run(c, x, g, gn, tol, max_it, minv, 0.0, w, s, ncg, neg);
+  if (st != TMOP_OK) return st;
+  if (*neg && *ncg == 1)
+    HIP_TRY(hipMemcpyAsync(w.d, w.v[1], c->n_dof * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return TMOP_OK;
+}
+
+// CG on the modified Hessian H + tau I, the added multiple of the identity
+// of Nocedal and Wright (Numerical Optimization, 2nd ed., Algorithm 3.3)
+// with a CG run in place of their Cholesky factorization as the test of
+// positive definiteness: beta = shift_beta mean |diag H| over the free DOFs
+// (diag: the Hessian diagonal at x), tau_0 = 0 if every free diagonal entry
+// is positive, else -min diag + beta; while CG meets curvature
+// p.(H + tau I)p <= 0, tau <- max(2 tau, beta) and CG restarts from d = 0.
+// The direction then solves a positive definite system, so it descends.
+// After 64 restarts the direction is -M^{-1} g.  *nrestart: CG restarts.
+int inner_shifted_cg(tmop_ctx* c, const double* x, const double* g, double gn, double tol, int max_it,
+                     const double* minv, const double* diag, double shift_beta, Inner& w, hipStream_t s, int* ncg,
+                     int* nrestart) {
+  const int64_t N = c->n_dof;
+  HIP_TRY(free_stats(diag, c->has_fixed ? c->d_mask : nullptr, N, c->d_scratch, c->d_res + 2, s));
+  HIP_TRY(hipMemcpyAsync(c->h_res + 2, c->d_res + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double beta = shift_beta * c->h_res[2] / (double)std::max<int64_t>(c->n_free, 1);
+  const double dmin = c->h_res[3];
+  double tau = dmin > 0.0 ? 0.0 : -dmin + beta;
+  *ncg = 0;
+  *nrestart = 0;
+  for (int k = 0; k < 64; ++k) {
+    int n = 0;
+    bool neg = false;
+    const int st = cg_run(c, x, g, gn, tol, max_it, minv, tau, w, s, &n, &neg);
+    if (st != TMOP_OK) return st;
+    *ncg += n;
+    if (!neg) return TMOP_OK;
+    ++*nrestart;
+    tau = std::max(2.0 * tau, beta);
+  }
+  HIP_TRY(scale_copy(-1.0, g, w.d, N, s));
+  if (minv) HIP_TRY(mul(minv, w.d, w.d, N, s));
   return TMOP_OK;
 }
 
@@ -521,7 +644,8 @@ int inner_tcg(tmop_ctx* c, const double* x, const double* g, double gn, double t
 // product; Givens rotations keep its QR factorization current, so the
 // iterate that minimizes the M^{-1}-norm of the residual over the Krylov
 // space follows from a three-term recurrence of the directions w_k, and
-// |phibar| is that residual norm.  Stops when |phibar| <= tol beta_1.
+// |phibar| is that residual norm.  Stops when |phibar| <= tol beta_1.  The
+// scalar recurrences run on the device between the vector kernels.
 int inner_minres(tmop_ctx* c, const double* x, const double* g, double tol, int max_it, const double* minv,
                  Inner& w, hipStream_t s, int* nit) {
   const int64_t N = c->n_dof;
@@ -541,57 +665,44 @@ int inner_minres(tmop_ctx* c, const double* x, const double* g, double tol, int 
     HIP_TRY(mul(minv, r_cur, ybuf, N, s));
     y = ybuf;
   }
-  double beta;
-  if ((st = dot_sync(c, r_cur, y, s, &beta)) != TMOP_OK) return st;
-  beta = sqrt(beta);
+  double beta1;
+  if ((st = dot_sync(c, r_cur, y, s, &beta1)) != TMOP_OK) return st;
+  beta1 = sqrt(beta1);
   *nit = 0;
-  const double beta1 = beta;
   if (!(beta1 > 0.0)) return TMOP_OK;
   HIP_TRY(fill(w_prev, 0.0, N, s));
   HIP_TRY(fill(w_cur, 0.0, N, s));
-  HIP_TRY(scale_copy(1.0 / beta, y, vbuf, N, s));          // Lanczos vector v_1
-  double beta_prev = 0.0, cs = -1.0, sn = 0.0, dbar = 0.0, eps = 0.0, phibar = beta1;
-  for (int k = 1; k <= max_it; ++k) {
-    ++*nit;
+  HIP_TRY(scale_copy(1.0 / beta1, y, vbuf, N, s));          // Lanczos vector v_1
+  for (int k = 0; k < SC_COUNT; ++k) c->h_sc[k] = 0.0;
+  c->h_sc[SC_ACTIVE] = 1.0;
+  c->h_sc[SC_MAXIT] = max_it;
+  c->h_sc[SC_BETA] = beta1;
+  c->h_sc[SC_BETA1] = beta1;
+  c->h_sc[SC_PHIBAR] = beta1;
+  c->h_sc[SC_CS] = -1.0;
+  c->h_sc[SC_TOL] = tol;
+  if ((st = sc_upload(c, s)) != TMOP_OK) return st;
+  bool active = true;
+  for (int k = 1, check = 1; k <= max_it; ++k) {
     // H v over all DOFs; v vanishes on the fixed DOFs, so v . Hv = v . (m .* Hv)
     if ((st = assemble(c, OP_HESS, x, vbuf, hbuf, s)) != TMOP_OK) return st;
-    double alpha;
-    if ((st = dot_sync(c, vbuf, hbuf, s, &alpha)) != TMOP_OK) return st;
-    // r_{k+1} = m .* H v_k - (alpha / beta_k) r_k - (beta_k / beta_{k-1}) r_{k-1}, y = M^{-1} r_{k+1}
-    HIP_TRY(minres_r(hbuf, mask, -alpha / beta, r_cur, k > 1 ? -beta / beta_prev : 0.0, k > 1 ? r_prev : nullptr,
-                     minv, ybuf, N, c->d_scratch, c->d_res + 2, s));
-    HIP_TRY(hipMemcpyAsync(c->h_res + 2, c->d_res + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const double beta_next = sqrt(std::max(c->h_res[2], 0.0));
-    y = minv ? ybuf : hbuf;
-    // previous rotation on this column and on the next column's beta
-    const double eps_k = eps;
-    const double delta = cs * dbar + sn * alpha;
-    const double gbar = sn * dbar - cs * alpha;
-    eps = sn * beta_next;
-    dbar = -cs * beta_next;
-    // new rotation annihilating beta_next
-    double gamma = hypot(gbar, beta_next);
-    if (gamma == 0.0) gamma = 2.2250738585072014e-308;
-    cs = gbar / gamma;
-    sn = beta_next / gamma;
-    const double phi = cs * phibar;
-    phibar = sn * phibar;
-    const bool done = fabs(phibar) <= tol * beta1 || !(beta_next > 0.0) || k == max_it;
-    // w_k = (v_k - eps_k w_{k-2} - delta w_{k-1}) / gamma (into w_prev's storage), d += phi w_k, and the next
-    // Lanczos vector v_{k+1} = y / beta_{k+1}
-    HIP_TRY(minres_wd(vbuf, eps_k, w_prev, delta, w_cur, 1.0 / gamma, phi, w.d, done ? nullptr : y,
-                      done ? 0.0 : 1.0 / beta_next, N, s));
+    HIP_TRY(mr_dev_alpha(vbuf, hbuf, N, c->d_scratch, c->d_sc, s));
+    HIP_TRY(mr_dev_step(hbuf, mask, r_cur, r_prev, minv, ybuf, vbuf, w_prev, w_cur, w.d, N, c->d_scratch, c->d_sc,
+                        s));
     std::swap(w_prev, w_cur);
     // r_{k-1} <- r_k <- r_{k+1}; the oldest buffer takes the next H v
     double* spare = r_prev;
     r_prev = r_cur;
     r_cur = hbuf;
     hbuf = spare;
-    beta_prev = beta;
-    beta = beta_next;
-    if (done) break;
+    if (k == check || k == max_it) {
+      if ((st = sc_read(c, s, &active)) != TMOP_OK) return st;
+      if (!active) break;
+      check = next_check(check);
+    }
   }
+  if (active && (st = sc_read(c, s, &active)) != TMOP_OK) return st;
+  *nit = (int)c->h_sc[SC_ITERS];
   return TMOP_OK;
 }
 
@@ -630,8 +741,9 @@ void tmop_newton_default_opts(tmop_newton_opts* o) {
   o->g_growth = 1.2;
   o->ftarget = -HUGE_VAL;
   o->cg_forcing = 0;
-  o->inner = TMOP_INNER_CG;
+  o->inner = TMOP_INNER_SHIFTED_CG;
   o->precond = TMOP_PREC_NONE;
+  o->shift_beta = 1e-3;
 }
 
 int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_target* target, int32_t metric,
@@ -652,17 +764,49 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
     return TMOP_E_ARG;
   if (d == 3 && metric != TMOP_MU302 && metric != TMOP_MU303) return TMOP_E_ARG;
   if (precision != TMOP_FP64 && precision != TMOP_MIXED_FP32) return TMOP_E_ARG;
-  if ((target->kind != TMOP_TGT_CONST && target->kind != TMOP_TGT_ISO_PER_QP) || !target->W) return TMOP_E_ARG;
+  const int kind = target->kind;
+  if ((kind != TMOP_TGT_CONST && kind != TMOP_TGT_ISO_PER_QP && kind != TMOP_TGT_PER_ELEM &&
+       kind != TMOP_TGT_PER_QP) || !target->W)
+    return TMOP_E_ARG;
   const int npe = d == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
   const int nq = d == 2 ? Q * Q : Q * Q * Q;
   for (int64_t k = 0; k < mesh->n_elem * npe; ++k)
     if (mesh->elem_node[k] < 0 || mesh->elem_node[k] >= mesh->n_node) return TMOP_E_ARG;
-  const bool per_qp = target->kind == TMOP_TGT_ISO_PER_QP;
+  const bool per_qp = kind == TMOP_TGT_ISO_PER_QP;
+  const bool gen_tgt = kind == TMOP_TGT_PER_ELEM || kind == TMOP_TGT_PER_QP;
   static const double eye2[4] = {1, 0, 0, 1}, eye3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-  const double* Wc = per_qp ? (d == 2 ? eye2 : eye3) : target->W;
+  const double* Wc = per_qp || gen_tgt ? (d == 2 ? eye2 : eye3) : target->W;
   if (per_qp) {                                          // Section 3.1: det W = s^d > 0
     for (int64_t k = 0; k < mesh->n_elem * nq; ++k)
       if (!(target->W[k] > 0.0)) return TMOP_E_TARGET;
+  }
+  // General targets per element or per point (Section 3.1: W may differ at
+  // every point): W^{-1} row-major and det W > 0, d^2 + 1 values each, and
+  // (det W_q)^(1/d) per point for the displacement penalty
+  const int ts = d * d + 1;
+  std::vector<double> ptgt, psize;
+  if (gen_tgt) {
+    const int64_t nt = kind == TMOP_TGT_PER_ELEM ? mesh->n_elem : mesh->n_elem * nq;
+    ptgt.resize((size_t)nt * ts);
+    psize.resize((size_t)mesh->n_elem * nq);
+    for (int64_t k = 0; k < nt; ++k) {
+      const double* Wk = target->W + k * d * d;
+      for (int j = 0; j < d * d; ++j)
+        if (!std::isfinite(Wk[j])) return TMOP_E_TARGET;
+      const double dW = det3(Wk, d);
+      if (!(dW > 0.0) || !std::isfinite(dW)) return TMOP_E_TARGET;
+      double Wi[3][3];
+      inv3(Wk, d, Wi);
+      double* o = &ptgt[(size_t)k * ts];
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) o[i * d + j] = Wi[i][j];
+      o[d * d] = dW;
+    }
+    for (int64_t e = 0; e < mesh->n_elem; ++e)
+      for (int q = 0; q < nq; ++q) {
+        const double dW = ptgt[(size_t)(kind == TMOP_TGT_PER_ELEM ? e : e * nq + q) * ts + d * d];
+        psize[(size_t)(e * nq + q)] = d == 2 ? sqrt(dW) : cbrt(dW);
+      }
   }
   const double detW = det3(Wc, d);
   if (!(detW > 0.0)) return TMOP_E_TARGET;               // Section 3.1: det W > 0
@@ -744,10 +888,27 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
       if (gather_rows(c->d_tsize, c->d_colors, mesh->n_elem, nq, c->d_tsize_col, nullptr) != hipSuccess ||
           hipDeviceSynchronize() != hipSuccess) { st = TMOP_E_HIP; break; }
     }
+    if (gen_tgt) {  // general targets and their penalty sizes, element order and colour order
+      c->ptgt_elem = kind == TMOP_TGT_PER_ELEM;
+      c->ptgt_stride = ts;
+      const size_t pb = ptgt.size() * sizeof(double), sb = psize.size() * sizeof(double);
+      const int width = (c->ptgt_elem ? 1 : nq) * ts;
+      if (hipMalloc(&c->d_ptgt, pb) != hipSuccess) { c->d_ptgt = nullptr; st = TMOP_E_NOMEM; break; }
+      if (hipMalloc(&c->d_ptgt_col, pb) != hipSuccess) { c->d_ptgt_col = nullptr; st = TMOP_E_NOMEM; break; }
+      if (hipMalloc(&c->d_psize, sb) != hipSuccess) { c->d_psize = nullptr; st = TMOP_E_NOMEM; break; }
+      if (hipMalloc(&c->d_psize_col, sb) != hipSuccess) { c->d_psize_col = nullptr; st = TMOP_E_NOMEM; break; }
+      if (hipMemcpy(c->d_ptgt, ptgt.data(), pb, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(c->d_psize, psize.data(), sb, hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
+      if (gather_rows(c->d_ptgt, c->d_colors, mesh->n_elem, width, c->d_ptgt_col, nullptr) != hipSuccess ||
+          gather_rows(c->d_psize, c->d_colors, mesh->n_elem, nq, c->d_psize_col, nullptr) != hipSuccess ||
+          hipDeviceSynchronize() != hipSuccess) { st = TMOP_E_HIP; break; }
+    }
     std::vector<double> mask(c->n_dof, 1.0);
     if (mesh->fixed)
       for (int64_t k = 0; k < c->n_dof; ++k)
         if (mesh->fixed[k]) { mask[k] = 0.0; c->has_fixed = true; }
+    c->n_free = 0;
+    for (int64_t k = 0; k < c->n_dof; ++k) c->n_free += mask[k] > 0.0;
     if (hipMemcpy(c->d_mask, mask.data(), c->n_dof * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
   } while (0);
   if (st != TMOP_OK) { free_ctx(c); return st; }
@@ -917,7 +1078,7 @@ int install_second_term(tmop_ctx* c, int metric2, double* d_tm, int ts, double e
 int tmop_set_combo(tmop_ctx* c, int32_t metric2, const double* W2, double eta1, double eta2, const double* eta2_q,
                    void* stream) {
   if (!c || !(eta1 >= 0.0) || !std::isfinite(eta1)) return TMOP_E_ARG;
-  if (c->d_tsize) return TMOP_E_UNSUPPORTED;             // per-point targets carry their own weights
+  if (c->d_tsize || c->d_ptgt) return TMOP_E_UNSUPPORTED;   // per-point targets carry their own weights
   if (metric2 == 0) {          // back to the single term eta_1 mu
     c->metric2 = 0;
     c->base.wdetW = eta1 * c->base.detW;
@@ -954,7 +1115,7 @@ int tmop_set_combo(tmop_ctx* c, int32_t metric2, const double* W2, double eta1, 
 
 int tmop_set_replication(tmop_ctx* c, double gamma, const double* x_init, void* stream) {
   if (!c || !x_init || !(gamma >= 0.0 && gamma <= 1.0)) return TMOP_E_ARG;
-  if (c->d_tsize) return TMOP_E_UNSUPPORTED;
+  if (c->d_tsize || c->d_ptgt) return TMOP_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   double* d_tm = nullptr;
   const int ts = c->dim * c->dim + 1;
@@ -962,7 +1123,7 @@ int tmop_set_replication(tmop_ctx* c, double gamma, const double* x_init, void* 
   // W_0 = A(x_init) at every point; both parts weigh with the primary det W
   int grid = 0;
   int r = elem_launch(c, OP_JINV, x_init, nullptr, d_tm, c->d_elem_node, nullptr, c->n_elem, s, &grid, nullptr, 0,
-                      nullptr, nullptr, TermSel{-1, nullptr, (1.0 - gamma) * c->base.detW});
+                      nullptr, nullptr, [&] { TermSel t; t.omega = (1.0 - gamma) * c->base.detW; return t; }());
   double F = 0, m = 0;
   if (r == TMOP_OK) {
     r = finalize_sum_min(c->d_part, grid, (int)c->part_cap, c->d_scratch, c->d_res, s) == hipSuccess ? TMOP_OK
@@ -1105,7 +1266,7 @@ int tmop_dfo_sweep(tmop_ctx* c, double* x, const tmop_dfo_opts* opts, double* ma
   if (opts) o = *opts;
   else tmop_dfo_default_opts(&o);
   if (!dfo_opts_ok(o)) return TMOP_E_ARG;
-  if (c->d_tsize || c->metric2 || c->delta > 0.0) return TMOP_E_UNSUPPORTED;
+  if (c->d_tsize || c->d_ptgt || c->metric2 || c->delta > 0.0) return TMOP_E_UNSUPPORTED;
   return dfo_sweep(c, x, o, (hipStream_t)stream, max_move);
 }
 
@@ -1115,7 +1276,7 @@ int tmop_dfo_solve(tmop_ctx* c, double* x, const tmop_dfo_opts* opts, tmop_dfo_r
   if (opts) o = *opts;
   else tmop_dfo_default_opts(&o);
   if (!dfo_opts_ok(o)) return TMOP_E_ARG;
-  if (c->d_tsize || c->metric2 || c->delta > 0.0) return TMOP_E_UNSUPPORTED;
+  if (c->d_tsize || c->d_ptgt || c->metric2 || c->delta > 0.0) return TMOP_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   tmop_dfo_report r{};
   double F = 0, m = 0;
@@ -1155,8 +1316,9 @@ int tmop_newton_solve(tmop_ctx* c, double* x, const tmop_newton_opts* opts_in, t
   else tmop_newton_default_opts(&o);
   if (o.max_it < 0 || o.cg_max_it < 1 || o.ls_max < 0 || !(o.ls_shrink > 0.0 && o.ls_shrink < 1.0))
     return TMOP_E_ARG;
-  if ((o.inner != TMOP_INNER_CG && o.inner != TMOP_INNER_MINRES) ||
-      (o.precond != TMOP_PREC_NONE && o.precond != TMOP_PREC_JACOBI))
+  if ((o.inner != TMOP_INNER_CG && o.inner != TMOP_INNER_MINRES && o.inner != TMOP_INNER_SHIFTED_CG) ||
+      (o.precond != TMOP_PREC_NONE && o.precond != TMOP_PREC_JACOBI) ||
+      (o.inner == TMOP_INNER_SHIFTED_CG && !(o.shift_beta > 0.0 && std::isfinite(o.shift_beta))))
     return TMOP_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   const auto t_start = std::chrono::steady_clock::now();
@@ -1167,6 +1329,18 @@ int tmop_newton_solve(tmop_ctx* c, double* x, const tmop_newton_opts* opts_in, t
   if (!c->d_work) {
     if (hipMalloc(&c->d_work, (size_t)NEWTON_VECTORS * N * sizeof(double)) != hipSuccess) {
       c->d_work = nullptr;
+      return TMOP_E_NOMEM;
+    }
+  }
+  if (!c->d_sc) {
+    if (hipMalloc(&c->d_sc, SC_COUNT * sizeof(double)) != hipSuccess) {
+      c->d_sc = nullptr;
+      return TMOP_E_NOMEM;
+    }
+  }
+  if (!c->h_sc) {
+    if (hipHostMalloc(&c->h_sc, SC_COUNT * sizeof(double), 0) != hipSuccess) {
+      c->h_sc = nullptr;
       return TMOP_E_NOMEM;
     }
   }
@@ -1208,18 +1382,28 @@ int tmop_newton_solve(tmop_ctx* c, double* x, const tmop_newton_opts* opts_in, t
     double cg_tol = o.cg_rtol;
     if (o.cg_forcing) cg_tol = std::max(o.cg_rtol, std::min(0.5, sqrt(gn / rep.gnorm0)));
     const double* minv = nullptr;
+    double* diag = w.v[6];               // the shifted CG uses w.v[0..3]; MINRES overwrites it later
+    if (o.precond == TMOP_PREC_JACOBI || o.inner == TMOP_INNER_SHIFTED_CG)
+      if ((st = assemble(c, OP_DIAG, x, nullptr, diag, s)) != TMOP_OK) return st;
     if (o.precond == TMOP_PREC_JACOBI) {   // M = |diag H| at x on the free DOFs
-      if ((st = assemble(c, OP_DIAG, x, nullptr, w.minv, s)) != TMOP_OK) return st;
+      HIP_TRY(hipMemcpyAsync(w.minv, diag, N * sizeof(double), hipMemcpyDeviceToDevice, s));
       HIP_TRY(jacobi_inv(c->d_mask, w.minv, N, s));
       minv = w.minv;
     }
     int ncg = 0;
-    bool neg = false;
-    st = o.inner == TMOP_INNER_MINRES ? inner_minres(c, x, g, cg_tol, o.cg_max_it, minv, w, s, &ncg)
-                                      : inner_tcg(c, x, g, gn, cg_tol, o.cg_max_it, minv, w, s, &ncg, &neg);
+    if (o.inner == TMOP_INNER_MINRES) {
+      st = inner_minres(c, x, g, cg_tol, o.cg_max_it, minv, w, s, &ncg);
+    } else if (o.inner == TMOP_INNER_SHIFTED_CG) {
+      int nrestart = 0;
+      st = inner_shifted_cg(c, x, g, gn, cg_tol, o.cg_max_it, minv, diag, o.shift_beta, w, s, &ncg, &nrestart);
+      rep.neg_curv += nrestart;
+    } else {
+      bool neg = false;
+      st = inner_tcg(c, x, g, gn, cg_tol, o.cg_max_it, minv, w, s, &ncg, &neg);
+      if (neg) rep.neg_curv++;
+    }
     if (st != TMOP_OK) return st;
     rep.cg_iters += ncg;
-    if (neg) rep.neg_curv++;
     // ---- line search (Section 3.4): det A > 0, F and |g| growth below 1.2x
     bool accepted = false;
     double Ft = 0, mindt = 0, ggt = 0;

@@ -211,6 +211,236 @@ __global__ void __launch_bounds__(RED_THREADS) k_fold_chunks(const double* __res
   }
 }
 
+
+// ------------------------------------------------------------------------
+// Krylov solvers with device-resident scalars.  The scalar state of a CG or
+// MINRES run lives in a small device array sc (layout SC_* in
+// tmop_internal.h); one-block kernels update it between the vector kernels,
+// which read their coefficients from it, so the host enqueues iterations
+// without waiting and only reads sc back at check points.  An iteration
+// runs while sc[SC_ACTIVE] is set: the first kernel of each iteration copies
+// it to sc[SC_RUN], which every later kernel of the iteration tests; a run
+// that ends clears SC_ACTIVE for the iterations still in the queue.
+
+// Fixed-order fold of RED_BLOCKS partial sums by one block.
+__device__ __forceinline__ double fold_parts(const double* __restrict__ part, double* red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += RED_THREADS) s += part[i];
+  return block_sum(s, red);
+}
+
+// Block partial sums of p . (m .* Hp + tau p) (p vanishes where m does).
+__global__ void __launch_bounds__(RED_THREADS) k_dot_shift_part(const double* __restrict__ p,
+                                                                const double* __restrict__ Hp, double tau, int64_t n,
+                                                                const double* __restrict__ sc, double* __restrict__ part) {
+  __shared__ double red[RED_THREADS / 64];
+  if (sc[SC_ACTIVE] == 0.0) return;
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)RED_BLOCKS * RED_THREADS) {
+    const double pi = p[i];
+    s += pi * (Hp[i] + tau * pi);
+  }
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// CG: pHp from the partials; curvature test; alpha = rz / pHp.
+__global__ void __launch_bounds__(RED_THREADS) k_cg_alpha(const double* __restrict__ part, double* __restrict__ sc) {
+  __shared__ double red[RED_THREADS / 64];
+  const double run = sc[SC_ACTIVE];
+  if (run == 0.0) {
+    if (threadIdx.x == 0) sc[SC_RUN] = 0.0;
+    return;
+  }
+  const double pHp = fold_parts(part, red);
+  if (threadIdx.x == 0) {
+    sc[SC_RUN] = 1.0;
+    sc[SC_ITERS] += 1.0;
+    sc[SC_PHP] = pHp;
+    if (!(pHp > 0.0)) {               // non-positive curvature (or NaN): the run ends here, d unchanged
+      sc[SC_NEG] = 1.0;
+      sc[SC_RUN] = 0.0;
+      sc[SC_ACTIVE] = 0.0;
+    } else {
+      sc[SC_ALPHA] = sc[SC_RZ] / pHp;
+    }
+  }
+}
+
+// CG update: d += alpha p; r -= alpha (m .* Hp + tau p); z = minv .* r;
+// block partial sums of r . r and, with minv, r . z.
+__global__ void __launch_bounds__(RED_THREADS) k_cg_update(const double* __restrict__ p, const double* __restrict__ Hp,
+                                                           double tau, const double* __restrict__ m,
+                                                           const double* __restrict__ minv, double* __restrict__ d,
+                                                           double* __restrict__ r, double* __restrict__ z, int64_t n,
+                                                           const double* __restrict__ sc, double* __restrict__ part) {
+  __shared__ double red[2][RED_THREADS / 64];
+  if (sc[SC_RUN] == 0.0) return;
+  const double a = sc[SC_ALPHA];
+  double srr = 0.0, srz = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)RED_BLOCKS * RED_THREADS) {
+    const double pi = p[i];
+    const double hi = (m ? Hp[i] * m[i] : Hp[i]) + tau * pi;
+    d[i] += a * pi;
+    const double ri = r[i] - a * hi;
+    r[i] = ri;
+    srr += ri * ri;
+    if (minv) {
+      const double zi = minv[i] * ri;
+      z[i] = zi;
+      srz += ri * zi;
+    }
+  }
+  const double trr = block_sum(srr, red[0]);
+  const double trz = block_sum(srz, red[1]);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = trr;
+    part[RED_BLOCKS + blockIdx.x] = trz;
+  }
+}
+
+// CG: convergence test |r| <= tol_abs, then beta = rz_new / rz.
+__global__ void __launch_bounds__(RED_THREADS) k_cg_beta(const double* __restrict__ part, int precond, double tol_abs,
+                                                         double* __restrict__ sc) {
+  __shared__ double red[2][RED_THREADS / 64];
+  if (sc[SC_RUN] == 0.0) return;
+  const double rr = fold_parts(part, red[0]);
+  const double rz = precond ? fold_parts(part + RED_BLOCKS, red[1]) : rr;
+  if (threadIdx.x == 0) {
+    sc[SC_RR] = rr;
+    if (sqrt(rr) <= tol_abs || sc[SC_ITERS] >= sc[SC_MAXIT]) {
+      sc[SC_RUN] = 0.0;
+      sc[SC_ACTIVE] = 0.0;
+    } else {
+      sc[SC_BETA] = rz / sc[SC_RZ];
+      sc[SC_RZ] = rz;
+    }
+  }
+}
+
+// CG: p = z + beta p.
+__global__ void __launch_bounds__(VB) k_cg_dir(const double* __restrict__ z, double* __restrict__ p, int64_t n,
+                                               const double* __restrict__ sc) {
+  if (sc[SC_RUN] == 0.0) return;
+  const double b = sc[SC_BETA];
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) p[i] = z[i] + b * p[i];
+}
+
+// MINRES: alpha = v . Hv (iteration start: SC_ACTIVE -> SC_RUN).
+__global__ void __launch_bounds__(RED_THREADS) k_mr_alpha(const double* __restrict__ part, double* __restrict__ sc) {
+  __shared__ double red[RED_THREADS / 64];
+  if (sc[SC_ACTIVE] == 0.0) {
+    if (threadIdx.x == 0) sc[SC_RUN] = 0.0;
+    return;
+  }
+  const double a = fold_parts(part, red);
+  if (threadIdx.x == 0) {
+    sc[SC_RUN] = 1.0;
+    sc[SC_ITERS] += 1.0;
+    sc[SC_ALPHA] = a;
+  }
+}
+
+// MINRES: r_next = m .* Hv - (alpha / beta) r_cur - (beta / beta_prev) r_prev
+// over Hv (first iteration: no r_prev term), y = minv .* r_next, partial sums
+// of r_next . y.
+__global__ void __launch_bounds__(RED_THREADS) k_mr_r(double* __restrict__ Hv, const double* __restrict__ m,
+                                                      const double* __restrict__ r_cur,
+                                                      const double* __restrict__ r_prev,
+                                                      const double* __restrict__ minv, double* __restrict__ y,
+                                                      int64_t n, const double* __restrict__ sc,
+                                                      double* __restrict__ part) {
+  __shared__ double red[RED_THREADS / 64];
+  if (sc[SC_RUN] == 0.0) return;
+  const double beta = sc[SC_BETA], bprev = sc[SC_BPREV];
+  const double a1 = -sc[SC_ALPHA] / beta;
+  const double a2 = bprev > 0.0 ? -beta / bprev : 0.0;
+  double sum = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)RED_BLOCKS * RED_THREADS) {
+    double t = m ? Hv[i] * m[i] : Hv[i];
+    t += a1 * r_cur[i];
+    if (a2 != 0.0) t += a2 * r_prev[i];
+    Hv[i] = t;
+    if (minv) {
+      const double yi = minv[i] * t;
+      y[i] = yi;
+      sum += t * yi;
+    } else {
+      sum += t * t;
+    }
+  }
+  const double ts = block_sum(sum, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = ts;
+}
+
+// MINRES scalars (Paige and Saunders): beta_{k+1}, the previous rotation on
+// the new column, the rotation that annihilates beta_{k+1}, phi and phibar,
+// the coefficients of the direction update, and the stopping test.
+__global__ void __launch_bounds__(RED_THREADS) k_mr_rot(const double* __restrict__ part, double* __restrict__ sc) {
+  __shared__ double red[RED_THREADS / 64];
+  if (sc[SC_RUN] == 0.0) return;
+  const double bn2 = fold_parts(part, red);
+  if (threadIdx.x != 0) return;
+  const double bnext = sqrt(fmax(bn2, 0.0));
+  const double cs = sc[SC_CS], sn = sc[SC_SN], dbar = sc[SC_DBAR], alpha = sc[SC_ALPHA];
+  const double eps_k = sc[SC_EPS];
+  const double delta = cs * dbar + sn * alpha;
+  const double gbar = sn * dbar - cs * alpha;
+  sc[SC_EPS] = sn * bnext;
+  sc[SC_DBAR] = -cs * bnext;
+  double gamma = hypot(gbar, bnext);
+  if (gamma == 0.0) gamma = 2.2250738585072014e-308;
+  const double c2 = gbar / gamma, s2 = bnext / gamma;
+  sc[SC_CS] = c2;
+  sc[SC_SN] = s2;
+  const double phibar = sc[SC_PHIBAR];
+  sc[SC_PHI] = c2 * phibar;
+  sc[SC_PHIBAR] = s2 * phibar;
+  sc[SC_WE] = eps_k;
+  sc[SC_WDL] = delta;
+  sc[SC_WSG] = 1.0 / gamma;
+  const bool last = fabs(s2 * phibar) <= sc[SC_TOL] * sc[SC_BETA1] || !(bnext > 0.0) || sc[SC_ITERS] >= sc[SC_MAXIT];
+  sc[SC_RB] = last ? 0.0 : 1.0 / bnext;
+  sc[SC_BPREV] = sc[SC_BETA];
+  sc[SC_BETA] = bnext;
+  if (last) sc[SC_ACTIVE] = 0.0;
+}
+
+// MINRES: w_prev <- (v - eps w_prev - delta w_cur) / gamma; d += phi w_prev;
+// the next Lanczos vector v <- y / beta_{k+1} unless the run ends here.
+__global__ void __launch_bounds__(VB) k_mr_wd(double* __restrict__ v, double* __restrict__ w_prev,
+                                              const double* __restrict__ w_cur, double* __restrict__ d,
+                                              const double* __restrict__ y, int64_t n, const double* __restrict__ sc) {
+  if (sc[SC_RUN] == 0.0) return;
+  const double e = sc[SC_WE], dl = sc[SC_WDL], sg = sc[SC_WSG], phi = sc[SC_PHI], rb = sc[SC_RB];
+  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+    const double wn = (v[i] - e * w_prev[i] - dl * w_cur[i]) * sg;
+    w_prev[i] = wn;
+    d[i] += phi * wn;
+    if (rb != 0.0) v[i] = rb * y[i];
+  }
+}
+
+// Over the free DOFs (m > 0): partial sums of |d| and partial minima of d.
+__global__ void __launch_bounds__(RED_THREADS) k_free_stats_part(const double* __restrict__ d,
+                                                                 const double* __restrict__ m, int64_t n,
+                                                                 double* __restrict__ part) {
+  __shared__ double red[2][RED_THREADS / 64];
+  double s = 0.0, mn = __builtin_huge_val();
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)RED_BLOCKS * RED_THREADS) {
+    if (!m || m[i] > 0.0) {
+      s += fabs(d[i]);
+      mn = fmin(mn, d[i]);
+    }
+  }
+  const double ts = block_sum(s, red[0]);
+  const double tm = block_min(mn, red[1]);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = ts;
+    part[RED_BLOCKS + blockIdx.x] = tm;
+  }
+}
+
 }  // namespace
 
 hipError_t fill(double* y, double v, int64_t n, hipStream_t s) {
@@ -295,6 +525,43 @@ hipError_t gather_rows(const double* src, const int32_t* rows, int64_t n, int w,
 
 hipError_t mask_mul(const double* m, double* y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_mask_mul, dim3(vgrid(n)), dim3(VB), 0, s, m, y, n);
+  return hipGetLastError();
+}
+
+hipError_t cg_dev_curvature(const double* p, const double* Hp, double tau, int64_t n, double* scratch, double* sc,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_shift_part, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, p, Hp, tau, n, sc, scratch);
+  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(RED_THREADS), 0, s, scratch, sc);
+  return hipGetLastError();
+}
+
+hipError_t cg_dev_update(const double* p, const double* Hp, double tau, const double* m, const double* minv, double* d,
+                         double* r, double* z, int64_t n, double tol_abs, double* scratch, double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_update, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, p, Hp, tau, m, minv, d, r, z, n, sc,
+                     scratch);
+  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(RED_THREADS), 0, s, scratch, minv ? 1 : 0, tol_abs, sc);
+  hipLaunchKernelGGL(k_cg_dir, dim3(vgrid(n)), dim3(VB), 0, s, minv ? z : r, (double*)p, n, sc);
+  return hipGetLastError();
+}
+
+hipError_t mr_dev_alpha(const double* v, const double* Hv, int64_t n, double* scratch, double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_shift_part, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, v, Hv, 0.0, n, sc, scratch);
+  hipLaunchKernelGGL(k_mr_alpha, dim3(1), dim3(RED_THREADS), 0, s, scratch, sc);
+  return hipGetLastError();
+}
+
+hipError_t mr_dev_step(double* Hv, const double* m, const double* r_cur, const double* r_prev, const double* minv,
+                       double* y, double* v, double* w_prev, const double* w_cur, double* d, int64_t n,
+                       double* scratch, double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_mr_r, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, Hv, m, r_cur, r_prev, minv, y, n, sc, scratch);
+  hipLaunchKernelGGL(k_mr_rot, dim3(1), dim3(RED_THREADS), 0, s, scratch, sc);
+  hipLaunchKernelGGL(k_mr_wd, dim3(vgrid(n)), dim3(VB), 0, s, v, w_prev, w_cur, d, minv ? y : Hv, n, sc);
+  return hipGetLastError();
+}
+
+hipError_t free_stats(const double* d, const double* m, int64_t n, double* scratch, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(k_free_stats_part, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, d, m, n, scratch);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RED_THREADS), 0, s, scratch, RED_BLOCKS, RED_BLOCKS, 1, res);
   return hipGetLastError();
 }
 

@@ -72,8 +72,11 @@ struct ElemArgs {
   const double* __restrict__ scale;      // OP_GRAD: optional device scalar multiplying g (nullptr = 1)
   const double* __restrict__ tsize;      // TGT_QPS: [n_list][Q^dim] target sizes s_q (W_q = s_q I), point
                                          // index q0 + Q q1 (+ Q^2 q2), in the order of elem_node
-  const double* __restrict__ tmat;       // TGT_MAT: [n_list][Q^dim][dim^2 + 1] W_q^{-1} (row-major) and omega_q;
+  const double* __restrict__ tmat;       // TGT_MAT: W_q^{-1} (row-major) and omega_q, dim^2 + 1 values per point,
+                                         // per point [n_list][Q^dim] or per element [n_list] (tm_el, tm_pt);
                                          // TGT_CW: [n_list][Q^dim] omega_q (W^{-1} = Winv)
+  int32_t tm_el;                         // TGT_MAT: values between consecutive elements of tmat
+  int32_t tm_pt;                         // TGT_MAT: values between consecutive points (0: one target per element)
   int64_t n_node;
   int32_t n_list;
   R B[Q][P];
@@ -258,6 +261,15 @@ __device__ __forceinline__ double load_point_target3(const double* __restrict__ 
       Wi[i][j] = (R)Wid[i][j];
     }
   return tm[9];
+}
+
+// TGT_MAT / TGT_CW: the target data of point row `row` (q0 = 0 there) of
+// element e; the row's points follow at steps of a.tm_pt (TGT_MAT) or 1.
+template <int NQ, int TGT, typename Args>
+__device__ __forceinline__ const double* target_row(const Args& a, int e, int row) {
+  if constexpr (TGT == TGT_MAT) return a.tmat + (int64_t)e * a.tm_el + (int64_t)row * a.tm_pt;
+  else if constexpr (TGT == TGT_CW) return a.tmat + (int64_t)e * NQ + row;
+  else return nullptr;
 }
 
 // Per-point kernel of the operations.  Given A (and dA) -- already divided
@@ -634,9 +646,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
-    const double* tm = TGT == TGT_MAT || TGT == TGT_CW
-                           ? a.tmat + ((int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb) * (TGT == TGT_MAT ? 10 : 1)
-                           : nullptr;
+    const double* tm = target_row<Q * Q * Q, TGT>(a, e, Q * ta + Q * Q * tb);
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[3][3], dA[3][3];
@@ -669,7 +679,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
       if constexpr (TGT == TGT_MAT) {
         R Wi[3][3];
         double Wid[3][3];
-        wdet *= load_point_target3<R>(tm + 10 * q0, Wi, Wid);
+        wdet *= load_point_target3<R>(tm + a.tm_pt * q0, Wi, Wid);
         kY = wdet;
         point_op<3, METRIC, R, OP, false>(Wi, Wid, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
       } else {
@@ -967,8 +977,7 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
-    const double* tm =
-        TGT == TGT_MAT || TGT == TGT_CW ? a.tmat + ((int64_t)e * (Q * Q) + Q * ta) * (TGT == TGT_MAT ? 5 : 1) : nullptr;
+    const double* tm = target_row<Q * Q, TGT>(a, e, Q * ta);
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[2][2], dA[2][2];
@@ -993,7 +1002,7 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
       if constexpr (TGT == TGT_MAT) {
         R Wi[3][3];
         double Wid[3][3];
-        wdet *= load_point_target2<R>(tm + 5 * q0, Wi, Wid);
+        wdet *= load_point_target2<R>(tm + a.tm_pt * q0, Wi, Wid);
         kY = wdet;
         point_op<2, METRIC, R, OP, false>(Wi, Wid, A, dA, wdet, detWq, kY, acc, mind, Y, detA);
       } else {
@@ -1203,9 +1212,7 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
-    const double* tm = TGT == TGT_MAT || TGT == TGT_CW
-                           ? a.tmat + ((int64_t)e * (Q * Q * Q) + Q * ta + Q * Q * tb) * (TGT == TGT_MAT ? 10 : 1)
-                           : nullptr;
+    const double* tm = target_row<Q * Q * Q, TGT>(a, e, Q * ta + Q * Q * tb);
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[3][3];
@@ -1234,7 +1241,7 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
       if constexpr (TGT == TGT_MAT) {
         R Wi[3][3];
         double Wid[3][3];
-        kK *= load_point_target3<R>(tm + 10 * q0, Wi, Wid);
+        kK *= load_point_target3<R>(tm + a.tm_pt * q0, Wi, Wid);
         right_mul<3, R, false>(A, Wi, T);
         mu_second_rows<METRIC, R>(T, (R)kK, K);
         target_congruence<3, R>(Wi, K);
@@ -1371,8 +1378,7 @@ diag_kernel_2d(const DiagArgs<P, Q, R> a) {
 #pragma unroll
       for (int q0 = 0; q0 < Q; ++q0) sq[q0] = ts[q0];
     }
-    const double* tm =
-        TGT == TGT_MAT || TGT == TGT_CW ? a.tmat + ((int64_t)e * (Q * Q) + Q * ta) * (TGT == TGT_MAT ? 5 : 1) : nullptr;
+    const double* tm = target_row<Q * Q, TGT>(a, e, Q * ta);
 #pragma unroll
     for (int q0 = 0; q0 < Q; ++q0) {
       R A[2][2];
@@ -1396,7 +1402,7 @@ diag_kernel_2d(const DiagArgs<P, Q, R> a) {
       if constexpr (TGT == TGT_MAT) {
         R Wi[3][3];
         double Wid[3][3];
-        kK *= load_point_target2<R>(tm + 5 * q0, Wi, Wid);
+        kK *= load_point_target2<R>(tm + a.tm_pt * q0, Wi, Wid);
         right_mul<2, R, false>(A, Wi, T);
         mu_second_rows<METRIC, R>(T, (R)kK, K);
         target_congruence<2, R>(Wi, K);

@@ -41,6 +41,8 @@ struct LaunchParams {
   const double* tmat;      // per-point targets [n_list][Q^dim][tms]: W^{-1} row-major and the weight
                            // omega_q (the term is sum_q w_q omega_q mu(A W_q^{-1})), or nullptr
   int tms;                 // values per point of tmat: dim^2 + 1, or 1 (omega_q alone, W^{-1} = Winv)
+  int tm_el, tm_pt;        // tms == dim^2 + 1: values between elements and between points of tmat
+                           // (tm_pt = 0: one target per element)
   double B[MAXQ][MAXP];
   double G[MAXQ][MAXP];
   double w[MAXQ];
@@ -54,6 +56,7 @@ struct LaunchParams {
   bool pen;
   double M1[MAXP][MAXP];   // 1D mass matrix of the quadrature
   double kpen;             // 2 delta det W
+  bool dry;                // only report the grid (*grid), launch nothing
 };
 
 // Everything one launch of the displacement-penalty kernels (eq. 4.2)
@@ -73,6 +76,7 @@ struct MassParams {
   double B[MAXQ][MAXP];
   double w[MAXQ];
   double k;                // 2 delta det W (per-point sizes: 2 delta, times s_q^d in the kernel)
+  bool dry;                // only report the grid (*grid), launch nothing
 };
 int launch_mass(int dim, int p, int Q, int op, const MassParams& mp, hipStream_t s, int* grid);
 
@@ -135,6 +139,32 @@ hipError_t minres_r(double* Hv, const double* m, double a1, const double* r_cur,
 // MINRES: w_prev <- (v - e w_prev - dl w_cur) sg; d += phi w_prev; v <- rb y (y may be nullptr: v kept)
 hipError_t minres_wd(double* v, double e, double* w_prev, double dl, const double* w_cur, double sg, double phi,
                      double* d, const double* y, double rb, int64_t n, hipStream_t s);
+// Krylov solvers with device-resident scalars: the run state lives in sc
+// [SC_COUNT] doubles (indices below); see tmop_blas.hip.
+enum {
+  SC_ACTIVE = 0, SC_RUN, SC_ITERS, SC_MAXIT, SC_NEG,        // run control (flags as 0/1), counters
+  SC_RZ, SC_ALPHA, SC_BETA, SC_PHP, SC_RR,                  // CG
+  SC_BPREV, SC_CS, SC_SN, SC_DBAR, SC_EPS, SC_PHI, SC_PHIBAR, SC_BETA1, SC_TOL,   // MINRES
+  SC_WE, SC_WDL, SC_WSG, SC_RB,
+  SC_COUNT
+};
+// CG iteration, part 1: sc[SC_PHP] = p . (Hp + tau p); non-positive
+// curvature ends the run (SC_NEG); else sc[SC_ALPHA] = sc[SC_RZ] / pHp.
+hipError_t cg_dev_curvature(const double* p, const double* Hp, double tau, int64_t n, double* scratch, double* sc,
+                            hipStream_t s);
+// CG iteration, part 2: d += alpha p, r -= alpha (m .* Hp + tau p), z = minv .* r;
+// the run ends once |r| <= tol_abs or after SC_MAXIT iterations; else p = z + beta p.
+hipError_t cg_dev_update(const double* p, const double* Hp, double tau, const double* m, const double* minv, double* d,
+                         double* r, double* z, int64_t n, double tol_abs, double* scratch, double* sc, hipStream_t s);
+// MINRES iteration: alpha = v . Hv, then the residual recurrence, the
+// rotations and the direction update (the run ends at the tolerance
+// SC_TOL * SC_BETA1 on |phibar|, a zero beta or SC_MAXIT iterations).
+hipError_t mr_dev_alpha(const double* v, const double* Hv, int64_t n, double* scratch, double* sc, hipStream_t s);
+hipError_t mr_dev_step(double* Hv, const double* m, const double* r_cur, const double* r_prev, const double* minv,
+                       double* y, double* v, double* w_prev, const double* w_cur, double* d, int64_t n,
+                       double* scratch, double* sc, hipStream_t s);
+// res[0] = sum of |d| over the free DOFs (m > 0; m = nullptr: all), res[1] = their min.
+hipError_t free_stats(const double* d, const double* m, int64_t n, double* scratch, double* res, hipStream_t s);
 hipError_t axpy(double a, const double* x, double* y, int64_t n, hipStream_t s);          // y += a x
 hipError_t xpay(const double* x, double a, double* y, int64_t n, hipStream_t s);          // y = x + a y
 hipError_t waxpy(const double* x, double a, const double* d, double* w, int64_t n, hipStream_t s);  // w = x + a d
@@ -162,6 +192,13 @@ struct tmop_ctx {
   int nq = 0;                          // quadrature points per element, Q^dim
   double* d_tsize = nullptr;           // TMOP_TGT_ISO_PER_QP: [n_elem][nq] sizes s_q, element order
   double* d_tsize_col = nullptr;       // the same in colour order
+  double* d_ptgt = nullptr;            // TMOP_TGT_PER_ELEM / PER_QP: per element or per point W^{-1}
+                                       // (row-major) and det W, ptgt_stride values each, element order
+  double* d_ptgt_col = nullptr;        // the same in colour order
+  bool ptgt_elem = false;              // d_ptgt holds one target per element
+  int ptgt_stride = 0;                 // dim^2 + 1
+  double* d_psize = nullptr;           // [n_elem][nq] (det W_q)^(1/dim) of those targets (the penalty's
+  double* d_psize_col = nullptr;       // det W), element and colour order
   double* d_mask = nullptr;            // [n_dof], 1 = free DOF
   bool has_fixed = false;
   double* d_part = nullptr;            // [2 * part_cap] energy partials: sums, then minima
@@ -186,6 +223,9 @@ struct tmop_ctx {
   double* d_res = nullptr;             // [4] reduction results
   double* h_res = nullptr;             // [4] pinned mirror
   double* d_work = nullptr;            // Newton work vectors, allocated on first use
+  double* d_sc = nullptr;              // [SC_COUNT] scalar state of the Krylov solvers
+  double* h_sc = nullptr;              // its pinned host mirror
+  int64_t n_free = 0;                  // free DOFs (mask 1)
   // optional per-launch timing of the element kernels (HIP events)
   struct TimedLaunch { int op; hipEvent_t a, b; };
   bool timing = false;

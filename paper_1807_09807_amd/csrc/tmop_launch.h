@@ -19,6 +19,8 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   a.n_node = lp.n_node; a.n_list = lp.n_list;
   a.tsize = lp.tsize;
   a.tmat = lp.tmat;
+  a.tm_el = lp.tm_el;
+  a.tm_pt = lp.tm_pt;
   a.wdetW = lp.wdetW;
   a.kpen = lp.kpen;
   for (int i = 0; i < P; ++i)
@@ -37,7 +39,7 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
     for (int j = 0; j < 3; ++j) a.Winvd[i][j] = lp.Winv[i][j];
   const int g = (lp.n_list + C::EPB - 1) / C::EPB;
   *grid = g;
-  if (g == 0) return 0;
+  if (g == 0 || lp.dry) return 0;
   if constexpr (OP == OP_DIAG) {
     // products of the 1D tables for the squared gradients of the diagonal
     for (int q = 0; q < Q; ++q)

@@ -369,7 +369,7 @@ static int mass_one(const MassParams& mp, hipStream_t s, int* grid) {
   }
   const int g = (mp.n_list + C::EPB - 1) / C::EPB;
   *grid = g;
-  if (g == 0) return 0;
+  if (g == 0 || mp.dry) return 0;
   if constexpr (DIM == 3) hipLaunchKernelGGL((mass_kernel_3d<P, Q, OP, QPS>), dim3(g), dim3(C::BLOCK), 0, s, a);
   else hipLaunchKernelGGL((mass_kernel_2d<P, Q, OP, QPS>), dim3(g), dim3(C::BLOCK), 0, s, a);
   return hipGetLastError() == hipSuccess ? 0 : -2;

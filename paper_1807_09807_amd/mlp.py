@@ -264,8 +264,10 @@ def evaluate(mlp, n: int = 512, seeds=(10000,), precision=T.TMOP_FP64, log=None)
     """Plain Newton from x0 against learned-guess Newton, per seed: wall
     seconds and iterations to F_tol = F_ref + 1e-8 F0 (F_ref: final F of
     plain Newton run to its relative gradient tolerance; the row records
-    whether that reference converged), with fallback to x0 if the
-    proposal is unusable."""
+    whether that reference converged).  Plain Newton from x0 is the
+    fallback, both when the proposal is unusable (inverted or not below
+    F0) and when Newton from the proposal does not reach F_tol; the
+    fallback's time counts against the learned run."""
     import torch
     mesh, ctx = box_context(n, precision)
     bad = _valid_by_library(ctx)
@@ -296,15 +298,27 @@ def evaluate(mlp, n: int = 512, seeds=(10000,), precision=T.TMOP_FP64, log=None)
             used = stm == T.TMOP_OK and md > 0 and Fm < F0
         xs = xl if used else x0.clone()
         st_l, rl = ctx.newton_solve(xs, ftarget=F_tol, **EVAL_OPTS)
+        # a learned start that does not reach F_tol falls back to plain Newton
+        # from x0, whose time is added to the learned run's
+        fell_back = used and (st_l != T.TMOP_OK or not rl["F"] <= F_tol)
+        iters_l, cg_l = rl["iters"], rl["cg_iters"]
+        if fell_back:
+            xs = x0.clone()
+            st_l, rl = ctx.newton_solve(xs, ftarget=F_tol, **EVAL_OPTS)
+            iters_l += rl["iters"]
+            cg_l += rl["cg_iters"]
         torch.cuda.synchronize()
         t_learn = time.perf_counter() - t0
         row = dict(seed=sd, F0=F0, F_tol=F_tol, F_proposal=Fm if mlp is not None else None, used_proposal=used,
                    reference=dict(iters=ref["iters"], F=ref["F"], status=st_ref, converged=st_ref == T.TMOP_OK),
-                   plain=dict(iters=rp["iters"], cg=rp["cg_iters"], wall_s=t_plain, F=rp["F"], status=st_p),
-                   learned=dict(iters=rl["iters"], cg=rl["cg_iters"], wall_s=t_learn, F=rl["F"], status=st_l))
+                   plain=dict(iters=rp["iters"], cg=rp["cg_iters"], wall_s=t_plain, F=rp["F"], status=st_p,
+                              reached_F_tol=bool(rp["F"] <= F_tol)),
+                   learned=dict(iters=iters_l, cg=cg_l, wall_s=t_learn, F=rl["F"], status=st_l,
+                                reached_F_tol=bool(rl["F"] <= F_tol), fell_back_after_solve=fell_back))
         rows.append(row)
         if log:
-            log(f"  eval seed {sd}: reference {ref['iters']} it (status {st_ref}); plain {rp['iters']} it / {rp['cg_iters']} CG / {t_plain:.3f} s; learned "
-                f"{'(proposal used) ' if used else '(fallback) '}{rl['iters']} it / {rl['cg_iters']} CG / "
+            kind = "(proposal used, then fallback) " if fell_back else "(proposal used) " if used else "(fallback) "
+            log(f"  eval seed {sd}: reference {ref['iters']} it (status {st_ref}); plain {rp['iters']} it / "
+                f"{rp['cg_iters']} CG / {t_plain:.3f} s; learned {kind}{iters_l} it / {cg_l} CG / "
                 f"{t_learn:.3f} s; F0 {F0:.4e} -> proposal {row['F_proposal']}")
     return rows

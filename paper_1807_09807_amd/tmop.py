@@ -25,8 +25,8 @@ TMOP_MU1, TMOP_MU2, TMOP_MU7, TMOP_MU9, TMOP_MU14, TMOP_MU77, TMOP_MU98 = 1, 2, 
 TMOP_MU302, TMOP_MU303 = 302, 303
 TMOP_GAUSS_LEGENDRE, TMOP_GAUSS_LOBATTO = 0, 1
 TMOP_FP64, TMOP_MIXED_FP32 = 0, 1
-TMOP_TGT_CONST, TMOP_TGT_ISO_PER_QP = 0, 1
-TMOP_INNER_CG, TMOP_INNER_MINRES = 0, 1
+TMOP_TGT_CONST, TMOP_TGT_ISO_PER_QP, TMOP_TGT_PER_ELEM, TMOP_TGT_PER_QP = 0, 1, 2, 3
+TMOP_INNER_CG, TMOP_INNER_MINRES, TMOP_INNER_SHIFTED_CG = 0, 1, 2
 TMOP_PREC_NONE, TMOP_PREC_JACOBI = 0, 1
 
 EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_gradient_scaled", "tmop_hessian_apply",
@@ -66,7 +66,7 @@ class tmop_newton_opts(ctypes.Structure):
                 ("hist_F", ctypes.POINTER(ctypes.c_double)), ("hist_gnorm", ctypes.POINTER(ctypes.c_double)),
                 ("hist_cg", ctypes.POINTER(ctypes.c_int32)), ("ftarget", ctypes.c_double),
                 ("cg_forcing", ctypes.c_int32), ("hist_time", ctypes.POINTER(ctypes.c_double)),
-                ("inner", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("inner", ctypes.c_int32), ("precond", ctypes.c_int32), ("shift_beta", ctypes.c_double)]
 
 
 class tmop_newton_report(ctypes.Structure):
@@ -164,8 +164,10 @@ def _check_field(t, dim, n_node, name):
 
 class Context:
     """Owns one tmop_ctx (tmop_setup ... tmop_destroy).  The target is the
-    constant matrix W, or, when `target_sizes` ([n_elem][n_q1d^dim] host
-    array) is given, the per-point isotropic targets W_q = s_q I."""
+    constant matrix W; or, when `target_sizes` ([n_elem][n_q1d^dim] host
+    array) is given, the per-point isotropic targets W_q = s_q I; or, when W
+    is a host array of shape (n_elem, dim, dim) or (n_elem, n_q1d^dim, dim,
+    dim), general targets per element or per quadrature point."""
 
     def __init__(self, dim: int, order: int, elem_node: np.ndarray, n_node: int, n_q1d: int, metric: int,
                  W, fixed: Optional[np.ndarray] = None, precision: int = TMOP_FP64,
@@ -189,8 +191,18 @@ class Context:
                 raise ValueError(f"target_sizes must have shape ({self.n_elem}, {self.nq})")
             t = tmop_target(TMOP_TGT_ISO_PER_QP, Wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         else:
-            Wa = np.ascontiguousarray(np.asarray(W, dtype=np.float64).reshape(dim, dim))
-            t = tmop_target(TMOP_TGT_CONST, Wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+            Wa = np.ascontiguousarray(np.asarray(W, dtype=np.float64))
+            if Wa.shape == (self.n_elem, dim, dim) and Wa.ndim == 3:
+                kind = TMOP_TGT_PER_ELEM
+            elif Wa.shape == (self.n_elem, self.nq, dim, dim):
+                kind = TMOP_TGT_PER_QP
+            elif Wa.size == dim * dim:
+                kind = TMOP_TGT_CONST
+                Wa = Wa.reshape(dim, dim)
+            else:
+                raise ValueError(f"W must be ({dim}, {dim}), (n_elem, {dim}, {dim}) or "
+                                 f"(n_elem, {self.nq}, {dim}, {dim}), got {Wa.shape}")
+            t = tmop_target(kind, Wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         h = ctypes.c_void_p()
         st = lib.tmop_setup(ctypes.byref(m), ctypes.byref(q), ctypes.byref(t), metric, precision, ctypes.byref(h))
         if st < 0:

@@ -90,24 +90,17 @@ def rel_max_err(got, ref):
     return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
 
 
-EPS32 = 2.0 ** -24
+def mixed_tol(prob, x, v=None, diag=False):
+    """Bars of the mixed FP32 path, one per result: the first-order
+    worst-case rounding bounds of oracle/fp32_bound.py (F and min det A
+    relative to their values; g, Hv and the diagonal as max DOF error over
+    the largest exact entry).  Derived from the arithmetic, not fitted; the
+    CPU tests hold an FP32 emulation to them."""
+    from oracle import fp32_bound
+    return fp32_bound.bounds(prob, x, v, diag=diag)
 
 
-def mixed_tol(prob, x, elems=None):
-    """Tolerance of the mixed FP32 path: 1e-5, or 8 eps32 kappa on meshes
-    whose worst point has condition kappa > 21.  Rounding A to FP32 perturbs
-    it by eps32 relative; the metric derivatives amplify a relative
-    perturbation of A by up to kappa = (|T|^2/d)^(d/2) / det T.  The
-    constant covers the FP32 sums over the P and Q terms of the three
-    contractions: the largest error seen over every case, metric and
-    operation is 7.1 eps32 kappa (Hessian action and diagonal of a Q3 mu_9
-    mesh with W = h I, kappa 57, at the node of its largest Hessian entry;
-    mu_9's second derivative carries 1/tau^3, so its amplification can
-    exceed kappa)."""
-    return max(1e-5, MIXED_C * EPS32 * prob.max_condition(x, elems))
-
-
-MIXED_C = 8.0
+TARGET_FP32 = 1e-5   # the stated accuracy target of the FP32 path (F, |dF/dx|, Hessian action)
 
 
 def say(*a):

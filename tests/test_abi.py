@@ -35,7 +35,7 @@ def test_strerror():
 
 
 def _setup_status(dim=2, order=2, n=2, Q=4, metric=2, W=None, prec=0, rule=0, elem_node=None, n_node=None,
-                  n_elem=None):
+                  n_elem=None, kind=0):
     lib = T.load()
     mesh = meshgen.box_mesh(dim if dim in (2, 3) else 2, n, max(order, 1))
     en = np.ascontiguousarray(mesh.elem_node if elem_node is None else elem_node, dtype=np.int32)
@@ -44,7 +44,7 @@ def _setup_status(dim=2, order=2, n=2, Q=4, metric=2, W=None, prec=0, rule=0, el
                     en.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None)
     Wa = np.ascontiguousarray(np.eye(dim) if W is None else W, dtype=np.float64)
     q = T.tmop_quadrature(rule, Q)
-    t = T.tmop_target(0, Wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    t = T.tmop_target(kind, Wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     h = ctypes.c_void_p()
     return lib.tmop_setup(ctypes.byref(m), ctypes.byref(q), ctypes.byref(t), metric, prec, ctypes.byref(h)), h
 
@@ -62,11 +62,15 @@ def _setup_status(dim=2, order=2, n=2, Q=4, metric=2, W=None, prec=0, rule=0, el
     (dict(W=np.array([[1.0, 0.0], [0.0, -1.0]])), T.TMOP_E_TARGET),   # det W <= 0 (Section 3.1)
     (dict(W=np.zeros((2, 2))), T.TMOP_E_TARGET),
     (dict(order=5, Q=6), T.TMOP_E_UNSUPPORTED),
-    (dict(order=2, Q=5, dim=3, metric=303), T.TMOP_OK if False else "skip"),
+    (dict(kind=9), T.TMOP_E_ARG),                     # unknown target kind
+    # general targets per element / per point (4 elements, 16 points each): one det W <= 0
+    (dict(kind=T.TMOP_TGT_PER_ELEM, W=np.stack([np.eye(2)] * 3 + [np.diag([1.0, -1.0])])), T.TMOP_E_TARGET),
+    (dict(kind=T.TMOP_TGT_PER_QP, W=np.concatenate([np.tile(np.eye(2), (63, 1, 1)), np.zeros((1, 2, 2))])),
+     T.TMOP_E_TARGET),
+    (dict(kind=T.TMOP_TGT_PER_QP, W=np.concatenate([np.tile(np.eye(2), (63, 1, 1)), np.full((1, 2, 2), np.nan)])),
+     T.TMOP_E_TARGET),
 ])
 def test_setup_validation(kw, status):
-    if status == "skip":
-        pytest.skip("valid arguments need a GPU")
     st, h = _setup_status(**kw)
     assert st == status
     assert not h.value
@@ -78,7 +82,7 @@ def test_newton_default_opts():
     lib.tmop_newton_default_opts(ctypes.byref(o))
     assert o.rtol == 1e-12 and o.f_growth == 1.2 and o.g_growth == 1.2 and o.ls_shrink == 0.5
     assert o.max_it == 50 and o.ls_max == 30 and not o.hist_F
-    assert o.inner == T.TMOP_INNER_CG and o.precond == T.TMOP_PREC_NONE
+    assert o.inner == T.TMOP_INNER_SHIFTED_CG and o.precond == T.TMOP_PREC_NONE and o.shift_beta == 1e-3
 
 
 def test_null_arguments():

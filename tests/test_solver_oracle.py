@@ -125,13 +125,57 @@ def test_preconditioned_cg_first_step_negative_curvature():
     np.testing.assert_array_equal(d, -minv * g)
 
 
+def test_shifted_cg_positive_definite_is_cg():
+    """With H positive definite and a positive diagonal no shift is made:
+    the direction is CG's solution of H d = -g (numpy.linalg.solve)."""
+    rng = np.random.default_rng(6)
+    Qm, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    A = (Qm * rng.uniform(0.5, 20.0, 40)) @ Qm.T
+    g = rng.standard_normal(40)
+    d, it, nshift, tau = O.shifted_cg(lambda v: A @ v, g, 1e-13, 400, np.diag(A))
+    assert nshift == 0 and tau == 0.0
+    x = np.linalg.solve(A, -g)
+    assert np.max(np.abs(d - x)) <= 1e-10 * np.max(np.abs(x))
+
+
+@pytest.mark.parametrize("neg_diag", [False, True])
+def test_shifted_cg_indefinite(neg_diag):
+    """An indefinite H (smallest eigenvalue -3): tau follows Nocedal and
+    Wright's Algorithm 3.3 -- tau_0 = 0 for a positive diagonal, else
+    beta - min diag; then tau <- max(2 tau, beta) -- until H + tau I is
+    positive definite, and the direction solves (H + tau I) d = -g, so
+    g . d < 0."""
+    rng = np.random.default_rng(7)
+    Qm, _ = np.linalg.qr(rng.standard_normal((30, 30)))
+    ev = np.concatenate([[-3.0, -0.5], rng.uniform(1.0, 8.0, 28)])
+    A = (Qm * ev) @ Qm.T
+    if neg_diag:
+        A[4, 4] = -2.0                     # a negative diagonal entry sets tau_0 = beta - min diag
+    g = rng.standard_normal(30)
+    diag = np.diag(A)
+    beta = 1e-3 * np.mean(np.abs(diag))
+    d, it, nshift, tau = O.shifted_cg(lambda v: A @ v, g, 1e-13, 400, diag)
+    lam_min = np.linalg.eigvalsh(A)[0]
+    # the sequence of shifts tried, by the rule
+    seq = [0.0 if diag.min() > 0 else -diag.min() + beta]
+    while len(seq) <= nshift:
+        seq.append(max(2.0 * seq[-1], beta))
+    assert tau == seq[-1]
+    assert tau > -lam_min                  # H + tau I is positive definite ...
+    assert nshift == 0 or seq[-2] < -lam_min + 1e-12   # ... and the shift before was not (up to CG's test)
+    x = np.linalg.solve(A + tau * np.eye(30), -g)
+    assert np.max(np.abs(d - x)) <= 1e-9 * np.max(np.abs(x))
+    assert float(np.dot(g, d)) < 0.0
+
+
 def test_jacobi_inverse():
     m = np.array([1.0, 1.0, 0.0, 1.0])
     D = np.array([-4.0, 2.0, 7.0, 0.0])
     np.testing.assert_array_equal(O.jacobi_inverse(D, m), [0.25, 0.5, 1.0, 1.0])
 
 
-@pytest.mark.parametrize("inner,precond", [("minres", "none"), ("minres", "jacobi"), ("cg", "jacobi")])
+@pytest.mark.parametrize("inner,precond", [("minres", "none"), ("minres", "jacobi"), ("cg", "jacobi"),
+                                          ("shifted_cg", "none"), ("shifted_cg", "jacobi")])
 def test_newton_variants_reach_grid(inner, precond):
     """The Q2 mu_2 workload on 5x5 elements: with each inner solver and
     preconditioner Newton returns to the unperturbed grid, the known

@@ -1,8 +1,9 @@
 """The Hessian diagonal and the Newton inner solvers of the HIP library:
 the diagonal against the oracle element by element (FP64 within 1e-12
-relative, mixed FP32 within the mixed tolerance), and Newton with MINRES
-(Section 5) and with the Jacobi preconditioner against the oracle's
-implementation of the same rules on the 8x8 Q2 workload."""
+relative, mixed FP32 within its first-order rounding bound), and Newton
+with each inner solver (the shifted CG, truncated CG, MINRES of Section 5)
+and with the Jacobi preconditioner against the oracle's implementation of
+the same rules on the 8x8 Q2 workload."""
 import numpy as np
 import pytest
 
@@ -21,7 +22,7 @@ def setup(request):
     case = request.param
     say(f"[diag] case {case.name}")
     mesh, prob, W = build(case)
-    return case, mesh, W, prob.hessian_diagonal(mesh.x), mixed_tol(prob, mesh.x)
+    return case, mesh, W, prob.hessian_diagonal(mesh.x), mixed_tol(prob, mesh.x, diag=True)["diag"]
 
 
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
@@ -31,7 +32,7 @@ def test_hessian_diagonal(setup, precision):
     x = to_dev(mesh.x)
     D = ctx.hessian_diagonal(x)
     err = rel_max_err(D.cpu().numpy(), ref)
-    say(f"  {case.name} prec={precision} diag rel err {err:.2e}")
+    say(f"  {case.name} prec={precision} diag rel err {err:.2e} (bar {mtol:.1e})")
     assert err <= (1e-12 if precision == 0 else mtol)
     assert torch.equal(D, ctx.hessian_diagonal(x))          # bitwise reproducible
 
@@ -45,7 +46,11 @@ def _c1(n=None):
     return w, mesh, W, prob, x0
 
 
-@pytest.mark.parametrize("inner,precond", [("minres", "none"), ("minres", "jacobi"), ("cg", "jacobi")])
+INNER = {"cg": 0, "minres": 1, "shifted_cg": 2}
+
+
+@pytest.mark.parametrize("inner,precond", [("minres", "none"), ("minres", "jacobi"), ("cg", "jacobi"),
+                                          ("shifted_cg", "none"), ("shifted_cg", "jacobi")])
 def test_newton_inner_solvers_match_oracle(inner, precond):
     """Same rules on both sides, compared where the result is unique: the
     end state (the grid) and the early F history.  Truncated CG: F within
@@ -66,14 +71,13 @@ def test_newton_inner_solvers_match_oracle(inner, precond):
     xo, rep_o = O.newton_solve(prob, x0, mesh.fixed, opts)
     ctx = T.Context(2, w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=mesh.fixed)
     xd = to_dev(x0)
-    st, rep = ctx.newton_solve(xd, max_it=60, cg_rtol=1e-10,
-                               inner=T.TMOP_INNER_MINRES if inner == "minres" else T.TMOP_INNER_CG,
+    st, rep = ctx.newton_solve(xd, max_it=60, cg_rtol=1e-10, inner=INNER[inner],
                                precond=T.TMOP_PREC_JACOBI if precond == "jacobi" else T.TMOP_PREC_NONE)
     F_o = [h[0] for h in rep_o.history]
     F_g = rep["history_F"]
     say(f"  oracle iters {rep_o.iters} inner {rep_o.cg_iters}; gpu iters {rep['iters']} inner {rep['cg_iters']}")
     worst = 0.0
-    n_cmp = min(len(F_o), len(F_g)) if inner == "cg" else 3
+    n_cmp = min(len(F_o), len(F_g)) if inner != "minres" else 3
     for k in range(max(len(F_o), len(F_g))):
         a = F_o[k] if k < len(F_o) else float("nan")
         b = F_g[k] if k < len(F_g) else float("nan")
@@ -92,7 +96,7 @@ def test_newton_inner_solvers_match_oracle(inner, precond):
     np.testing.assert_array_equal(x[mesh.fixed.astype(bool)], x0[mesh.fixed.astype(bool)])
 
 
-@pytest.mark.parametrize("inner", ["cg", "minres"])
+@pytest.mark.parametrize("inner", ["cg", "minres", "shifted_cg"])
 def test_newton_3d_jacobi_returns_to_grid(inner):
     """Q2 hex mu_303 (6^3 elements) with the Jacobi preconditioner."""
     from paper_1807_09807_amd import tmop as T
@@ -104,8 +108,7 @@ def test_newton_3d_jacobi_returns_to_grid(inner):
     x0 = meshgen.perturb(mesh, w["noise"], w["seed"], bad_elements=prob.bad_elements)
     ctx = T.Context(3, 2, mesh.elem_node, mesh.n_node, 4, 303, W, fixed=mesh.fixed)
     xd = to_dev(x0)
-    st, rep = ctx.newton_solve(xd, max_it=60, rtol=1e-10, precond=T.TMOP_PREC_JACOBI,
-                               inner=T.TMOP_INNER_MINRES if inner == "minres" else T.TMOP_INNER_CG)
+    st, rep = ctx.newton_solve(xd, max_it=60, rtol=1e-10, precond=T.TMOP_PREC_JACOBI, inner=INNER[inner])
     say(f"  status {st} iters {rep['iters']} inner {rep['cg_iters']} F {rep['F0']:.3e} -> {rep['F']:.3e}")
     assert st == T.TMOP_OK
     assert np.max(np.abs(xd.cpu().numpy() - mesh.x_grid)) / mesh.h < 1e-8
@@ -116,7 +119,7 @@ def test_newton_rejects_unknown_solver():
     w, mesh, W, prob, x0 = _c1(4)
     ctx = T.Context(2, w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=mesh.fixed)
     xd = to_dev(x0)
-    for bad in (dict(inner=7), dict(precond=-1)):
+    for bad in (dict(inner=7), dict(precond=-1), dict(shift_beta=0.0), dict(shift_beta=float("nan"))):
         with pytest.raises(T.TMOPError):
             ctx.newton_solve(xd, **bad)
     assert torch.equal(xd, to_dev(x0))
