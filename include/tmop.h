@@ -53,7 +53,9 @@ enum {
   TMOP_E_TARGET = -2,      /* a target matrix has det W <= 0 (Section 3.1) */
   TMOP_E_NOMEM = -3,       /* device or host allocation failed */
   TMOP_E_HIP = -4,         /* a HIP runtime call failed */
-  TMOP_E_UNSUPPORTED = -5  /* valid, but no kernel is built for this (dim, p, Q) */
+  TMOP_E_UNSUPPORTED = -5, /* valid, but no kernel is built for this (dim, p, Q) */
+  TMOP_E_SCRATCH = -6      /* tmop_energy_noalloc: the problem needs more
+                              energy partials than its fixed scratch holds */
 };
 
 /* Quality metrics mu(T), tau = det T, |.| the Frobenius norm (Section 3.2). */
@@ -217,6 +219,26 @@ int tmop_setup(const tmop_mesh *mesh, const tmop_quadrature *quad,
  * written) when min_detA <= 0.  Deterministic.  Syncs `stream`. */
 int tmop_energy(tmop_ctx *ctx, const double *x, double *F, double *min_detA,
                 void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): F and
+ * min det A exactly as tmop_energy (same kernels, same reduction order, so
+ * bitwise the same values), with the energy partials, the final reduction
+ * and its result in a fixed file-scope device array of the library instead
+ * of the context's buffers.  The call allocates nothing (no hipMalloc,
+ * hipFree, event or library allocation); the per-launch timing of
+ * tmop_timing_enable does not cover it.  Limit: at most 65,536 workgroups
+ * of partials summed over the objective's terms (1 MiB + 4 KiB of scratch
+ * per GPU, held until the process ends); the 64^3 Q2 hexahedral mesh with
+ * its single term needs exactly 65,536.  Larger problems return
+ * TMOP_E_SCRATCH before any device work.  The context's device must be
+ * current (else TMOP_E_ARG).  Every call on one GPU shares that GPU's
+ * array and leaves the last call's contents there: calls that overlap in
+ * time on one GPU (other streams, threads or contexts) race and must be
+ * serialized by the caller.  Nothing in the array needs to start at zero.
+ * Syncs `stream` (the result is read back to the host). */
+int tmop_energy_noalloc(tmop_ctx *ctx, const double *x, double *F, double *min_detA,
+                        void *stream);
 
 /* g = dF/dx (Section 3.4) over all DOFs, fixed ones included.  x, g: device
  * [dim][n_node]; g is overwritten.  Deterministic.  Async. */

@@ -723,6 +723,7 @@ const char* tmop_strerror(int status) {
     case TMOP_E_NOMEM: return "error: out of memory";
     case TMOP_E_HIP: return "error: HIP runtime failure";
     case TMOP_E_UNSUPPORTED: return "error: no kernel built for this (dim, order, quadrature)";
+    case TMOP_E_SCRATCH: return "error: the problem needs more than the fixed scratch of the allocation-free call";
     default: return "unknown status";
   }
 }
@@ -817,6 +818,9 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
   c->dim = d; c->p = p; c->Q = Q; c->metric = metric; c->precision = precision;
   c->n_elem = mesh->n_elem; c->n_node = mesh->n_node; c->n_dof = (int64_t)d * mesh->n_node;
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return TMOP_E_HIP; }
+  // the allocation-free entry point's scratch on this device (its address,
+  // taken once per device while the device is current)
+  if (noalloc_scratch(c->device, &c->d_noalloc) != 0) { delete c; return TMOP_E_HIP; }
 
   // 1D tables: B[q][i] = l_i(s_q), G[q][i] = l_i'(s_q), weights w[q]
   double xi[MAXP], s[MAXQ], w[MAXQ];
@@ -938,6 +942,30 @@ int tmop_timing_read(tmop_ctx* c, int op, double* ms_total, int64_t* launches) {
   *ms_total = c->t_ms[op];
   *launches = c->t_launches[op];
   return st;
+}
+
+int tmop_energy_noalloc(tmop_ctx* c, const double* x, double* F, double* min_detA, void* stream) {
+  if (!c || !x || !F || !min_detA) return TMOP_E_ARG;
+  if (!c->d_noalloc) return TMOP_E_HIP;
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return TMOP_E_HIP;
+  if (cur != c->device) return TMOP_E_ARG;     // the scratch address belongs to the context's device
+  hipStream_t s = (hipStream_t)stream;
+  // count the workgroups of every term first: the partials must fit
+  RedDst rd{c->d_noalloc, NOALLOC_MAX_BLOCKS, c->d_noalloc + 2 * NOALLOC_MAX_BLOCKS,
+            c->d_noalloc + 2 * NOALLOC_MAX_BLOCKS + 2 * FIN_BLOCKS, true};
+  int64_t nb = 0;
+  int r = energy_async(c, x, s, &rd, &nb);
+  if (r != TMOP_OK) return r;
+  if (nb > NOALLOC_MAX_BLOCKS) return TMOP_E_SCRATCH;
+  // every partial is written before it is read: nothing needs clearing
+  rd.dry = false;
+  if ((r = energy_async(c, x, s, &rd)) != TMOP_OK) return r;
+  HIP_TRY(hipMemcpyAsync(c->h_res, rd.res, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *F = c->h_res[0];
+  *min_detA = c->h_res[1];
+  return *min_detA > 0.0 ? TMOP_OK : TMOP_W_INVERTED;
 }
 
 int tmop_energy(tmop_ctx* c, const double* x, double* F, double* min_detA, void* stream) {

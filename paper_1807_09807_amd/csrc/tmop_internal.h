@@ -115,12 +115,23 @@ int launch_elem_3d_f64(int p, int Q, int metric, int op, const LaunchParams& lp,
 int launch_elem_3d_f32(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
 bool elem_supported(int dim, int p, int Q);
 
+// The allocation-free energy entry point (tmop_noalloc.hip): its partials,
+// the final reduction's scratch and the result live in one file-scope
+// device array per GPU of NOALLOC_DOUBLES doubles: at most
+// NOALLOC_MAX_BLOCKS workgroups of energy partials (sums, then minima),
+// then 2 FIN_BLOCKS doubles of reduction scratch, then the result.
+constexpr int64_t NOALLOC_MAX_BLOCKS = 65536;
+// Device address of that array on `device`, which must be current;
+// hipGetSymbolAddress once per device, cached.  0 or a HIP error code.
+int noalloc_scratch(int device, double** out);
+
 // BLAS-1 and reductions (tmop_blas.hip).  Every reduction is deterministic:
 // fixed grid, fixed tree order.
 constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;
 hipError_t fill(double* y, double v, int64_t n, hipStream_t s);
 constexpr int FIN_BLOCKS = 256;
+constexpr int64_t NOALLOC_DOUBLES = 2 * NOALLOC_MAX_BLOCKS + 2 * FIN_BLOCKS + 8;
 // res[0] = sum of part[0, n), res[1] = min of part[moff, moff + n)
 // (scratch: >= 2 * FIN_BLOCKS doubles).
 hipError_t finalize_sum_min(const double* part, int n, int moff, double* scratch, double* res, hipStream_t s);
@@ -226,6 +237,7 @@ struct tmop_ctx {
   double* d_sc = nullptr;              // [SC_COUNT] scalar state of the Krylov solvers
   double* h_sc = nullptr;              // its pinned host mirror
   int64_t n_free = 0;                  // free DOFs (mask 1)
+  double* d_noalloc = nullptr;         // the allocation-free entry point's scratch on this device
   // optional per-launch timing of the element kernels (HIP events)
   struct TimedLaunch { int op; hipEvent_t a, b; };
   bool timing = false;

@@ -20,7 +20,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libtmop.so")
 
 TMOP_OK, TMOP_W_INVERTED, TMOP_W_MAXIT, TMOP_W_LSFAIL = 0, 1, 2, 3
-TMOP_E_ARG, TMOP_E_TARGET, TMOP_E_NOMEM, TMOP_E_HIP, TMOP_E_UNSUPPORTED = -1, -2, -3, -4, -5
+TMOP_E_ARG, TMOP_E_TARGET, TMOP_E_NOMEM, TMOP_E_HIP, TMOP_E_UNSUPPORTED, TMOP_E_SCRATCH = -1, -2, -3, -4, -5, -6
 TMOP_MU1, TMOP_MU2, TMOP_MU7, TMOP_MU9, TMOP_MU14, TMOP_MU77, TMOP_MU98 = 1, 2, 7, 9, 14, 77, 98
 TMOP_MU302, TMOP_MU303 = 302, 303
 TMOP_GAUSS_LEGENDRE, TMOP_GAUSS_LOBATTO = 0, 1
@@ -33,7 +33,8 @@ EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_gradient_scaled",
            "tmop_newton_solve", "tmop_destroy", "tmop_strerror", "tmop_newton_default_opts",
            "tmop_timing_enable", "tmop_timing_read", "tmop_energy_gradient", "tmop_hessian_diagonal",
            "tmop_target_sizes_w3", "tmop_set_target_sizes", "tmop_set_restriction", "tmop_set_combo",
-           "tmop_set_replication", "tmop_dfo_default_opts", "tmop_dfo_sweep", "tmop_dfo_solve")
+           "tmop_set_replication", "tmop_dfo_default_opts", "tmop_dfo_sweep", "tmop_dfo_solve",
+           "tmop_energy_noalloc")
 # timing slots: the element-kernel operations, then the W_0 data and the penalty kernels
 TIMING_ENERGY, TIMING_GRAD, TIMING_HESS, TIMING_EG, TIMING_DIAG, TIMING_SIZE = 0, 1, 2, 3, 4, 5
 TIMING_W0, TIMING_PENALTY = 6, 7
@@ -102,6 +103,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tmop_setup.restype = ctypes.c_int
     lib.tmop_energy.argtypes = [P, P, ctypes.POINTER(dbl), ctypes.POINTER(dbl), P]
     lib.tmop_energy.restype = ctypes.c_int
+    lib.tmop_energy_noalloc.argtypes = [P, P, ctypes.POINTER(dbl), ctypes.POINTER(dbl), P]
+    lib.tmop_energy_noalloc.restype = ctypes.c_int
     lib.tmop_gradient.argtypes = [P, P, P, P]
     lib.tmop_gradient.restype = ctypes.c_int
     lib.tmop_gradient_scaled.argtypes = [P, P, P, P, P]
@@ -231,6 +234,17 @@ class Context:
         st = self._lib.tmop_energy(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.byref(F), ctypes.byref(md), _stream(x))
         if st < 0:
             raise TMOPError(st, "tmop_energy")
+        return F.value, md.value, st
+
+    def energy_noalloc(self, x):
+        """(F, min det A, status) as energy(), from the library's fixed
+        scratch (tmop_energy_noalloc: no device allocation)."""
+        _check_field(x, self.dim, self.n_node, "x")
+        F, md = ctypes.c_double(), ctypes.c_double()
+        st = self._lib.tmop_energy_noalloc(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.byref(F), ctypes.byref(md),
+                                           _stream(x))
+        if st < 0:
+            raise TMOPError(st, "tmop_energy_noalloc")
         return F.value, md.value, st
 
     def energy_gradient(self, x, out=None):

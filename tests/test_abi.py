@@ -88,6 +88,7 @@ def test_newton_default_opts():
 def test_null_arguments():
     lib = T.load()
     assert lib.tmop_energy(None, None, None, None, None) == T.TMOP_E_ARG
+    assert lib.tmop_energy_noalloc(None, None, None, None, None) == T.TMOP_E_ARG
     assert lib.tmop_gradient(None, None, None, None) == T.TMOP_E_ARG
     assert lib.tmop_hessian_apply(None, None, None, None, None) == T.TMOP_E_ARG
     assert lib.tmop_hessian_diagonal(None, None, None, None) == T.TMOP_E_ARG
