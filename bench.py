@@ -259,9 +259,16 @@ def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
     log(f"# workload {name}: {mesh.n_elem} elements, {mesh.n_dof} DOFs, repair rounds "
         f"{mesh.info.get('repair_rounds', 0)}")
     results = {}
-    for prec, pname in ((T.TMOP_FP64, "f64"), (T.TMOP_MIXED_FP32, "mixed")):
+    variants = [(T.TMOP_FP64, "f64", T.TMOP_SCATTER_COLOURS), (T.TMOP_MIXED_FP32, "mixed", T.TMOP_SCATTER_COLOURS)]
+    if w["dim"] == 2:   # the owner-computes tile scatter beside the colour launches
+        variants += [(T.TMOP_FP64, "f64_tiles", T.TMOP_SCATTER_TILES),
+                     (T.TMOP_MIXED_FP32, "mixed_tiles", T.TMOP_SCATTER_TILES)]
+    for prec, pname, scatter in variants:
+        t_set = time.perf_counter()   # set-up on the host: tables, colouring, 2D tiles, uploads
         ctx = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W,
                         fixed=mesh.fixed, precision=prec)
+        t_set = time.perf_counter() - t_set
+        ctx.set_scatter(scatter)
         F, md, st = ctx.energy(x)
         if st != 0 or not md > 0:
             raise SystemExit(f"{name}: inverted input mesh (min det A = {md})")
@@ -312,6 +319,7 @@ def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
         ctx.timing_enable(False)
         results[pname] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), ops=ops, F=F, ctx=ctx,
                               launch=launch)
+        results[pname]["setup_s"] = t_set
         log(f"# {pname}: {ms:.3f} ms/step, E {ops['energy']*1e6:.1f} us, G {ops['gradient']*1e6:.1f} us, "
             f"E+G {ops['energy_gradient']*1e6:.1f} us, Hv {ops['hessian']*1e6:.1f} us, "
             f"diag {ops['hessian_diagonal']*1e6:.1f} us; per launch "
@@ -613,6 +621,8 @@ def workload_summary(w, mesh, results):
                       "frac_hbm_peak": round(nbytes[k] * mesh.n_elem / t / HBM_PEAK, 4)}
         if "rel_err_vs_f64" in r:
             d["rel_err_vs_f64"] = r["rel_err_vs_f64"]
+        if "setup_s" in r:
+            d["setup_s"] = round(r["setup_s"], 3)
         out[pname] = d
     return out
 
@@ -632,7 +642,8 @@ def main():
     if args.calibrate_copy:
         copy_calibration(torch, dev)
     log = lambda m: print(m, file=sys.stderr, flush=True)
-    w, mesh, x, v, W, results = time_workload(T, torch, dev, args.workload, args.steps, args.warmup, log)
+    w, mesh, x, v, W, results = time_workload(T, torch, dev, args.workload, args.steps, args.warmup, log,
+                                              gpu_repair=True)
     x_np = mesh.x
     v_np = v.cpu().numpy()
     flops, nbytes = algorithmic(w)

@@ -280,6 +280,29 @@ int tmop_set_target_sizes(tmop_ctx *ctx, const double *sizes, void *stream);
  * Async. */
 int tmop_hessian_diagonal(tmop_ctx *ctx, const double *x, double *diag, void *stream);
 
+/* How the gradient, the energy + gradient and the Hessian action add the
+ * element contributions to shared nodes (Section 3.4 sums them over the
+ * elements holding each node):
+ *  TMOP_SCATTER_COLOURS (the default of 3D meshes): one launch per element
+ *    colour; the elements of a colour share no node, each adds to its
+ *    nodes in place.
+ *  TMOP_SCATTER_TILES (the default of 2D meshes): one launch over every
+ *    element in tiles of neighbouring elements; each workgroup accumulates
+ *    its tile's nodes on chip, adding its elements in rounds of elements
+ *    that share no node, and writes the nodes only its tile holds; a second
+ *    pass adds the tiles' partial sums at nodes shared by several tiles.
+ *    tmop_setup builds the tiles of a 2D mesh on the host (device memory:
+ *    about 2 bytes per element node, 8 per tile node and 24 per node on a
+ *    tile border); a mesh beyond the tile limits keeps the colours.
+ * Both are deterministic (fixed summation orders, which differ between the
+ * two, so results agree to rounding).  The other calls are not affected. */
+enum { TMOP_SCATTER_COLOURS = 0, TMOP_SCATTER_TILES = 1 };
+
+/* Selects the scatter mode of ctx.  TMOP_E_ARG for an unknown mode,
+ * TMOP_E_UNSUPPORTED (mode unchanged) for tiles on a context without them
+ * (3D, or a 2D mesh beyond the tile limits). */
+int tmop_set_scatter(tmop_ctx *ctx, int32_t mode);
+
 /* ------------------------------------------------------------------------
  * Section 4 objectives.  Each adds a term to the F of every call above
  * (energy, gradient, Hessian action, diagonal, energy + gradient, Newton);
@@ -386,7 +409,10 @@ void tmop_dfo_default_opts(tmop_dfo_opts *opts);
  * (fixed components keep their value).  opts: host, NULL = defaults.
  * *max_move: the largest max-norm move of a node.  TMOP_E_ARG for invalid
  * options (step <= 0, xtol < 0, max_evals < 1).  The first call builds the
- * node colouring on the host.  Syncs. */
+ * node colouring on the host; TMOP_E_UNSUPPORTED (x untouched) when a node
+ * belongs to more elements than one workgroup's patch holds (at least 2^dim:
+ * 4 for 2D and 8 for 3D meshes with 4 points per direction, e.g. a
+ * valence-5 vertex of a 2D mesh).  Syncs. */
 int tmop_dfo_sweep(tmop_ctx *ctx, double *x, const tmop_dfo_opts *opts, double *max_move, void *stream);
 
 /* Sweeps until the largest move of a sweep is below t (TMOP_OK) or

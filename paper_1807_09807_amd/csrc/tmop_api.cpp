@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include <hip/hip_runtime.h>
@@ -241,8 +242,9 @@ bool fused_penalty(const tmop_ctx* c, int op) {
 int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* out, const int32_t* conn,
                 const int32_t* list, int64_t n_list, hipStream_t s, int* grid, const double* scale = nullptr,
                 int64_t part_off = 0, const uint32_t* first = nullptr, const double* tsize = nullptr,
-                TermSel term = TermSel{}, const RedDst* rd = nullptr) {
+                TermSel term = TermSel{}, const RedDst* rd = nullptr, const TileParams* tile = nullptr) {
   LaunchParams lp = c->base;
+  lp.tile = tile;
   lp.first = first;
   lp.tsize = tsize;
   lp.tmat = term.tmat;
@@ -348,16 +350,25 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
   if (!c->all_touched) HIP_TRY(fill(out, 0.0, c->n_dof, s));
   int64_t off = 0;
   const int ncol = (int)c->color_off.size() - 1;
-  for (int k = 0; k < ncol; ++k) {
-    const int64_t n = c->color_off[k + 1] - c->color_off[k];
-    if (n == 0) continue;
+  if (c->scatter == TMOP_SCATTER_TILES && (op == OP_GRAD || op == OP_EG || op == OP_HESS)) {
+    // one launch in owner-computes tiles (2D), element order
     int grid = 0;
-    const int r = elem_launch(c, op, x, v, out, c->d_elem_node_col + c->color_off[k] * c->npe, nullptr, n, s,
-                              &grid, scale, off, c->d_first + c->color_off[k] * c->first_words,
-                              c->d_tsize_col ? c->d_tsize_col + c->color_off[k] * c->nq : nullptr,
-                              primary_term(c, true, c->color_off[k], fused_penalty(c, op)));
+    const int r = elem_launch(c, op, x, v, out, nullptr, nullptr, c->n_elem, s, &grid, scale, off, nullptr,
+                              c->d_tsize, primary_term(c, false, 0, fused_penalty(c, op)), nullptr, &c->tile);
     if (r != TMOP_OK) return r;
     off += grid;
+  } else {
+    for (int k = 0; k < ncol; ++k) {
+      const int64_t n = c->color_off[k + 1] - c->color_off[k];
+      if (n == 0) continue;
+      int grid = 0;
+      const int r = elem_launch(c, op, x, v, out, c->d_elem_node_col + c->color_off[k] * c->npe, nullptr, n, s,
+                                &grid, scale, off, c->d_first + c->color_off[k] * c->first_words,
+                                c->d_tsize_col ? c->d_tsize_col + c->color_off[k] * c->nq : nullptr,
+                                primary_term(c, true, c->color_off[k], fused_penalty(c, op)));
+      if (r != TMOP_OK) return r;
+      off += grid;
+    }
   }
   for (int k = 0; c->metric2 && k < ncol; ++k) {   // second metric term (Sections 4.2, 4.3.2)
     const int64_t n = c->color_off[k + 1] - c->color_off[k];
@@ -441,6 +452,66 @@ int dot_sync(tmop_ctx* c, const double* a, const double* b, hipStream_t s, doubl
   return TMOP_OK;
 }
 
+void free_tiles(tmop_ctx* c) {
+  TileParams& t = c->tile;
+  (void)hipFree((void*)t.round_off);
+  (void)hipFree((void*)t.slot_elem);
+  (void)hipFree((void*)t.slot_lnode);
+  (void)hipFree((void*)t.node_off);
+  (void)hipFree((void*)t.node);
+  (void)hipFree((void*)t.slot);
+  (void)hipFree(t.halo);
+  (void)hipFree((void*)t.halo_node);
+  (void)hipFree((void*)t.halo_off);
+  t = TileParams{};
+}
+
+// Builds the owner-computes tiles of a 2D mesh on the host (connectivity
+// en, the element order of the colouring) and uploads them.
+// TMOP_E_UNSUPPORTED when the mesh does not fit the tile limits.
+int make_tiles(tmop_ctx* c, const int32_t* en, const std::vector<int32_t>& order) {
+  std::vector<int32_t> colour(c->n_elem);
+  for (size_t k = 0; k + 1 < c->color_off.size(); ++k)
+    for (int64_t j = c->color_off[k]; j < c->color_off[k + 1]; ++j) colour[order[j]] = (int32_t)k;
+  TileLayout L;
+  if (build_tiles(en, c->n_elem, c->npe, c->n_node, colour.data(), c->p, c->Q, L) != 0)
+    return TMOP_E_UNSUPPORTED;
+  TileParams t{};
+  int st = TMOP_OK;
+  auto up = [&](const auto& v, auto** dst) {
+    using T = typename std::decay_t<decltype(v)>::value_type;
+    *dst = nullptr;
+    if (st != TMOP_OK) return;
+    const size_t b = std::max<size_t>(v.size(), 1) * sizeof(T);
+    void* p = nullptr;
+    if (hipMalloc(&p, b) != hipSuccess) { st = TMOP_E_NOMEM; return; }
+    *dst = static_cast<T*>(p);
+    if (!v.empty() && hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+      st = TMOP_E_HIP;
+  };
+  int32_t *ro, *se, *no, *nd, *sl, *hn, *ho;
+  uint16_t* ln;
+  up(L.round_off, &ro); t.round_off = ro;
+  up(L.slot_elem, &se); t.slot_elem = se;
+  up(L.slot_lnode, &ln); t.slot_lnode = ln;
+  up(L.node_off, &no); t.node_off = no;
+  up(L.node, &nd); t.node = nd;
+  up(L.slot, &sl); t.slot = sl;
+  up(L.halo_node, &hn); t.halo_node = hn;
+  up(L.halo_off, &ho); t.halo_off = ho;
+  if (st == TMOP_OK && hipMalloc(&t.halo, std::max<int64_t>(2 * L.n_slot, 1) * sizeof(double)) != hipSuccess) {
+    t.halo = nullptr;
+    st = TMOP_E_NOMEM;
+  }
+  t.n_slot = L.n_slot;
+  t.n_halo = (int64_t)L.halo_node.size();
+  t.n_tile = (int32_t)(L.node_off.size() - 1);
+  t.nn_max = L.nn_max;
+  c->tile = t;
+  if (st != TMOP_OK) free_tiles(c);
+  return st;
+}
+
 void free_ctx(tmop_ctx* c) {
   if (!c) return;
   int cur = 0;
@@ -469,6 +540,7 @@ void free_ctx(tmop_ctx* c) {
   (void)hipFree(c->d_res);
   (void)hipFree(c->d_work);
   (void)hipFree(c->d_sc);
+  free_tiles(c);
   if (c->h_res) (void)hipHostFree(c->h_res);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
   (void)collect_timing(c);
@@ -907,6 +979,11 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
           gather_rows(c->d_psize, c->d_colors, mesh->n_elem, nq, c->d_psize_col, nullptr) != hipSuccess ||
           hipDeviceSynchronize() != hipSuccess) { st = TMOP_E_HIP; break; }
     }
+    if (d == 2) {   // owner-computes tiles, the default scatter of 2D meshes that fit their limits
+      const int r = make_tiles(c, mesh->elem_node, order);
+      if (r == TMOP_OK) c->scatter = TMOP_SCATTER_TILES;
+      else if (r != TMOP_E_UNSUPPORTED) { st = r; break; }
+    }
     std::vector<double> mask(c->n_dof, 1.0);
     if (mesh->fixed)
       for (int64_t k = 0; k < c->n_dof; ++k)
@@ -1179,6 +1256,10 @@ int dfo_prepare(tmop_ctx* c) {
   HIP_TRY(hipMemcpy(en.data(), c->d_elem_node, ne_tot * sizeof(int32_t), hipMemcpyDeviceToHost));
   std::vector<int32_t> off(c->n_node + 1, 0), code((size_t)ne_tot);
   for (int64_t k = 0; k < ne_tot; ++k) off[en[k] + 1]++;
+  // every element holding a node must fit in that node's workgroup
+  const int cap = dfo_patch_capacity(c->dim, c->Q);
+  for (int64_t I = 0; I < c->n_node; ++I)
+    if (off[I + 1] > cap) return TMOP_E_UNSUPPORTED;
   for (int64_t I = 0; I < c->n_node; ++I) off[I + 1] += off[I];
   {
     std::vector<int32_t> pos(off.begin(), off.end() - 1);
@@ -1329,6 +1410,13 @@ int tmop_dfo_solve(tmop_ctx* c, double* x, const tmop_dfo_opts* opts, tmop_dfo_r
   r.F = F;
   if (rep) *rep = r;
   return r.converged ? TMOP_OK : TMOP_W_MAXIT;
+}
+
+int tmop_set_scatter(tmop_ctx* c, int32_t mode) {
+  if (!c || (mode != TMOP_SCATTER_COLOURS && mode != TMOP_SCATTER_TILES)) return TMOP_E_ARG;
+  if (mode == TMOP_SCATTER_TILES && !c->tile.node) return TMOP_E_UNSUPPORTED;   // 3D, or no tiles built
+  c->scatter = mode;
+  return TMOP_OK;
 }
 
 int tmop_hessian_diagonal(tmop_ctx* c, const double* x, double* diag, void* stream) {

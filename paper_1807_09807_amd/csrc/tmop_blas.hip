@@ -523,6 +523,30 @@ hipError_t gather_rows(const double* src, const int32_t* rows, int64_t n, int w,
   return hipGetLastError();
 }
 
+namespace {
+// Halo pass of the owner-computes tiles: each shared node's slots, one per
+// touching tile, added in tile order.
+__global__ void __launch_bounds__(VB) k_halo_sum(const TileParams tp, int64_t n_node, double* __restrict__ out) {
+  const int64_t h = blockIdx.x * (int64_t)VB + threadIdx.x;
+  if (h >= tp.n_halo) return;
+  const int64_t g = tp.halo_node[h];
+  const int j0 = tp.halo_off[h], j1 = tp.halo_off[h + 1];
+  for (int c = 0; c < 2; ++c) {
+    const double* hc = tp.halo + c * tp.n_slot;
+    double sum = hc[j0];
+    for (int j = j0 + 1; j < j1; ++j) sum += hc[j];
+    out[c * n_node + g] = sum;
+  }
+}
+}  // namespace
+
+hipError_t halo_sum(const TileParams& tp, int64_t n_node, double* out, hipStream_t s) {
+  if (tp.n_halo == 0) return hipSuccess;
+  const int64_t g = (tp.n_halo + VB - 1) / VB;
+  hipLaunchKernelGGL(k_halo_sum, dim3((unsigned)g), dim3(VB), 0, s, tp, n_node, out);
+  return hipGetLastError();
+}
+
 hipError_t mask_mul(const double* m, double* y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_mask_mul, dim3(vgrid(n)), dim3(VB), 0, s, m, y, n);
   return hipGetLastError();

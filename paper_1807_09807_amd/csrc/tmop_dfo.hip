@@ -364,6 +364,13 @@ static int dfo_dispatch(int p, int Q, int metric, const DfoParams& dp, hipStream
   return -1;
 }
 
+int dfo_patch_capacity(int dim, int Q) {
+  const int block = dim == 2 ? DfoCfg<2>::BLOCK : DfoCfg<3>::BLOCK;
+  const int nq = dim == 2 ? Q * Q : Q * Q * Q;
+  const int ppl = ((1 << dim) * nq + block - 1) / block;   // as PPL in dfo_kernel
+  return ppl * block / nq;
+}
+
 int launch_dfo(int dim, int p, int Q, int metric, const DfoParams& dp, hipStream_t s) {
   return dim == 3 ? dfo_dispatch<3>(p, Q, metric, dp, s) : dfo_dispatch<2>(p, Q, metric, dp, s);
 }

@@ -137,24 +137,22 @@ template <int P, int Q> struct Lds3 {
   static __device__ __forceinline__ constexpr int av(int t, int c, int q1) { return (t * 3 + c) * Q + q1; }
 };
 
-// LDS padding of the per-element block (values, 3D and 2D): it sets the
-// bank pattern of the accesses of neighbouring elements.  Measured on the
-// 2D workloads, 5 extra values cut the LDS bank conflicts of the 16
+// LDS padding of the per-element block (values, 3D; the 2D padding,
+// TMOP_ELEM_PAD2, sits with elem2d_lds_values): it sets the bank pattern of
+// the accesses of neighbouring elements.  Measured on the 2D workloads, 5
+// extra values cut the LDS bank conflicts of the 16
 // elements of a wave: FP64 energy launch 24.0 -> 19.6 us (512^2 Q2),
 // Hessian action 19.6 -> 16.8 us.
 #ifndef TMOP_ELEM_PAD
 #define TMOP_ELEM_PAD 2
-#endif
-#ifndef TMOP_ELEM_PAD2
-#define TMOP_ELEM_PAD2 5
 #endif
 
 template <int DIM, int P, int Q, typename R>
 struct Cfg {
   static constexpr int TPE = DIM == 3 ? Q * Q : Q;
   // LDS values per element: energy / gradient, Hessian action
-  static constexpr int NE = DIM == 3 ? Lds3<P, Q>::N + TMOP_ELEM_PAD : 2 * 2 * Q * P + TMOP_ELEM_PAD2;
-  static constexpr int NEH = DIM == 3 ? Lds3<P, Q>::NH + TMOP_ELEM_PAD : 2 * 2 * Q * P + TMOP_ELEM_PAD2;
+  static constexpr int NE = DIM == 3 ? Lds3<P, Q>::N + TMOP_ELEM_PAD : elem2d_lds_values(P, Q);
+  static constexpr int NEH = DIM == 3 ? Lds3<P, Q>::NH + TMOP_ELEM_PAD : elem2d_lds_values(P, Q);
   static constexpr int EPB = pick_epb(TPE, NEH * (int)sizeof(R));
   static constexpr int BLOCK = (EPB * TPE + 63) / 64 * 64;
 };
@@ -921,38 +919,21 @@ __device__ __forceinline__ void fwd_2d(const ElemArgs<P, Q, R>& a, const R (&X)[
   }
 }
 
+// The work of one 2D element on lane ta once its field pencils X (and dX for
+// the Hessian action) are in registers: the forward contraction through the
+// element's LDS area s, the point loop (the energy terms add to acc and
+// mind; OP_SIZE and OP_JINV write their per-point results), and for the
+// operations with a scatter the transposed contraction back through s, after
+// which lane ta < P holds in V[c][i1] the element's share of local node
+// (ta, i1).  Every lane of the block calls it (it holds barriers); e is the
+// element's index in the order of the per-point target data.
 template <int P, int Q, int METRIC, typename R, int OP, int TGT>
-__global__ void __launch_bounds__((Cfg<2, P, Q, R>::BLOCK))
-elem_kernel_2d(const ElemArgs<P, Q, R> a) {
-  using C = Cfg<2, P, Q, R>;
+__device__ __forceinline__ void elem2d_work(const ElemArgs<P, Q, R>& a, int e, int ta, bool active, R* __restrict__ s,
+                                            const R (&X)[2][P], const R (&dX)[2][P], const R (&J0x)[2][2],
+                                            const R (&J0v)[2][2], double& acc, double& mind, R (&V)[2][P]) {
   constexpr bool ISO = TGT == TGT_ISO || TGT == TGT_QPS;
   constexpr bool ENERGY_LIKE = OP == OP_ENERGY || OP == OP_SIZE || OP == OP_JINV;
-  constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P;
   constexpr bool AFFINE = sizeof(R) == 4;
-  constexpr int NE = OP == OP_HESS ? C::NEH : C::NE;
-  __shared__ R s_all[EPB * NE];
-  __shared__ double red[2 * (C::BLOCK / 64)];
-
-  const int tid = threadIdx.x;
-  const int le_raw = tid / TPE;
-  const int le = le_raw < EPB ? le_raw : EPB - 1;
-  const int ta = le_raw < EPB ? tid - le_raw * TPE : Q;
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int k = blk * EPB + le;
-  const bool active = le_raw < EPB && k < a.n_list;
-  const int kk = k < a.n_list ? k : a.n_list - 1;
-  const int e = a.list ? a.list[kk] : kk;
-  R* s = s_all + le * C::NE;
-  const bool p1 = ta < P;
-
-  const int32_t* en = a.elem_node + (int64_t)e * NPE;
-  int node[P];
-#pragma unroll
-  for (int i1 = 0; i1 < P; ++i1) node[i1] = p1 ? en[ta + P * i1] : en[0];
-  R X[2][P], dX[2][P], J0x[2][2], J0v[2][2];
-  load_pencil_2d<P, Q, R, AFFINE>(a, a.x, node, en, p1 ? ta : 0, X, J0x);
-  if constexpr (OP == OP_HESS) load_pencil_2d<P, Q, R, AFFINE>(a, a.v, node, en, p1 ? ta : 0, dX, J0v);
-
   R U[2][2][P], dU[2][2][P];
   fwd_2d<P, Q, R>(a, X, ta, s, U);
   if constexpr (OP == OP_HESS) {
@@ -960,7 +941,6 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
     fwd_2d<P, Q, R>(a, dX, ta, s, dU);
   }
 
-  double acc = 0.0, mind = __builtin_huge_val();
   R Racc[2][2][P];
 #pragma unroll
   for (int tt = 0; tt < 2; ++tt)
@@ -1038,20 +1018,7 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
     }
   }
 
-  if constexpr (OP == OP_ENERGY || OP == OP_EG || OP == OP_SIZE || OP == OP_JINV) {
-    if (!active) { acc = 0.0; mind = __builtin_huge_val(); }
-    block_reduce_sum_min<C::BLOCK>(acc, mind, red, a.part + blk, a.part_min + blk);
-  }
   if constexpr (!ENERGY_LIKE) {
-    double old[2][P];
-    if (active && p1) {
-#pragma unroll
-      for (int i1 = 0; i1 < P; ++i1) {
-        const bool fresh = first_touch<NPE>(a.first, kk, ta + P * i1);
-#pragma unroll
-        for (int c = 0; c < 2; ++c) old[c][i1] = fresh ? 0.0 : a.out[c * a.n_node + node[i1]];
-      }
-    }
     // pass 2': lane q1 writes its own U slots, no barrier needed first
     if (ta < Q) {
 #pragma unroll
@@ -1062,8 +1029,8 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
           for (int i0 = 0; i0 < P; ++i0) s[uidx2<P, Q>(tt, c, ta, i0)] = Racc[tt][c][i0];
     }
     __syncthreads();
-    // pass 1': lane i0 = ta, then the scatter
-    if (active && p1) {
+    // pass 1': lane i0 = ta
+    if (ta < P) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         R rb[Q], rg[Q];
@@ -1074,11 +1041,195 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
           R v = 0;
 #pragma unroll
           for (int q1 = 0; q1 < Q; ++q1) v += a.B[q1][i1] * rb[q1] + a.G[q1][i1] * rg[q1];
-          a.out[c * a.n_node + node[i1]] = old[c][i1] + (double)v;
+          V[c][i1] = v;
         }
       }
     }
   }
+}
+
+template <int P, int Q, int METRIC, typename R, int OP, int TGT>
+__global__ void __launch_bounds__((Cfg<2, P, Q, R>::BLOCK))
+elem_kernel_2d(const ElemArgs<P, Q, R> a) {
+  using C = Cfg<2, P, Q, R>;
+  constexpr bool ENERGY_LIKE = OP == OP_ENERGY || OP == OP_SIZE || OP == OP_JINV;
+  constexpr int TPE = C::TPE, EPB = C::EPB, NPE = P * P;
+  constexpr bool AFFINE = sizeof(R) == 4;
+  constexpr int NE = OP == OP_HESS ? C::NEH : C::NE;
+  __shared__ R s_all[EPB * NE];
+  __shared__ double red[2 * (C::BLOCK / 64)];
+
+  const int tid = threadIdx.x;
+  const int le_raw = tid / TPE;
+  const int le = le_raw < EPB ? le_raw : EPB - 1;
+  const int ta = le_raw < EPB ? tid - le_raw * TPE : Q;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int k = blk * EPB + le;
+  const bool active = le_raw < EPB && k < a.n_list;
+  const int kk = k < a.n_list ? k : a.n_list - 1;
+  const int e = a.list ? a.list[kk] : kk;
+  R* s = s_all + le * C::NE;
+  const bool p1 = ta < P;
+
+  const int32_t* en = a.elem_node + (int64_t)e * NPE;
+  int node[P];
+#pragma unroll
+  for (int i1 = 0; i1 < P; ++i1) node[i1] = p1 ? en[ta + P * i1] : en[0];
+  R X[2][P], dX[2][P], J0x[2][2], J0v[2][2];
+  load_pencil_2d<P, Q, R, AFFINE>(a, a.x, node, en, p1 ? ta : 0, X, J0x);
+  if constexpr (OP == OP_HESS) load_pencil_2d<P, Q, R, AFFINE>(a, a.v, node, en, p1 ? ta : 0, dX, J0v);
+  // the scatter's old values, loaded with the fields: a 2D colour launch
+  // holds about one round of waves, so their latency would otherwise add to
+  // the launch's dependent chain
+  double old[2][P];
+  if constexpr (!ENERGY_LIKE) {
+    if (active && p1) {
+#pragma unroll
+      for (int i1 = 0; i1 < P; ++i1) {
+        const bool fresh = first_touch<NPE>(a.first, kk, ta + P * i1);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) old[c][i1] = fresh ? 0.0 : a.out[c * a.n_node + node[i1]];
+      }
+    }
+  }
+
+  double acc = 0.0, mind = __builtin_huge_val();
+  R V[2][P];
+  elem2d_work<P, Q, METRIC, R, OP, TGT>(a, e, ta, active, s, X, dX, J0x, J0v, acc, mind, V);
+
+  if constexpr (OP == OP_ENERGY || OP == OP_EG || OP == OP_SIZE || OP == OP_JINV) {
+    if (!active) { acc = 0.0; mind = __builtin_huge_val(); }
+    block_reduce_sum_min<C::BLOCK>(acc, mind, red, a.part + blk, a.part_min + blk);
+  }
+  if constexpr (!ENERGY_LIKE) {
+    if (active && p1) {   // the scatter
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int i1 = 0; i1 < P; ++i1) a.out[c * a.n_node + node[i1]] = old[c][i1] + (double)V[c][i1];
+    }
+  }
+}
+
+// ------------------------------------------------- 2D owner-computes tiles
+
+template <int P, int Q, typename R>
+struct TileCfg {
+  static constexpr int EPR = tile_epr(Q);              // elements per round
+  static constexpr int NE = elem2d_lds_values(P, Q);   // LDS values per element
+};
+
+// load_pencil_2d for an element of a tile: the same FP64 operations on the
+// same global values, with the nodes' global ids gn (this lane's pencil)
+// and c00, c10, c01 (the corners of the element frame).
+template <int P, int Q, typename R, bool AFFINE>
+__device__ __forceinline__ void tile_pencil_2d(const ElemArgs<P, Q, R>& a, const double* __restrict__ f,
+                                               const int (&gn)[P], int c00, int c10, int c01, int i0,
+                                               R (&X)[2][P], R (&J0r)[2][2]) {
+  double org[2], J0[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+  for (int c = 0; c < 2; ++c) org[c] = f[c * a.n_node + c00];
+  if constexpr (AFFINE) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      J0[c][0] = f[c * a.n_node + c10] - org[c];
+      J0[c][1] = f[c * a.n_node + c01] - org[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int l = 0; l < 2; ++l) J0r[c][l] = (R)(J0[c][l] * a.jscale);
+#pragma unroll
+  for (int i1 = 0; i1 < P; ++i1)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if constexpr (AFFINE)
+        X[c][i1] = (R)(f[c * a.n_node + gn[i1]] - org[c] - J0[c][0] * a.xi[i0] - J0[c][1] * a.xi[i1]);
+      else
+        X[c][i1] = (R)(f[c * a.n_node + gn[i1]] - org[c]);
+    }
+}
+
+// One workgroup per tile (OP_GRAD, OP_EG, OP_HESS; see TileParams): the
+// element work is elem2d_work, as in the colour launches, on the same
+// gathered field values; only where the contributions go differs.  LDS:
+// the accumulators [2][nn] (FP64), the element areas, the node ids [nn].
+// Energy partials (OP_EG): one per tile.
+template <int P, int Q, int METRIC, typename R, int OP, int TGT>
+__global__ void __launch_bounds__(TILE_BLOCK)
+tile_kernel_2d(const ElemArgs<P, Q, R> a, const TileParams tp) {
+  using TC = TileCfg<P, Q, R>;
+  constexpr int NPE = P * P, EPR = TC::EPR;
+  constexpr bool AFFINE = sizeof(R) == 4;
+  constexpr bool HESS = OP == OP_HESS;
+  extern __shared__ double lds[];
+  __shared__ double red[2 * (TILE_BLOCK / 64)];
+
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int tid = threadIdx.x;
+  const int n0 = tp.node_off[tile], nn = tp.node_off[tile + 1] - n0;
+  double* acc = lds;                                           // [2][nn]
+  R* s_all = reinterpret_cast<R*>(acc + 2 * nn);               // [EPR][NE]
+  int* ids = reinterpret_cast<int*>(s_all + EPR * TC::NE);     // [nn]
+  for (int l = tid; l < nn; l += TILE_BLOCK) {
+    ids[l] = tp.node[n0 + l];
+    acc[l] = 0.0;
+    acc[nn + l] = 0.0;
+  }
+  __syncthreads();
+
+  const int le_raw = tid / Q;
+  const int le = le_raw < EPR ? le_raw : EPR - 1;
+  const int ta = le_raw < EPR ? tid - le_raw * Q : Q;   // idle pad lanes take no part
+  const bool p1 = ta < P;
+  R* s = s_all + le * TC::NE;
+  const int r0 = tp.round_off[tile], nr = tp.round_off[tile + 1] - r0;
+  double eacc = 0.0, emin = __builtin_huge_val();
+  for (int r = 0; r < nr; ++r) {
+    const int64_t slot = (int64_t)(r0 + r) * EPR + le;
+    const int e_raw = le_raw < EPR ? tp.slot_elem[slot] : -1;
+    const bool active = e_raw >= 0;
+    const int e = active ? e_raw : 0;              // empty slots compute on local node 0, write nothing
+    const uint16_t* en = tp.slot_lnode + slot * NPE;
+    int ln[P], gn[P];
+#pragma unroll
+    for (int i1 = 0; i1 < P; ++i1) {
+      ln[i1] = p1 ? en[ta + P * i1] : en[0];
+      gn[i1] = ids[ln[i1]];
+    }
+    const int c00 = ids[en[0]], c10 = ids[en[P - 1]], c01 = ids[en[P * (P - 1)]];
+    R X[2][P], dX[2][P], J0x[2][2], J0v[2][2];
+    tile_pencil_2d<P, Q, R, AFFINE>(a, a.x, gn, c00, c10, c01, p1 ? ta : 0, X, J0x);
+    if constexpr (HESS) tile_pencil_2d<P, Q, R, AFFINE>(a, a.v, gn, c00, c10, c01, p1 ? ta : 0, dX, J0v);
+    double racc = 0.0, rmin = __builtin_huge_val();
+    R V[2][P];
+    elem2d_work<P, Q, METRIC, R, OP, TGT>(a, e, ta, active, s, X, dX, J0x, J0v, racc, rmin, V);
+    if (active) {
+      eacc += racc;
+      emin = fmin(emin, rmin);
+    }
+    if (active && p1) {   // the elements of a round share no node, lanes of one element own distinct nodes
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int i1 = 0; i1 < P; ++i1) acc[c * nn + ln[i1]] += (double)V[c][i1];
+    }
+    __syncthreads();   // the next round reuses the element areas and may share these nodes
+  }
+
+  for (int l = tid; l < nn; l += TILE_BLOCK) {
+    const int64_t g = ids[l];
+    const int sl = tp.slot[n0 + l];
+    if (sl < 0) {
+      a.out[g] = acc[l];
+      a.out[a.n_node + g] = acc[nn + l];
+    } else {
+      tp.halo[sl] = acc[l];
+      tp.halo[tp.n_slot + sl] = acc[nn + l];
+    }
+  }
+  if constexpr (OP == OP_EG) block_reduce_sum_min<TILE_BLOCK>(eacc, emin, red, a.part + tile, a.part_min + tile);
 }
 
 // ------------------------------------------------------- Hessian diagonal

@@ -24,6 +24,63 @@ constexpr int MU98_3D = 398;
 constexpr int MAXP = 5;   // nodes per direction (order p <= 4)
 constexpr int MAXQ = 6;   // quadrature points per direction
 
+// LDS values per element of the 2D element kernels: the forward data of
+// both components and directions (2 x 2 x Q x P), padded against bank
+// conflicts.
+#ifndef TMOP_ELEM_PAD2
+#define TMOP_ELEM_PAD2 5
+#endif
+constexpr int elem2d_lds_values(int P, int Q) { return 2 * 2 * Q * P + TMOP_ELEM_PAD2; }
+
+// Owner-computes tiles of a 2D mesh: the gradient, energy + gradient and
+// Hessian action in one launch over every element instead of one launch per
+// colour.  A workgroup of TILE_BLOCK lanes holds in LDS its tile's node ids
+// and an FP64 accumulator per node component, runs the tile's elements in
+// rounds of node-disjoint elements (Q lanes each, TILE_BLOCK / Q per round)
+// in a fixed order, adding each element's contribution to the accumulators,
+// then writes every node only its tile touches and, for a node shared with
+// other tiles, its partial sum into that node's slot for this tile.  The
+// halo pass adds the slots of each shared node in tile order.  Every sum
+// has a fixed order, so the results are reproducible.
+constexpr int TILE_BLOCK = 128;
+// dynamic LDS of a tile workgroup: 64 KiB less room for its static arrays
+constexpr int TILE_LDS_BYTES = 64 * 1024 - 256;
+constexpr int tile_epr(int Q) { return TILE_BLOCK / Q; }
+// LDS bytes per tile node: two FP64 accumulators and the node id
+constexpr int TILE_NODE_BYTES = 2 * 8 + 4;
+// LDS bytes of a tile workgroup with nn nodes and element data of rsize bytes
+constexpr int64_t tile_lds_bytes(int P, int Q, int rsize, int64_t nn) {
+  return nn * TILE_NODE_BYTES + (int64_t)tile_epr(Q) * elem2d_lds_values(P, Q) * rsize;
+}
+struct TileParams {
+  const int32_t* round_off;    // [n_tile + 1]: the rounds of tile t are round_off[t] .. round_off[t + 1] - 1
+  const int32_t* slot_elem;    // [rounds][tile_epr(Q)]: the element of each round slot, -1: empty
+  const uint16_t* slot_lnode;  // [rounds][tile_epr(Q)][P^2]: its nodes' tile-local ids (0 in empty slots)
+  const int32_t* node_off;     // [n_tile + 1]: the nodes of tile t are node[node_off[t] ..]
+  const int32_t* node;         // global node ids, ascending within each tile
+  const int32_t* slot;         // per tile node: its halo slot, or -1 when no other tile touches it
+  double* halo;                // [2][n_slot] the tiles' partial sums at shared nodes
+  const int32_t* halo_node;    // [n_halo] the shared nodes, ascending
+  const int32_t* halo_off;     // [n_halo + 1]: node halo_node[h] has slots halo_off[h] .. (tile order)
+  int64_t n_slot, n_halo;
+  int32_t n_tile;
+  int32_t nn_max;              // most nodes of one tile: sizes the LDS of the launch
+};
+// out[c][halo_node[h]] = sum of its slots, in order
+hipError_t halo_sum(const TileParams& tp, int64_t n_node, double* out, hipStream_t s);
+// The host form of the TileParams arrays (tmop_tiles.cpp).
+struct TileLayout {
+  std::vector<int32_t> round_off, slot_elem, node_off, node, slot, halo_node, halo_off;
+  std::vector<uint16_t> slot_lnode;
+  int32_t nn_max = 0;
+  int64_t n_slot = 0;
+};
+// Tiles of a 2D mesh of order p with Q points per direction: elem_node
+// [n_elem][npe], colour[e] its element colour.  0, or -1 when the mesh does
+// not fit the tile limits (a round index or a node count out of range).
+int build_tiles(const int32_t* elem_node, int64_t n_elem, int npe, int64_t n_node, const int32_t* colour, int p,
+                int Q, TileLayout& out);
+
 // Everything one element-kernel launch needs, in host form.
 struct LaunchParams {
   const double* x;
@@ -57,6 +114,9 @@ struct LaunchParams {
   double M1[MAXP][MAXP];   // 1D mass matrix of the quadrature
   double kpen;             // 2 delta det W
   bool dry;                // only report the grid (*grid), launch nothing
+  // 2D OP_GRAD / OP_EG / OP_HESS over every element in owner-computes tiles
+  // (nullptr: the colour launch described by elem_node / list / first)
+  const TileParams* tile;
 };
 
 // Everything one launch of the displacement-penalty kernels (eq. 4.2)
@@ -100,6 +160,9 @@ struct DfoParams {
   double detW, step, xtol;
 };
 int launch_dfo(int dim, int p, int Q, int metric, const DfoParams& dp, hipStream_t s);
+// Elements a node's patch may have in the derivative-free kernel: its
+// workgroup's lanes hold that many elements' quadrature points (at least 2^dim).
+int dfo_patch_capacity(int dim, int Q);
 
 // Launch one element operation (OP_ENERGY / OP_GRAD / OP_HESS / OP_EG) on
 // n_list elements: element k has the nodes lp.elem_node[e * npe ...] with
@@ -238,6 +301,10 @@ struct tmop_ctx {
   double* h_sc = nullptr;              // its pinned host mirror
   int64_t n_free = 0;                  // free DOFs (mask 1)
   double* d_noalloc = nullptr;         // the allocation-free entry point's scratch on this device
+  // 2D owner-computes tiles (TMOP_SCATTER_TILES), built on first use
+  int scatter = 0;                     // TMOP_SCATTER_COLOURS or TMOP_SCATTER_TILES
+  int tile_elems = 0;                  // elements per tile they were built for
+  tmop::TileParams tile{};             // its device arrays, owned by the context
   // optional per-launch timing of the element kernels (HIP events)
   struct TimedLaunch { int op; hipEvent_t a, b; };
   bool timing = false;

@@ -37,6 +37,21 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   a.detW = lp.detW;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) a.Winvd[i][j] = lp.Winv[i][j];
+  if constexpr (DIM == 2 && (OP == OP_GRAD || OP == OP_EG || OP == OP_HESS)) {
+    if (lp.tile) {   // owner-computes tiles: one workgroup per tile, then the halo sums
+      const TileParams& tp = *lp.tile;
+      *grid = tp.n_tile;
+      if (tp.n_tile == 0 || lp.dry) return 0;
+      const int64_t lds = tile_lds_bytes(P, Q, (int)sizeof(R), tp.nn_max);
+      if (lds > TILE_LDS_BYTES) return -2;
+      const ElemArgs<P, Q, R>& ea = a;
+      hipLaunchKernelGGL((tile_kernel_2d<P, Q, METRIC, R, OP, TGT>), dim3(tp.n_tile), dim3(TILE_BLOCK), (size_t)lds, s,
+                         ea, tp);
+      if (hipGetLastError() != hipSuccess) return -2;
+      return halo_sum(tp, lp.n_node, lp.out, s) == hipSuccess ? 0 : -2;
+    }
+  }
+  if (lp.tile) return -1;
   const int g = (lp.n_list + C::EPB - 1) / C::EPB;
   *grid = g;
   if (g == 0 || lp.dry) return 0;

@@ -28,13 +28,14 @@ TMOP_FP64, TMOP_MIXED_FP32 = 0, 1
 TMOP_TGT_CONST, TMOP_TGT_ISO_PER_QP, TMOP_TGT_PER_ELEM, TMOP_TGT_PER_QP = 0, 1, 2, 3
 TMOP_INNER_CG, TMOP_INNER_MINRES, TMOP_INNER_SHIFTED_CG = 0, 1, 2
 TMOP_PREC_NONE, TMOP_PREC_JACOBI = 0, 1
+TMOP_SCATTER_COLOURS, TMOP_SCATTER_TILES = 0, 1
 
 EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_gradient_scaled", "tmop_hessian_apply",
            "tmop_newton_solve", "tmop_destroy", "tmop_strerror", "tmop_newton_default_opts",
            "tmop_timing_enable", "tmop_timing_read", "tmop_energy_gradient", "tmop_hessian_diagonal",
            "tmop_target_sizes_w3", "tmop_set_target_sizes", "tmop_set_restriction", "tmop_set_combo",
            "tmop_set_replication", "tmop_dfo_default_opts", "tmop_dfo_sweep", "tmop_dfo_solve",
-           "tmop_energy_noalloc")
+           "tmop_energy_noalloc", "tmop_set_scatter")
 # timing slots: the element-kernel operations, then the W_0 data and the penalty kernels
 TIMING_ENERGY, TIMING_GRAD, TIMING_HESS, TIMING_EG, TIMING_DIAG, TIMING_SIZE = 0, 1, 2, 3, 4, 5
 TIMING_W0, TIMING_PENALTY = 6, 7
@@ -113,6 +114,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tmop_hessian_apply.restype = ctypes.c_int
     lib.tmop_hessian_diagonal.argtypes = [P, P, P, P]
     lib.tmop_hessian_diagonal.restype = ctypes.c_int
+    lib.tmop_set_scatter.argtypes = [P, ctypes.c_int32]
+    lib.tmop_set_scatter.restype = ctypes.c_int
     lib.tmop_target_sizes_w3.argtypes = [P, P, P, P]
     lib.tmop_target_sizes_w3.restype = ctypes.c_int
     lib.tmop_set_target_sizes.argtypes = [P, P, P]
@@ -298,6 +301,13 @@ class Context:
         if st < 0:
             raise TMOPError(st, "tmop_hessian_apply")
         return out
+
+    def set_scatter(self, mode):
+        """TMOP_SCATTER_COLOURS or TMOP_SCATTER_TILES (2D): how the gradient
+        and Hessian action add element contributions at shared nodes."""
+        st = self._lib.tmop_set_scatter(self._h, int(mode))
+        if st < 0:
+            raise TMOPError(st, "tmop_set_scatter")
 
     def hessian_diagonal(self, x, out=None):
         """diag(d^2F/dx^2) over all DOFs, shape (dim, n_node)."""

@@ -121,3 +121,58 @@ def test_arguments_and_unsupported_contexts():
     with pytest.raises(T.TMOPError) as ei:
         qps.dfo_solve(xd)
     assert ei.value.status == T.TMOP_E_UNSUPPORTED
+
+
+def _pentagon():
+    """Five Q2 quadrilaterals around one interior vertex (valence 5); every
+    node but that vertex is fixed.  Each element is the bilinear map of its
+    corners (centre, spoke k, spoke k+1, rim k: counter-clockwise frames)
+    evaluated at the order-2 nodes 0, 1/2, 1, shared nodes merged."""
+    ang = 2 * np.pi * np.arange(5) / 5
+    spoke = np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    rim = 1.3 * np.stack([np.cos(ang + np.pi / 5), np.sin(ang + np.pi / 5)], axis=1)
+    centre = np.array([0.05, -0.03])
+    t = np.array([0.0, 0.5, 1.0])
+    ids, xy, en = {}, [], []
+    for k in range(5):
+        c00, c10, c01, c11 = centre, spoke[k], spoke[(k + 1) % 5], rim[k]
+        row = []
+        for b in t:
+            for a in t:
+                pt = (1 - a) * (1 - b) * c00 + a * (1 - b) * c10 + (1 - a) * b * c01 + a * b * c11
+                key = tuple(np.round(pt, 9))
+                if key not in ids:
+                    ids[key] = len(xy)
+                    xy.append(pt)
+                row.append(ids[key])
+        en.append(row)
+    xy = np.array(xy)
+    fixed = np.ones((2, len(xy)), dtype=np.uint8)
+    fixed[:, ids[tuple(np.round(centre, 9))]] = 0
+    return xy.T.copy(), np.array(en, dtype=np.int32), fixed
+
+
+def test_patch_beyond_workgroup_capacity_is_refused():
+    """A valence-5 vertex with 4 points per direction: its patch has more
+    quadrature points than the node's workgroup holds (4 elements), so the
+    sweep refuses (x untouched) instead of dropping an element's points from
+    the patch quality and from the positivity guard.  With 3 points per
+    direction the same patch fits (7 elements) and the sweep runs, never
+    raising F."""
+    from paper_1807_09807_amd import tmop as T
+    x, en, fixed = _pentagon()
+    n = x.shape[1]
+    for Q, ok in ((4, False), (3, True)):
+        ctx = T.Context(2, 2, en, n, Q, 2, 0.8 * np.eye(2), fixed=fixed)
+        xd = to_dev(x)
+        F0, md, st = ctx.energy(xd)
+        assert st == 0 and md > 0
+        if ok:
+            ctx.dfo_sweep(xd)
+            assert ctx.energy(xd)[0] <= F0
+        else:
+            with pytest.raises(T.TMOPError) as ei:
+                ctx.dfo_sweep(xd)
+            assert ei.value.status == T.TMOP_E_UNSUPPORTED
+            assert torch.equal(xd, to_dev(x))
+        ctx.close()
