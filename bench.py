@@ -605,6 +605,44 @@ def small_newton(T, torch, dev, log):
     return out
 
 
+def cg_iteration_cost(T, torch, dev, log, name="q2_square_512"):
+    """Device time of one inner-solver iteration (a Hessian action plus the
+    solver's vector kernels and device-side scalars, with its occasional
+    host checks) against the Hessian action alone, on the learned-guess
+    evaluation workload: one Newton iteration whose inner solve runs to its
+    iteration cap (tolerance 1e-30), at two caps; the difference over the
+    difference in iterations is the cost of one."""
+    w, mesh, W = build_mesh(T, torch, dev, name, True)
+    x0 = torch.from_numpy(mesh.x).to(dev)
+    v = torch.from_numpy(meshgen.random_direction(mesh, w["seed"] + 100)).to(dev)
+    out = {"workload": name}
+    for prec, pname in ((T.TMOP_FP64, "f64"), (T.TMOP_MIXED_FP32, "mixed")):
+        ctx = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W,
+                        fixed=mesh.fixed, precision=prec)
+        hess = op_times(torch, ctx, x0, v, 20)["hessian"]
+        res = {"hessian_us": round(hess * 1e6, 2)}
+        for inner, iname in ((T.TMOP_INNER_SHIFTED_CG, "shifted_cg"), (T.TMOP_INNER_CG, "cg"),
+                             (T.TMOP_INNER_MINRES, "minres")):
+            pts = []
+            for cap in (40, 40, 140):   # the first run warms up
+                x = x0.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, rep = ctx.newton_solve(x, max_it=1, cg_rtol=1e-30, cg_max_it=cap, inner=inner)
+                torch.cuda.synchronize()
+                pts.append((rep["cg_iters"], time.perf_counter() - t0))
+            (n1, t1), (n2, t2) = pts[1], pts[2]
+            per = (t2 - t1) / (n2 - n1) if n2 > n1 else None
+            res[iname] = {"iterations": [n1, n2], "us_per_iteration": round(per * 1e6, 2) if per else None,
+                          "ratio_to_hessian": round(per / hess, 3) if per else None}
+        ctx.close()
+        out[pname] = res
+        log(f"# inner iteration cost {name} {pname}: Hv {res['hessian_us']} us; "
+            + ", ".join(f"{k} {res[k]['us_per_iteration']} us ({res[k]['ratio_to_hessian']}x)"
+                        for k in ("shifted_cg", "cg", "minres")))
+    return out
+
+
 def workload_summary(w, mesh, results):
     """Per-operation rates of one workload against the FP64 VALU and HBM
     peaks (algorithmic flops and unique L-vector bytes per element)."""
@@ -686,6 +724,8 @@ def main():
                   f"negative-curvature exits or CG restarts, {rep['wall_s']:.2f} s, F {rep['F0']:.4e} -> "
                   f"{rep['F']:.4e}", file=sys.stderr, flush=True)
         newton["q2_square_8"] = small_newton(T, torch, dev, lambda m: print(m, file=sys.stderr, flush=True))
+        newton["inner_iteration_cost"] = cg_iteration_cost(T, torch, dev,
+                                                           lambda m: print(m, file=sys.stderr, flush=True))
 
     tgt = None
     if not args.no_targets:

@@ -522,6 +522,7 @@ void free_ctx(tmop_ctx* c) {
   (void)hipFree(c->d_elem_node_col);
   (void)hipFree(c->d_first);
   (void)hipFree(c->d_mask);
+  (void)hipFree(c->d_mask8);
   (void)hipFree(c->d_tsize);
   (void)hipFree(c->d_tsize_col);
   (void)hipFree(c->d_tmat);
@@ -625,7 +626,7 @@ int cg_run(tmop_ctx* c, const double* x, const double* g, double gn, double tol,
   double* p = w.v[1];
   double* Hp = w.v[2];
   double* z = minv ? w.v[3] : r;
-  const double* mask = c->has_fixed ? c->d_mask : nullptr;
+  const uint8_t* mask8 = c->has_fixed ? c->d_mask8 : nullptr;
   int st;
   HIP_TRY(fill(w.d, 0.0, N, s));
   HIP_TRY(scale_copy(-1.0, g, r, N, s));
@@ -641,6 +642,7 @@ int cg_run(tmop_ctx* c, const double* x, const double* g, double gn, double tol,
   c->h_sc[SC_ACTIVE] = 1.0;
   c->h_sc[SC_MAXIT] = max_it;
   c->h_sc[SC_RZ] = rz;
+  c->h_sc[SC_RZP] = rz;
   if ((st = sc_upload(c, s)) != TMOP_OK) return st;
   bool active = true;
   for (int j = 1, check = 1; j <= max_it; ++j) {
@@ -648,7 +650,7 @@ int cg_run(tmop_ctx* c, const double* x, const double* g, double gn, double tol,
     // p . (m .* Hp), and the update applies the mask to Hp
     if ((st = assemble(c, OP_HESS, x, p, Hp, s)) != TMOP_OK) return st;
     HIP_TRY(cg_dev_curvature(p, Hp, tau, N, c->d_scratch, c->d_sc, s));
-    HIP_TRY(cg_dev_update(p, Hp, tau, mask, minv, w.d, r, z, N, tol * gn, c->d_scratch, c->d_sc, s));
+    HIP_TRY(cg_dev_update(p, Hp, tau, mask8, minv, w.d, r, z, N, tol * gn, c->d_scratch, c->d_sc, s));
     if (j == check || j == max_it) {
       if ((st = sc_read(c, s, &active)) != TMOP_OK) return st;
       if (!active) break;
@@ -926,7 +928,7 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
     if (hipMalloc(&c->d_elem_node, en_bytes) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipMalloc(&c->d_colors, order.size() * sizeof(int32_t)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipMalloc(&c->d_part, 2 * (size_t)c->part_cap * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
-    if (hipMalloc(&c->d_scratch, 2 * RED_BLOCKS * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
+    if (hipMalloc(&c->d_scratch, 4 * RED_BLOCKS * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipMalloc(&c->d_res, 4 * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipHostMalloc(&c->h_res, 4 * sizeof(double), 0) != hipSuccess) { st = TMOP_E_NOMEM; break; }
     if (hipMalloc(&c->d_mask, c->n_dof * sizeof(double)) != hipSuccess) { st = TMOP_E_NOMEM; break; }
@@ -991,6 +993,12 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
     c->n_free = 0;
     for (int64_t k = 0; k < c->n_dof; ++k) c->n_free += mask[k] > 0.0;
     if (hipMemcpy(c->d_mask, mask.data(), c->n_dof * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
+    {
+      std::vector<uint8_t> m8(c->n_dof);
+      for (int64_t k = 0; k < c->n_dof; ++k) m8[k] = mask[k] > 0.0 ? 1 : 0;
+      if (hipMalloc(&c->d_mask8, c->n_dof) != hipSuccess) { c->d_mask8 = nullptr; st = TMOP_E_NOMEM; break; }
+      if (hipMemcpy(c->d_mask8, m8.data(), c->n_dof, hipMemcpyHostToDevice) != hipSuccess) { st = TMOP_E_HIP; break; }
+    }
   } while (0);
   if (st != TMOP_OK) { free_ctx(c); return st; }
   *out = c;

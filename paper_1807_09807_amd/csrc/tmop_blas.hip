@@ -244,43 +244,49 @@ __global__ void __launch_bounds__(RED_THREADS) k_dot_shift_part(const double* __
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// CG: pHp from the partials; curvature test; alpha = rz / pHp.
-__global__ void __launch_bounds__(RED_THREADS) k_cg_alpha(const double* __restrict__ part, double* __restrict__ sc) {
-  __shared__ double red[RED_THREADS / 64];
-  const double run = sc[SC_ACTIVE];
-  if (run == 0.0) {
-    if (threadIdx.x == 0) sc[SC_RUN] = 0.0;
-    return;
-  }
-  const double pHp = fold_parts(part, red);
-  if (threadIdx.x == 0) {
-    sc[SC_RUN] = 1.0;
-    sc[SC_ITERS] += 1.0;
-    sc[SC_PHP] = pHp;
-    if (!(pHp > 0.0)) {               // non-positive curvature (or NaN): the run ends here, d unchanged
-      sc[SC_NEG] = 1.0;
-      sc[SC_RUN] = 0.0;
-      sc[SC_ACTIVE] = 0.0;
-    } else {
-      sc[SC_ALPHA] = sc[SC_RZ] / pHp;
-    }
-  }
-}
+// The CG scalars ride in the vector kernels that use them: every block
+// folds the same partial sums in the same order, so every block takes the
+// same decision and the same alpha or beta; block 0 alone writes the run
+// state.  A value that the blocks of a kernel read is never written by that
+// kernel: the new r . z goes to SC_RZP, which the next update commits to
+// SC_RZ.
 
-// CG update: d += alpha p; r -= alpha (m .* Hp + tau p); z = minv .* r;
-// block partial sums of r . r and, with minv, r . z.
+// CG update: pHp from the partials php_part (curvature test, alpha =
+// rz / pHp), then d += alpha p; r -= alpha (m .* Hp + tau p); z = minv .* r
+// and block partial sums of r . r (part[0, RED_BLOCKS)) and, with minv,
+// r . z (part[RED_BLOCKS, 2 RED_BLOCKS)).  m: byte mask (1 = free DOF).
 __global__ void __launch_bounds__(RED_THREADS) k_cg_update(const double* __restrict__ p, const double* __restrict__ Hp,
-                                                           double tau, const double* __restrict__ m,
+                                                           double tau, const uint8_t* __restrict__ m,
                                                            const double* __restrict__ minv, double* __restrict__ d,
                                                            double* __restrict__ r, double* __restrict__ z, int64_t n,
-                                                           const double* __restrict__ sc, double* __restrict__ part) {
+                                                           double* __restrict__ sc, const double* __restrict__ php_part,
+                                                           double* __restrict__ part) {
   __shared__ double red[2][RED_THREADS / 64];
-  if (sc[SC_RUN] == 0.0) return;
-  const double a = sc[SC_ALPHA];
+  if (sc[SC_ACTIVE] == 0.0) {   // ended earlier, or block 0 has just found non-positive curvature
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[SC_RUN] = 0.0;
+    return;
+  }
+  const double pHp = fold_parts(php_part, red[0]);
+  const double rz = sc[SC_RZP];
+  const bool neg = !(pHp > 0.0);   // non-positive curvature (or NaN): the run ends here, d unchanged
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[SC_ITERS] += 1.0;
+    sc[SC_PHP] = pHp;
+    sc[SC_RZ] = rz;
+    sc[SC_RUN] = neg ? 0.0 : 1.0;
+    if (neg) {
+      sc[SC_NEG] = 1.0;
+      sc[SC_ACTIVE] = 0.0;
+    } else {
+      sc[SC_ALPHA] = rz / pHp;
+    }
+  }
+  if (neg) return;
+  const double a = rz / pHp;
   double srr = 0.0, srz = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)RED_BLOCKS * RED_THREADS) {
     const double pi = p[i];
-    const double hi = (m ? Hp[i] * m[i] : Hp[i]) + tau * pi;
+    const double hi = (m && !m[i] ? 0.0 : Hp[i]) + tau * pi;
     d[i] += a * pi;
     const double ri = r[i] - a * hi;
     r[i] = ri;
@@ -299,31 +305,31 @@ __global__ void __launch_bounds__(RED_THREADS) k_cg_update(const double* __restr
   }
 }
 
-// CG: convergence test |r| <= tol_abs, then beta = rz_new / rz.
-__global__ void __launch_bounds__(RED_THREADS) k_cg_beta(const double* __restrict__ part, int precond, double tol_abs,
-                                                         double* __restrict__ sc) {
+// CG direction: r . r (and r . z) from the partials, the stopping test
+// |r| <= tol_abs or the iteration cap, then beta = rz_new / rz and
+// p = z + beta p.
+__global__ void __launch_bounds__(RED_THREADS) k_cg_dir(const double* __restrict__ z, double* __restrict__ p, int64_t n,
+                                                        const double* __restrict__ part, int precond, double tol_abs,
+                                                        double* __restrict__ sc) {
   __shared__ double red[2][RED_THREADS / 64];
-  if (sc[SC_RUN] == 0.0) return;
+  if (sc[SC_RUN] == 0.0) return;   // ended, or block 0 has just stopped the run
   const double rr = fold_parts(part, red[0]);
   const double rz = precond ? fold_parts(part + RED_BLOCKS, red[1]) : rr;
-  if (threadIdx.x == 0) {
+  const bool stop = sqrt(rr) <= tol_abs || sc[SC_ITERS] >= sc[SC_MAXIT];
+  const double b = rz / sc[SC_RZ];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[SC_RR] = rr;
-    if (sqrt(rr) <= tol_abs || sc[SC_ITERS] >= sc[SC_MAXIT]) {
+    if (stop) {
       sc[SC_RUN] = 0.0;
       sc[SC_ACTIVE] = 0.0;
     } else {
-      sc[SC_BETA] = rz / sc[SC_RZ];
-      sc[SC_RZ] = rz;
+      sc[SC_BETA] = b;
+      sc[SC_RZP] = rz;
     }
   }
-}
-
-// CG: p = z + beta p.
-__global__ void __launch_bounds__(VB) k_cg_dir(const double* __restrict__ z, double* __restrict__ p, int64_t n,
-                                               const double* __restrict__ sc) {
-  if (sc[SC_RUN] == 0.0) return;
-  const double b = sc[SC_BETA];
-  for (int64_t i = blockIdx.x * (int64_t)VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) p[i] = z[i] + b * p[i];
+  if (stop) return;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)RED_BLOCKS * RED_THREADS)
+    p[i] = z[i] + b * p[i];
 }
 
 // MINRES: alpha = v . Hv (iteration start: SC_ACTIVE -> SC_RUN).
@@ -554,17 +560,17 @@ hipError_t mask_mul(const double* m, double* y, int64_t n, hipStream_t s) {
 
 hipError_t cg_dev_curvature(const double* p, const double* Hp, double tau, int64_t n, double* scratch, double* sc,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_dot_shift_part, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, p, Hp, tau, n, sc, scratch);
-  hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(RED_THREADS), 0, s, scratch, sc);
+  hipLaunchKernelGGL(k_dot_shift_part, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, p, Hp, tau, n, sc,
+                     scratch + 2 * RED_BLOCKS);
   return hipGetLastError();
 }
 
-hipError_t cg_dev_update(const double* p, const double* Hp, double tau, const double* m, const double* minv, double* d,
+hipError_t cg_dev_update(const double* p, const double* Hp, double tau, const uint8_t* m, const double* minv, double* d,
                          double* r, double* z, int64_t n, double tol_abs, double* scratch, double* sc, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_update, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, p, Hp, tau, m, minv, d, r, z, n, sc,
-                     scratch);
-  hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(RED_THREADS), 0, s, scratch, minv ? 1 : 0, tol_abs, sc);
-  hipLaunchKernelGGL(k_cg_dir, dim3(vgrid(n)), dim3(VB), 0, s, minv ? z : r, (double*)p, n, sc);
+                     scratch + 2 * RED_BLOCKS, scratch);
+  hipLaunchKernelGGL(k_cg_dir, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, minv ? z : r, (double*)p, n, scratch,
+                     minv ? 1 : 0, tol_abs, sc);
   return hipGetLastError();
 }
 

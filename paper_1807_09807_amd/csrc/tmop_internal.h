@@ -217,18 +217,22 @@ hipError_t minres_wd(double* v, double e, double* w_prev, double dl, const doubl
 // [SC_COUNT] doubles (indices below); see tmop_blas.hip.
 enum {
   SC_ACTIVE = 0, SC_RUN, SC_ITERS, SC_MAXIT, SC_NEG,        // run control (flags as 0/1), counters
-  SC_RZ, SC_ALPHA, SC_BETA, SC_PHP, SC_RR,                  // CG
+  SC_RZ, SC_ALPHA, SC_BETA, SC_PHP, SC_RR, SC_RZP,          // CG (SC_RZP: r . z of the next iteration)
   SC_BPREV, SC_CS, SC_SN, SC_DBAR, SC_EPS, SC_PHI, SC_PHIBAR, SC_BETA1, SC_TOL,   // MINRES
   SC_WE, SC_WDL, SC_WSG, SC_RB,
   SC_COUNT
 };
-// CG iteration, part 1: sc[SC_PHP] = p . (Hp + tau p); non-positive
-// curvature ends the run (SC_NEG); else sc[SC_ALPHA] = sc[SC_RZ] / pHp.
+// CG iteration, part 1: block partial sums of p . (Hp + tau p) into
+// scratch[2 RED_BLOCKS, 3 RED_BLOCKS).
 hipError_t cg_dev_curvature(const double* p, const double* Hp, double tau, int64_t n, double* scratch, double* sc,
                             hipStream_t s);
-// CG iteration, part 2: d += alpha p, r -= alpha (m .* Hp + tau p), z = minv .* r;
-// the run ends once |r| <= tol_abs or after SC_MAXIT iterations; else p = z + beta p.
-hipError_t cg_dev_update(const double* p, const double* Hp, double tau, const double* m, const double* minv, double* d,
+// CG iteration, part 2: pHp; non-positive curvature ends the run (SC_NEG,
+// d unchanged); else alpha = rz / pHp, d += alpha p, r -= alpha (m .* Hp +
+// tau p), z = minv .* r; the run ends once |r| <= tol_abs or after SC_MAXIT
+// iterations; else p = z + beta p.  m: byte mask of the free DOFs or
+// nullptr.  scratch: >= 3 RED_BLOCKS doubles; the run state starts with
+// SC_RZP = SC_RZ = the first r . z.
+hipError_t cg_dev_update(const double* p, const double* Hp, double tau, const uint8_t* m, const double* minv, double* d,
                          double* r, double* z, int64_t n, double tol_abs, double* scratch, double* sc, hipStream_t s);
 // MINRES iteration: alpha = v . Hv, then the residual recurrence, the
 // rotations and the direction update (the run ends at the tolerance
@@ -274,6 +278,7 @@ struct tmop_ctx {
   double* d_psize = nullptr;           // [n_elem][nq] (det W_q)^(1/dim) of those targets (the penalty's
   double* d_psize_col = nullptr;       // det W), element and colour order
   double* d_mask = nullptr;            // [n_dof], 1 = free DOF
+  uint8_t* d_mask8 = nullptr;          // the same as bytes (the CG update reads it every iteration)
   bool has_fixed = false;
   double* d_part = nullptr;            // [2 * part_cap] energy partials: sums, then minima
   int64_t part_cap = 0;                // partials per kind (3 n_elem + 16: up to three terms)
@@ -293,7 +298,7 @@ struct tmop_ctx {
   int32_t* d_ne_off = nullptr;         // node -> (element, local node) CSR offsets
   int32_t* d_ne = nullptr;             // element * npe + local node
   double* d_dfo_move = nullptr;        // [n_node] per-node moves of a sweep (negated)
-  double* d_scratch = nullptr;         // [2 * RED_BLOCKS] dot partials
+  double* d_scratch = nullptr;         // [4 * RED_BLOCKS] dot partials
   double* d_res = nullptr;             // [4] reduction results
   double* h_res = nullptr;             // [4] pinned mirror
   double* d_work = nullptr;            // Newton work vectors, allocated on first use
