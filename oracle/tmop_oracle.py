@@ -42,7 +42,7 @@ from typing import Optional
 import numpy as np
 
 METRICS_2D = (1, 2, 7, 9, 14, 77, 98)
-METRICS_3D = (302, 303)
+METRICS_3D = (7, 302, 303)
 
 
 # ---------------------------------------------------------------------------
@@ -168,7 +168,7 @@ def mu(metric: int, T: np.ndarray) -> np.ndarray:
     """mu(T) for T of shape (..., d, d).
     1:   |T|^2                                (Table 3.1, no barrier, 2D)
     2:   |T|^2 / (2 tau) - 1                 (Table 3.1, shape, 2D)
-    7:   |T - T^{-t}|^2                       (Section 3.2, shape+size, 2D)
+    7:   |T - T^{-t}|^2                       (Section 3.2, shape+size, 2D and 3D)
     9:   tau |T - T^{-t}|^2                   (Table 3.1, shape+size, 2D)
     14:  |T - I|^2                            (Section 3.2, shape+size+alignment, 2D)
     77:  (tau - 1/tau)^2 / 2                  (Table 3.1, size, 2D)
@@ -268,6 +268,9 @@ def _partials(metric, I1, I2, tau, J=None, d=2):
     if metric == 2:          # f = I1/(2 tau) - 1
         return dict(f1=1.0 / (2.0 * tau), f2=z, ft=-I1 / (2.0 * tau ** 2),
                     f11=z, f12=z, f1t=-1.0 / (2.0 * tau ** 2), f22=z, f2t=z, ftt=I1 / tau ** 3)
+    if metric == 7 and d == 3:   # |T - T^-t|^2 = I1 + |T^-1|^2 - 6, |T^-1|^2 = |cof T|^2/tau^2 = I2/tau^2
+        return dict(f1=1.0 + z, f2=tau ** -2, ft=-2.0 * I2 * tau ** -3,
+                    f11=z, f12=z, f1t=z, f22=z, f2t=-2.0 * tau ** -3, ftt=6.0 * I2 * tau ** -4)
     if metric == 7:          # |T - T^-t|^2 = I1 + |T^-1|^2 - 4, |T^-1|^2 = I1/tau^2 in 2D
         return dict(f1=1.0 + tau ** -2, f2=z, ft=-2.0 * I1 * tau ** -3,
                     f11=z, f12=z, f1t=-2.0 * tau ** -3, f22=z, f2t=z, ftt=6.0 * I1 * tau ** -4)

@@ -116,10 +116,13 @@ def test_features_labels_propose_match_oracle():
 
 def test_trained_network_gains_over_plain_newton():
     """Train on the method's own Newton solutions of 96 seeded 32^2 meshes,
-    then on unseen 64^2 meshes compare: the proposal's F against F(x0), and
-    Newton iterations / wall time to F_tol from the proposal against plain
-    Newton.  A network whose output layer is zero proposes x0 itself and is
-    never used (the fallback)."""
+    then on two unseen 64^2 meshes: the proposal lowers F below F(x0),
+    Newton from it reaches the plain-Newton F_tol without the fallback, and
+    it takes no more Newton iterations than plain Newton on either mesh and
+    fewer in total (the gain claimed; the inner CG iterations and the wall
+    time are printed, not asserted: one of the two meshes needs more CG
+    iterations from the proposal).  A network whose output layer is zero
+    proposes x0 itself and is never used (the fallback)."""
     from paper_1807_09807_amd import mlp as ML
     logs = []
     data = ML.generate_training_data(n_mesh=96, n=32, seed0=1000, log=say)
@@ -130,10 +133,15 @@ def test_trained_network_gains_over_plain_newton():
     rows = ML.evaluate(net, n=64, seeds=(10000, 10001), log=say)
     for r in rows:
         assert r["F_proposal"] < r["F0"], "the trained proposal must lower the objective"
-        assert r["used_proposal"]
+        assert r["used_proposal"] and not r["learned"]["fell_back_after_solve"]
         assert r["learned"]["F"] <= r["F_tol"] and r["plain"]["F"] <= r["F_tol"]
+        assert r["learned"]["iters"] <= r["plain"]["iters"]
+        say(f"[mlp] seed {r['seed']}: Newton {r['plain']['iters']} -> {r['learned']['iters']}, CG "
+            f"{r['plain']['cg']} -> {r['learned']['cg']}, wall {r['plain']['wall_s']:.4f} -> "
+            f"{r['learned']['wall_s']:.4f} s")
     gain_it = np.mean([r["plain"]["iters"] - r["learned"]["iters"] for r in rows])
     say(f"[mlp] mean Newton iterations saved: {gain_it:.2f}")
+    assert gain_it > 0
     # zero-output control
     p0 = ML.init_params(0)
     p0[-64 * 18 - 18:] = 0.0

@@ -127,3 +127,31 @@ def test_newton_3d_returns_to_grid(precision):
     assert err < (1e-8 if precision == 0 else 1e-4)
     Fs = rep["history_F"]
     assert all(b < a for a, b in zip(Fs, Fs[1:]))
+
+
+def test_newton_default_options_full_size_hex():
+    """The full 64^3 Q2 hex mu_303 workload with the default options (the
+    shifted-CG inner solver): Newton reaches F_tol = F_ref + 1e-8 F0, where
+    F_ref = 0 is F at the workload's minimizer, the unperturbed grid (T = I
+    at every point), F decreases monotonically, and the nodes return to the
+    grid within 1e-6 h."""
+    from paper_1807_09807_amd import tmop as T
+    w = meshgen.WORKLOADS["q2_cube_64"]
+    mesh = meshgen.box_mesh(3, w["n"], w["p"])
+    W = mesh.h * np.eye(3)
+    prob = O.Problem(3, w["p"], w["Q"], mesh.elem_node, w["metric"], W)
+    say("[newton] q2_cube_64 default options: building the workload")
+    mesh = meshgen.make_workload("q2_cube_64", bad_elements=lambda x, e: prob.bad_elements(x, e, w["tau_min"]))
+    ctx = _ctx(mesh, w["Q"], w["metric"], W)
+    xd = to_dev(mesh.x)
+    st, rep = ctx.newton_solve(xd)
+    ctx.close()
+    F_tol = 1e-8 * rep["F0"]
+    err = float(np.max(np.abs(xd.cpu().numpy() - mesh.x_grid)) / mesh.h)
+    say(f"  status {st} iters {rep['iters']} cg {rep['cg_iters']} F {rep['F0']:.3e} -> {rep['F']:.3e} "
+        f"(F_tol {F_tol:.3e}), max |x - x_grid| / h {err:.2e}")
+    assert st == T.TMOP_OK
+    assert rep["F"] <= F_tol
+    Fs = rep["history_F"]
+    assert all(b < a for a, b in zip(Fs, Fs[1:]) if a > F_tol)
+    assert err <= 1e-6

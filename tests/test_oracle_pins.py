@@ -58,9 +58,8 @@ def test_metric_closed_forms(row):
 
 
 # ---------------------------------------------------------------- P2 invariances
-@pytest.mark.parametrize("metric", [2, 7, 303, 302])
-def test_metric_invariances(metric):
-    d = 2 if metric in (2, 7) else 3
+@pytest.mark.parametrize("metric,d", [(2, 2), (7, 2), (7, 3), (303, 3), (302, 3)])
+def test_metric_invariances(metric, d):
     T = _rand_T(d, 50)
     m = O.mu(metric, T)
     assert np.all(m >= -1e-14)                                # well-behaved: mu >= 0
@@ -75,10 +74,11 @@ def test_metric_invariances(metric):
         R = 2.5 * (_rot2(0.3) if d == 2 else _rot3())
         assert np.max(np.abs(O.dmu(metric, R[None]))) < 1e-14
         assert abs(O.mu(metric, R[None])[0]) < 1e-14
-    else:             # shape+size: rotations are minimizers, scaled ones are not
-        R = _rot2(0.3)
+    else:             # shape+size: rotations are minimizers, scaled ones are not (3 (s - 1/s)^2 in 3D)
+        R = _rot2(0.3) if d == 2 else _rot3()
         assert np.max(np.abs(O.dmu(metric, R[None]))) < 1e-14
-        assert O.mu(metric, 2.0 * R[None])[0] > 1.0
+        assert abs(O.mu(metric, R[None])[0]) < 1e-14
+        assert O.mu(metric, 2.0 * R[None])[0] == pytest.approx(d * 1.5 ** 2, rel=1e-13)
 
 
 # ---------------------------------------------------------------- P3 complex step
@@ -163,12 +163,13 @@ def test_second_variation_at_identity_more(metric, kind):
 
 
 # ---------------------------------------------------------------- P4 second variation at T = I
-@pytest.mark.parametrize("metric,coef,dev", [(2, 2.0, True), (7, 8.0, False),
-                                             (303, 4.0 / 3.0, True), (302, 8.0 / 3.0, True)])
-def test_second_variation_at_identity(metric, coef, dev):
+@pytest.mark.parametrize("metric,d,coef,dev", [(2, 2, 2.0, True), (7, 2, 8.0, False), (7, 3, 8.0, False),
+                                               (303, 3, 4.0 / 3.0, True), (302, 3, 8.0 / 3.0, True)])
+def test_second_variation_at_identity(metric, d, coef, dev):
     """Near T = I the metrics behave like deviatoric (or full) linear
-    elasticity: E:dP(I)[E] = coef |dev sym E|^2 (or coef |sym E|^2)."""
-    d = 2 if metric in (2, 7) else 3
+    elasticity: E:dP(I)[E] = coef |dev sym E|^2 (or coef |sym E|^2).  For
+    mu_7 in any dimension T - T^{-t} = e (E + E^t) + O(e^2) at T = I + e E,
+    so mu_7 = 4 e^2 |sym E|^2 + O(e^3) and the coefficient is 8."""
     E = RNG.standard_normal((30, d, d))
     S = 0.5 * (E + np.swapaxes(E, 1, 2))
     if dev:
@@ -255,7 +256,8 @@ def test_affine_mesh_2d(metric):
     det(W0) mu(T) exactly (sum of w_q det W over the mesh = det W0).  T is
     chosen as a matrix with a closed-form value; W0 is not symmetric, so a
     transposed Jacobian would change the result."""
-    rows = {r[0]: r for r in _golden_rows() if r[0] == metric and r[1][0, 1] == 1 and r[1][1, 0] == 0}
+    rows = {r[0]: r for r in _golden_rows()
+            if r[0] == metric and r[1].shape == (2, 2) and r[1][0, 1] == 1 and r[1][1, 0] == 0}
     _, Tstar, expected = rows[metric]
     W0 = np.array([[1.0, 0.5], [0.0, 2.0]])
     M = Tstar @ W0
