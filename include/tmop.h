@@ -62,7 +62,7 @@ enum {
 enum {
   TMOP_MU1 = 1,       /* 2D, no barrier: |T|^2                    (Table 3.1) */
   TMOP_MU2 = 2,       /* 2D shape:      |T|^2 / (2 tau) - 1       (Table 3.1) */
-  TMOP_MU7 = 7,       /* 2D shape+size: |T - T^{-t}|^2            (Section 3.2) */
+  TMOP_MU7 = 7,       /* shape+size, 2D and 3D: |T - T^{-t}|^2    (Section 3.2) */
   TMOP_MU9 = 9,       /* 2D shape+size: tau |T - T^{-t}|^2        (Table 3.1) */
   TMOP_MU14 = 14,     /* 2D shape+size+alignment: |T - I|^2       (Section 3.2) */
   TMOP_MU77 = 77,     /* 2D size:       (tau - 1/tau)^2 / 2       (Table 3.1) */

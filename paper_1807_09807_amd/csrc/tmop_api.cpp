@@ -837,7 +837,7 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
   if (d == 2 && metric != TMOP_MU1 && metric != TMOP_MU2 && metric != TMOP_MU7 && metric != TMOP_MU9 &&
       metric != TMOP_MU14 && metric != TMOP_MU77 && metric != TMOP_MU98)
     return TMOP_E_ARG;
-  if (d == 3 && metric != TMOP_MU302 && metric != TMOP_MU303) return TMOP_E_ARG;
+  if (d == 3 && metric != TMOP_MU302 && metric != TMOP_MU303 && metric != TMOP_MU7) return TMOP_E_ARG;
   if (precision != TMOP_FP64 && precision != TMOP_MIXED_FP32) return TMOP_E_ARG;
   const int kind = target->kind;
   if ((kind != TMOP_TGT_CONST && kind != TMOP_TGT_ISO_PER_QP && kind != TMOP_TGT_PER_ELEM &&
@@ -889,7 +889,8 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
 
   tmop_ctx* c = new (std::nothrow) tmop_ctx();
   if (!c) return TMOP_E_NOMEM;
-  c->dim = d; c->p = p; c->Q = Q; c->metric = metric; c->precision = precision;
+  c->dim = d; c->p = p; c->Q = Q; c->precision = precision;
+  c->metric = d == 3 && metric == TMOP_MU7 ? MU7_3D : metric;   // the kernels' id of the 3D form
   c->n_elem = mesh->n_elem; c->n_node = mesh->n_node; c->n_dof = (int64_t)d * mesh->n_node;
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return TMOP_E_HIP; }
   // the allocation-free entry point's scratch on this device (its address,
@@ -1198,7 +1199,8 @@ int tmop_set_combo(tmop_ctx* c, int32_t metric2, const double* W2, double eta1, 
     return TMOP_OK;
   }
   const int d = c->dim;
-  const bool metric_ok = d == 2 ? metric_2d(metric2) : (metric2 == TMOP_MU302 || metric2 == TMOP_MU303);
+  const bool metric_ok =
+      d == 2 ? metric_2d(metric2) : (metric2 == TMOP_MU302 || metric2 == TMOP_MU303 || metric2 == TMOP_MU7);
   if (!metric_ok || !W2 || !(eta2 >= 0.0) || !std::isfinite(eta2)) return TMOP_E_ARG;
   const double det2 = det3(W2, d);
   if (!(det2 > 0.0)) return TMOP_E_TARGET;               // Section 3.1: det W > 0
@@ -1216,7 +1218,7 @@ int tmop_set_combo(tmop_ctx* c, int32_t metric2, const double* W2, double eta1, 
     (void)hipFree(d_tm);
     return TMOP_E_HIP;
   }
-  const int r = install_second_term(c, metric2, d_tm, 1, eta1, s);
+  const int r = install_second_term(c, d == 3 && metric2 == TMOP_MU7 ? MU7_3D : metric2, d_tm, 1, eta1, s);
   if (r == TMOP_OK) {
     double Wi[3][3];
     inv3(W2, d, Wi);

@@ -346,6 +346,7 @@ static int dfo_metric(int metric, const DfoParams& dp, hipStream_t s) {
     switch (metric) {
       case 302: return dfo_one<3, P, Q, 302>(dp, s);
       case 303: return dfo_one<3, P, Q, 303>(dp, s);
+      case MU7_3D: return dfo_one<3, P, Q, MU7_3D>(dp, s);
       default: return -1;
     }
   }

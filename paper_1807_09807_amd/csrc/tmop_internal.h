@@ -20,6 +20,8 @@ constexpr int TIMING_SLOTS = 8;
 // mu_98 = |T - I|^2 / tau on 3x3 T (the replication metric of Section
 // 4.3.2 in 3D): an internal metric id of the 3D kernels
 constexpr int MU98_3D = 398;
+// mu_7 = |T - T^{-t}|^2 on 3x3 T: the internal id of TMOP_MU7 on 3D meshes
+constexpr int MU7_3D = 307;
 
 constexpr int MAXP = 5;   // nodes per direction (order p <= 4)
 constexpr int MAXQ = 6;   // quadrature points per direction
@@ -176,6 +178,8 @@ int launch_elem_2d_f64_b(int p, int Q, int metric, int op, const LaunchParams& l
 int launch_elem_2d_f32_b(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
 int launch_elem_3d_f64(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
 int launch_elem_3d_f32(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
+int launch_elem_3d_f64_b(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
+int launch_elem_3d_f32_b(int p, int Q, int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid);
 bool elem_supported(int dim, int p, int Q);
 
 // The allocation-free energy entry point (tmop_noalloc.hip): its partials,

@@ -108,8 +108,8 @@ static int launch_metric(int op, const LaunchParams& lp, hipStream_t s, int* gri
 }
 
 // The metrics of each dimension (Table 3.1, Sections 3.2 and 4.3; mu_302 in
-// 3D).  The 2D metrics come in two groups, instantiated by separate
-// translation units so that they compile in parallel.
+// 3D).  The metrics of each dimension come in two groups, instantiated by
+// separate translation units so that they compile in parallel.
 template <int DIM, int GROUP, int P, int Q, typename R>
 static int launch_pq(int metric, int op, const LaunchParams& lp, hipStream_t s, int* grid) {
   if (op == OP_SIZE || op == OP_JINV) metric = DIM == 2 ? 1 : 302;
@@ -128,11 +128,16 @@ static int launch_pq(int metric, int op, const LaunchParams& lp, hipStream_t s, 
       case 98: return launch_metric<2, P, Q, 98, R>(op, lp, s, grid);
       default: return -1;
     }
-  } else {
+  } else if constexpr (GROUP == 0) {
     switch (metric) {
       case 302: return launch_metric<3, P, Q, 302, R>(op, lp, s, grid);
       case 303: return launch_metric<3, P, Q, 303, R>(op, lp, s, grid);
       case 398: return lp.tmat ? launch_op<3, P, Q, 398, R, TGT_MAT>(op, lp, s, grid) : -1;   // replication, 3D
+      default: return -1;
+    }
+  } else {
+    switch (metric) {
+      case 307: return launch_metric<3, P, Q, 307, R>(op, lp, s, grid);   // mu_7, 3D
       default: return -1;
     }
   }

@@ -104,6 +104,8 @@ template <> struct MetricInfo<98>  { static constexpr int dim = 2; static conste
 // 3D primary metrics are 302 and 303)
 template <> struct MetricInfo<398> { static constexpr int dim = 3; static constexpr bool i2 = false, tr = true; };
 template <> struct MetricInfo<302> { static constexpr int dim = 3; static constexpr bool i2 = true, tr = false; };
+// mu_7 = |T - T^{-t}|^2 for 3x3 T (Section 3.2 gives it for any dimension): an internal id of the 3D kernels
+template <> struct MetricInfo<307> { static constexpr int dim = 3; static constexpr bool i2 = true, tr = false; };
 template <> struct MetricInfo<303> { static constexpr int dim = 3; static constexpr bool i2 = false, tr = false; };
 
 template <int METRIC, typename R>
@@ -145,6 +147,11 @@ __device__ __forceinline__ Partials<R> partials(R I1, R I2, R tau, R J = R(0)) {
     p.f1t = R(-2.0 / 9.0) * c * rt;
     p.ft = p.f1t * I1;
     p.ftt = R(10.0 / 27.0) * I1 * c * rt * rt;
+  } else if constexpr (METRIC == 307) {   // f = I1 + I2 tau^-2 - 6  (|T^-1|^2 = |cof T|^2 / tau^2 in 3D)
+    const R rt = rcp(tau);
+    const R rt2 = rt * rt, rt3 = rt2 * rt;
+    p.f1 = R(1);  p.f2 = rt2;  p.ft = R(-2) * I2 * rt3;
+    p.f2t = R(-2) * rt3;  p.ftt = R(6) * I2 * rt2 * rt2;
   } else if constexpr (METRIC == 302) {   // f = I1 I2 tau^-2 / 9 - 1
     const R rt = rcp(tau);
     const R s = rt * rt * R(1.0 / 9.0);
@@ -176,6 +183,19 @@ __device__ __forceinline__ R mu_value(const R (&T)[MetricInfo<METRIC>::dim][Metr
     const R n = a * a + b * b + T[0][1] * T[0][1] + T[1][0] * T[1][0];
     if constexpr (METRIC == 14) return n;
     else return n * rcp(tau);
+  } else if constexpr (METRIC == 307) {   // sum of squares of T - T^{-t} = T - cof(T) / tau, free of cancellation
+    R C[3][3];
+    cofactor<3, R>(T, C);
+    const R rt = rcp(tau);
+    R n = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const R t = T[i][j] - C[i][j] * rt;
+        n += t * t;
+      }
+    return n;
   } else if constexpr (METRIC == 398) {
     R n = 0;
 #pragma unroll

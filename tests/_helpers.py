@@ -57,6 +57,8 @@ def small_cases():
         C("p2_q3_2d_mu14", 2, 7, 2, 3, 14, 0.10, seed=32),
         C("p1_q2_2d_mu77", 2, 9, 1, 2, 77, 0.15, seed=33),
         C("p4_q5_2d_mu98_lobatto", 2, 3, 4, 5, 98, 0.03, seed=34, rule="gll"),
+        # mu_7 in 3D (Section 3.2 states it for any dimension), general target
+        C("p2_q4_3d_mu7", 3, 3, 2, 4, 7, 0.08, seed=35, W0=((1.0, 0.1, 0.0), (0.0, 0.9, 0.2), (0.1, 0.0, 1.1))),
     ]
 
 

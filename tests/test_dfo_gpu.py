@@ -21,6 +21,7 @@ CASES = [  # dim, n, p, Q, metric, W0, noise, seed, slide
     (2, 5, 2, 3, 77, None, 0.12, 203, False),
     (3, 2, 2, 3, 303, None, 0.1, 204, False),
     (3, 2, 1, 2, 302, ((1.0, 0.2, 0.0), (0.0, 1.1, 0.3), (0.1, 0.0, 0.9)), 0.12, 205, True),
+    (3, 2, 2, 3, 7, None, 0.1, 206, False),
 ]
 
 
