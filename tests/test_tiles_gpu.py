@@ -168,8 +168,11 @@ def test_tiles_with_section4_terms():
 
 
 def test_newton_with_tiles():
-    """Newton on the 8 x 8 Q2 workload: the tile scatter gives the colour
-    scatter's solve (same iteration count, F to rounding)."""
+    """Newton on the 8 x 8 Q2 workload with each scatter.  The inner CG
+    iterates are not unique in floating point (the two scatters sum the
+    Hessian action in different orders), so the trajectories may separate
+    slowly, as against the oracle's Newton: the same bar as there, F within
+    1e-6 relative while F > 1e-8 F0, and the same iteration count."""
     from paper_1807_09807_amd import tmop as T
     w = meshgen.WORKLOADS["q2_square_8"]
     mesh = meshgen.box_mesh(2, w["n"], w["p"])
@@ -182,13 +185,16 @@ def test_newton_with_tiles():
         ctx.set_scatter(mode)
         x = to_dev(mesh.x)
         st, rep = ctx.newton_solve(x, max_it=10)
-        res.append((rep, x.cpu().numpy()))
+        res.append((st, rep))
         ctx.close()
-    (rc, xc), (rt, xt) = res
-    say(f"  newton colours: it {rc['iters']} F {rc['F']:.6e}; tiles: it {rt['iters']} F {rt['F']:.6e}")
-    assert rt["iters"] == rc["iters"]
-    assert abs(rt["F"] - rc["F"]) <= 1e-9 * abs(rc["F"]) + 1e-300
-    assert np.max(np.abs(xt - xc)) <= 1e-9 * mesh.h
+    (sc, rc), (stt, rt) = res
+    Fc, Ft = rc["history_F"], rt["history_F"]
+    worst = max(abs(b - a) / a for a, b in zip(Fc, Ft) if a > 1e-8 * Fc[0])
+    say(f"  newton colours: it {rc['iters']} F {rc['F']:.6e}; tiles: it {rt['iters']} F {rt['F']:.6e}; "
+        f"worst relative F difference {worst:.2e}")
+    assert sc == stt and rt["iters"] == rc["iters"] and len(Fc) == len(Ft)
+    assert worst <= 1e-6
+    assert all(b < a for a, b in zip(Ft, Ft[1:]))
 
 
 def test_tiles_refused_in_3d():
