@@ -259,10 +259,15 @@ def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
     log(f"# workload {name}: {mesh.n_elem} elements, {mesh.n_dof} DOFs, repair rounds "
         f"{mesh.info.get('repair_rounds', 0)}")
     results = {}
-    variants = [(T.TMOP_FP64, "f64", T.TMOP_SCATTER_COLOURS), (T.TMOP_MIXED_FP32, "mixed", T.TMOP_SCATTER_COLOURS)]
-    if w["dim"] == 2:   # the owner-computes tile scatter beside the colour launches
-        variants += [(T.TMOP_FP64, "f64_tiles", T.TMOP_SCATTER_TILES),
-                     (T.TMOP_MIXED_FP32, "mixed_tiles", T.TMOP_SCATTER_TILES)]
+    # 2D: the tile scatter (the 2D default) beside the colour launches; 3D: the
+    # colour launches beside the element-vector scatter (the default of 3D
+    # meshes with colours of at most 8,192 elements, such as q2_cube_32)
+    if w["dim"] == 2:
+        main, other, oname = T.TMOP_SCATTER_TILES, T.TMOP_SCATTER_COLOURS, "colours"
+    else:
+        main, other, oname = T.TMOP_SCATTER_COLOURS, T.TMOP_SCATTER_ELEMENTS, "elements"
+    variants = [(T.TMOP_FP64, "f64", main), (T.TMOP_MIXED_FP32, "mixed", main),
+                (T.TMOP_FP64, f"f64_{oname}", other), (T.TMOP_MIXED_FP32, f"mixed_{oname}", other)]
     for prec, pname, scatter in variants:
         t_set = time.perf_counter()   # set-up on the host: tables, colouring, 2D tiles, uploads
         ctx = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W,

@@ -283,9 +283,9 @@ int tmop_hessian_diagonal(tmop_ctx *ctx, const double *x, double *diag, void *st
 /* How the gradient, the energy + gradient and the Hessian action add the
  * element contributions to shared nodes (Section 3.4 sums them over the
  * elements holding each node):
- *  TMOP_SCATTER_COLOURS (the default of 3D meshes): one launch per element
- *    colour; the elements of a colour share no node, each adds to its
- *    nodes in place.
+ *  TMOP_SCATTER_COLOURS (the default of 3D meshes with colours of more
+ *    than 8,192 elements on average): one launch per element colour; the
+ *    elements of a colour share no node, each adds to its nodes in place.
  *  TMOP_SCATTER_TILES (the default of 2D meshes): one launch over every
  *    element in tiles of neighbouring elements; each workgroup accumulates
  *    its tile's nodes on chip, adding its elements in rounds of elements
@@ -294,13 +294,23 @@ int tmop_hessian_diagonal(tmop_ctx *ctx, const double *x, double *diag, void *st
  *    tmop_setup builds the tiles of a 2D mesh on the host (device memory:
  *    about 2 bytes per element node, 8 per tile node and 24 per node on a
  *    tile border); a mesh beyond the tile limits keeps the colours.
- * Both are deterministic (fixed summation orders, which differ between the
- * two, so results agree to rounding).  The other calls are not affected. */
-enum { TMOP_SCATTER_COLOURS = 0, TMOP_SCATTER_TILES = 1 };
+ *  TMOP_SCATTER_ELEMENTS (3D only; the default of 3D meshes with smaller
+ *    colours, whose colour launches cannot fill the chip): one launch over
+ *    every element writing each element's contributions to an element vector
+ *    (dim x (p+1)^3 doubles per element), then a pass that sums each node's
+ *    entries in ascending element order.  Selecting it on a context that did
+ *    not start with it builds the node-to-entry map on the host (a
+ *    device-to-host copy of the connectivity) and allocates the vector; it
+ *    syncs the device.
+ * All are deterministic (fixed summation orders, which differ between
+ * them, so results agree to rounding).  The other calls are not affected. */
+enum { TMOP_SCATTER_COLOURS = 0, TMOP_SCATTER_TILES = 1, TMOP_SCATTER_ELEMENTS = 2 };
 
 /* Selects the scatter mode of ctx.  TMOP_E_ARG for an unknown mode,
  * TMOP_E_UNSUPPORTED (mode unchanged) for tiles on a context without them
- * (3D, or a 2D mesh beyond the tile limits). */
+ * (3D, or a 2D mesh beyond the tile limits), for the element vector on a 2D
+ * context or past 2^31 entries; TMOP_E_NOMEM if its buffer cannot be
+ * allocated. */
 int tmop_set_scatter(tmop_ctx *ctx, int32_t mode);
 
 /* ------------------------------------------------------------------------

@@ -242,9 +242,11 @@ bool fused_penalty(const tmop_ctx* c, int op) {
 int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* out, const int32_t* conn,
                 const int32_t* list, int64_t n_list, hipStream_t s, int* grid, const double* scale = nullptr,
                 int64_t part_off = 0, const uint32_t* first = nullptr, const double* tsize = nullptr,
-                TermSel term = TermSel{}, const RedDst* rd = nullptr, const TileParams* tile = nullptr) {
+                TermSel term = TermSel{}, const RedDst* rd = nullptr, const TileParams* tile = nullptr,
+                double* evec = nullptr) {
   LaunchParams lp = c->base;
   lp.tile = tile;
+  lp.evec = evec;
   lp.first = first;
   lp.tsize = tsize;
   lp.tmat = term.tmat;
@@ -357,6 +359,14 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
                               c->d_tsize, primary_term(c, false, 0, fused_penalty(c, op)), nullptr, &c->tile);
     if (r != TMOP_OK) return r;
     off += grid;
+  } else if (c->scatter == TMOP_SCATTER_ELEMENTS && (op == OP_GRAD || op == OP_EG || op == OP_HESS)) {
+    // one launch over every element into the element vector, then the gather (3D)
+    int grid = 0;
+    const int r = elem_launch(c, op, x, v, out, c->d_elem_node, nullptr, c->n_elem, s, &grid, scale, off, nullptr,
+                              c->d_tsize, primary_term(c, false, 0, fused_penalty(c, op)), nullptr, nullptr, c->d_evec);
+    if (r != TMOP_OK) return r;
+    off += grid;
+    HIP_TRY(evec_gather(c->d_evec, c->d_ev_off, c->d_ev, c->n_node, c->npe, c->dim, out, s));
   } else {
     for (int k = 0; k < ncol; ++k) {
       const int64_t n = c->color_off[k + 1] - c->color_off[k];
@@ -452,6 +462,12 @@ int dot_sync(tmop_ctx* c, const double* a, const double* b, hipStream_t s, doubl
   return TMOP_OK;
 }
 
+// 3D meshes whose colours average at most this many elements default to the
+// element-vector scatter.  Measured per operation on MI355X: 4,096 Q2 hexes
+// per colour (32^3 mesh) 17-28% faster than the colour launches, 13,824 Q3
+// hexes (48^3) even, 32,768 Q2 hexes (64^3) 22-31% slower.
+constexpr int64_t EVEC_DEFAULT_ELEMS_PER_COLOUR = 8192;
+
 void free_tiles(tmop_ctx* c) {
   TileParams& t = c->tile;
   (void)hipFree((void*)t.round_off);
@@ -512,6 +528,43 @@ int make_tiles(tmop_ctx* c, const int32_t* en, const std::vector<int32_t>& order
   return st;
 }
 
+void free_evec(tmop_ctx* c) {
+  (void)hipFree(c->d_evec);
+  (void)hipFree(c->d_ev_off);
+  (void)hipFree(c->d_ev);
+  c->d_evec = nullptr;
+  c->d_ev_off = nullptr;
+  c->d_ev = nullptr;
+}
+
+// The element-vector scatter's buffer and its node -> entry map (3D), from
+// the host connectivity en.  TMOP_E_UNSUPPORTED when the entries overflow
+// 32-bit offsets.
+int make_evec(tmop_ctx* c, const int32_t* en) {
+  const int npe = c->npe, d = c->dim;
+  const int64_t ne_tot = c->n_elem * npe;
+  if (c->n_elem * d * npe > INT32_MAX) return TMOP_E_UNSUPPORTED;
+  std::vector<int32_t> off(c->n_node + 1, 0), ev((size_t)ne_tot);
+  for (int64_t k = 0; k < ne_tot; ++k) off[en[k] + 1]++;
+  for (int64_t I = 0; I < c->n_node; ++I) off[I + 1] += off[I];
+  {
+    std::vector<int32_t> pos(off.begin(), off.end() - 1);
+    for (int64_t e = 0; e < c->n_elem; ++e)   // ascending element ids per node
+      for (int l = 0; l < npe; ++l) ev[pos[en[e * npe + l]]++] = (int32_t)(e * d * npe + l);
+  }
+  int st = TMOP_OK;
+  if (hipMalloc(&c->d_evec, (size_t)c->n_elem * d * npe * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_ev_off, off.size() * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&c->d_ev, ev.size() * sizeof(int32_t)) != hipSuccess) {
+    st = TMOP_E_NOMEM;
+  } else if (hipMemcpy(c->d_ev_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(c->d_ev, ev.data(), ev.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+    st = TMOP_E_HIP;
+  }
+  if (st != TMOP_OK) free_evec(c);
+  return st;
+}
+
 void free_ctx(tmop_ctx* c) {
   if (!c) return;
   int cur = 0;
@@ -542,6 +595,7 @@ void free_ctx(tmop_ctx* c) {
   (void)hipFree(c->d_work);
   (void)hipFree(c->d_sc);
   free_tiles(c);
+  free_evec(c);
   if (c->h_res) (void)hipHostFree(c->h_res);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
   (void)collect_timing(c);
@@ -986,6 +1040,11 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
       const int r = make_tiles(c, mesh->elem_node, order);
       if (r == TMOP_OK) c->scatter = TMOP_SCATTER_TILES;
       else if (r != TMOP_E_UNSUPPORTED) { st = r; break; }
+    } else if (mesh->n_elem <= EVEC_DEFAULT_ELEMS_PER_COLOUR * (int64_t)(c->color_off.size() - 1)) {
+      // small colours cannot fill the chip: the element vector, one launch
+      const int r = make_evec(c, mesh->elem_node);
+      if (r == TMOP_OK) c->scatter = TMOP_SCATTER_ELEMENTS;
+      else if (r != TMOP_E_UNSUPPORTED) { st = r; break; }
     }
     std::vector<double> mask(c->n_dof, 1.0);
     if (mesh->fixed)
@@ -1423,8 +1482,23 @@ int tmop_dfo_solve(tmop_ctx* c, double* x, const tmop_dfo_opts* opts, tmop_dfo_r
 }
 
 int tmop_set_scatter(tmop_ctx* c, int32_t mode) {
-  if (!c || (mode != TMOP_SCATTER_COLOURS && mode != TMOP_SCATTER_TILES)) return TMOP_E_ARG;
+  if (!c || (mode != TMOP_SCATTER_COLOURS && mode != TMOP_SCATTER_TILES && mode != TMOP_SCATTER_ELEMENTS))
+    return TMOP_E_ARG;
   if (mode == TMOP_SCATTER_TILES && !c->tile.node) return TMOP_E_UNSUPPORTED;   // 3D, or no tiles built
+  if (mode == TMOP_SCATTER_ELEMENTS) {
+    if (c->dim != 3) return TMOP_E_UNSUPPORTED;
+    if (!c->d_evec) {
+      int cur = 0;
+      HIP_TRY(hipGetDevice(&cur));
+      HIP_TRY(hipSetDevice(c->device));
+      std::vector<int32_t> en((size_t)c->n_elem * c->npe);
+      int r = hipMemcpy(en.data(), c->d_elem_node, en.size() * sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess
+                  ? make_evec(c, en.data())
+                  : TMOP_E_HIP;
+      (void)hipSetDevice(cur);
+      if (r != TMOP_OK) return r;
+    }
+  }
   c->scatter = mode;
   return TMOP_OK;
 }

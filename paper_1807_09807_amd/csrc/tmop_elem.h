@@ -90,6 +90,7 @@ struct ElemArgs {
   double wdetW;                          // weight factor of a constant target: eta det W
   double M1[P][P];                       // PEN: 1D mass matrix sum_k w_k l_i(s_k) l_j(s_k)
   double kpen;                           // PEN: 2 delta det W
+  double* evec;                          // 3D scatter ops: [n_list][3][P^3] element vector instead of out, or nullptr
 };
 
 // Elements per block and block size: the smallest element count that best
@@ -722,16 +723,22 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
 
   // the scatter's old values, loaded now so the passes below hide latency
   // (with the penalty: before it, which then adds its share to them)
+  // (with an element vector: no old values, the element's own share only)
   double old[3][P];
   auto load_old = [&]() {
     if (active && p1) {
 #pragma unroll
       for (int i2 = 0; i2 < P; ++i2) {
-        const bool fresh = first_touch<NPE>(a.first, kk, ta + P * tb + P * P * i2);
+        const bool fresh = a.evec || first_touch<NPE>(a.first, kk, ta + P * tb + P * P * i2);
 #pragma unroll
         for (int c = 0; c < 3; ++c) old[c][i2] = fresh ? 0.0 : a.out[c * a.n_node + node[i2]];
       }
     }
+  };
+  // the scatter of the value of local node (ta, tb, i2), component c
+  auto put = [&](int c, int i2, double val) {
+    if (a.evec) a.evec[((int64_t)kk * 3 + c) * NPE + ta + P * tb + P * P * i2] = val;
+    else a.out[c * a.n_node + node[i2]] = val;
   };
   if constexpr (PEN) {   // the penalty's share 2 delta det W (M1 x M1 x M1 v) joins the old values
     __syncthreads();   // the forward data is dead
@@ -807,7 +814,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
             R v = 0;
 #pragma unroll
             for (int q2 = 0; q2 < Q; ++q2) v += a.B[q2][i2] * sb[q2] + a.G[q2][i2] * sg[q2];
-            a.out[c * a.n_node + node[i2]] = old[c][i2] + (double)v;
+            put(c, i2, old[c][i2] + (double)v);
           }
         }
       }
@@ -855,7 +862,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
           R v = 0;
 #pragma unroll
           for (int q2 = 0; q2 < Q; ++q2) v += a.B[q2][i2] * sb[q2] + a.G[q2][i2] * sg[q2];
-          a.out[c * a.n_node + node[i2]] = old[c][i2] + (double)v;
+          put(c, i2, old[c][i2] + (double)v);
         }
       }
     }

@@ -68,6 +68,12 @@ struct TileParams {
   int32_t n_tile;
   int32_t nn_max;              // most nodes of one tile: sizes the LDS of the launch
 };
+// out[c][I] = the sum of node I's element-vector entries, in ascending
+// element order: entries ev[off[I] .. off[I+1]) are offsets (e dim + 0) npe + l
+// into evec (component c at + c npe); nodes without entries get 0.
+hipError_t evec_gather(const double* evec, const int32_t* off, const int32_t* ev, int64_t n_node, int npe, int dim,
+                       double* out, hipStream_t s);
+
 // out[c][halo_node[h]] = sum of its slots, in order
 hipError_t halo_sum(const TileParams& tp, int64_t n_node, double* out, hipStream_t s);
 // The host form of the TileParams arrays (tmop_tiles.cpp).
@@ -119,6 +125,10 @@ struct LaunchParams {
   // 2D OP_GRAD / OP_EG / OP_HESS over every element in owner-computes tiles
   // (nullptr: the colour launch described by elem_node / list / first)
   const TileParams* tile;
+  // 3D OP_GRAD / OP_EG / OP_HESS: each element's contributions go to this
+  // element vector [n_list][3][P^3] instead of the scatter to out (nullptr:
+  // the scatter)
+  double* evec;
 };
 
 // Everything one launch of the displacement-penalty kernels (eq. 4.2)
@@ -314,6 +324,10 @@ struct tmop_ctx {
   int scatter = 0;                     // TMOP_SCATTER_COLOURS or TMOP_SCATTER_TILES
   int tile_elems = 0;                  // elements per tile they were built for
   tmop::TileParams tile{};             // its device arrays, owned by the context
+  // element-vector scatter (TMOP_SCATTER_ELEMENTS, 3D), built on first use
+  double* d_evec = nullptr;            // [n_elem][dim][npe]
+  int32_t* d_ev_off = nullptr;         // [n_node + 1] node -> entries
+  int32_t* d_ev = nullptr;             // entry: (e dim) npe + l, ascending e per node
   // optional per-launch timing of the element kernels (HIP events)
   struct TimedLaunch { int op; hipEvent_t a, b; };
   bool timing = false;

@@ -28,7 +28,7 @@ TMOP_FP64, TMOP_MIXED_FP32 = 0, 1
 TMOP_TGT_CONST, TMOP_TGT_ISO_PER_QP, TMOP_TGT_PER_ELEM, TMOP_TGT_PER_QP = 0, 1, 2, 3
 TMOP_INNER_CG, TMOP_INNER_MINRES, TMOP_INNER_SHIFTED_CG = 0, 1, 2
 TMOP_PREC_NONE, TMOP_PREC_JACOBI = 0, 1
-TMOP_SCATTER_COLOURS, TMOP_SCATTER_TILES = 0, 1
+TMOP_SCATTER_COLOURS, TMOP_SCATTER_TILES, TMOP_SCATTER_ELEMENTS = 0, 1, 2
 
 EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_gradient_scaled", "tmop_hessian_apply",
            "tmop_newton_solve", "tmop_destroy", "tmop_strerror", "tmop_newton_default_opts",
@@ -303,8 +303,9 @@ class Context:
         return out
 
     def set_scatter(self, mode):
-        """TMOP_SCATTER_COLOURS or TMOP_SCATTER_TILES (2D): how the gradient
-        and Hessian action add element contributions at shared nodes."""
+        """TMOP_SCATTER_COLOURS, TMOP_SCATTER_TILES (2D) or
+        TMOP_SCATTER_ELEMENTS (3D): how the gradient and Hessian action add
+        element contributions at shared nodes."""
         st = self._lib.tmop_set_scatter(self._h, int(mode))
         if st < 0:
             raise TMOPError(st, "tmop_set_scatter")

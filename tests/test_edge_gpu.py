@@ -99,13 +99,17 @@ def test_unused_nodes_get_zero():
     assert g[0, -1] == 0.0 and g[1, -1] == 0.0 and Hv[0, -1] == 0.0 and Hv[1, -1] == 0.0
 
 
-def test_kernel_timing_counts_launches():
-    """Timing on: one energy launch per energy call, one launch per colour
-    for gradient and Hessian action (2^dim colours on a box mesh with at
-    least two elements per direction); results unchanged by timing."""
-    say("[edge] kernel timing")
+@pytest.mark.parametrize("mode,launches", [("COLOURS", 8), ("ELEMENTS", 1)])
+def test_kernel_timing_counts_launches(mode, launches):
+    """Timing on: one energy launch per energy call; for gradient and
+    Hessian action one launch per colour (2^dim colours on a box mesh with at
+    least two elements per direction) or one launch over every element with
+    the element vector; results unchanged by timing."""
+    from paper_1807_09807_amd import tmop as T
+    say(f"[edge] kernel timing {mode}")
     mesh = meshgen.box_mesh(3, 4, 2)
     ctx = _ctx(mesh, 4, 303)
+    ctx.set_scatter(getattr(T, f"TMOP_SCATTER_{mode}"))
     x = to_dev(meshgen.perturb(mesh, 0.05, 1))
     v = to_dev(meshgen.random_direction(mesh, 2))
     h0 = ctx.hessian_apply(x, v).clone()
@@ -116,7 +120,7 @@ def test_kernel_timing_counts_launches():
         h1 = ctx.hessian_apply(x, v)
     counts = [ctx.timing_read(op) for op in range(3)]
     ctx.timing_enable(False)
-    assert [n for _, n in counts] == [3, 24, 24]
+    assert [n for _, n in counts] == [3, 3 * launches, 3 * launches]
     assert all(ms > 0 for ms, _ in counts)
     assert torch.equal(h0, h1)
     ctx.energy(x)
