@@ -293,7 +293,11 @@ int tmop_hessian_diagonal(tmop_ctx *ctx, const double *x, double *diag, void *st
  *    pass adds the tiles' partial sums at nodes shared by several tiles.
  *    tmop_setup builds the tiles of a 2D mesh on the host (device memory:
  *    about 2 bytes per element node, 8 per tile node and 24 per node on a
- *    tile border); a mesh beyond the tile limits keeps the colours.
+ *    tile border); a mesh beyond the tile limits keeps the colours.  FP64
+ *    gradient tiles stage one vector component at a time when the tiles
+ *    would not otherwise all fit on the device at once; the environment
+ *    variable TMOP_TILE_SPLIT=0 or =1, read when the tiles are built,
+ *    forces that choice off or on (same results bit for bit).
  *  TMOP_SCATTER_ELEMENTS (3D only; the default of 3D meshes with smaller
  *    colours, whose colour launches cannot fill the chip): one launch over
  *    every element writing each element's contributions to an element vector

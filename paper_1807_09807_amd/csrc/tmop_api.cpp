@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <new>
 #include <type_traits>
@@ -523,6 +524,25 @@ int make_tiles(tmop_ctx* c, const int32_t* en, const std::vector<int32_t>& order
   t.n_halo = (int64_t)L.halo_node.size();
   t.n_tile = (int32_t)(L.node_off.size() - 1);
   t.nn_max = L.nn_max;
+  // FP64 gradient kernels: split passes when the tiles with both components
+  // would not all be resident at once (LDS per compute unit); the
+  // environment variable TMOP_TILE_SPLIT=0 / 1 forces the choice
+  {
+    int dev = 0, n_cu = 0, lds_cu = 0;
+    bool split = false;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+        n_cu > 0 && lds_cu > 0) {
+      const int64_t per_tile = tile_lds_bytes(c->p + 1, c->Q, 8, false, t.nn_max) + TILE_STATIC_LDS_BYTES;
+      split = (int64_t)(lds_cu / per_tile) * n_cu < t.n_tile;
+    }
+    if (const char* f = std::getenv("TMOP_TILE_SPLIT")) {
+      if (f[0] == '0' && f[1] == 0) split = false;
+      if (f[0] == '1' && f[1] == 0) split = true;
+    }
+    t.split = split ? 1 : 0;
+  }
   c->tile = t;
   if (st != TMOP_OK) free_tiles(c);
   return st;

@@ -926,6 +926,44 @@ __device__ __forceinline__ void fwd_2d(const ElemArgs<P, Q, R>& a, const R (&X)[
   }
 }
 
+// fwd_2d for one component c through an LDS area of 2 Q P values
+// [t][q1][i0] (the split passes of elem2d_work).
+template <int P, int Q, typename R>
+__device__ __forceinline__ void fwd_2d_c(const ElemArgs<P, Q, R>& a, const R (&X)[2][P], int c, int ta,
+                                         R* __restrict__ s, R (&U)[2][2][P]) {
+  if (ta < P) {   // lane i0 = ta
+#pragma unroll
+    for (int q1 = 0; q1 < Q; ++q1) {
+      R ub = 0, ug = 0;
+#pragma unroll
+      for (int i1 = 0; i1 < P; ++i1) { ub += a.B[q1][i1] * X[c][i1]; ug += a.G[q1][i1] * X[c][i1]; }
+      s[q1 * P + ta] = ub;
+      s[(Q + q1) * P + ta] = ug;
+    }
+  }
+  __syncthreads();
+  if (ta < Q) {
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int i0 = 0; i0 < P; ++i0) U[tt][c][i0] = s[(tt * Q + ta) * P + i0];
+  }
+}
+
+// The forward contraction of one field: both components through the LDS
+// area at once, or (split) one after the other through half the area.
+template <int P, int Q, typename R>
+__device__ __forceinline__ void fwd_2d_field(const ElemArgs<P, Q, R>& a, const R (&X)[2][P], int ta,
+                                             R* __restrict__ s, R (&U)[2][2][P], bool split) {
+  if (split) {
+    fwd_2d_c<P, Q, R>(a, X, 0, ta, s, U);
+    __syncthreads();
+    fwd_2d_c<P, Q, R>(a, X, 1, ta, s, U);
+  } else {
+    fwd_2d<P, Q, R>(a, X, ta, s, U);
+  }
+}
+
 // The work of one 2D element on lane ta once its field pencils X (and dX for
 // the Hessian action) are in registers: the forward contraction through the
 // element's LDS area s, the point loop (the energy terms add to acc and
@@ -933,19 +971,23 @@ __device__ __forceinline__ void fwd_2d(const ElemArgs<P, Q, R>& a, const R (&X)[
 // operations with a scatter the transposed contraction back through s, after
 // which lane ta < P holds in V[c][i1] the element's share of local node
 // (ta, i1).  Every lane of the block calls it (it holds barriers); e is the
-// element's index in the order of the per-point target data.
+// element's index in the order of the per-point target data.  split (uniform
+// over the block): the LDS area holds one component at a time
+// (elem2d_lds_values(P, Q, true)), at the cost of four more barriers (six
+// for the Hessian action); the sums and their order are the same.
 template <int P, int Q, int METRIC, typename R, int OP, int TGT>
 __device__ __forceinline__ void elem2d_work(const ElemArgs<P, Q, R>& a, int e, int ta, bool active, R* __restrict__ s,
                                             const R (&X)[2][P], const R (&dX)[2][P], const R (&J0x)[2][2],
-                                            const R (&J0v)[2][2], double& acc, double& mind, R (&V)[2][P]) {
+                                            const R (&J0v)[2][2], double& acc, double& mind, R (&V)[2][P],
+                                            bool split) {
   constexpr bool ISO = TGT == TGT_ISO || TGT == TGT_QPS;
   constexpr bool ENERGY_LIKE = OP == OP_ENERGY || OP == OP_SIZE || OP == OP_JINV;
   constexpr bool AFFINE = sizeof(R) == 4;
   R U[2][2][P], dU[2][2][P];
-  fwd_2d<P, Q, R>(a, X, ta, s, U);
+  fwd_2d_field<P, Q, R>(a, X, ta, s, U, split);
   if constexpr (OP == OP_HESS) {
     __syncthreads();
-    fwd_2d<P, Q, R>(a, dX, ta, s, dU);
+    fwd_2d_field<P, Q, R>(a, dX, ta, s, dU, split);
   }
 
   R Racc[2][2][P];
@@ -1025,7 +1067,35 @@ __device__ __forceinline__ void elem2d_work(const ElemArgs<P, Q, R>& a, int e, i
     }
   }
 
-  if constexpr (!ENERGY_LIKE) {
+  if (!ENERGY_LIKE && split) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      // pass 2': lane q1 writes its own row of slots (the ones it read
+      // last), so only the second component waits for the first's readers
+      if (c == 1) __syncthreads();
+      if (ta < Q) {
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+          for (int i0 = 0; i0 < P; ++i0) s[(tt * Q + ta) * P + i0] = Racc[tt][c][i0];
+      }
+      __syncthreads();
+      // pass 1': lane i0 = ta
+      if (ta < P) {
+        R rb[Q], rg[Q];
+#pragma unroll
+        for (int q1 = 0; q1 < Q; ++q1) { rb[q1] = s[q1 * P + ta]; rg[q1] = s[(Q + q1) * P + ta]; }
+#pragma unroll
+        for (int i1 = 0; i1 < P; ++i1) {
+          R v = 0;
+#pragma unroll
+          for (int q1 = 0; q1 < Q; ++q1) v += a.B[q1][i1] * rb[q1] + a.G[q1][i1] * rg[q1];
+          V[c][i1] = v;
+        }
+      }
+    }
+  }
+  if (!ENERGY_LIKE && !split) {
     // pass 2': lane q1 writes its own U slots, no barrier needed first
     if (ta < Q) {
 #pragma unroll
@@ -1102,7 +1172,7 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
 
   double acc = 0.0, mind = __builtin_huge_val();
   R V[2][P];
-  elem2d_work<P, Q, METRIC, R, OP, TGT>(a, e, ta, active, s, X, dX, J0x, J0v, acc, mind, V);
+  elem2d_work<P, Q, METRIC, R, OP, TGT>(a, e, ta, active, s, X, dX, J0x, J0v, acc, mind, V, false);
 
   if constexpr (OP == OP_ENERGY || OP == OP_EG || OP == OP_SIZE || OP == OP_JINV) {
     if (!active) { acc = 0.0; mind = __builtin_huge_val(); }
@@ -1120,10 +1190,12 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
 
 // ------------------------------------------------- 2D owner-computes tiles
 
-template <int P, int Q, typename R>
+template <int P, int Q, typename R, int OP>
 struct TileCfg {
   static constexpr int EPR = tile_epr(Q);              // elements per round
-  static constexpr int NE = elem2d_lds_values(P, Q);   // LDS values per element
+  static constexpr bool CAN_SPLIT = tile_can_split((int)sizeof(R), OP == OP_HESS);
+  static constexpr int NE = elem2d_lds_values(P, Q);              // LDS values per element
+  static constexpr int NE_SPLIT = elem2d_lds_values(P, Q, true);  // the same, split passes
 };
 
 // load_pencil_2d for an element of a tile: the same FP64 operations on the
@@ -1166,7 +1238,7 @@ __device__ __forceinline__ void tile_pencil_2d(const ElemArgs<P, Q, R>& a, const
 template <int P, int Q, int METRIC, typename R, int OP, int TGT>
 __global__ void __launch_bounds__(TILE_BLOCK)
 tile_kernel_2d(const ElemArgs<P, Q, R> a, const TileParams tp) {
-  using TC = TileCfg<P, Q, R>;
+  using TC = TileCfg<P, Q, R, OP>;
   constexpr int NPE = P * P, EPR = TC::EPR;
   constexpr bool AFFINE = sizeof(R) == 4;
   constexpr bool HESS = OP == OP_HESS;
@@ -1176,9 +1248,11 @@ tile_kernel_2d(const ElemArgs<P, Q, R> a, const TileParams tp) {
   const int tile = xcd_block(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   const int n0 = tp.node_off[tile], nn = tp.node_off[tile + 1] - n0;
+  const bool split = TC::CAN_SPLIT && tp.split;
+  const int ne = split ? TC::NE_SPLIT : TC::NE;
   double* acc = lds;                                           // [2][nn]
-  R* s_all = reinterpret_cast<R*>(acc + 2 * nn);               // [EPR][NE]
-  int* ids = reinterpret_cast<int*>(s_all + EPR * TC::NE);     // [nn]
+  R* s_all = reinterpret_cast<R*>(acc + 2 * nn);               // [EPR][ne]
+  int* ids = reinterpret_cast<int*>(s_all + EPR * ne);         // [nn]
   for (int l = tid; l < nn; l += TILE_BLOCK) {
     ids[l] = tp.node[n0 + l];
     acc[l] = 0.0;
@@ -1190,7 +1264,7 @@ tile_kernel_2d(const ElemArgs<P, Q, R> a, const TileParams tp) {
   const int le = le_raw < EPR ? le_raw : EPR - 1;
   const int ta = le_raw < EPR ? tid - le_raw * Q : Q;   // idle pad lanes take no part
   const bool p1 = ta < P;
-  R* s = s_all + le * TC::NE;
+  R* s = s_all + le * ne;
   const int r0 = tp.round_off[tile], nr = tp.round_off[tile + 1] - r0;
   double eacc = 0.0, emin = __builtin_huge_val();
   for (int r = 0; r < nr; ++r) {
@@ -1211,7 +1285,7 @@ tile_kernel_2d(const ElemArgs<P, Q, R> a, const TileParams tp) {
     if constexpr (HESS) tile_pencil_2d<P, Q, R, AFFINE>(a, a.v, gn, c00, c10, c01, p1 ? ta : 0, dX, J0v);
     double racc = 0.0, rmin = __builtin_huge_val();
     R V[2][P];
-    elem2d_work<P, Q, METRIC, R, OP, TGT>(a, e, ta, active, s, X, dX, J0x, J0v, racc, rmin, V);
+    elem2d_work<P, Q, METRIC, R, OP, TGT>(a, e, ta, active, s, X, dX, J0x, J0v, racc, rmin, V, split);
     if (active) {
       eacc += racc;
       emin = fmin(emin, rmin);

@@ -27,12 +27,12 @@ constexpr int MAXP = 5;   // nodes per direction (order p <= 4)
 constexpr int MAXQ = 6;   // quadrature points per direction
 
 // LDS values per element of the 2D element kernels: the forward data of
-// both components and directions (2 x 2 x Q x P), padded against bank
-// conflicts.
+// both components and directions (2 x 2 x Q x P), or with split passes of
+// one component at a time (2 x Q x P), padded against bank conflicts.
 #ifndef TMOP_ELEM_PAD2
 #define TMOP_ELEM_PAD2 5
 #endif
-constexpr int elem2d_lds_values(int P, int Q) { return 2 * 2 * Q * P + TMOP_ELEM_PAD2; }
+constexpr int elem2d_lds_values(int P, int Q, bool split = false) { return (split ? 2 : 4) * Q * P + TMOP_ELEM_PAD2; }
 
 // Owner-computes tiles of a 2D mesh: the gradient, energy + gradient and
 // Hessian action in one launch over every element instead of one launch per
@@ -47,12 +47,23 @@ constexpr int elem2d_lds_values(int P, int Q) { return 2 * 2 * Q * P + TMOP_ELEM
 constexpr int TILE_BLOCK = 128;
 // dynamic LDS of a tile workgroup: 64 KiB less room for its static arrays
 constexpr int TILE_LDS_BYTES = 64 * 1024 - 256;
+// the static LDS of a tile workgroup (its block-reduction buffer)
+constexpr int TILE_STATIC_LDS_BYTES = 2 * (TILE_BLOCK / 64) * 8;
 constexpr int tile_epr(int Q) { return TILE_BLOCK / Q; }
+// The FP64 gradient tile kernels (gradient, energy + gradient) can stage
+// one component at a time (TileParams::split): with both, a Q2 tile of FP64
+// workgroups needs 24.9 KB of LDS and six fit on a compute unit, so the
+// 512^2 mesh's eight tiles per unit would run in two batches; split, all
+// eight are resident at once.  Where every tile is resident anyway the
+// extra barriers only cost, and the Hessian action keeps both components
+// (its six extra barriers per round cost more than the extra workgroups
+// gain).
+constexpr bool tile_can_split(int rsize, bool hess) { return rsize == 8 && !hess; }
 // LDS bytes per tile node: two FP64 accumulators and the node id
 constexpr int TILE_NODE_BYTES = 2 * 8 + 4;
 // LDS bytes of a tile workgroup with nn nodes and element data of rsize bytes
-constexpr int64_t tile_lds_bytes(int P, int Q, int rsize, int64_t nn) {
-  return nn * TILE_NODE_BYTES + (int64_t)tile_epr(Q) * elem2d_lds_values(P, Q) * rsize;
+constexpr int64_t tile_lds_bytes(int P, int Q, int rsize, bool split, int64_t nn) {
+  return nn * TILE_NODE_BYTES + (int64_t)tile_epr(Q) * elem2d_lds_values(P, Q, split) * rsize;
 }
 struct TileParams {
   const int32_t* round_off;    // [n_tile + 1]: the rounds of tile t are round_off[t] .. round_off[t + 1] - 1
@@ -67,6 +78,7 @@ struct TileParams {
   int64_t n_slot, n_halo;
   int32_t n_tile;
   int32_t nn_max;              // most nodes of one tile: sizes the LDS of the launch
+  int32_t split;               // 1: the FP64 gradient kernels stage one component at a time
 };
 // out[c][I] = the sum of node I's element-vector entries, in ascending
 // element order: entries ev[off[I] .. off[I+1]) are offsets (e dim + 0) npe + l

@@ -43,7 +43,8 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
       const TileParams& tp = *lp.tile;
       *grid = tp.n_tile;
       if (tp.n_tile == 0 || lp.dry) return 0;
-      const int64_t lds = tile_lds_bytes(P, Q, (int)sizeof(R), tp.nn_max);
+      const bool split = tile_can_split((int)sizeof(R), OP == OP_HESS) && tp.split;
+      const int64_t lds = tile_lds_bytes(P, Q, (int)sizeof(R), split, tp.nn_max);
       if (lds > TILE_LDS_BYTES) return -2;
       const ElemArgs<P, Q, R>& ea = a;
       hipLaunchKernelGGL((tile_kernel_2d<P, Q, METRIC, R, OP, TGT>), dim3(tp.n_tile), dim3(TILE_BLOCK), (size_t)lds, s,

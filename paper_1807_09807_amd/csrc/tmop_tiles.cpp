@@ -52,8 +52,9 @@ void pick_shape(int p, int epr, int64_t nn_cap, int* s_out, int* m_out) {
 int build_tiles(const int32_t* en, int64_t n_elem, int npe, int64_t n_node, const int32_t* colour, int p, int Q,
                 TileLayout& out) {
   const int P = p + 1, epr = tile_epr(Q);
-  // the node budget of the largest case, FP64 element data
-  const int64_t nn_cap = std::min<int64_t>(65535, (TILE_LDS_BYTES - tile_lds_bytes(P, Q, 8, 0)) / TILE_NODE_BYTES);
+  // the node budget of the largest element data (FP64 or FP32, both components)
+  const int64_t elem_bytes = std::max(tile_lds_bytes(P, Q, 8, false, 0), tile_lds_bytes(P, Q, 4, false, 0));
+  const int64_t nn_cap = std::min<int64_t>(65535, (TILE_LDS_BYTES - elem_bytes) / TILE_NODE_BYTES);
   if (nn_cap < npe || n_elem < 1) return -1;
   int side = 2, merge = 1;
   pick_shape(p, epr, nn_cap, &side, &merge);

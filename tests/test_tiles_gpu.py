@@ -88,6 +88,25 @@ def test_tiles_bitwise_repeatable(setup):
     ctx.close()
 
 
+def test_split_passes_match_bitwise(setup, monkeypatch):
+    """The FP64 gradient tile kernels' split passes (one component at a time
+    through the LDS area, forced on with TMOP_TILE_SPLIT=1) give the same
+    gradient and energy + gradient bit for bit as the passes over both
+    components (forced off), and match the oracle."""
+    case, mesh, W, v, ref = setup
+    x = to_dev(mesh.x)
+    out = {}
+    for force in ("0", "1"):
+        monkeypatch.setenv("TMOP_TILE_SPLIT", force)
+        ctx = _tiles(context(case, mesh, W, 0))
+        out[force] = (ctx.gradient(x), ctx.energy_gradient(x))
+        ctx.close()
+    (g0, eg0), (g1, eg1) = out["0"], out["1"]
+    assert torch.equal(g0, g1) and torch.equal(eg0[3], eg1[3]) and eg0[:3] == eg1[:3]
+    assert rel_max_err(g1.cpu().numpy(), ref["g"]) <= FP64_TOL
+    assert abs(eg1[0] - ref["F"]) <= FP64_TOL * abs(ref["F"])
+
+
 def test_switching_modes(setup):
     """Tiles are the 2D default; the mode is a per-call choice: tiles,
     colours, tiles again."""

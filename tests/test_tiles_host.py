@@ -32,7 +32,7 @@ def lib(tmp_path_factory):
     L.tiles_copy.argtypes = [ctypes.c_int, ctypes.c_void_p]
     L.tiles_n_slot.restype = ctypes.c_int64
     L.tiles_lds_bytes.restype = ctypes.c_int64
-    L.tiles_lds_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64]
+    L.tiles_lds_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64]
     return L
 
 
@@ -111,8 +111,10 @@ def check(L, en, n_node, p, Q, col=None):
     for I, ts in touch.items():
         if len(ts) == 1:
             assert A["slot"][ts[0][1]] == -1
-    # the LDS of the largest case (FP64 element data) fits
-    assert L.tiles_lds_bytes(p + 1, Q, 8, A["nn_max"]) <= L.tiles_lds_limit()
+    # the LDS of every tile kernel (both precisions, both components or split) fits
+    for rsize in (4, 8):
+        for split in (0, 1):
+            assert L.tiles_lds_bytes(p + 1, Q, rsize, split, A["nn_max"]) <= L.tiles_lds_limit()
     return A, epr
 
 

@@ -41,6 +41,6 @@ void tiles_copy(int which, void* dst) {
 int64_t tiles_n_slot() { return g_layout.n_slot; }
 int32_t tiles_nn_max() { return g_layout.nn_max; }
 int tiles_epr(int Q) { return tmop::tile_epr(Q); }
-int64_t tiles_lds_bytes(int P, int Q, int rsize, int64_t nn) { return tmop::tile_lds_bytes(P, Q, rsize, nn); }
+int64_t tiles_lds_bytes(int P, int Q, int rsize, int split, int64_t nn) { return tmop::tile_lds_bytes(P, Q, rsize, split != 0, nn); }
 int tiles_lds_limit() { return tmop::TILE_LDS_BYTES; }
 }
