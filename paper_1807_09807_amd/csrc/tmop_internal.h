@@ -43,8 +43,11 @@ constexpr int elem2d_lds_values(int P, int Q, bool split = false) { return (spli
 // then writes every node only its tile touches and, for a node shared with
 // other tiles, its partial sum into that node's slot for this tile.  The
 // halo pass adds the slots of each shared node in tile order.  Every sum
-// has a fixed order, so the results are reproducible.
-constexpr int TILE_BLOCK = 128;
+// has a fixed order, so the results are reproducible.  One wave per
+// workgroup: the rounds' barriers then hold no wave waiting on another
+// (measured against 128 and 256 lanes: 512^2 Q2 FP64 Hessian tile launch
+// 60.4 -> 53.5 us, 256^2 Q3 mixed 39.0 -> 34.1 us).
+constexpr int TILE_BLOCK = 64;
 // dynamic LDS of a tile workgroup: 64 KiB less room for its static arrays
 constexpr int TILE_LDS_BYTES = 64 * 1024 - 256;
 // the static LDS of a tile workgroup (its block-reduction buffer)

@@ -146,7 +146,8 @@ def test_unused_nodes_and_two_components(lib):
 
 def test_structured_rounds_are_full(lib):
     """The 512^2 Q2 workload's mesh at a size that holds whole tiles: each
-    tile is four full rounds (32 elements of one colour each)."""
+    tile is four full rounds (tile_epr(4) elements of one colour each) of a
+    square of side 2 sqrt(tile_epr(4))."""
     m = meshgen.box_mesh(2, 64, 2)
     e = np.arange(m.elem_node.shape[0])
     col = (e % 64) % 2 + 2 * ((e // 64) % 2)        # the 2 x 2 colouring of the grid
@@ -154,5 +155,9 @@ def test_structured_rounds_are_full(lib):
     rounds = np.diff(A["round_off"])
     assert np.all(rounds == 4)
     assert np.all(A["slot_elem"] >= 0)
-    # shared nodes: the tile borders only (8 x 16 tiles of a 64 x 64 grid)
-    assert len(A["halo_node"]) / m.n_node < 0.1
+    # shared nodes: the tile borders only, lines of nodes every 2 s along
+    # each direction (s x s tiles of a 64 x 64 grid, s = 2 sqrt(epr))
+    s = int(round(2 * np.sqrt(epr)))
+    lines = 64 // s - 1
+    assert 64 % s == 0 and s * s == 4 * epr
+    assert len(A["halo_node"]) == 2 * lines * 129 - lines * lines
