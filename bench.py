@@ -66,8 +66,8 @@ POINT_FLOPS = {2: (15, 31, 72), 7: (21, 32, 74), 303: (40, 87, 232), 302: (85, 2
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ("tmop_elem.h", "tmop_metrics.h", "tmop_launch.h")
 MEASURED_TRAFFIC = {
-    "q2_cube_64": dict(src_sha256="f1e83bb7da9da8968e37a189f727189fe0680e956c90c32e45d3c81050656de8",
-                       fetch_kib=41952.1, write_kib=27967.8),
+    "q2_cube_64": dict(src_sha256="7710fb2741a03bf3cebbe538763179be17034d061b219c0ea5c389a15fdd54e4",
+                       fetch_kib=41955.6, write_kib=27966.6),
 }
 
 
@@ -259,13 +259,20 @@ def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
     log(f"# workload {name}: {mesh.n_elem} elements, {mesh.n_dof} DOFs, repair rounds "
         f"{mesh.info.get('repair_rounds', 0)}")
     results = {}
-    # 2D: the tile scatter (the 2D default) beside the colour launches; 3D: the
-    # colour launches beside the element-vector scatter (the default of 3D
-    # meshes with colours of at most 8,192 elements, such as q2_cube_32)
+    # the mesh's default scatter beside the other one: 2D, the tiles beside the
+    # colour launches; 3D, the colour launches and the element-vector scatter
+    # (the default of 3D meshes with colours of at most 16,384 elements on
+    # average, such as q2_cube_32 and q3_cube_48)
+    probe = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=mesh.fixed)
+    main = probe.scatter
+    probe.close()
+    names = {T.TMOP_SCATTER_TILES: "tiles", T.TMOP_SCATTER_COLOURS: "colours", T.TMOP_SCATTER_ELEMENTS: "elements"}
     if w["dim"] == 2:
-        main, other, oname = T.TMOP_SCATTER_TILES, T.TMOP_SCATTER_COLOURS, "colours"
+        other = T.TMOP_SCATTER_COLOURS if main == T.TMOP_SCATTER_TILES else T.TMOP_SCATTER_TILES
     else:
-        main, other, oname = T.TMOP_SCATTER_COLOURS, T.TMOP_SCATTER_ELEMENTS, "elements"
+        other = T.TMOP_SCATTER_ELEMENTS if main == T.TMOP_SCATTER_COLOURS else T.TMOP_SCATTER_COLOURS
+    oname = names[other]
+    log(f"# {name}: default scatter {names[main]}, also timed: {oname}")
     variants = [(T.TMOP_FP64, "f64", main), (T.TMOP_MIXED_FP32, "mixed", main),
                 (T.TMOP_FP64, f"f64_{oname}", other), (T.TMOP_MIXED_FP32, f"mixed_{oname}", other)]
     for prec, pname, scatter in variants:

@@ -284,7 +284,7 @@ int tmop_hessian_diagonal(tmop_ctx *ctx, const double *x, double *diag, void *st
  * element contributions to shared nodes (Section 3.4 sums them over the
  * elements holding each node):
  *  TMOP_SCATTER_COLOURS (the default of 3D meshes with colours of more
- *    than 8,192 elements on average): one launch per element colour; the
+ *    than 16,384 elements on average): one launch per element colour; the
  *    elements of a colour share no node, each adds to its nodes in place.
  *  TMOP_SCATTER_TILES (the default of 2D meshes): one launch over every
  *    element in tiles of neighbouring elements; each workgroup accumulates
@@ -298,14 +298,15 @@ int tmop_hessian_diagonal(tmop_ctx *ctx, const double *x, double *diag, void *st
  *    would not otherwise all fit on the device at once; the environment
  *    variable TMOP_TILE_SPLIT=0 or =1, read when the tiles are built,
  *    forces that choice off or on (same results bit for bit).
- *  TMOP_SCATTER_ELEMENTS (3D only; the default of 3D meshes with smaller
- *    colours, whose colour launches cannot fill the chip): one launch over
- *    every element writing each element's contributions to an element vector
- *    (dim x (p+1)^3 doubles per element), then a pass that sums each node's
- *    entries in ascending element order.  Selecting it on a context that did
- *    not start with it builds the node-to-entry map on the host (a
- *    device-to-host copy of the connectivity) and allocates the vector; it
- *    syncs the device.
+ *  TMOP_SCATTER_ELEMENTS (3D only; the default of 3D meshes with colours
+ *    of at most 16,384 elements on average): one launch over every element,
+ *    each element writing its contributions to the entries of its nodes in
+ *    an element vector (dim x (p+1)^3 doubles per element, each node's
+ *    entries contiguous, in ascending element order), then a pass that sums
+ *    each node's entries in that order.  Selecting it on a context that did
+ *    not start with it builds the entry map on the host (a device-to-host
+ *    copy of the connectivity; 4 bytes per element node and per node) and
+ *    allocates the vector; it syncs the device.
  * All are deterministic (fixed summation orders, which differ between
  * them, so results agree to rounding).  The other calls are not affected. */
 enum { TMOP_SCATTER_COLOURS = 0, TMOP_SCATTER_TILES = 1, TMOP_SCATTER_ELEMENTS = 2 };
@@ -316,6 +317,10 @@ enum { TMOP_SCATTER_COLOURS = 0, TMOP_SCATTER_TILES = 1, TMOP_SCATTER_ELEMENTS =
  * context or past 2^31 entries; TMOP_E_NOMEM if its buffer cannot be
  * allocated. */
 int tmop_set_scatter(tmop_ctx *ctx, int32_t mode);
+
+/* The scatter mode in effect on ctx (the mesh's default until
+ * tmop_set_scatter changes it).  TMOP_E_ARG for a null argument. */
+int tmop_get_scatter(const tmop_ctx *ctx, int32_t *mode);
 
 /* ------------------------------------------------------------------------
  * Section 4 objectives.  Each adds a term to the F of every call above

@@ -248,6 +248,8 @@ int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* o
   LaunchParams lp = c->base;
   lp.tile = tile;
   lp.evec = evec;
+  lp.evpos = evec ? c->d_ev_pos : nullptr;
+  lp.n_ent = c->n_elem * c->npe;
   lp.first = first;
   lp.tsize = tsize;
   lp.tmat = term.tmat;
@@ -367,7 +369,7 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
                               c->d_tsize, primary_term(c, false, 0, fused_penalty(c, op)), nullptr, nullptr, c->d_evec);
     if (r != TMOP_OK) return r;
     off += grid;
-    HIP_TRY(evec_gather(c->d_evec, c->d_ev_off, c->d_ev, c->n_node, c->npe, c->dim, out, s));
+    HIP_TRY(evec_gather(c->d_evec, c->d_ev_off, c->n_node, c->n_elem * c->npe, c->dim, out, s));
   } else {
     for (int k = 0; k < ncol; ++k) {
       const int64_t n = c->color_off[k + 1] - c->color_off[k];
@@ -464,10 +466,11 @@ int dot_sync(tmop_ctx* c, const double* a, const double* b, hipStream_t s, doubl
 }
 
 // 3D meshes whose colours average at most this many elements default to the
-// element-vector scatter.  Measured per operation on MI355X: 4,096 Q2 hexes
-// per colour (32^3 mesh) 17-28% faster than the colour launches, 13,824 Q3
-// hexes (48^3) even, 32,768 Q2 hexes (64^3) 22-31% slower.
-constexpr int64_t EVEC_DEFAULT_ELEMS_PER_COLOUR = 8192;
+// element-vector scatter.  Measured per operation on MI355X against the
+// colour launches: 4,096 Q2 hexes per colour (32^3 mesh) 27-38% faster,
+// 13,824 Q3 hexes (48^3) 5-9% faster, 32,768 Q2 hexes (64^3) from 2%
+// faster to 4% slower.
+constexpr int64_t EVEC_DEFAULT_ELEMS_PER_COLOUR = 16384;
 
 void free_tiles(tmop_ctx* c) {
   TileParams& t = c->tile;
@@ -551,10 +554,10 @@ int make_tiles(tmop_ctx* c, const int32_t* en, const std::vector<int32_t>& order
 void free_evec(tmop_ctx* c) {
   (void)hipFree(c->d_evec);
   (void)hipFree(c->d_ev_off);
-  (void)hipFree(c->d_ev);
+  (void)hipFree(c->d_ev_pos);
   c->d_evec = nullptr;
   c->d_ev_off = nullptr;
-  c->d_ev = nullptr;
+  c->d_ev_pos = nullptr;
 }
 
 // The element-vector scatter's buffer and its node -> entry map (3D), from
@@ -564,21 +567,20 @@ int make_evec(tmop_ctx* c, const int32_t* en) {
   const int npe = c->npe, d = c->dim;
   const int64_t ne_tot = c->n_elem * npe;
   if (c->n_elem * d * npe > INT32_MAX) return TMOP_E_UNSUPPORTED;
-  std::vector<int32_t> off(c->n_node + 1, 0), ev((size_t)ne_tot);
+  std::vector<int32_t> off(c->n_node + 1, 0), epos((size_t)ne_tot);
   for (int64_t k = 0; k < ne_tot; ++k) off[en[k] + 1]++;
   for (int64_t I = 0; I < c->n_node; ++I) off[I + 1] += off[I];
   {
-    std::vector<int32_t> pos(off.begin(), off.end() - 1);
-    for (int64_t e = 0; e < c->n_elem; ++e)   // ascending element ids per node
-      for (int l = 0; l < npe; ++l) ev[pos[en[e * npe + l]]++] = (int32_t)(e * d * npe + l);
+    std::vector<int32_t> next(off.begin(), off.end() - 1);
+    for (int64_t k = 0; k < ne_tot; ++k) epos[k] = next[en[k]]++;   // ascending element ids per node
   }
   int st = TMOP_OK;
   if (hipMalloc(&c->d_evec, (size_t)c->n_elem * d * npe * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->d_ev_off, off.size() * sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&c->d_ev, ev.size() * sizeof(int32_t)) != hipSuccess) {
+      hipMalloc(&c->d_ev_pos, epos.size() * sizeof(int32_t)) != hipSuccess) {
     st = TMOP_E_NOMEM;
   } else if (hipMemcpy(c->d_ev_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(c->d_ev, ev.data(), ev.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+             hipMemcpy(c->d_ev_pos, epos.data(), epos.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
     st = TMOP_E_HIP;
   }
   if (st != TMOP_OK) free_evec(c);
@@ -1520,6 +1522,12 @@ int tmop_set_scatter(tmop_ctx* c, int32_t mode) {
     }
   }
   c->scatter = mode;
+  return TMOP_OK;
+}
+
+int tmop_get_scatter(const tmop_ctx* c, int32_t* mode) {
+  if (!c || !mode) return TMOP_E_ARG;
+  *mode = c->scatter;
   return TMOP_OK;
 }
 

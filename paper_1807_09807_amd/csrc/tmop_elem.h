@@ -90,7 +90,9 @@ struct ElemArgs {
   double wdetW;                          // weight factor of a constant target: eta det W
   double M1[P][P];                       // PEN: 1D mass matrix sum_k w_k l_i(s_k) l_j(s_k)
   double kpen;                           // PEN: 2 delta det W
-  double* evec;                          // 3D scatter ops: [n_list][3][P^3] element vector instead of out, or nullptr
+  double* evec;                          // 3D scatter ops: element vector [3][n_ent] instead of out, or nullptr
+  const int32_t* evpos;                  // with evec: [n_elem][P^3] the entry of each element node
+  int64_t n_ent;                         // with evec: entries per component
 };
 
 // Elements per block and block size: the smallest element count that best
@@ -725,10 +727,12 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
   // (with the penalty: before it, which then adds its share to them)
   // (with an element vector: no old values, the element's own share only)
   double old[3][P];
+  int epos[P] = {};   // with an element vector: the entries of this lane's nodes
   auto load_old = [&]() {
     if (active && p1) {
 #pragma unroll
       for (int i2 = 0; i2 < P; ++i2) {
+        if (a.evec) epos[i2] = a.evpos[(int64_t)e * NPE + ta + P * tb + P * P * i2];
         const bool fresh = a.evec || first_touch<NPE>(a.first, kk, ta + P * tb + P * P * i2);
 #pragma unroll
         for (int c = 0; c < 3; ++c) old[c][i2] = fresh ? 0.0 : a.out[c * a.n_node + node[i2]];
@@ -737,7 +741,7 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
   };
   // the scatter of the value of local node (ta, tb, i2), component c
   auto put = [&](int c, int i2, double val) {
-    if (a.evec) a.evec[((int64_t)kk * 3 + c) * NPE + ta + P * tb + P * P * i2] = val;
+    if (a.evec) a.evec[(int64_t)c * a.n_ent + epos[i2]] = val;
     else a.out[c * a.n_node + node[i2]] = val;
   };
   if constexpr (PEN) {   // the penalty's share 2 delta det W (M1 x M1 x M1 v) joins the old values

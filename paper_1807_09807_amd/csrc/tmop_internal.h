@@ -83,11 +83,12 @@ struct TileParams {
   int32_t nn_max;              // most nodes of one tile: sizes the LDS of the launch
   int32_t split;               // 1: the FP64 gradient kernels stage one component at a time
 };
-// out[c][I] = the sum of node I's element-vector entries, in ascending
-// element order: entries ev[off[I] .. off[I+1]) are offsets (e dim + 0) npe + l
-// into evec (component c at + c npe); nodes without entries get 0.
-hipError_t evec_gather(const double* evec, const int32_t* off, const int32_t* ev, int64_t n_node, int npe, int dim,
-                       double* out, hipStream_t s);
+// out[c][I] = the sum of node I's element-vector entries
+// evec[c n_ent + k], k = off[I] .. off[I+1] - 1 (one entry per element
+// holding the node, in ascending element order); nodes without entries
+// get 0.
+hipError_t evec_gather(const double* evec, const int32_t* off, int64_t n_node, int64_t n_ent, int dim, double* out,
+                       hipStream_t s);
 
 // out[c][halo_node[h]] = sum of its slots, in order
 hipError_t halo_sum(const TileParams& tp, int64_t n_node, double* out, hipStream_t s);
@@ -141,9 +142,12 @@ struct LaunchParams {
   // (nullptr: the colour launch described by elem_node / list / first)
   const TileParams* tile;
   // 3D OP_GRAD / OP_EG / OP_HESS: each element's contributions go to this
-  // element vector [n_list][3][P^3] instead of the scatter to out (nullptr:
-  // the scatter)
+  // element vector [3][n_ent] instead of the scatter to out (nullptr: the
+  // scatter): element e's value for local node l, component c, to entry
+  // c n_ent + evpos[e npe + l]
   double* evec;
+  const int32_t* evpos;
+  int64_t n_ent;
 };
 
 // Everything one launch of the displacement-penalty kernels (eq. 4.2)
@@ -340,9 +344,9 @@ struct tmop_ctx {
   int tile_elems = 0;                  // elements per tile they were built for
   tmop::TileParams tile{};             // its device arrays, owned by the context
   // element-vector scatter (TMOP_SCATTER_ELEMENTS, 3D), built on first use
-  double* d_evec = nullptr;            // [n_elem][dim][npe]
-  int32_t* d_ev_off = nullptr;         // [n_node + 1] node -> entries
-  int32_t* d_ev = nullptr;             // entry: (e dim) npe + l, ascending e per node
+  double* d_evec = nullptr;            // [dim][n_elem npe]: each node's entries contiguous
+  int32_t* d_ev_off = nullptr;         // [n_node + 1] node -> its entries (ascending element order)
+  int32_t* d_ev_pos = nullptr;         // [n_elem][npe] the entry of element e's local node l
   // optional per-launch timing of the element kernels (HIP events)
   struct TimedLaunch { int op; hipEvent_t a, b; };
   bool timing = false;

@@ -24,6 +24,8 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   a.wdetW = lp.wdetW;
   a.kpen = lp.kpen;
   a.evec = DIM == 3 && (OP == OP_GRAD || OP == OP_EG || OP == OP_HESS) ? lp.evec : nullptr;
+  a.evpos = lp.evpos;
+  a.n_ent = lp.n_ent;
   for (int i = 0; i < P; ++i)
     for (int j = 0; j < P; ++j) a.M1[i][j] = lp.M1[i][j];
   const double gs = TGT == TGT_ISO ? lp.s_inv : 1.0;   // constant isotropic target: G carries 1/s

@@ -35,7 +35,7 @@ EXPORTS = ("tmop_setup", "tmop_energy", "tmop_gradient", "tmop_gradient_scaled",
            "tmop_timing_enable", "tmop_timing_read", "tmop_energy_gradient", "tmop_hessian_diagonal",
            "tmop_target_sizes_w3", "tmop_set_target_sizes", "tmop_set_restriction", "tmop_set_combo",
            "tmop_set_replication", "tmop_dfo_default_opts", "tmop_dfo_sweep", "tmop_dfo_solve",
-           "tmop_energy_noalloc", "tmop_set_scatter")
+           "tmop_energy_noalloc", "tmop_set_scatter", "tmop_get_scatter")
 # timing slots: the element-kernel operations, then the W_0 data and the penalty kernels
 TIMING_ENERGY, TIMING_GRAD, TIMING_HESS, TIMING_EG, TIMING_DIAG, TIMING_SIZE = 0, 1, 2, 3, 4, 5
 TIMING_W0, TIMING_PENALTY = 6, 7
@@ -116,6 +116,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tmop_hessian_diagonal.restype = ctypes.c_int
     lib.tmop_set_scatter.argtypes = [P, ctypes.c_int32]
     lib.tmop_set_scatter.restype = ctypes.c_int
+    lib.tmop_get_scatter.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    lib.tmop_get_scatter.restype = ctypes.c_int
     lib.tmop_target_sizes_w3.argtypes = [P, P, P, P]
     lib.tmop_target_sizes_w3.restype = ctypes.c_int
     lib.tmop_set_target_sizes.argtypes = [P, P, P]
@@ -309,6 +311,15 @@ class Context:
         st = self._lib.tmop_set_scatter(self._h, int(mode))
         if st < 0:
             raise TMOPError(st, "tmop_set_scatter")
+
+    @property
+    def scatter(self):
+        """The scatter mode in effect (the mesh's default until set_scatter)."""
+        m = ctypes.c_int32(-1)
+        st = self._lib.tmop_get_scatter(self._h, ctypes.byref(m))
+        if st < 0:
+            raise TMOPError(st, "tmop_get_scatter")
+        return m.value
 
     def hessian_diagonal(self, x, out=None):
         """diag(d^2F/dx^2) over all DOFs, shape (dim, n_node)."""

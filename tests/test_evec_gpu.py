@@ -133,6 +133,23 @@ def test_newton_with_evec():
     assert np.max(np.abs(xe - mesh.x_grid)) < 1e-8 * mesh.h
 
 
+@pytest.mark.parametrize("dim,n,expect", [(3, 8, "ELEMENTS"), (3, 50, "ELEMENTS"), (3, 52, "COLOURS"),
+                                            (2, 16, "TILES")])
+def test_default_scatter(dim, n, expect):
+    """The default mode follows the mesh: 2D tiles; in 3D the element vector
+    while the 2^3 colours average at most 16,384 elements (50^3 Q2: 15,625),
+    the colour launches above (52^3: 17,576).  tmop_get_scatter reports it,
+    and then what tmop_set_scatter selects."""
+    from paper_1807_09807_amd import tmop as T
+    say(f"[evec] default scatter dim={dim} n={n}")
+    mesh = meshgen.box_mesh(dim, n, 2)
+    ctx = T.Context(dim, 2, mesh.elem_node, mesh.n_node, 4, 303 if dim == 3 else 2, mesh.h * np.eye(dim))
+    assert ctx.scatter == getattr(T, f"TMOP_SCATTER_{expect}")
+    ctx.set_scatter(T.TMOP_SCATTER_COLOURS)
+    assert ctx.scatter == T.TMOP_SCATTER_COLOURS
+    ctx.close()
+
+
 def test_evec_refused_in_2d():
     from paper_1807_09807_amd import tmop as T
     mesh = meshgen.box_mesh(2, 3, 2)
