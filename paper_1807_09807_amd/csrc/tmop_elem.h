@@ -567,8 +567,14 @@ __device__ __forceinline__ void penalty_pass_3d(const ElemArgs<P, Q, double>& a,
   }
 }
 
-template <int P, int Q, int METRIC, typename R, int OP, int TGT, bool PEN = false>
+// EV: the element-vector instantiation.  Its gradient kinds with a constant
+// target, up to order 3, are asked for two waves per SIMD: with no old
+// values their schedule otherwise lands a register or two above 256 for the
+// Q3 energy + gradient (one wave per SIMD).  Under the same request the
+// Hessian action, order 4 and the per-point targets spill.
+template <int P, int Q, int METRIC, typename R, int OP, int TGT, bool PEN = false, bool EV = false>
 __global__ void __launch_bounds__((Cfg<3, P, Q, R>::BLOCK))
+__attribute__((amdgpu_waves_per_eu(EV && OP != OP_HESS && P <= 4 && (TGT == TGT_GEN || TGT == TGT_ISO) ? 2 : 1)))
 elem_kernel_3d(const ElemArgs<P, Q, R> a) {
   static_assert(!PEN || (sizeof(R) == 8 && OP == OP_HESS && (TGT == TGT_ISO || TGT == TGT_GEN)),
                 "the fused penalty is the FP64 constant-target Hessian action");
@@ -727,21 +733,20 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
   // (with the penalty: before it, which then adds its share to them)
   // (with an element vector: no old values, the element's own share only)
   double old[3][P];
-  int epos[P] = {};   // with an element vector: the entries of this lane's nodes
   auto load_old = [&]() {
     if (active && p1) {
 #pragma unroll
       for (int i2 = 0; i2 < P; ++i2) {
-        if (a.evec) epos[i2] = a.evpos[(int64_t)e * NPE + ta + P * tb + P * P * i2];
-        const bool fresh = a.evec || first_touch<NPE>(a.first, kk, ta + P * tb + P * P * i2);
+        const bool fresh = EV || first_touch<NPE>(a.first, kk, ta + P * tb + P * P * i2);
 #pragma unroll
         for (int c = 0; c < 3; ++c) old[c][i2] = fresh ? 0.0 : a.out[c * a.n_node + node[i2]];
       }
     }
   };
-  // the scatter of the value of local node (ta, tb, i2), component c
+  // the scatter of the value of local node (ta, tb, i2), component c (EV:
+  // to the node's entry in the element vector)
   auto put = [&](int c, int i2, double val) {
-    if (a.evec) a.evec[(int64_t)c * a.n_ent + epos[i2]] = val;
+    if constexpr (EV) a.evec[(int64_t)c * a.n_ent + a.evpos[(int64_t)e * NPE + ta + P * tb + P * P * i2]] = val;
     else a.out[c * a.n_node + node[i2]] = val;
   };
   if constexpr (PEN) {   // the penalty's share 2 delta det W (M1 x M1 x M1 v) joins the old values

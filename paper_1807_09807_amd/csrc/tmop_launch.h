@@ -72,8 +72,17 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
     else hipLaunchKernelGGL((diag_kernel_2d<P, Q, METRIC, R, TGT>), dim3(g), dim3(C::BLOCK), 0, s, a);
   } else {
     const ElemArgs<P, Q, R>& ea = a;
-    if constexpr (DIM == 3) hipLaunchKernelGGL((elem_kernel_3d<P, Q, METRIC, R, OP, TGT, PEN>), dim3(g), dim3(C::BLOCK), 0, s, ea);
-    else hipLaunchKernelGGL((elem_kernel_2d<P, Q, METRIC, R, OP, TGT>), dim3(g), dim3(C::BLOCK), 0, s, ea);
+    if constexpr (DIM == 3) {
+      // the element-vector stores are a separate instantiation: the colour
+      // launches' kernels then hold no register for them
+      constexpr bool SCATTER = OP == OP_GRAD || OP == OP_EG || OP == OP_HESS;
+      if (SCATTER && a.evec)
+        hipLaunchKernelGGL((elem_kernel_3d<P, Q, METRIC, R, OP, TGT, PEN, SCATTER>), dim3(g), dim3(C::BLOCK), 0, s, ea);
+      else
+        hipLaunchKernelGGL((elem_kernel_3d<P, Q, METRIC, R, OP, TGT, PEN, false>), dim3(g), dim3(C::BLOCK), 0, s, ea);
+    } else {
+      hipLaunchKernelGGL((elem_kernel_2d<P, Q, METRIC, R, OP, TGT>), dim3(g), dim3(C::BLOCK), 0, s, ea);
+    }
   }
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
