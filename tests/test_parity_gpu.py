@@ -67,8 +67,10 @@ def test_energy_gradient_one_pass(setup, precision):
     """The fused pass gives the oracle's F, min det A and g, and the separate
     calls' g to rounding: the same arithmetic in another kernel
     instantiation, where the compiler may fuse a different set of products
-    and sums into FMAs (often bit for bit, not always); F differs from the
-    energy call only in its summation order."""
+    and sums into FMAs (often bit for bit, not always: FP64 within 1e-14;
+    mixed, two FP32 evaluations each within the first-order rounding bound
+    of the oracle's g, so within twice that bound of each other); F differs
+    from the energy call only in its summation order."""
     case, mesh, W, v, ref = setup
     ctx = context(case, mesh, W, precision)
     x = to_dev(mesh.x)
@@ -84,7 +86,7 @@ def test_energy_gradient_one_pass(setup, precision):
     d = rel_max_err(g.cpu().numpy(), g1.cpu().numpy())
     if d > 0.0:
         say(f"  {case.name} prec={precision}: fused and separate gradients differ by {d:.2e} (relative)")
-    assert d <= 1e-14
+    assert d <= (1e-14 if precision == 0 else 2 * tol["g"])
 
 
 def test_bitwise_deterministic(setup):
