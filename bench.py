@@ -104,8 +104,12 @@ def algorithmic(w):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # 20 warmup steps: the first calls load the kernels' code objects and the
+    # first tens of milliseconds of work run below the steady clock (20-step
+    # blocks from a cold start on 64^3 Q2: 2.42, 0.688, then 0.662-0.668 ms per
+    # step); 100 timed steps are well under a second of work
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="q2_cube_64", choices=sorted(meshgen.WORKLOADS))
     ap.add_argument("--no-newton", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
