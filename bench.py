@@ -58,16 +58,21 @@ def contraction_macs(dim, P, Q):
 #             dP = kE E + kd dcof + sT T + sC cof T (+ the I2 terms of mu_302)
 POINT_FLOPS = {2: (15, 31, 72), 7: (21, 32, 74), 303: (40, 87, 232), 302: (85, 242, 717)}
 
-# HBM traffic of one Hessian-action colour launch (FP64), from rocprofv3
-# --pmc FETCH_SIZE and WRITE_SIZE passes (KiB per dispatch), valid for the
-# element-kernel sources whose SHA-256 is recorded with them.  The counters
-# are scaled by what they read for a 256 MiB device copy in the same
-# profile: FETCH_SIZE 131,089 KiB (factor 2.0), WRITE_SIZE 262,144 KiB (1.0).
+# HBM traffic of one Hessian-action launch (FP64) of the workload's default
+# scatter, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE passes (KiB per
+# dispatch), valid for the element-kernel sources whose SHA-256 is recorded
+# with them.  The counters are scaled by what they read for a 256 MiB device
+# copy in the same profile: FETCH_SIZE 131,089 KiB (factor 2.0), WRITE_SIZE
+# 262,144 KiB (1.0).
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ("tmop_elem.h", "tmop_metrics.h", "tmop_launch.h")
 MEASURED_TRAFFIC = {
-    "q2_cube_64": dict(src_sha256="6ad9771846eff7e8664daef82aa2c9f3b35433c1477605cb6800c91c09701926",
-                       fetch_kib=41950.5, write_kib=27966.8),
+    # colour launch of 32,768 elements
+    ("q2_cube_64", "colours"): dict(src_sha256="6ad9771846eff7e8664daef82aa2c9f3b35433c1477605cb6800c91c09701926",
+                                    fetch_kib=41950.5, write_kib=27966.8),
+    # element-vector launch over all 262,144 elements (the gather is a kernel of its own)
+    ("q2_cube_64", "elements"): dict(src_sha256="6ad9771846eff7e8664daef82aa2c9f3b35433c1477605cb6800c91c09701926",
+                                     fetch_kib=102674.1, write_kib=227990.0),
 }
 
 
@@ -80,10 +85,11 @@ def kernel_digest():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """Calibrated HBM bytes per Hessian-action colour launch, or None when
-    no counters were taken for this workload at the current kernel sources."""
-    m = MEASURED_TRAFFIC.get(workload)
+def measured_traffic(workload, scatter):
+    """Calibrated HBM bytes per Hessian-action launch of the given scatter
+    ("colours" or "elements"), or None when no counters were taken for it at
+    the current kernel sources."""
+    m = MEASURED_TRAFFIC.get((workload, scatter))
     if m is None or m["src_sha256"] != kernel_digest():
         return None
     return 1024.0 * (FETCH_SCALE * m["fetch_kib"] + WRITE_SCALE * m["write_kib"])
@@ -265,8 +271,8 @@ def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
     results = {}
     # the mesh's default scatter beside the other one: 2D, the tiles beside the
     # colour launches; 3D, the colour launches and the element-vector scatter
-    # (the default of 3D meshes with colours of at most 16,384 elements on
-    # average, such as q2_cube_32 and q3_cube_48)
+    # (the default of 3D meshes with colours of at most 32,768 elements on
+    # average, such as q2_cube_64, q2_cube_32 and q3_cube_48)
     probe = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=mesh.fixed)
     main = probe.scatter
     probe.close()
@@ -334,7 +340,7 @@ def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
             launch[oname] = dict(launches=n, us_per_launch=tot_ms * 1e3 / n, us_per_op=tot_ms * 1e3 / steps)
         ctx.timing_enable(False)
         results[pname] = dict(ms_per_step=ms, value=mesh.n_dof / (ms * 1e-3), ops=ops, F=F, ctx=ctx,
-                              launch=launch)
+                              launch=launch, scatter=names[scatter])
         results[pname]["setup_s"] = t_set
         log(f"# {pname}: {ms:.3f} ms/step, E {ops['energy']*1e6:.1f} us, G {ops['gradient']*1e6:.1f} us, "
             f"E+G {ops['energy_gradient']*1e6:.1f} us, Hv {ops['hessian']*1e6:.1f} us, "
@@ -411,8 +417,8 @@ def op_times(torch, ctx, x, v, reps):
 def targets(T, torch, dev, args, w, mesh, x, v, W, log):
     """Per-point targets and sliding boundaries on the main workload.
     W_3 (Section 3.1: W_q = (det A(x_0))^(1/d) I at every point, from the
-    input mesh itself): FP64 operation times and the Hessian colour launch
-    against the constant target W = h I.  Sliding (Section 4.1: only the
+    input mesh itself): FP64 operation times and the Hessian launch (of the
+    mesh's default scatter) against the constant target W = h I.  Sliding (Section 4.1: only the
     normal component of a boundary node is fixed): Newton with the
     inexact-Newton forcing from the same mesh, against the fixed
     boundary."""
@@ -440,7 +446,7 @@ def targets(T, torch, dev, args, w, mesh, x, v, W, log):
     w3_l = hess_launch(cq)
     cq.close()
     log(f"# targets W_3 on {args.workload}: Hv {const['hessian']*1e6:.1f} -> {w3['hessian']*1e6:.1f} us "
-        f"(colour launch {const_l:.1f} -> {w3_l:.1f} us), E+G {const['energy_gradient']*1e6:.1f} -> "
+        f"(Hessian launch {const_l:.1f} -> {w3_l:.1f} us), E+G {const['energy_gradient']*1e6:.1f} -> "
         f"{w3['energy_gradient']*1e6:.1f} us")
     newton = {}
     for key, slide in (("fixed", False), ("sliding", True)):
@@ -773,10 +779,13 @@ def main():
 
     r64 = results["f64"]
     hl = r64["launch"]["hessian"]
-    per_op = hl["launches"] / args.steps                      # colour launches per Hessian action
+    per_op = hl["launches"] / args.steps                      # launches per Hessian action
     t_l = hl["us_per_launch"] * 1e-6
     fl = flops[2] * mesh.n_elem / per_op                     # algorithmic flops per launch
-    traffic = measured_traffic(args.workload)
+    scatter = r64["scatter"]
+    traffic = measured_traffic(args.workload, scatter)
+    kernel_label = ("Hessian-action element kernel (FP64), one colour launch" if scatter == "colours" else
+                    "Hessian-action element kernel (FP64), one element-vector launch over every element")
     line = {
         "metric": "DOF-iterations/s of energy+grad+Hv (FP64 vs FP32), Newton wall-s to F tol",
         "value": r64["value"],
@@ -793,7 +802,7 @@ def main():
         "config": {"workload": args.workload, "dim": w["dim"], "order": w["p"], "elements": mesh.n_elem,
                    "dofs": mesh.n_dof, "quadrature": f"{w['Q']}^{w['dim']} Gauss-Legendre",
                    "metric": f"mu_{w['metric']}", "target": "W = h I"},
-        "roofline": {"kernel": "Hessian-action element kernel (FP64), one colour launch",
+        "roofline": {"kernel": kernel_label, "scatter": scatter,
                      "bound": "alu", "achieved": fl / t_l / 1e12, "peak": FP64_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": fl / t_l / FP64_PEAK, "traffic": traffic,
                      "launch_us": hl["us_per_launch"], "launches_per_op": per_op,

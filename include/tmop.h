@@ -284,7 +284,7 @@ int tmop_hessian_diagonal(tmop_ctx *ctx, const double *x, double *diag, void *st
  * element contributions to shared nodes (Section 3.4 sums them over the
  * elements holding each node):
  *  TMOP_SCATTER_COLOURS (the default of 3D meshes with colours of more
- *    than 16,384 elements on average): one launch per element colour; the
+ *    than 32,768 elements on average): one launch per element colour; the
  *    elements of a colour share no node, each adds to its nodes in place.
  *  TMOP_SCATTER_TILES (the default of 2D meshes): one launch over every
  *    element in tiles of neighbouring elements; each workgroup accumulates
@@ -299,7 +299,7 @@ int tmop_hessian_diagonal(tmop_ctx *ctx, const double *x, double *diag, void *st
  *    variable TMOP_TILE_SPLIT=0 or =1, read when the tiles are built,
  *    forces that choice off or on (same results bit for bit).
  *  TMOP_SCATTER_ELEMENTS (3D only; the default of 3D meshes with colours
- *    of at most 16,384 elements on average): one launch over every element,
+ *    of at most 32,768 elements on average): one launch over every element,
  *    each element writing its contributions to the entries of its nodes in
  *    an element vector (dim x (p+1)^3 doubles per element, each node's
  *    entries contiguous, in ascending element order), then a pass that sums

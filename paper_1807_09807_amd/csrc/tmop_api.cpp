@@ -467,10 +467,14 @@ int dot_sync(tmop_ctx* c, const double* a, const double* b, hipStream_t s, doubl
 
 // 3D meshes whose colours average at most this many elements default to the
 // element-vector scatter.  Measured per operation on MI355X against the
-// colour launches: 4,096 Q2 hexes per colour (32^3 mesh) 27-38% faster,
-// 13,824 Q3 hexes (48^3) 5-9% faster, 32,768 Q2 hexes (64^3) from 2%
-// faster to 4% slower.
-constexpr int64_t EVEC_DEFAULT_ELEMS_PER_COLOUR = 16384;
+// colour launches: 4,096 Q2 hexes per colour (32^3 mesh) 31-37% faster,
+// 13,824 Q3 hexes (48^3) 8-11% faster, 32,768 Q2 hexes (64^3) Hessian
+// action 4% faster, energy + gradient 2% slower, the step even.  Its one
+// launch over every element keeps the chip fuller than eight colour
+// launches (VALU busy 55% against 40% for the 64^3 FP64 Hessian action);
+// larger colours fill the chip by themselves while the element vector's
+// traffic keeps growing with the mesh.
+constexpr int64_t EVEC_DEFAULT_ELEMS_PER_COLOUR = 32768;
 
 void free_tiles(tmop_ctx* c) {
   TileParams& t = c->tile;

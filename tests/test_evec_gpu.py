@@ -133,13 +133,13 @@ def test_newton_with_evec():
     assert np.max(np.abs(xe - mesh.x_grid)) < 1e-8 * mesh.h
 
 
-@pytest.mark.parametrize("dim,n,expect", [(3, 8, "ELEMENTS"), (3, 50, "ELEMENTS"), (3, 52, "COLOURS"),
+@pytest.mark.parametrize("dim,n,expect", [(3, 8, "ELEMENTS"), (3, 64, "ELEMENTS"), (3, 66, "COLOURS"),
                                             (2, 16, "TILES")])
 def test_default_scatter(dim, n, expect):
     """The default mode follows the mesh: 2D tiles; in 3D the element vector
-    while the 2^3 colours average at most 16,384 elements (50^3 Q2: 15,625),
-    the colour launches above (52^3: 17,576).  tmop_get_scatter reports it,
-    and then what tmop_set_scatter selects."""
+    while the 2^3 colours average at most 32,768 elements (64^3 Q2: exactly
+    that), the colour launches above (66^3: 35,937).  tmop_get_scatter
+    reports it, and then what tmop_set_scatter selects."""
     from paper_1807_09807_amd import tmop as T
     say(f"[evec] default scatter dim={dim} n={n}")
     mesh = meshgen.box_mesh(dim, n, 2)
