@@ -98,3 +98,6 @@ def test_null_arguments():
     assert lib.tmop_timing_enable(None, 1) == T.TMOP_E_ARG
     ms, n = ctypes.c_double(), ctypes.c_int64()
     assert lib.tmop_timing_read(None, 2, ctypes.byref(ms), ctypes.byref(n)) == T.TMOP_E_ARG
+    mode = ctypes.c_int32(-1)
+    assert lib.tmop_set_scatter(None, T.TMOP_SCATTER_COLOURS) == T.TMOP_E_ARG
+    assert lib.tmop_get_scatter(None, ctypes.byref(mode)) == T.TMOP_E_ARG and mode.value == -1
