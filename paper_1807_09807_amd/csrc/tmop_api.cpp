@@ -244,10 +244,11 @@ int elem_launch(tmop_ctx* c, int op, const double* x, const double* v, double* o
                 const int32_t* list, int64_t n_list, hipStream_t s, int* grid, const double* scale = nullptr,
                 int64_t part_off = 0, const uint32_t* first = nullptr, const double* tsize = nullptr,
                 TermSel term = TermSel{}, const RedDst* rd = nullptr, const TileParams* tile = nullptr,
-                double* evec = nullptr) {
+                void* evec = nullptr) {
   LaunchParams lp = c->base;
   lp.tile = tile;
   lp.evec = evec;
+  lp.evec_esize = c->evec_esize;
   lp.evpos = evec ? c->d_ev_pos : nullptr;
   lp.n_ent = c->n_elem * c->npe;
   lp.first = first;
@@ -369,7 +370,7 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
                               c->d_tsize, primary_term(c, false, 0, fused_penalty(c, op)), nullptr, nullptr, c->d_evec);
     if (r != TMOP_OK) return r;
     off += grid;
-    HIP_TRY(evec_gather(c->d_evec, c->d_ev_off, c->n_node, c->n_elem * c->npe, c->dim, out, s));
+    HIP_TRY(evec_gather(c->d_evec, c->evec_esize, c->d_ev_off, c->n_node, c->n_elem * c->npe, c->dim, out, s));
   } else {
     for (int k = 0; k < ncol; ++k) {
       const int64_t n = c->color_off[k + 1] - c->color_off[k];
@@ -579,7 +580,9 @@ int make_evec(tmop_ctx* c, const int32_t* en) {
     for (int64_t k = 0; k < ne_tot; ++k) epos[k] = next[en[k]]++;   // ascending element ids per node
   }
   int st = TMOP_OK;
-  if (hipMalloc(&c->d_evec, (size_t)c->n_elem * d * npe * sizeof(double)) != hipSuccess ||
+  // the mixed path's element results are FP32 values: FP32 entries hold them exactly
+  c->evec_esize = c->precision == TMOP_MIXED_FP32 ? 4 : 8;
+  if (hipMalloc(&c->d_evec, (size_t)c->n_elem * d * npe * c->evec_esize) != hipSuccess ||
       hipMalloc(&c->d_ev_off, off.size() * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&c->d_ev_pos, epos.size() * sizeof(int32_t)) != hipSuccess) {
     st = TMOP_E_NOMEM;

@@ -555,27 +555,35 @@ hipError_t halo_sum(const TileParams& tp, int64_t n_node, double* out, hipStream
 
 namespace {
 // Gather of the element-vector scatter: each node's entries, contiguous
-// and in ascending element order, every component.  Consecutive nodes read
-// consecutive runs of entries.
-__global__ void __launch_bounds__(VB) k_evec_gather(const double* __restrict__ evec, const int32_t* __restrict__ off,
+// and in ascending element order, every component, summed in FP64.
+// Consecutive nodes read consecutive runs of entries.
+template <typename E>
+__global__ void __launch_bounds__(VB) k_evec_gather(const E* __restrict__ evec, const int32_t* __restrict__ off,
                                                     int64_t n_node, int64_t n_ent, int dim, double* __restrict__ out) {
   const int64_t I = blockIdx.x * (int64_t)VB + threadIdx.x;
   if (I >= n_node) return;
   const int k0 = off[I], k1 = off[I + 1];
   for (int c = 0; c < dim; ++c) {
-    const double* ec = evec + c * n_ent;
+    const E* ec = evec + c * n_ent;
     double sum = 0.0;
-    for (int k = k0; k < k1; ++k) sum += ec[k];
+    for (int k = k0; k < k1; ++k) sum += (double)ec[k];
     out[c * n_node + I] = sum;
   }
 }
 }  // namespace
 
-hipError_t evec_gather(const double* evec, const int32_t* off, int64_t n_node, int64_t n_ent, int dim, double* out,
-                       hipStream_t s) {
+hipError_t evec_gather(const void* evec, int esize, const int32_t* off, int64_t n_node, int64_t n_ent, int dim,
+                       double* out, hipStream_t s) {
   if (n_node == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_evec_gather, dim3((unsigned)((n_node + VB - 1) / VB)), dim3(VB), 0, s, evec, off, n_node,
-                     n_ent, dim, out);
+  const dim3 g((unsigned)((n_node + VB - 1) / VB));
+  if (esize == 4)
+    hipLaunchKernelGGL(k_evec_gather<float>, g, dim3(VB), 0, s, static_cast<const float*>(evec), off, n_node, n_ent,
+                       dim, out);
+  else if (esize == 8)
+    hipLaunchKernelGGL(k_evec_gather<double>, g, dim3(VB), 0, s, static_cast<const double*>(evec), off, n_node,
+                       n_ent, dim, out);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -90,7 +90,7 @@ struct ElemArgs {
   double wdetW;                          // weight factor of a constant target: eta det W
   double M1[P][P];                       // PEN: 1D mass matrix sum_k w_k l_i(s_k) l_j(s_k)
   double kpen;                           // PEN: 2 delta det W
-  double* evec;                          // 3D scatter ops: element vector [3][n_ent] instead of out, or nullptr
+  R* evec;                               // 3D scatter ops: element vector [3][n_ent] instead of out, or nullptr
   const int32_t* evpos;                  // with evec: [n_elem][P^3] the entry of each element node
   int64_t n_ent;                         // with evec: entries per component
 };
@@ -746,7 +746,8 @@ elem_kernel_3d(const ElemArgs<P, Q, R> a) {
   // the scatter of the value of local node (ta, tb, i2), component c (EV:
   // to the node's entry in the element vector)
   auto put = [&](int c, int i2, double val) {
-    if constexpr (EV) a.evec[(int64_t)c * a.n_ent + a.evpos[(int64_t)e * NPE + ta + P * tb + P * P * i2]] = val;
+    // (EV: val is the element's own FP64 or FP32 value, exact in R)
+    if constexpr (EV) a.evec[(int64_t)c * a.n_ent + a.evpos[(int64_t)e * NPE + ta + P * tb + P * P * i2]] = (R)val;
     else a.out[c * a.n_node + node[i2]] = val;
   };
   if constexpr (PEN) {   // the penalty's share 2 delta det W (M1 x M1 x M1 v) joins the old values

@@ -83,12 +83,13 @@ struct TileParams {
   int32_t nn_max;              // most nodes of one tile: sizes the LDS of the launch
   int32_t split;               // 1: the FP64 gradient kernels stage one component at a time
 };
-// out[c][I] = the sum of node I's element-vector entries
+// out[c][I] = the sum, in FP64, of node I's element-vector entries
 // evec[c n_ent + k], k = off[I] .. off[I+1] - 1 (one entry per element
 // holding the node, in ascending element order); nodes without entries
-// get 0.
-hipError_t evec_gather(const double* evec, const int32_t* off, int64_t n_node, int64_t n_ent, int dim, double* out,
-                       hipStream_t s);
+// get 0.  esize: bytes per entry, 8 (FP64) or 4 (FP32, the mixed path's
+// element results, which are FP32 values).
+hipError_t evec_gather(const void* evec, int esize, const int32_t* off, int64_t n_node, int64_t n_ent, int dim,
+                       double* out, hipStream_t s);
 
 // out[c][halo_node[h]] = sum of its slots, in order
 hipError_t halo_sum(const TileParams& tp, int64_t n_node, double* out, hipStream_t s);
@@ -144,8 +145,10 @@ struct LaunchParams {
   // 3D OP_GRAD / OP_EG / OP_HESS: each element's contributions go to this
   // element vector [3][n_ent] instead of the scatter to out (nullptr: the
   // scatter): element e's value for local node l, component c, to entry
-  // c n_ent + evpos[e npe + l]
-  double* evec;
+  // c n_ent + evpos[e npe + l]; entries of evec_esize bytes, the element
+  // kernels' arithmetic type
+  void* evec;
+  int evec_esize;
   const int32_t* evpos;
   int64_t n_ent;
 };
@@ -344,7 +347,8 @@ struct tmop_ctx {
   int tile_elems = 0;                  // elements per tile they were built for
   tmop::TileParams tile{};             // its device arrays, owned by the context
   // element-vector scatter (TMOP_SCATTER_ELEMENTS, 3D), built on first use
-  double* d_evec = nullptr;            // [dim][n_elem npe]: each node's entries contiguous
+  void* d_evec = nullptr;              // [dim][n_elem npe]: each node's entries contiguous
+  int evec_esize = 8;                  // bytes per entry: 8, or 4 in the mixed FP32 path
   int32_t* d_ev_off = nullptr;         // [n_node + 1] node -> its entries (ascending element order)
   int32_t* d_ev_pos = nullptr;         // [n_elem][npe] the entry of element e's local node l
   // optional per-launch timing of the element kernels (HIP events)

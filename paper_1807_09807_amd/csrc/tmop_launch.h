@@ -23,7 +23,8 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   a.tm_pt = lp.tm_pt;
   a.wdetW = lp.wdetW;
   a.kpen = lp.kpen;
-  a.evec = DIM == 3 && (OP == OP_GRAD || OP == OP_EG || OP == OP_HESS) ? lp.evec : nullptr;
+  a.evec = DIM == 3 && (OP == OP_GRAD || OP == OP_EG || OP == OP_HESS) ? static_cast<R*>(lp.evec) : nullptr;
+  if (a.evec && lp.evec_esize != (int)sizeof(R)) return -1;   // the vector holds the kernels' arithmetic type
   a.evpos = lp.evpos;
   a.n_ent = lp.n_ent;
   for (int i = 0; i < P; ++i)
