@@ -286,36 +286,38 @@ int tmop_hessian_diagonal(tmop_ctx *ctx, const double *x, double *diag, void *st
  *  TMOP_SCATTER_COLOURS (the default of 3D meshes with colours of more
  *    than 32,768 elements on average): one launch per element colour; the
  *    elements of a colour share no node, each adds to its nodes in place.
- *  TMOP_SCATTER_TILES (the default of 2D meshes): one launch over every
+ *  TMOP_SCATTER_TILES (2D only, on request): one launch over every
  *    element in tiles of neighbouring elements; each workgroup accumulates
  *    its tile's nodes on chip, adding its elements in rounds of elements
  *    that share no node, and writes the nodes only its tile holds; a second
  *    pass adds the tiles' partial sums at nodes shared by several tiles.
- *    tmop_setup builds the tiles of a 2D mesh on the host (device memory:
- *    about 2 bytes per element node, 8 per tile node and 24 per node on a
- *    tile border); a mesh beyond the tile limits keeps the colours.  FP64
+ *    Selecting it the first time builds the tiles on the host from a
+ *    device-to-host copy of the connectivity (device memory: about 2 bytes
+ *    per element node, 8 per tile node and 24 per node on a tile border);
+ *    a mesh beyond the tile limits is refused.  FP64
  *    gradient tiles stage one vector component at a time when the tiles
  *    would not otherwise all fit on the device at once; the environment
  *    variable TMOP_TILE_SPLIT=0 or =1, read when the tiles are built,
  *    forces that choice off or on (same results bit for bit).
- *  TMOP_SCATTER_ELEMENTS (3D only; the default of 3D meshes with colours
- *    of at most 32,768 elements on average): one launch over every element,
- *    each element writing its contributions to the entries of its nodes in
- *    an element vector (dim x (p+1)^3 doubles per element, each node's
- *    entries contiguous, in ascending element order), then a pass that sums
- *    each node's entries in that order.  Selecting it on a context that did
- *    not start with it builds the entry map on the host (a device-to-host
- *    copy of the connectivity; 4 bytes per element node and per node) and
- *    allocates the vector; it syncs the device.
+ *  TMOP_SCATTER_ELEMENTS (the default of 2D meshes and of 3D meshes with
+ *    colours of at most 32,768 elements on average): one launch over every
+ *    element, each element writing its contributions to the entries of its
+ *    nodes in an element vector (dim x (p+1)^dim values per element, FP64
+ *    or, in the mixed path, FP32; each node's entries contiguous, in
+ *    ascending element order), then a pass that sums each node's entries in
+ *    that order, in FP64.  Selecting it on a context that did not start
+ *    with it builds the entry map on the host (a device-to-host copy of the
+ *    connectivity; 4 bytes per element node and per node) and allocates the
+ *    vector; it syncs the device.
  * All are deterministic (fixed summation orders, which differ between
  * them, so results agree to rounding).  The other calls are not affected. */
 enum { TMOP_SCATTER_COLOURS = 0, TMOP_SCATTER_TILES = 1, TMOP_SCATTER_ELEMENTS = 2 };
 
 /* Selects the scatter mode of ctx.  TMOP_E_ARG for an unknown mode,
- * TMOP_E_UNSUPPORTED (mode unchanged) for tiles on a context without them
- * (3D, or a 2D mesh beyond the tile limits), for the element vector on a 2D
- * context or past 2^31 entries; TMOP_E_NOMEM if its buffer cannot be
- * allocated. */
+ * TMOP_E_UNSUPPORTED (mode unchanged) for tiles on a 3D context or a 2D
+ * mesh beyond the tile limits, and for the element vector past 2^31
+ * entries; TMOP_E_NOMEM if a buffer cannot be allocated.  Building the
+ * tiles or the element vector on first selection syncs the device. */
 int tmop_set_scatter(tmop_ctx *ctx, int32_t mode);
 
 /* The scatter mode in effect on ctx (the mesh's default until

@@ -1065,12 +1065,10 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
           gather_rows(c->d_psize, c->d_colors, mesh->n_elem, nq, c->d_psize_col, nullptr) != hipSuccess ||
           hipDeviceSynchronize() != hipSuccess) { st = TMOP_E_HIP; break; }
     }
-    if (d == 2) {   // owner-computes tiles, the default scatter of 2D meshes that fit their limits
-      const int r = make_tiles(c, mesh->elem_node, order);
-      if (r == TMOP_OK) c->scatter = TMOP_SCATTER_TILES;
-      else if (r != TMOP_E_UNSUPPORTED) { st = r; break; }
-    } else if (mesh->n_elem <= EVEC_DEFAULT_ELEMS_PER_COLOUR * (int64_t)(c->color_off.size() - 1)) {
-      // small colours cannot fill the chip: the element vector, one launch
+    if (d == 2 || mesh->n_elem <= EVEC_DEFAULT_ELEMS_PER_COLOUR * (int64_t)(c->color_off.size() - 1)) {
+      // the element vector, one launch over every element: the 2D default (faster than the tiles, whose
+      // workgroups run their tile's colours one after the other) and that of 3D meshes whose colours
+      // cannot fill the chip
       const int r = make_evec(c, mesh->elem_node);
       if (r == TMOP_OK) c->scatter = TMOP_SCATTER_ELEMENTS;
       else if (r != TMOP_E_UNSUPPORTED) { st = r; break; }
@@ -1513,9 +1511,21 @@ int tmop_dfo_solve(tmop_ctx* c, double* x, const tmop_dfo_opts* opts, tmop_dfo_r
 int tmop_set_scatter(tmop_ctx* c, int32_t mode) {
   if (!c || (mode != TMOP_SCATTER_COLOURS && mode != TMOP_SCATTER_TILES && mode != TMOP_SCATTER_ELEMENTS))
     return TMOP_E_ARG;
-  if (mode == TMOP_SCATTER_TILES && !c->tile.node) return TMOP_E_UNSUPPORTED;   // 3D, or no tiles built
+  if (mode == TMOP_SCATTER_TILES && !c->tile.node) {   // built on first use, 2D only
+    if (c->dim != 2) return TMOP_E_UNSUPPORTED;
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    HIP_TRY(hipSetDevice(c->device));
+    std::vector<int32_t> en((size_t)c->n_elem * c->npe), order((size_t)c->n_elem);
+    int r = hipMemcpy(en.data(), c->d_elem_node, en.size() * sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess &&
+                    hipMemcpy(order.data(), c->d_colors, order.size() * sizeof(int32_t), hipMemcpyDeviceToHost) ==
+                        hipSuccess
+                ? make_tiles(c, en.data(), order)
+                : TMOP_E_HIP;
+    (void)hipSetDevice(cur);
+    if (r != TMOP_OK) return r;   // TMOP_E_UNSUPPORTED: a mesh beyond the tile limits
+  }
   if (mode == TMOP_SCATTER_ELEMENTS) {
-    if (c->dim != 3) return TMOP_E_UNSUPPORTED;
     if (!c->d_evec) {
       int cur = 0;
       HIP_TRY(hipGetDevice(&cur));

@@ -1135,7 +1135,10 @@ __device__ __forceinline__ void elem2d_work(const ElemArgs<P, Q, R>& a, int e, i
   }
 }
 
-template <int P, int Q, int METRIC, typename R, int OP, int TGT>
+// EV: the element-vector instantiation (gradient kinds only): each lane
+// stores its nodes' values at their entries of the element vector instead of
+// the read-modify-write.
+template <int P, int Q, int METRIC, typename R, int OP, int TGT, bool EV = false>
 __global__ void __launch_bounds__((Cfg<2, P, Q, R>::BLOCK))
 elem_kernel_2d(const ElemArgs<P, Q, R> a) {
   using C = Cfg<2, P, Q, R>;
@@ -1169,7 +1172,7 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
   // holds about one round of waves, so their latency would otherwise add to
   // the launch's dependent chain
   double old[2][P];
-  if constexpr (!ENERGY_LIKE) {
+  if constexpr (!ENERGY_LIKE && !EV) {
     if (active && p1) {
 #pragma unroll
       for (int i1 = 0; i1 < P; ++i1) {
@@ -1193,7 +1196,10 @@ elem_kernel_2d(const ElemArgs<P, Q, R> a) {
 #pragma unroll
       for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int i1 = 0; i1 < P; ++i1) a.out[c * a.n_node + node[i1]] = old[c][i1] + (double)V[c][i1];
+        for (int i1 = 0; i1 < P; ++i1) {
+          if constexpr (EV) a.evec[(int64_t)c * a.n_ent + a.evpos[(int64_t)e * NPE + ta + P * i1]] = V[c][i1];
+          else a.out[c * a.n_node + node[i1]] = old[c][i1] + (double)V[c][i1];
+        }
     }
   }
 }

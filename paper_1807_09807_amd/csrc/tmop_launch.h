@@ -23,7 +23,7 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   a.tm_pt = lp.tm_pt;
   a.wdetW = lp.wdetW;
   a.kpen = lp.kpen;
-  a.evec = DIM == 3 && (OP == OP_GRAD || OP == OP_EG || OP == OP_HESS) ? static_cast<R*>(lp.evec) : nullptr;
+  a.evec = (OP == OP_GRAD || OP == OP_EG || OP == OP_HESS) ? static_cast<R*>(lp.evec) : nullptr;
   if (a.evec && lp.evec_esize != (int)sizeof(R)) return -1;   // the vector holds the kernels' arithmetic type
   a.evpos = lp.evpos;
   a.n_ent = lp.n_ent;
@@ -82,7 +82,11 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
       else
         hipLaunchKernelGGL((elem_kernel_3d<P, Q, METRIC, R, OP, TGT, PEN, false>), dim3(g), dim3(C::BLOCK), 0, s, ea);
     } else {
-      hipLaunchKernelGGL((elem_kernel_2d<P, Q, METRIC, R, OP, TGT>), dim3(g), dim3(C::BLOCK), 0, s, ea);
+      constexpr bool SCATTER = OP == OP_GRAD || OP == OP_EG || OP == OP_HESS;
+      if (SCATTER && a.evec)
+        hipLaunchKernelGGL((elem_kernel_2d<P, Q, METRIC, R, OP, TGT, SCATTER>), dim3(g), dim3(C::BLOCK), 0, s, ea);
+      else
+        hipLaunchKernelGGL((elem_kernel_2d<P, Q, METRIC, R, OP, TGT, false>), dim3(g), dim3(C::BLOCK), 0, s, ea);
     }
   }
   return hipGetLastError() == hipSuccess ? 0 : -2;

@@ -1,4 +1,4 @@
-"""The element-vector scatter of 3D meshes (TMOP_SCATTER_ELEMENTS): one
+"""The element-vector scatter (TMOP_SCATTER_ELEMENTS, 2D and 3D): one
 launch over every element writing each element's gradient / Hessian-action
 share, then a pass summing each node's entries in ascending element order.
 Against the FP64 oracle element by element (FP64 within 1e-12 relative,
@@ -6,7 +6,7 @@ mixed FP32 within each result's first-order rounding bound), against the
 colour launches (FP64 to rounding: the same element contributions summed in
 another order), bitwise repeatable, with per-point targets, with the fused
 displacement penalty and the second metric term, inside Newton, and at full
-size; and refused on 2D contexts."""
+size."""
 import numpy as np
 import pytest
 
@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 FP64_TOL = 1e-12
-CASES = [c for c in small_cases() if c.dim == 3]
+CASES = small_cases()
 
 
 def _mode(ctx, name):
@@ -134,12 +134,12 @@ def test_newton_with_evec():
 
 
 @pytest.mark.parametrize("dim,n,expect", [(3, 8, "ELEMENTS"), (3, 64, "ELEMENTS"), (3, 66, "COLOURS"),
-                                            (2, 16, "TILES")])
+                                            (2, 16, "ELEMENTS"), (2, 512, "ELEMENTS")])
 def test_default_scatter(dim, n, expect):
-    """The default mode follows the mesh: 2D tiles; in 3D the element vector
-    while the 2^3 colours average at most 32,768 elements (64^3 Q2: exactly
-    that), the colour launches above (66^3: 35,937).  tmop_get_scatter
-    reports it, and then what tmop_set_scatter selects."""
+    """The default mode follows the mesh: in 2D the element vector; in 3D the
+    element vector while the 2^3 colours average at most 32,768 elements
+    (64^3 Q2: exactly that), the colour launches above (66^3: 35,937).
+    tmop_get_scatter reports it, and then what tmop_set_scatter selects."""
     from paper_1807_09807_amd import tmop as T
     say(f"[evec] default scatter dim={dim} n={n}")
     mesh = meshgen.box_mesh(dim, n, 2)
@@ -150,14 +150,31 @@ def test_default_scatter(dim, n, expect):
     ctx.close()
 
 
-def test_evec_refused_in_2d():
+def test_modes_switch_back_and_forth_2d():
+    """2D: the element vector (default), tiles (built on first selection),
+    colours, then the element vector again, bit for bit as the first time;
+    tiles refused in 3D."""
     from paper_1807_09807_amd import tmop as T
-    mesh = meshgen.box_mesh(2, 3, 2)
-    ctx = T.Context(2, 2, mesh.elem_node, mesh.n_node, 4, 2, mesh.h * np.eye(2))
-    with pytest.raises(T.TMOPError) as ei:
-        ctx.set_scatter(T.TMOP_SCATTER_ELEMENTS)
-    assert ei.value.status == T.TMOP_E_UNSUPPORTED
+    mesh = meshgen.box_mesh(2, 6, 2)
+    x = to_dev(meshgen.perturb(mesh, 0.05, 1))
+    ctx = T.Context(2, 2, mesh.elem_node, mesh.n_node, 4, 2, mesh.h * np.eye(2), fixed=mesh.fixed)
+    assert ctx.scatter == T.TMOP_SCATTER_ELEMENTS
+    g0 = ctx.gradient(x).clone()
+    out = {}
+    for mode in (T.TMOP_SCATTER_TILES, T.TMOP_SCATTER_COLOURS, T.TMOP_SCATTER_ELEMENTS):
+        ctx.set_scatter(mode)
+        assert ctx.scatter == mode
+        out[mode] = ctx.gradient(x).clone()
+    assert torch.equal(out[T.TMOP_SCATTER_ELEMENTS], g0)
+    for mode in (T.TMOP_SCATTER_TILES, T.TMOP_SCATTER_COLOURS):
+        assert rel_max_err(out[mode].cpu().numpy(), g0.cpu().numpy()) <= 1e-14
     ctx.close()
+    m3 = meshgen.box_mesh(3, 2, 2)
+    c3 = T.Context(3, 2, m3.elem_node, m3.n_node, 4, 303, m3.h * np.eye(3))
+    with pytest.raises(T.TMOPError) as ei:
+        c3.set_scatter(T.TMOP_SCATTER_TILES)
+    assert ei.value.status == T.TMOP_E_UNSUPPORTED
+    c3.close()
 
 
 @pytest.mark.parametrize("name", ["q2_cube_32", "q2_cube_64"])

@@ -1,5 +1,5 @@
-"""The owner-computes tile scatter of 2D meshes (TMOP_SCATTER_TILES, the
-2D default): the gradient, energy + gradient and Hessian action in one tile
+"""The owner-computes tile scatter of 2D meshes (TMOP_SCATTER_TILES, on
+request): the gradient, energy + gradient and Hessian action in one tile
 launch plus the halo sums, against the FP64 oracle element by element (FP64 within 1e-12
 relative, mixed FP32 within each result's first-order rounding bound),
 against the colour launches (to rounding: the two add the same element
@@ -108,13 +108,13 @@ def test_split_passes_match_bitwise(setup, monkeypatch):
 
 
 def test_switching_modes(setup):
-    """Tiles are the 2D default; the mode is a per-call choice: tiles,
-    colours, tiles again."""
+    """The mode is a per-call choice: tiles, colours, tiles again (bit for
+    bit as the first time)."""
     from paper_1807_09807_amd import tmop as T
     case, mesh, W, v, ref = setup
-    ctx = context(case, mesh, W, 0)
+    ctx = _tiles(context(case, mesh, W, 0))
     x = to_dev(mesh.x)
-    g0 = ctx.gradient(x)
+    g0 = ctx.gradient(x).clone()
     ctx.set_scatter(T.TMOP_SCATTER_COLOURS)
     g1 = ctx.gradient(x)
     ctx.set_scatter(T.TMOP_SCATTER_TILES)
