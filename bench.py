@@ -68,11 +68,11 @@ FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ("tmop_elem.h", "tmop_metrics.h", "tmop_launch.h")
 MEASURED_TRAFFIC = {
     # colour launch of 32,768 elements
-    ("q2_cube_64", "colours"): dict(src_sha256="ed92edec3e93ddcf6fa10df8884868618de3f12feee41374cf0d95ca0cf2ace5",
-                                    fetch_kib=41950.5, write_kib=27967.3),
+    ("q2_cube_64", "colours"): dict(src_sha256="65875487cf28d8271c1b3140ec4c426c840552fffd15963fcfd2f12372e19e4b",
+                                    fetch_kib=41950.5, write_kib=27968.6),
     # element-vector launch over all 262,144 elements (the gather is a kernel of its own)
-    ("q2_cube_64", "elements"): dict(src_sha256="ed92edec3e93ddcf6fa10df8884868618de3f12feee41374cf0d95ca0cf2ace5",
-                                     fetch_kib=102675.1, write_kib=228000.7),
+    ("q2_cube_64", "elements"): dict(src_sha256="65875487cf28d8271c1b3140ec4c426c840552fffd15963fcfd2f12372e19e4b",
+                                     fetch_kib=102675.7, write_kib=227960.4),
 }
 
 
