@@ -305,9 +305,9 @@ class Context:
         return out
 
     def set_scatter(self, mode):
-        """TMOP_SCATTER_COLOURS, TMOP_SCATTER_TILES (2D) or
-        TMOP_SCATTER_ELEMENTS (3D): how the gradient and Hessian action add
-        element contributions at shared nodes."""
+        """TMOP_SCATTER_ELEMENTS, TMOP_SCATTER_COLOURS or TMOP_SCATTER_TILES
+        (2D): how the gradient and Hessian action add element contributions
+        at shared nodes."""
         st = self._lib.tmop_set_scatter(self._h, int(mode))
         if st < 0:
             raise TMOPError(st, "tmop_set_scatter")
