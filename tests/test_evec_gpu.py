@@ -177,25 +177,28 @@ def test_modes_switch_back_and_forth_2d():
     c3.close()
 
 
-@pytest.mark.parametrize("name", ["q2_cube_32", "q2_cube_64"])
+@pytest.mark.parametrize("name", ["q2_cube_32", "q2_cube_64", "q2_square_512", "q3_square_256"])
 def test_evec_full_size(name):
-    """Full workloads, FP64: every DOF against the colour launches, 64 seeded
+    """Full workloads, FP64: every DOF against the colour launches (selected
+    explicitly: the element vector is these meshes' default), 64 seeded
     nodes against the oracle."""
     from paper_1807_09807_amd import tmop as T
     w = meshgen.WORKLOADS[name]
-    mesh = meshgen.box_mesh(3, w["n"], w["p"])
-    W = mesh.h * np.eye(3)
-    prob = O.Problem(3, w["p"], w["Q"], mesh.elem_node, w["metric"], W)
+    d = w["dim"]
+    mesh = meshgen.box_mesh(d, w["n"], w["p"])
+    W = mesh.h * np.eye(d)
+    prob = O.Problem(d, w["p"], w["Q"], mesh.elem_node, w["metric"], W)
     say(f"[evec full] {name}: building")
     mesh = meshgen.make_workload(name, bad_elements=lambda x, e: prob.bad_elements(x, e, w["tau_min"]))
     x = mesh.x
     v = meshgen.random_direction(mesh, w["seed"] + 100)
     nodes = np.random.default_rng(w["seed"] + 200).choice(mesh.n_node, 64, replace=False)
-    ctx = T.Context(3, w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=mesh.fixed)
+    ctx = T.Context(d, w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=mesh.fixed)
+    assert ctx.scatter == T.TMOP_SCATTER_ELEMENTS
     xd, vd = to_dev(x), to_dev(v)
-    gc, hc = ctx.gradient(xd), ctx.hessian_apply(xd, vd)
-    ctx.set_scatter(T.TMOP_SCATTER_ELEMENTS)
     ge, he = ctx.gradient(xd), ctx.hessian_apply(xd, vd)
+    ctx.set_scatter(T.TMOP_SCATTER_COLOURS)
+    gc, hc = ctx.gradient(xd), ctx.hessian_apply(xd, vd)
     ctx.close()
     dg = rel_max_err(ge.cpu().numpy(), gc.cpu().numpy())
     dh = rel_max_err(he.cpu().numpy(), hc.cpu().numpy())
