@@ -474,8 +474,12 @@ int dot_sync(tmop_ctx* c, const double* a, const double* b, hipStream_t s, doubl
 // launch over every element keeps the chip fuller than eight colour
 // launches (VALU busy 55% against 40% for the 64^3 FP64 Hessian action);
 // larger colours fill the chip by themselves while the element vector's
-// traffic keeps growing with the mesh.
+// traffic keeps growing with the mesh (80^3 Q2, 64,000 per colour: step
+// 1.246 ms with colour launches against 1.304 ms).  The mixed path's FP32
+// entries halve that traffic: there the element vector still wins at 80^3
+// (0.973 against 1.021 ms), so its limit is twice as high.
 constexpr int64_t EVEC_DEFAULT_ELEMS_PER_COLOUR = 32768;
+constexpr int64_t EVEC_DEFAULT_ELEMS_PER_COLOUR_MIXED = 65536;
 
 void free_tiles(tmop_ctx* c) {
   TileParams& t = c->tile;
@@ -1065,7 +1069,9 @@ int tmop_setup(const tmop_mesh* mesh, const tmop_quadrature* quad, const tmop_ta
           gather_rows(c->d_psize, c->d_colors, mesh->n_elem, nq, c->d_psize_col, nullptr) != hipSuccess ||
           hipDeviceSynchronize() != hipSuccess) { st = TMOP_E_HIP; break; }
     }
-    if (d == 2 || mesh->n_elem <= EVEC_DEFAULT_ELEMS_PER_COLOUR * (int64_t)(c->color_off.size() - 1)) {
+    const int64_t evec_limit =
+        precision == TMOP_MIXED_FP32 ? EVEC_DEFAULT_ELEMS_PER_COLOUR_MIXED : EVEC_DEFAULT_ELEMS_PER_COLOUR;
+    if (d == 2 || mesh->n_elem <= evec_limit * (int64_t)(c->color_off.size() - 1)) {
       // the element vector, one launch over every element: the 2D default (faster than the tiles, whose
       // workgroups run their tile's colours one after the other) and that of 3D meshes whose colours
       // cannot fill the chip

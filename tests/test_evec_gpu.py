@@ -133,17 +133,21 @@ def test_newton_with_evec():
     assert np.max(np.abs(xe - mesh.x_grid)) < 1e-8 * mesh.h
 
 
-@pytest.mark.parametrize("dim,n,expect", [(3, 8, "ELEMENTS"), (3, 64, "ELEMENTS"), (3, 66, "COLOURS"),
-                                            (2, 16, "ELEMENTS"), (2, 512, "ELEMENTS")])
-def test_default_scatter(dim, n, expect):
+@pytest.mark.parametrize("dim,n,precision,expect", [(3, 8, 0, "ELEMENTS"), (3, 64, 0, "ELEMENTS"),
+                                                      (3, 66, 0, "COLOURS"), (3, 66, 1, "ELEMENTS"),
+                                                      (3, 81, 1, "COLOURS"), (2, 16, 0, "ELEMENTS"),
+                                                      (2, 512, 1, "ELEMENTS")])
+def test_default_scatter(dim, n, precision, expect):
     """The default mode follows the mesh: in 2D the element vector; in 3D the
     element vector while the 2^3 colours average at most 32,768 elements
-    (64^3 Q2: exactly that), the colour launches above (66^3: 35,937).
+    (64^3 Q2: exactly that; 65,536 in the mixed path, 80^3 Q2: 64,000), the
+    colour launches above (66^3: 35,937; mixed, 81^3: 66,430).
     tmop_get_scatter reports it, and then what tmop_set_scatter selects."""
     from paper_1807_09807_amd import tmop as T
-    say(f"[evec] default scatter dim={dim} n={n}")
+    say(f"[evec] default scatter dim={dim} n={n} precision={precision}")
     mesh = meshgen.box_mesh(dim, n, 2)
-    ctx = T.Context(dim, 2, mesh.elem_node, mesh.n_node, 4, 303 if dim == 3 else 2, mesh.h * np.eye(dim))
+    ctx = T.Context(dim, 2, mesh.elem_node, mesh.n_node, 4, 303 if dim == 3 else 2, mesh.h * np.eye(dim),
+                    precision=precision)
     assert ctx.scatter == getattr(T, f"TMOP_SCATTER_{expect}")
     ctx.set_scatter(T.TMOP_SCATTER_COLOURS)
     assert ctx.scatter == T.TMOP_SCATTER_COLOURS
