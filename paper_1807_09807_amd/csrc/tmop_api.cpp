@@ -363,8 +363,8 @@ int assemble(tmop_ctx* c, int op, const double* x, const double* v, double* out,
                               c->d_tsize, primary_term(c, false, 0, fused_penalty(c, op)), nullptr, &c->tile);
     if (r != TMOP_OK) return r;
     off += grid;
-  } else if (c->scatter == TMOP_SCATTER_ELEMENTS && (op == OP_GRAD || op == OP_EG || op == OP_HESS)) {
-    // one launch over every element into the element vector, then the gather (3D)
+  } else if (c->scatter == TMOP_SCATTER_ELEMENTS && (op == OP_GRAD || op == OP_EG || op == OP_HESS || op == OP_DIAG)) {
+    // one launch over every element into the element vector, then the gather
     int grid = 0;
     const int r = elem_launch(c, op, x, v, out, c->d_elem_node, nullptr, c->n_elem, s, &grid, scale, off, nullptr,
                               c->d_tsize, primary_term(c, false, 0, fused_penalty(c, op)), nullptr, nullptr, c->d_evec);

@@ -1399,8 +1399,12 @@ __device__ __forceinline__ void target_congruence(const R (&Wi)[3][3], R (&K6)[D
   }
 }
 
-template <int P, int Q, int METRIC, typename R, int TGT>
+template <int P, int Q, int METRIC, typename R, int TGT, bool EV = false>
+// EV (element-vector stores) asks for two waves per SIMD up to order 2 with
+// a constant target: without the request the Q2 kernel lands 6 registers
+// above 256, one wave.
 __global__ void __launch_bounds__((Cfg<3, P, Q, R>::BLOCK))
+__attribute__((amdgpu_waves_per_eu(EV && P <= 3 && (TGT == TGT_GEN || TGT == TGT_ISO) ? 2 : 1)))
 diag_kernel_3d(const DiagArgs<P, Q, R> a) {
   constexpr bool ISO = TGT == TGT_ISO || TGT == TGT_QPS;
   using C = Cfg<3, P, Q, R>;
@@ -1516,9 +1520,9 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
     }
   }
 
-  bool fresh[P];
+  bool fresh[P];   // EV: each element stores its own share, no old values
 #pragma unroll
-  for (int i2 = 0; i2 < P; ++i2) fresh[i2] = first_touch<NPE>(a.first, kk, ta + P * tb + P * P * i2);
+  for (int i2 = 0; i2 < P; ++i2) fresh[i2] = EV || first_touch<NPE>(a.first, kk, ta + P * tb + P * P * i2);
   __syncthreads();   // U is dead
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -1571,7 +1575,8 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
         R v = 0;
 #pragma unroll
         for (int q2 = 0; q2 < Q; ++q2) v += a.BB[q2][i2] * gbb[q2] + a.BG[q2][i2] * gbg[q2] + a.GG[q2][i2] * ggg[q2];
-        a.out[c * a.n_node + node[i2]] = old[i2] + (double)v;
+        if constexpr (EV) a.evec[(int64_t)c * a.n_ent + a.evpos[(int64_t)e * NPE + ta + P * tb + P * P * i2]] = v;
+        else a.out[c * a.n_node + node[i2]] = old[i2] + (double)v;
       }
     }
   }
@@ -1579,7 +1584,7 @@ diag_kernel_3d(const DiagArgs<P, Q, R> a) {
 
 // 2D pairs (l, m): 0 (0,0), 1 (1,1), 2 (0,1); x tables GG BB BG, y tables
 // BB GG BG.  LDS: the forward U, then the x-transposed sums [pair][c][q1][i0].
-template <int P, int Q, int METRIC, typename R, int TGT>
+template <int P, int Q, int METRIC, typename R, int TGT, bool EV = false>
 __global__ void __launch_bounds__((Cfg<2, P, Q, R>::BLOCK))
 diag_kernel_2d(const DiagArgs<P, Q, R> a) {
   constexpr bool ISO = TGT == TGT_ISO || TGT == TGT_QPS;
@@ -1677,7 +1682,7 @@ diag_kernel_2d(const DiagArgs<P, Q, R> a) {
   if (active && p1) {
 #pragma unroll
     for (int i1 = 0; i1 < P; ++i1) {
-      const bool fresh = first_touch<NPE>(a.first, kk, ta + P * i1);
+      const bool fresh = EV || first_touch<NPE>(a.first, kk, ta + P * i1);   // EV: no old values
 #pragma unroll
       for (int c = 0; c < 2; ++c) old[c][i1] = fresh ? 0.0 : a.out[c * a.n_node + node[i1]];
     }
@@ -1706,7 +1711,8 @@ diag_kernel_2d(const DiagArgs<P, Q, R> a) {
 #pragma unroll
         for (int q1 = 0; q1 < Q; ++q1)
           v += a.BB[q1][i1] * r[0][q1] + a.GG[q1][i1] * r[1][q1] + a.BG[q1][i1] * r[2][q1];
-        a.out[c * a.n_node + node[i1]] = old[c][i1] + (double)v;
+        if constexpr (EV) a.evec[(int64_t)c * a.n_ent + a.evpos[(int64_t)e * NPE + ta + P * i1]] = v;
+        else a.out[c * a.n_node + node[i1]] = old[c][i1] + (double)v;
       }
     }
   }

@@ -23,7 +23,7 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
   a.tm_pt = lp.tm_pt;
   a.wdetW = lp.wdetW;
   a.kpen = lp.kpen;
-  a.evec = (OP == OP_GRAD || OP == OP_EG || OP == OP_HESS) ? static_cast<R*>(lp.evec) : nullptr;
+  a.evec = (OP == OP_GRAD || OP == OP_EG || OP == OP_HESS || OP == OP_DIAG) ? static_cast<R*>(lp.evec) : nullptr;
   if (a.evec && lp.evec_esize != (int)sizeof(R)) return -1;   // the vector holds the kernels' arithmetic type
   a.evpos = lp.evpos;
   a.n_ent = lp.n_ent;
@@ -69,8 +69,13 @@ static int launch_one(const LaunchParams& lp, hipStream_t s, int* grid) {
         a.BG[q][i] = (R)(b * gg);
         a.GG[q][i] = (R)(gg * gg);
       }
-    if constexpr (DIM == 3) hipLaunchKernelGGL((diag_kernel_3d<P, Q, METRIC, R, TGT>), dim3(g), dim3(C::BLOCK), 0, s, a);
-    else hipLaunchKernelGGL((diag_kernel_2d<P, Q, METRIC, R, TGT>), dim3(g), dim3(C::BLOCK), 0, s, a);
+    if constexpr (DIM == 3) {
+      if (a.evec) hipLaunchKernelGGL((diag_kernel_3d<P, Q, METRIC, R, TGT, true>), dim3(g), dim3(C::BLOCK), 0, s, a);
+      else hipLaunchKernelGGL((diag_kernel_3d<P, Q, METRIC, R, TGT, false>), dim3(g), dim3(C::BLOCK), 0, s, a);
+    } else {
+      if (a.evec) hipLaunchKernelGGL((diag_kernel_2d<P, Q, METRIC, R, TGT, true>), dim3(g), dim3(C::BLOCK), 0, s, a);
+      else hipLaunchKernelGGL((diag_kernel_2d<P, Q, METRIC, R, TGT, false>), dim3(g), dim3(C::BLOCK), 0, s, a);
+    }
   } else {
     const ElemArgs<P, Q, R>& ea = a;
     if constexpr (DIM == 3) {
