@@ -68,11 +68,11 @@ FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ("tmop_elem.h", "tmop_metrics.h", "tmop_launch.h")
 MEASURED_TRAFFIC = {
     # colour launch of 32,768 elements
-    ("q2_cube_64", "colours"): dict(src_sha256="65875487cf28d8271c1b3140ec4c426c840552fffd15963fcfd2f12372e19e4b",
-                                    fetch_kib=41950.5, write_kib=27968.6),
+    ("q2_cube_64", "colours"): dict(src_sha256="aa216c61c303be4cf830bdfab16ac8fd415554b74081a6a2cf94206f3f901cee",
+                                    fetch_kib=41952.1, write_kib=27968.3),
     # element-vector launch over all 262,144 elements (the gather is a kernel of its own)
-    ("q2_cube_64", "elements"): dict(src_sha256="65875487cf28d8271c1b3140ec4c426c840552fffd15963fcfd2f12372e19e4b",
-                                     fetch_kib=102675.7, write_kib=227960.4),
+    ("q2_cube_64", "elements"): dict(src_sha256="aa216c61c303be4cf830bdfab16ac8fd415554b74081a6a2cf94206f3f901cee",
+                                     fetch_kib=102673.6, write_kib=227995.8),
 }
 
 
