@@ -212,3 +212,60 @@ def test_evec_full_size(name):
     eh = np.max(np.abs(he[:, idx].cpu().numpy() - h_ref)) / np.max(np.abs(h_ref))
     say(f"  {name}: elements vs colours g {dg:.1e} Hv {dh:.1e}; vs oracle at 64 nodes g {eg:.1e} Hv {eh:.1e}")
     assert dg <= 1e-14 and dh <= 1e-14 and eg <= FP64_TOL and eh <= FP64_TOL
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_evec_runs_of_any_length(precision):
+    """The sum over a node's entries for runs outside a structured quad
+    mesh's 1 to 4: five Q2 quadrilaterals around one vertex (a run of 5,
+    past the unrolled loads) and one node that no element uses (a run of 0,
+    whose gradient, Hessian action and diagonal are zero).  Against the
+    oracle at the FP64 bar, or the mixed path's rounding bound."""
+    from tests.test_dfo_gpu import _pentagon
+    from paper_1807_09807_amd import tmop as T
+    x, en, _ = _pentagon()
+    x = np.concatenate([x, [[2.0], [2.0]]], axis=1)          # the unused node
+    n = x.shape[1]
+    W = 0.8 * np.eye(2)
+    prob = O.Problem(2, 2, 4, en, 2, W)
+    v = np.random.default_rng(7).uniform(-1, 1, x.shape)
+    ref = dict(g=prob.gradient(x), Hv=prob.hessian_apply(x, v), D=prob.hessian_diagonal(x))
+    assert np.all(ref["g"][:, -1] == 0) and np.all(ref["D"][:, -1] == 0)
+    tol = dict(g=FP64_TOL, Hv=FP64_TOL, diag=FP64_TOL) if precision == 0 else mixed_tol(prob, x, v, diag=True)
+    ctx = T.Context(2, 2, en, n, 4, 2, W, precision=precision)
+    assert ctx.scatter == T.TMOP_SCATTER_ELEMENTS
+    xd, vd = to_dev(x), to_dev(v)
+    g, Hv, D = ctx.gradient(xd).cpu().numpy(), ctx.hessian_apply(xd, vd).cpu().numpy(), \
+        ctx.hessian_diagonal(xd).cpu().numpy()
+    eg, eh, ed = rel_max_err(g, ref["g"]), rel_max_err(Hv, ref["Hv"]), rel_max_err(D, ref["D"])
+    say(f"  pentagon prec={precision}: g {eg:.2e} Hv {eh:.2e} diag {ed:.2e}")
+    assert eg <= tol["g"] and eh <= tol["Hv"] and ed <= tol["diag"]
+    assert np.all(g[:, -1] == 0) and np.all(Hv[:, -1] == 0) and np.all(D[:, -1] == 0)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_evec_long_runs(precision):
+    """Every element of a 4x4 Q2 patch given 8 times: runs of 8 to 32 entries
+    per node, beyond the unrolled loads, and more entries per block of nodes
+    than the FP32 gather stages, so its per-lane fallback runs.  F, g, Hv
+    and the diagonal are 8 times one copy's; against the oracle on the same
+    connectivity."""
+    from paper_1807_09807_amd import tmop as T
+    mesh = meshgen.box_mesh(2, 4, 2)
+    x = meshgen.perturb(mesh, 0.1, seed=5)
+    en = np.tile(np.asarray(mesh.elem_node), (8, 1))
+    W = mesh.h * np.eye(2)
+    prob = O.Problem(2, 2, 4, en, 2, W)
+    v = np.random.default_rng(8).uniform(-1, 1, x.shape)
+    ref = dict(g=prob.gradient(x), Hv=prob.hessian_apply(x, v), D=prob.hessian_diagonal(x))
+    tol = dict(g=FP64_TOL, Hv=FP64_TOL, diag=FP64_TOL) if precision == 0 else mixed_tol(prob, x, v, diag=True)
+    ctx = T.Context(2, 2, en, mesh.n_node, 4, 2, W, precision=precision)
+    assert ctx.scatter == T.TMOP_SCATTER_ELEMENTS
+    xd, vd = to_dev(x), to_dev(v)
+    g, Hv, D = ctx.gradient(xd).cpu().numpy(), ctx.hessian_apply(xd, vd).cpu().numpy(), \
+        ctx.hessian_diagonal(xd).cpu().numpy()
+    eg, eh, ed = rel_max_err(g, ref["g"]), rel_max_err(Hv, ref["Hv"]), rel_max_err(D, ref["D"])
+    say(f"  8x patch prec={precision}: g {eg:.2e} Hv {eh:.2e} diag {ed:.2e}")
+    assert eg <= tol["g"] and eh <= tol["Hv"] and ed <= tol["diag"]
+    ctx.close()
