@@ -271,8 +271,9 @@ def time_workload(T, torch, dev, name, steps, warmup, log, gpu_repair=False):
     results = {}
     # the mesh's default scatter beside the other one: 2D, the tiles beside the
     # colour launches; 3D, the colour launches and the element-vector scatter
-    # (the default of 3D meshes with colours of at most 32,768 elements on
-    # average, such as q2_cube_64, q2_cube_32 and q3_cube_48)
+    # (the default of 3D meshes with colours of at most 49,152 elements on
+    # average, 131,072 in the mixed path, such as q2_cube_64, q2_cube_32 and
+    # q3_cube_48)
     probe = T.Context(w["dim"], w["p"], mesh.elem_node, mesh.n_node, w["Q"], w["metric"], W, fixed=mesh.fixed)
     main = probe.scatter
     probe.close()

@@ -284,7 +284,7 @@ int tmop_hessian_diagonal(tmop_ctx *ctx, const double *x, double *diag, void *st
  * element contributions to shared nodes (Section 3.4 sums them over the
  * elements holding each node):
  *  TMOP_SCATTER_COLOURS (the default of 3D meshes with colours of more
- *    than 32,768 elements on average, 65,536 in the mixed path): one launch
+ *    than 49,152 elements on average, 131,072 in the mixed path): one launch
  *    per element colour; the
  *    elements of a colour share no node, each adds to its nodes in place.
  *  TMOP_SCATTER_TILES (2D only, on request): one launch over every
@@ -301,7 +301,7 @@ int tmop_hessian_diagonal(tmop_ctx *ctx, const double *x, double *diag, void *st
  *    variable TMOP_TILE_SPLIT=0 or =1, read when the tiles are built,
  *    forces that choice off or on (same results bit for bit).
  *  TMOP_SCATTER_ELEMENTS (the default of 2D meshes and of 3D meshes with
- *    colours of at most 32,768 elements on average, 65,536 in the mixed
+ *    colours of at most 49,152 elements on average, 131,072 in the mixed
  *    path): one launch over every
  *    element, each element writing its contributions to the entries of its
  *    nodes in an element vector (dim x (p+1)^dim values per element, FP64

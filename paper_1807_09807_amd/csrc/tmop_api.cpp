@@ -467,19 +467,18 @@ int dot_sync(tmop_ctx* c, const double* a, const double* b, hipStream_t s, doubl
 }
 
 // 3D meshes whose colours average at most this many elements default to the
-// element-vector scatter.  Measured per operation on MI355X against the
-// colour launches: 4,096 Q2 hexes per colour (32^3 mesh) 31-37% faster,
-// 13,824 Q3 hexes (48^3) 8-11% faster, 32,768 Q2 hexes (64^3) Hessian
-// action 4% faster, energy + gradient 2% slower, the step even.  Its one
+// element-vector scatter.  Measured on MI355X against the colour launches,
+// Q2 hex meshes, energy + gradient and Hessian action per step: its one
 // launch over every element keeps the chip fuller than eight colour
-// launches (VALU busy 55% against 40% for the 64^3 FP64 Hessian action);
-// larger colours fill the chip by themselves while the element vector's
-// traffic keeps growing with the mesh (80^3 Q2, 64,000 per colour: step
-// 1.246 ms with colour launches against 1.304 ms).  The mixed path's FP32
-// entries halve that traffic: there the element vector still wins at 80^3
-// (0.973 against 1.021 ms), so its limit is twice as high.
-constexpr int64_t EVEC_DEFAULT_ELEMS_PER_COLOUR = 32768;
-constexpr int64_t EVEC_DEFAULT_ELEMS_PER_COLOUR_MIXED = 65536;
+// launches (VALU busy 55% against 40% for the 64^3 FP64 Hessian action),
+// while its traffic grows with the mesh and larger colours fill the chip by
+// themselves.  FP64 steps: 64^3 (32,768 per colour) 0.639 against 0.667 ms,
+// 72^3 (46,656) 0.930 against 0.947 ms, 80^3 (64,000) 1.274 against
+// 1.261 ms, 96^3 (110,592) 2.212 against 2.165 ms.  The mixed path's FP32
+// entries halve the vector's traffic and it wins at every size measured:
+// 80^3 0.921 against 1.027 ms, 96^3 1.575 against 1.724 ms.
+constexpr int64_t EVEC_DEFAULT_ELEMS_PER_COLOUR = 49152;
+constexpr int64_t EVEC_DEFAULT_ELEMS_PER_COLOUR_MIXED = 131072;
 
 void free_tiles(tmop_ctx* c) {
   TileParams& t = c->tile;

@@ -133,15 +133,15 @@ def test_newton_with_evec():
     assert np.max(np.abs(xe - mesh.x_grid)) < 1e-8 * mesh.h
 
 
-@pytest.mark.parametrize("dim,n,precision,expect", [(3, 8, 0, "ELEMENTS"), (3, 64, 0, "ELEMENTS"),
-                                                      (3, 66, 0, "COLOURS"), (3, 66, 1, "ELEMENTS"),
-                                                      (3, 81, 1, "COLOURS"), (2, 16, 0, "ELEMENTS"),
-                                                      (2, 512, 1, "ELEMENTS")])
+@pytest.mark.parametrize("dim,n,precision,expect", [(3, 8, 0, "ELEMENTS"), (3, 72, 0, "ELEMENTS"),
+                                                      (3, 74, 0, "COLOURS"), (3, 74, 1, "ELEMENTS"),
+                                                      (3, 101, 1, "ELEMENTS"), (3, 102, 1, "COLOURS"),
+                                                      (2, 16, 0, "ELEMENTS"), (2, 512, 1, "ELEMENTS")])
 def test_default_scatter(dim, n, precision, expect):
     """The default mode follows the mesh: in 2D the element vector; in 3D the
-    element vector while the 2^3 colours average at most 32,768 elements
-    (64^3 Q2: exactly that; 65,536 in the mixed path, 80^3 Q2: 64,000), the
-    colour launches above (66^3: 35,937; mixed, 81^3: 66,430).
+    element vector while the 2^3 colours average at most 49,152 elements
+    (72^3 Q2: 46,656; 131,072 in the mixed path, 101^3 Q2: 128,788), the
+    colour launches above (74^3: 50,653; mixed, 102^3: 132,651).
     tmop_get_scatter reports it, and then what tmop_set_scatter selects."""
     from paper_1807_09807_amd import tmop as T
     say(f"[evec] default scatter dim={dim} n={n} precision={precision}")
