@@ -244,28 +244,31 @@ def test_evec_runs_of_any_length(precision):
     ctx.close()
 
 
+@pytest.mark.parametrize("dim,copies", [(2, 8), (3, 4)], ids=["2d_x8", "3d_x4"])
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
-def test_evec_long_runs(precision):
-    """Every element of a 4x4 Q2 patch given 8 times: runs of 8 to 32 entries
-    per node, beyond the unrolled loads, and more entries per block of nodes
-    than the FP32 gather stages, so its per-lane fallback runs.  F, g, Hv
-    and the diagonal are 8 times one copy's; against the oracle on the same
+def test_evec_long_runs(precision, dim, copies):
+    """Every element of a Q2 block (4x4, or 3x3x3) given several times (8 in
+    2D, 4 in 3D): runs of up to 32 entries per node, beyond the unrolled
+    loads, and more entries in a block of 256 nodes than the FP32 gather
+    stages (1,024 in 2D, 2,048 in 3D), so its per-lane fallback runs (in 3D
+    the second block of nodes is staged).  Against the oracle on the same
     connectivity."""
     from paper_1807_09807_amd import tmop as T
-    mesh = meshgen.box_mesh(2, 4, 2)
+    mesh = meshgen.box_mesh(dim, 4 if dim == 2 else 3, 2)
     x = meshgen.perturb(mesh, 0.1, seed=5)
-    en = np.tile(np.asarray(mesh.elem_node), (8, 1))
-    W = mesh.h * np.eye(2)
-    prob = O.Problem(2, 2, 4, en, 2, W)
+    en = np.tile(np.asarray(mesh.elem_node), (copies, 1))
+    W = mesh.h * np.eye(dim)
+    metric = 2 if dim == 2 else 303
+    prob = O.Problem(dim, 2, 4, en, metric, W)
     v = np.random.default_rng(8).uniform(-1, 1, x.shape)
     ref = dict(g=prob.gradient(x), Hv=prob.hessian_apply(x, v), D=prob.hessian_diagonal(x))
     tol = dict(g=FP64_TOL, Hv=FP64_TOL, diag=FP64_TOL) if precision == 0 else mixed_tol(prob, x, v, diag=True)
-    ctx = T.Context(2, 2, en, mesh.n_node, 4, 2, W, precision=precision)
+    ctx = T.Context(dim, 2, en, mesh.n_node, 4, metric, W, precision=precision)
     assert ctx.scatter == T.TMOP_SCATTER_ELEMENTS
     xd, vd = to_dev(x), to_dev(v)
     g, Hv, D = ctx.gradient(xd).cpu().numpy(), ctx.hessian_apply(xd, vd).cpu().numpy(), \
         ctx.hessian_diagonal(xd).cpu().numpy()
     eg, eh, ed = rel_max_err(g, ref["g"]), rel_max_err(Hv, ref["Hv"]), rel_max_err(D, ref["D"])
-    say(f"  8x patch prec={precision}: g {eg:.2e} Hv {eh:.2e} diag {ed:.2e}")
+    say(f"  {dim}D x{copies} prec={precision}: g {eg:.2e} Hv {eh:.2e} diag {ed:.2e}")
     assert eg <= tol["g"] and eh <= tol["Hv"] and ed <= tol["diag"]
     ctx.close()
